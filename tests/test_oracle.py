@@ -1,0 +1,310 @@
+"""Pins for the CPU oracle: hand-worked values, exact-rational brute force,
+invariants and planted mistakes.  CPU only."""
+import json
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+from exact_rational import exact_knn
+from paper_2112_10408_amd import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _val(s):
+    if s is None:
+        return None
+    if isinstance(s, (int, float)):
+        return float(s)
+    if s == "inf":
+        return math.inf
+    return float(Fraction(s))
+
+
+def _soa(rows):
+    a = np.array([[float(Fraction(str(v))) for v in r] for r in rows], dtype=np.float64)
+    return tuple(a[:, i].astype(np.float32) for i in range(4))
+
+
+def _cases(name, key):
+    with open(os.path.join(GOLDEN, name)) as f:
+        return json.load(f)[key]
+
+
+@pytest.mark.parametrize("case", _cases("knn_cases.json", "cases"), ids=lambda c: c["name"])
+def test_knn_golden(case):
+    pts = _soa(case["points"])
+    qs = _soa(case["queries"])
+    idx, dist = oracle.knn(pts, qs, case["scale"], case["t_window"], case["k"])
+    assert idx.tolist() == case["idx"]
+    want = np.array([[_val(v) for v in row] for row in case["dist"]])
+    assert np.array_equal(dist, want)
+
+
+def _dyadic(rng, n, lo=-64, hi=64, den=8):
+    return (rng.integers(lo * den, hi * den, n) / den).astype(np.float32)
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_knn_equals_exact_rational_on_dyadic(seed):
+    rng = np.random.default_rng(seed)
+    n, nq, k = 40, 12, int(rng.integers(1, 9))
+    pts = tuple(_dyadic(rng, n) for _ in range(3)) + (_dyadic(rng, n, 0, 32, 4),)
+    qs = tuple(_dyadic(rng, nq) for _ in range(3)) + (_dyadic(rng, nq, 0, 32, 4),)
+    scale = [1.0, 1.0, 2.0, 0.25] if seed % 2 else [0.5, 0.5, 4.0, 0.125]
+    tw = [0.0, 0.5, 2.0][seed % 3]
+    idx, dist = oracle.knn(pts, qs, scale, tw, k)
+    ei, ed = exact_knn(pts, qs, scale, tw, k)
+    assert np.array_equal(idx, ei)
+    # dyadic inputs with a few bits: every binary64 operation is exact
+    assert np.array_equal(dist, np.array([[float(v) for v in row] for row in ed]))
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_knn_ranks_by_exact_distance_on_float_data(seed):
+    """On general float data the oracle's order may differ from the exact
+    real order only between distances within a few binary64 ulps."""
+    rng = np.random.default_rng(100 + seed)
+    n, nq, k = 60, 8, 6
+    pts = tuple(rng.uniform(0, 50, n).astype(np.float32) for _ in range(4))
+    qs = tuple(rng.uniform(0, 50, nq).astype(np.float32) for _ in range(4))
+    scale = [1.0, 1.0, 10.0, 0.05]
+    idx, dist = oracle.knn(pts, qs, scale, 0.0, k)
+    ei, ed = exact_knn(pts, qs, scale, 0.0, k)
+    for q in range(nq):
+        for r in range(k):
+            if ei[q, r] < 0:
+                assert idx[q, r] == -1
+                continue
+            assert abs(dist[q, r] - float(ed[q][r])) <= 1e-14 * float(ed[q][r])
+
+
+def test_knn_invariants_translation_and_scale():
+    rng = np.random.default_rng(7)
+    n, nq, k = 80, 16, 5
+    pts = tuple(_dyadic(rng, n) for _ in range(3)) + (_dyadic(rng, n, 0, 32, 4),)
+    qs = tuple(_dyadic(rng, nq) for _ in range(3)) + (_dyadic(rng, nq, 0, 32, 4),)
+    s = [1.0, 1.0, 2.0, 0.25]
+    i0, d0 = oracle.knn(pts, qs, s, 0.0, k)
+    # translation of every coordinate (dyadic shift keeps arithmetic exact)
+    sh = (np.float32(256.0), np.float32(-128.0), np.float32(64.0), np.float32(512.0))
+    i1, d1 = oracle.knn(tuple(p + c for p, c in zip(pts, sh)), tuple(q + c for q, c in zip(qs, sh)), s, 0.0, k)
+    assert np.array_equal(i0, i1) and np.array_equal(d0, d1)
+    # multiplying every scale by 4 multiplies every distance by 4
+    i2, d2 = oracle.knn(pts, qs, [4 * v for v in s], 0.0, k)
+    assert np.array_equal(i0, i2) and np.array_equal(d2, 4 * d0)
+    # swapping x and y together with their scales changes nothing
+    i3, d3 = oracle.knn((pts[1], pts[0], pts[2], pts[3]), (qs[1], qs[0], qs[2], qs[3]), [1.0, 1.0, 2.0, 0.25], 0.0, k)
+    assert np.array_equal(i0, i3) and np.array_equal(d0, d3)
+
+
+def test_knn_properties_on_trajectories():
+    ps = synth.trajectories(30, 40, 200.0, 1800.0, seed=11)
+    qs, _ = synth.sample_queries(ps, 200, seed=12)
+    k = 12
+    s = synth.SCALE
+    idx, dist = oracle.knn(ps.soa(), qs.soa(), s, 0.0, k)
+    P = np.stack([a.astype(np.float64) for a in ps.soa()], 1)
+    Q = np.stack([a.astype(np.float64) for a in qs.soa()], 1)
+    for q in range(qs.n):
+        valid = P[:, 3] < Q[q, 3]
+        diff = Q[q][None] - P
+        d = (((s[0] * diff[:, 0] ** 2 + s[1] * diff[:, 1] ** 2) + s[2] * diff[:, 2] ** 2) + s[3] * diff[:, 3] ** 2)
+        order = np.lexsort((np.arange(ps.n), d))
+        order = order[valid[order]][:k]
+        m = len(order)
+        assert idx[q, :m].tolist() == order.tolist()
+        assert np.array_equal(dist[q, :m], d[order])
+        assert np.all(idx[q, m:] == -1) and np.all(np.isinf(dist[q, m:]))
+
+
+def test_planted_mistake_is_caught():
+    """A dropped time term (a plausible slip) disagrees with T1's hand values."""
+    case = _cases("knn_cases.json", "cases")[0]
+    pts = _soa(case["points"])
+    qs = _soa(case["queries"])
+    idx, dist = oracle.knn(pts, qs, [1, 1, 1, 0], 0, 3)  # time term dropped
+    want = np.array([[_val(v) for v in row] for row in case["dist"]])
+    assert not np.array_equal(dist, want)
+
+
+# ---------------------------------------------------------------- segments --
+@pytest.mark.parametrize("case", _cases("segment_cases.json", "segments"), ids=lambda c: c["name"])
+def test_segments_golden(case):
+    pts = _soa(case["points"])
+    seg = oracle.segments(pts, np.array(case["offsets"]), case["seg_len"])
+    assert seg["start"].tolist() == case["start"]
+    assert seg["count"].tolist() == case["count"]
+    for key in ("a", "b", "tmin", "tmax", "e"):
+        assert np.array_equal(seg[key], np.array(case[key], dtype=np.float64)), key
+
+
+def _dist_to_segment_dense(P, A, B, s):
+    """Minimum over the segment by bounded scalar minimisation of the convex
+    distance along it (no projection formula involved)."""
+    from scipy.optimize import minimize_scalar
+    f = lambda u: float(np.sqrt((((P - (A + u * (B - A))) ** 2) * s).sum()))
+    r = minimize_scalar(f, bounds=(0.0, 1.0), method="bounded", options={"xatol": 1e-12})
+    return min(r.fun, f(0.0), f(1.0))
+
+
+def test_segment_radius_covers_members():
+    ps = synth.trajectories(6, 70, 500.0, 3600.0, seed=3)
+    seg = oracle.segments(ps.soa(), ps.offsets, 16)
+    P = np.stack([a.astype(np.float64) for a in ps.soa()], 1)
+    s = np.array([1.0, 1.0, 10.0])
+    assert seg["count"].sum() == ps.n
+    for j in range(seg["start"].shape[0]):
+        R = math.sqrt((s * seg["e"][j] ** 2).sum())
+        for i in range(seg["start"][j], seg["start"][j] + seg["count"][j]):
+            assert _dist_to_segment_dense(P[i, :3], seg["a"][j], seg["b"][j], s) <= R + 1e-9
+            assert seg["tmin"][j] <= P[i, 3] <= seg["tmax"][j]
+
+
+# ------------------------------------------------------------ lower bounds --
+def _printed_bound(seg, q, scale):
+    """The bound as printed in Algorithm 1 (Euclidean unit vector, squared
+    error subtracted, time gap t_B - t): a planted alternative reading."""
+    A, B = seg["a"][0], seg["b"][0]
+    AB = B - A
+    P = np.array(q[:3], dtype=np.float64)
+    n2 = (AB * AB).sum()
+    u = 0.0 if n2 == 0 else min(max(((P - A) * AB).sum() / n2, 0.0), 1.0)
+    Ps = A + u * AB
+    s = np.array(scale, dtype=np.float64)
+    D = (s[:3] * (Ps - P) ** 2).sum() + s[3] * max(seg["tmax"][0] - q[3], 0.0) ** 2
+    E = s[:3].max() * (seg["e"][0] ** 2).sum()
+    return max(D - E, 0.0)
+
+
+@pytest.mark.parametrize("case", _cases("segment_cases.json", "lower_bounds"), ids=lambda c: c["name"])
+def test_lower_bound_golden(case):
+    pts = _soa(case["points"])
+    seg = oracle.segments(pts, np.array(case["offsets"]), case["seg_len"])
+    q = tuple(np.array([v], dtype=np.float32) for v in case["query"])
+    lb = oracle.lower_bound(seg, q, case["scale"], case["t_window"])[0, 0]
+    want = _val(case["lb"])
+    if math.isinf(want):
+        assert math.isinf(lb)
+    else:
+        assert lb == pytest.approx(want, rel=1e-14, abs=1e-14)
+    _, d = oracle.knn(pts, q, case["scale"], case["t_window"], 1)
+    assert d[0, 0] == _val(case["nearest_member_dist"])
+    assert lb <= d[0, 0]
+    if case["printed_form"] is not None:
+        pb = _printed_bound(seg, case["query"], case["scale"])
+        assert pb == pytest.approx(_val(case["printed_form"]), rel=1e-14)
+        assert pb > d[0, 0]  # the printed reading would prune the true neighbour
+
+
+def _climbing(seed, n_traj=12, n_pts=45):
+    """Trajectories that also move in z and wiggle, so that anisotropic scales
+    matter for the projection."""
+    rng = np.random.default_rng(seed)
+    ps = synth.trajectories(n_traj, n_pts, 80.0, 600.0, seed)
+    ps.z = (ps.z + np.cumsum(rng.normal(0, 0.3, ps.n))).astype(np.float32)
+    ps.y = (ps.y + rng.normal(0, 0.4, ps.n)).astype(np.float32)
+    return ps
+
+
+@pytest.mark.parametrize("seed", range(3))
+@pytest.mark.parametrize("scale", [(1, 1, 10, 0.05), (1, 3, 100, 0.5), (0.2, 1, 1, 0.0)])
+def test_lower_bound_never_exceeds_member_distance(seed, scale):
+    ps = _climbing(seed)
+    seg = oracle.segments(ps.soa(), ps.offsets, 11)
+    rng = np.random.default_rng(seed + 50)
+    # queries: data points, points on segments, and random points nearby
+    qi = rng.choice(ps.n, 60, replace=False)
+    qx = np.concatenate([ps.x[qi], rng.uniform(-5, 90, 40).astype(np.float32)])
+    qy = np.concatenate([ps.y[qi], rng.uniform(-5, 90, 40).astype(np.float32)])
+    qz = np.concatenate([ps.z[qi], rng.uniform(0, 20, 40).astype(np.float32)])
+    qt = np.concatenate([ps.t[qi] + 0.5, rng.uniform(0, 700, 40)]).astype(np.float32)
+    lb = oracle.lower_bound(seg, (qx, qy, qz, qt), scale, 0.0)
+    P = np.stack([a.astype(np.float64) for a in ps.soa()], 1)
+    s = np.array(scale, dtype=np.float64)
+    for j in range(seg["start"].shape[0]):
+        mem = slice(seg["start"][j], seg["start"][j] + seg["count"][j])
+        diff = np.stack([qx, qy, qz, qt], 1).astype(np.float64)[:, None, :] - P[None, mem]
+        d = (s * diff ** 2).sum(-1)
+        valid = P[None, mem, 3] < qt.astype(np.float64)[:, None]
+        dmin = np.where(valid, d, np.inf).min(1)
+        assert np.all(lb[:, j] <= dmin * (1 + 1e-12))
+        # mask is exact: finite bound iff some member is valid
+        assert np.array_equal(np.isfinite(lb[:, j]), valid.any(1))
+
+
+def test_lower_bound_tight_for_exact_segments():
+    """Collinear, evenly timed points: R = 0, and a query on the line after
+    the last point has the last point's distance as its bound."""
+    x = np.arange(8, dtype=np.float32)
+    z = np.zeros(8, np.float32)
+    t = np.arange(8, dtype=np.float32) * 2
+    seg = oracle.segments((x, z, z, t), np.array([0, 8]), 8)
+    q = (np.array([10.0], np.float32), np.zeros(1, np.float32), np.zeros(1, np.float32), np.array([20.0], np.float32))
+    lb = oracle.lower_bound(seg, q, (1, 1, 1, 1), 0.0)[0, 0]
+    assert lb == 9.0 + 36.0
+
+
+# --------------------------------------------------------- learned radius --
+def test_mlp_backprop_matches_finite_differences():
+    rng = np.random.default_rng(5)
+    theta = rng.normal(0, 0.3, oracle.N_PARAMS)
+    X = rng.normal(0, 1, (17, oracle.N_IN))
+    y = rng.normal(1, 0.5, 17)
+    y[3] = np.nan  # unlabeled sample is ignored
+    loss, g = oracle.mlp_loss_grad(theta, X, y)
+    which = list(rng.choice(oracle.N_PARAMS, 120, replace=False)) + [oracle.N_PARAMS - 1]
+    fd = oracle.finite_difference_grad(theta, X, y, h=1e-6, which=which)
+    assert np.allclose(g[which], fd[which], rtol=1e-5, atol=1e-8)
+    assert loss == pytest.approx(oracle.mlp_loss(theta, X, y))
+
+
+def test_mlp_closed_form_constant_network():
+    """All weights zero: out = b3 everywhere, loss = mean (b3 - y)^2 and
+    only b3 has a gradient, 2 mean(b3 - y)."""
+    theta = np.zeros(oracle.N_PARAMS)
+    theta[-1] = 1.5
+    X = np.ones((4, oracle.N_IN))
+    y = np.array([1.0, 2.0, 3.0, 4.0])
+    loss, g = oracle.mlp_loss_grad(theta, X, y)
+    assert loss == pytest.approx(((1.5 - y) ** 2).mean())
+    assert g[-1] == pytest.approx(2 * (1.5 - y).mean())
+    assert np.all(g[:-1] == 0)
+
+
+def test_adam_first_step_closed_form():
+    """First Adam step: bias correction gives m_hat = g, v_hat = g^2, so the
+    update is -lr g / (|g| + eps)."""
+    g = np.array([0.5, -2.0, 1e-3, 0.0])
+    th, m, v = oracle.adam_step(np.zeros(4), g, np.zeros(4), np.zeros(4), 1, lr=0.01)
+    assert np.allclose(th, -0.01 * g / (np.abs(g) + 1e-8), rtol=1e-12)
+    assert np.allclose(m, 0.1 * g) and np.allclose(v, 0.001 * g * g)
+
+
+def test_radius_cells_and_label():
+    lo = np.array([0.0, 0.0, 0.0, 0.0], np.float32)
+    hi = np.array([32.0, 64.0, 1.0, 3200.0], np.float32)
+    cx, cy, ct = oracle.radius_cells(np.array([0.0, 31.999, 32.0, -5.0], np.float32),
+                                     np.array([63.99, 2.0, 1.0, 70.0], np.float32),
+                                     np.array([100.0, 3199.0, 3200.0, 0.0], np.float32), lo, hi)
+    assert cx.tolist() == [0, 31, 31, 0]
+    assert cy.tolist() == [31, 1, 0, 31]
+    assert ct.tolist() == [1, 31, 31, 0]
+    lab = oracle.radius_label(np.array([4.0, np.inf, 0.0]))
+    assert lab[0] == pytest.approx(math.log(2.0)) and np.isnan(lab[1]) and np.isnan(lab[2])
+
+
+def test_generator_is_seeded_and_sorted():
+    a = synth.trajectories(20, 33, 100.0, 600.0, seed=9)
+    b = synth.trajectories(20, 33, 100.0, 600.0, seed=9)
+    for u, v in zip(a.soa(), b.soa()):
+        assert u.tobytes() == v.tobytes()
+    for j in range(20):
+        tt = a.t[a.offsets[j]:a.offsets[j + 1]]
+        assert np.all(np.diff(tt) > 0)
+        step = np.hypot(np.diff(a.x[a.offsets[j]:a.offsets[j + 1]]), np.diff(a.y[a.offsets[j]:a.offsets[j + 1]]))
+        assert np.all((step > 0.6) & (step < 1.3))  # ~230 m/s over 4 s
