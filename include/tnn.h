@@ -1,0 +1,171 @@
+/*
+ * tnn.h -- exact Trajectory Nearest Neighbours (TNN) on AMD Instinct MI355X.
+ *
+ * Exact k-nearest-neighbour search over points that lie along time-sorted
+ * trajectories, under the per-feature scaled squared metric
+ *     d(q, p) = s_x dx^2 + s_y dy^2 + s_z dz^2 + s_t dt^2        (Sec. 3.4)
+ * with the strict causal mask  t_p < t_q - t_w                    (Sec. 3.4,
+ * masked temporal part; Sec. 3.5).  Trajectories are cut into segments of
+ * K consecutive points, each covered by a cylinder (segment plus radius,
+ * Sec. 3.4); a query ranks cylinders by a lower bound on the distance to any
+ * member, scans the members of the nearest ones and stops once its k-th
+ * distance is below every remaining bound (Algorithms 1 and 2).  Results are
+ * exactly those of a linear search (Sec. 4.2): ascending (distance, index),
+ * distance in binary64 computed as
+ *     ((s_x*(dx*dx) + s_y*(dy*dy)) + s_z*(dz*dz)) + s_t*(dt*dt)
+ * with dx = (double)q_x - (double)p_x etc., every operation rounded once.
+ *
+ * Conventions for every entry point:
+ *  - "device" pointers are HIP device memory of the current device; "host"
+ *    pointers are ordinary host memory read before the call returns.
+ *  - The library never allocates device memory: the caller sizes buffers with
+ *    the *_workspace / *_bytes calls and owns them.  Inputs and buffers must
+ *    stay alive until the work queued on `stream` (a hipStream_t, NULL = the
+ *    default stream) has completed.
+ *  - Argument checks run before anything is queued and return a negative
+ *    status; nothing is written then.  No C++ exception crosses this ABI.
+ *  - Calls that share a scratch buffer must not overlap in time.
+ */
+#ifndef TNN_H
+#define TNN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t tnn_status;
+#define TNN_OK 0
+#define TNN_E_ARG (-1)         /* null pointer, bad size, scale < 0 or not finite, k out of range */
+#define TNN_E_UNSORTED (-2)    /* a trajectory's times decrease */
+#define TNN_E_NONFINITE (-3)   /* a coordinate is NaN or infinite */
+#define TNN_E_WORKSPACE (-4)   /* buffer smaller than the size the matching *_workspace call gave */
+#define TNN_E_HIP (-5)         /* a HIP runtime call failed */
+#define TNN_E_UNSUPPORTED (-6) /* valid request outside this build's limits */
+
+/* Structure-of-arrays float32 points in device memory: x, y, z (km), t (s). */
+typedef struct {
+  const float *x, *y, *z, *t;
+  int64_t n;
+} tnn_points;
+
+/* Immutable segment index.  Plain data: it only describes device arrays that
+ * live in the caller's `d_mem` buffer given to tnn_build_segments, and may be
+ * copied freely while that buffer lives. */
+typedef struct {
+  uint64_t opaque[48];
+} tnn_index;
+
+/* Query flags. */
+#define TNN_PLAIN 0u       /* TNN, plain: seed from the nearest block, then expand */
+#define TNN_BRUTE 1u       /* linear search over every point (Sec. 3.6 baseline) */
+#define TNN_MIXED_BF16 2u  /* with TNN_BRUTE: BF16 MFMA distance tiles as a proven
+                              lower-bound filter, survivors rescored in binary64 */
+#define TNN_LEARNED 4u     /* TNN seeded with a predicted k-th distance d_radius2[q] */
+
+/* Statistics counters (TNN_STAT_*), unsigned 64-bit, accumulated with atomics
+ * when tnn_query_params.d_stats is not NULL. */
+#define TNN_STAT_QUERIES 0
+#define TNN_STAT_BLOCKS 1      /* block lower bounds evaluated */
+#define TNN_STAT_SEGMENTS 2    /* segment (cylinder) lower bounds evaluated */
+#define TNN_STAT_POINTS 3      /* point distances computed ("comparisons", Sec. 4.2) */
+#define TNN_STAT_MERGES 4      /* top-k merges */
+#define TNN_STAT_ROUNDS 5      /* expansion rounds over all queries */
+#define TNN_STAT_FALLBACKS 6   /* learned radius held fewer than k points */
+#define TNN_STAT_RESCORED 7    /* binary64 rescoring of filtered candidates */
+#define TNN_STAT_MAX_ERR 8     /* bit pattern of the largest |approx - exact| distance (double) */
+#define TNN_STAT_COUNT 16
+
+typedef struct {
+  double scale[4];          /* s_x, s_y, s_z, s_t >= 0, finite */
+  double t_window;          /* t_w >= 0: only points with t < t_q - t_w are candidates */
+  int32_t k;                /* 1 .. 64 */
+  uint32_t flags;           /* TNN_* flags above */
+  int32_t seed_segments;    /* F of Algorithm 2: segments of the nearest block scanned
+                               first (1..64; 0 = 4).  TNN only. */
+  int32_t waves_per_block;  /* launch shape: 1, 2, 4 or 8 waves of 64 lanes (0 = 4) */
+  const float *d_radius2;   /* device [n_queries] predicted k-th distance (metric units,
+                               squared).  Required with TNN_LEARNED, else ignored.  Any
+                               value (0, inf, NaN) keeps results exact; it only changes
+                               the work done. */
+  unsigned long long *d_stats; /* device [TNN_STAT_COUNT] or NULL */
+} tnn_query_params;
+
+/* Human-readable name of a status code (static string). */
+const char *tnn_status_string(tnn_status s);
+
+/*
+ * Size of the device buffer tnn_build_segments needs.
+ * h_traj_offsets: host int64 [n_traj + 1], non-decreasing, offsets[0] = 0;
+ * trajectory j holds points offsets[j] .. offsets[j+1]-1.  seg_len = K in 1..64.
+ */
+tnn_status tnn_build_segments_workspace(const int64_t *h_traj_offsets, int64_t n_traj,
+                                        int32_t seg_len, size_t *bytes);
+
+/*
+ * Build the segment index (Sec. 3.4, partition and segment approximation).
+ * Each trajectory is cut into runs of seg_len consecutive points (the last run
+ * may be shorter; no padding copies).  A run becomes a segment from its first
+ * point A to its last point B with t_min / t_max and a per-axis approximation
+ * error e_f = max |P_f - Q_f| over members P, Q the clamped Euclidean
+ * projection of P on AB, computed in binary64 and rounded up to float32.
+ * Segments are reordered into spatially compact blocks of 64 (recursive median
+ * split along the widest axis scaled by sqrt(order_scale); NULL keeps
+ * trajectory order), points are copied in segment order, and each block gets
+ * the bounding box of its points.
+ * pts: device SoA, trajectory-contiguous, times non-decreasing within each
+ * trajectory (else TNN_E_UNSORTED), finite (else TNN_E_NONFINITE).
+ * order_scale: host double[4] or NULL.  d_mem/bytes: device buffer of at least
+ * tnn_build_segments_workspace bytes; it holds the index afterwards.
+ * Synchronous: returns after the work on `stream` has finished.
+ */
+tnn_status tnn_build_segments(tnn_points pts, const int64_t *h_traj_offsets, int64_t n_traj,
+                              int32_t seg_len, const double *order_scale, void *d_mem,
+                              size_t bytes, void *stream, tnn_index *out);
+
+/* Sizes of a built index (any output pointer may be NULL). */
+tnn_status tnn_index_info(const tnn_index *index, int64_t *n_points, int64_t *n_segments,
+                          int64_t *n_blocks, int32_t *seg_len);
+
+/* Scratch bytes tnn_query needs for n_queries queries with these params. */
+tnn_status tnn_query_workspace(const tnn_index *index, int64_t n_queries,
+                               const tnn_query_params *params, size_t *bytes);
+
+/*
+ * k-NN of every query (Algorithms 1 and 2).  For query q, writes
+ * d_out_idx[q*k + r] (int32, caller's point index) and d_out_dist[q*k + r]
+ * (binary64 scaled squared distance), r = 0..k-1 ascending by (distance,
+ * index); empty slots are (-1, +inf).  Queries are device SoA float32 and need
+ * not be data points.  Asynchronous on `stream`.
+ */
+tnn_status tnn_query(const tnn_index *index, tnn_points queries, const tnn_query_params *params,
+                     int32_t *d_out_idx, double *d_out_dist, void *d_scratch,
+                     size_t scratch_bytes, void *stream);
+
+/*
+ * Test export of the index: per segment in index order
+ * d_seg_f32[12*s + 0..11] = A.xyz, B.xyz, t_min, t_max, e.xyz, 0;
+ * d_seg_i32[4*s + 0..3] = trajectory-order segment number, first point slot in
+ * index order, member count, block; d_point_id[i] = caller index of the point
+ * stored at slot i; d_block_box[8*b + 0..7] = lo.xyzt, hi.xyzt.
+ * Any output may be NULL.  Asynchronous.
+ */
+tnn_status tnn_debug_export_index(const tnn_index *index, float *d_seg_f32, int32_t *d_seg_i32,
+                                  int32_t *d_point_id, float *d_block_box, void *stream);
+
+/*
+ * Test export of the bounds the query kernels use: d_seg_lb[q*S + s]
+ * (binary64, segment s in index order) and d_block_lb[q*nb + b] (float32);
+ * +inf where masked.  Either output may be NULL.  Asynchronous.
+ */
+tnn_status tnn_debug_lower_bounds(const tnn_index *index, tnn_points queries,
+                                  const double *h_scale, double t_window, double *d_seg_lb,
+                                  float *d_block_lb, void *d_scratch, size_t scratch_bytes,
+                                  void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TNN_H */

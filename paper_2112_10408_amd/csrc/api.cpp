@@ -1,0 +1,397 @@
+// C ABI of the trajectory nearest-neighbour library (declared in tnn.h):
+// argument checks, buffer layouts and kernel launches.  No allocation.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <vector>
+
+#include "query.h"
+
+using namespace tnn;
+
+namespace {
+
+struct BuildLayout {
+  size_t px, py, pz, pt, pid;                  // index-order points
+  size_t f[11], pstart, pcount, sorig;          // index-order segments
+  size_t box;                                   // block boxes
+  size_t tf[11], tstart, tcf, keys, perm, dpstart, status;  // build temporaries
+  size_t total;
+};
+
+BuildLayout build_layout(int64_t n, int64_t S) {
+  BuildLayout L;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t r = o;
+    o = align_up(o + bytes);
+    return r;
+  };
+  const int64_t nb = (S + kBlockSegs - 1) / kBlockSegs;
+  L.px = take(4 * n);
+  L.py = take(4 * n);
+  L.pz = take(4 * n);
+  L.pt = take(4 * n);
+  L.pid = take(4 * n);
+  for (int i = 0; i < 11; ++i) L.f[i] = take(4 * S);
+  L.pstart = take(4 * S);
+  L.pcount = take(4 * S);
+  L.sorig = take(4 * S);
+  L.box = take(4 * 8 * nb);
+  for (int i = 0; i < 11; ++i) L.tf[i] = take(4 * S);
+  L.tstart = take(4 * S);
+  L.tcf = take(4 * S);
+  L.keys = take(16 * S);
+  L.perm = take(4 * S);
+  L.dpstart = take(4 * S);
+  L.status = take(32);
+  L.total = o;
+  return L;
+}
+
+bool offsets_ok(const int64_t *off, int64_t n_traj) {
+  if (!off || n_traj < 0 || off[0] != 0) return false;
+  for (int64_t j = 0; j < n_traj; ++j)
+    if (off[j + 1] < off[j]) return false;
+  return true;
+}
+
+int64_t count_segments(const int64_t *off, int64_t n_traj, int32_t K) {
+  int64_t s = 0;
+  for (int64_t j = 0; j < n_traj; ++j) s += (off[j + 1] - off[j] + K - 1) / K;
+  return s;
+}
+
+// Recursive median split along the widest axis; split points fall on
+// multiples of the block size so that every block but the last is full.
+void kd_order(int32_t *idx, int64_t n, const std::vector<float> &keys) {
+  if (n <= kBlockSegs) return;
+  float lo[4], hi[4];
+  for (int f = 0; f < 4; ++f) {
+    lo[f] = INFINITY;
+    hi[f] = -INFINITY;
+  }
+  for (int64_t i = 0; i < n; ++i)
+    for (int f = 0; f < 4; ++f) {
+      const float v = keys[4 * (size_t)idx[i] + f];
+      lo[f] = std::min(lo[f], v);
+      hi[f] = std::max(hi[f], v);
+    }
+  int axis = 0;
+  for (int f = 1; f < 4; ++f)
+    if (hi[f] - lo[f] > hi[axis] - lo[axis]) axis = f;
+  int64_t m = ((n / 2 + kBlockSegs - 1) / kBlockSegs) * kBlockSegs;
+  if (m >= n) m = (n - 1) / kBlockSegs * kBlockSegs;
+  std::nth_element(idx, idx + m, idx + n, [&](int32_t a, int32_t b) {
+    const float ka = keys[4 * (size_t)a + axis], kb = keys[4 * (size_t)b + axis];
+    return ka < kb || (ka == kb && a < b);
+  });
+  kd_order(idx, m, keys);
+  kd_order(idx + m, n - m, keys);
+}
+
+const IndexDesc *desc_of(const tnn_index *index) {
+  if (!index) return nullptr;
+  const IndexDesc *d = reinterpret_cast<const IndexDesc *>(index);
+  return d->magic == kIndexMagic ? d : nullptr;
+}
+
+bool points_ok(const tnn_points &p) {
+  if (p.n < 0) return false;
+  if (p.n == 0) return true;
+  return p.x && p.y && p.z && p.t && p.n <= INT32_MAX;
+}
+
+tnn_status check_params(const tnn_query_params *p) {
+  if (!p) return TNN_E_ARG;
+  for (int f = 0; f < 4; ++f)
+    if (!(p->scale[f] >= 0.0) || !std::isfinite(p->scale[f])) return TNN_E_ARG;
+  if (!(p->t_window >= 0.0) || !std::isfinite(p->t_window)) return TNN_E_ARG;
+  if (p->k < 1 || p->k > kMaxK) return TNN_E_ARG;
+  if (p->flags & ~(TNN_BRUTE | TNN_MIXED_BF16 | TNN_LEARNED)) return TNN_E_ARG;
+  if ((p->flags & TNN_LEARNED) && !p->d_radius2) return TNN_E_ARG;
+  if ((p->flags & TNN_MIXED_BF16) && !(p->flags & TNN_BRUTE)) return TNN_E_UNSUPPORTED;
+  if (p->seed_segments < 0 || p->seed_segments > 64) return TNN_E_ARG;
+  const int w = p->waves_per_block;
+  if (!(w == 0 || w == 1 || w == 2 || w == 4 || w == 8)) return TNN_E_ARG;
+  return TNN_OK;
+}
+
+QueryArgs make_args(const tnn_query_params *p) {
+  QueryArgs a;
+  a.inf = INFINITY;
+  for (int f = 0; f < 4; ++f) {
+    a.s[f] = p->scale[f];
+    float v = (float)p->scale[f];
+    if ((double)v > p->scale[f]) v = std::nextafter(v, 0.0f);  // round toward zero
+    a.sf[f] = v;
+  }
+  a.t_window = p->t_window;
+  a.k = p->k;
+  a.flags = p->flags;
+  a.seed_segments = p->seed_segments ? p->seed_segments : 4;
+  a.radius2 = p->d_radius2;
+  a.stats = p->d_stats;
+  return a;
+}
+
+size_t prep_bytes(int64_t S) { return 3 * align_up(8 * (size_t)S); }
+
+Prep prep_view(void *scratch, int64_t S) {
+  char *b = static_cast<char *>(scratch);
+  const size_t one = align_up(8 * (size_t)S);
+  Prep p;
+  p.inv_n2 = reinterpret_cast<const double *>(b);
+  p.rad = reinterpret_cast<const double *>(b + one);
+  p.slack = reinterpret_cast<const double *>(b + 2 * one);
+  return p;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *tnn_status_string(tnn_status s) {
+  switch (s) {
+    case TNN_OK: return "ok";
+    case TNN_E_ARG: return "invalid argument";
+    case TNN_E_UNSORTED: return "trajectory times decrease";
+    case TNN_E_NONFINITE: return "non-finite coordinate";
+    case TNN_E_WORKSPACE: return "workspace too small";
+    case TNN_E_HIP: return "HIP runtime error";
+    case TNN_E_UNSUPPORTED: return "unsupported request";
+    default: return "unknown status";
+  }
+}
+
+tnn_status tnn_build_segments_workspace(const int64_t *h_traj_offsets, int64_t n_traj,
+                                        int32_t seg_len, size_t *bytes) {
+  if (!bytes || seg_len < 1 || seg_len > kMaxSegLen || !offsets_ok(h_traj_offsets, n_traj))
+    return TNN_E_ARG;
+  const int64_t n = h_traj_offsets[n_traj];
+  if (n > INT32_MAX) return TNN_E_UNSUPPORTED;
+  *bytes = build_layout(n, count_segments(h_traj_offsets, n_traj, seg_len)).total;
+  return TNN_OK;
+}
+
+tnn_status tnn_build_segments(tnn_points pts, const int64_t *h_traj_offsets, int64_t n_traj,
+                              int32_t seg_len, const double *order_scale, void *d_mem,
+                              size_t bytes, void *stream, tnn_index *out) {
+  if (!out || !d_mem || seg_len < 1 || seg_len > kMaxSegLen || !points_ok(pts) ||
+      !offsets_ok(h_traj_offsets, n_traj) || h_traj_offsets[n_traj] != pts.n)
+    return TNN_E_ARG;
+  if (order_scale)
+    for (int f = 0; f < 4; ++f)
+      if (!(order_scale[f] >= 0.0) || !std::isfinite(order_scale[f])) return TNN_E_ARG;
+  const int64_t n = pts.n;
+  const int64_t S = count_segments(h_traj_offsets, n_traj, seg_len);
+  const int64_t nb = (S + kBlockSegs - 1) / kBlockSegs;
+  const BuildLayout L = build_layout(n, S);
+  if (bytes < L.total) return TNN_E_WORKSPACE;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  char *m = static_cast<char *>(d_mem);
+  auto F = [&](size_t off) { return reinterpret_cast<float *>(m + off); };
+  auto I = [&](size_t off) { return reinterpret_cast<int32_t *>(m + off); };
+
+  // segment table in trajectory order (host)
+  std::vector<int32_t> tstart(S), tcf(S);
+  {
+    int64_t s = 0;
+    for (int64_t j = 0; j < n_traj; ++j) {
+      bool first = true;
+      for (int64_t p = h_traj_offsets[j]; p < h_traj_offsets[j + 1]; p += seg_len) {
+        const int64_t c = std::min<int64_t>(seg_len, h_traj_offsets[j + 1] - p);
+        tstart[s] = (int32_t)p;
+        tcf[s] = (int32_t)c | (first ? (1 << 16) : 0);
+        first = false;
+        ++s;
+      }
+    }
+  }
+  float osc_h[4];
+  const float *osc_d = nullptr;
+  if (order_scale)
+    for (int f = 0; f < 4; ++f) osc_h[f] = (float)std::sqrt(order_scale[f]);
+  if (S > 0) {
+    TNN_HIP_CHECK(hipMemcpyAsync(I(L.tstart), tstart.data(), 4 * S, hipMemcpyHostToDevice, st));
+    TNN_HIP_CHECK(hipMemcpyAsync(I(L.tcf), tcf.data(), 4 * S, hipMemcpyHostToDevice, st));
+  }
+  // status word at +0, order scales at +16 of the status slot
+  uint32_t zero[4] = {0, 0, 0, 0};
+  TNN_HIP_CHECK(hipMemcpyAsync(m + L.status, zero, 16, hipMemcpyHostToDevice, st));
+  if (order_scale && S > 0) {
+    TNN_HIP_CHECK(hipMemcpyAsync(m + L.status + 16, osc_h, 16, hipMemcpyHostToDevice, st));
+    osc_d = reinterpret_cast<const float *>(m + L.status + 16);
+  }
+  uint32_t *status = reinterpret_cast<uint32_t *>(m + L.status);
+  TNN_HIP_CHECK(launch_seg_stats(pts, I(L.tstart), I(L.tcf), S, osc_d, F(L.tf[0]), F(L.tf[1]),
+                                 F(L.tf[2]), F(L.tf[3]), F(L.tf[4]), F(L.tf[5]), F(L.tf[6]),
+                                 F(L.tf[7]), F(L.tf[8]), F(L.tf[9]), F(L.tf[10]), F(L.keys), status,
+                                 st));
+  uint32_t status_h = 0;
+  std::vector<float> keys;
+  if (order_scale && S > 0) {
+    keys.resize(4 * (size_t)S);
+    TNN_HIP_CHECK(hipMemcpyAsync(keys.data(), F(L.keys), 16 * S, hipMemcpyDeviceToHost, st));
+  }
+  TNN_HIP_CHECK(hipMemcpyAsync(&status_h, status, 4, hipMemcpyDeviceToHost, st));
+  TNN_HIP_CHECK(hipStreamSynchronize(st));
+  if (status_h & 2u) return TNN_E_NONFINITE;
+  if (status_h & 1u) return TNN_E_UNSORTED;
+
+  std::vector<int32_t> perm(S);
+  std::iota(perm.begin(), perm.end(), 0);
+  if (order_scale && S > 0) kd_order(perm.data(), S, keys);
+  std::vector<int32_t> dpstart(S);
+  {
+    int64_t acc = 0;
+    for (int64_t j = 0; j < S; ++j) {
+      dpstart[j] = (int32_t)acc;
+      acc += tcf[perm[j]] & 0xffff;
+    }
+  }
+  if (S > 0) {
+    TNN_HIP_CHECK(hipMemcpyAsync(I(L.perm), perm.data(), 4 * S, hipMemcpyHostToDevice, st));
+    TNN_HIP_CHECK(hipMemcpyAsync(I(L.dpstart), dpstart.data(), 4 * S, hipMemcpyHostToDevice, st));
+  }
+  const float *src_f[11];
+  float *dst_f[11];
+  for (int i = 0; i < 11; ++i) {
+    src_f[i] = F(L.tf[i]);
+    dst_f[i] = F(L.f[i]);
+  }
+  TNN_HIP_CHECK(launch_seg_scatter(pts, S, I(L.perm), I(L.tstart), I(L.tcf), I(L.dpstart), src_f,
+                                   dst_f, I(L.pstart), I(L.pcount), I(L.sorig), F(L.px), F(L.py),
+                                   F(L.pz), F(L.pt), I(L.pid), st));
+
+  IndexDesc d;
+  std::memset(&d, 0, sizeof(d));
+  d.magic = kIndexMagic;
+  d.seg_len = seg_len;
+  int kp = 1;
+  while (kp < seg_len) kp <<= 1;
+  d.kpad = kp;
+  d.n_blocks = (int32_t)nb;
+  d.n_points = n;
+  d.n_seg = S;
+  d.px = F(L.px);
+  d.py = F(L.py);
+  d.pz = F(L.pz);
+  d.pt = F(L.pt);
+  d.pid = I(L.pid);
+  d.ax = F(L.f[0]);
+  d.ay = F(L.f[1]);
+  d.az = F(L.f[2]);
+  d.bx = F(L.f[3]);
+  d.by = F(L.f[4]);
+  d.bz = F(L.f[5]);
+  d.tmin = F(L.f[6]);
+  d.tmax = F(L.f[7]);
+  d.ex = F(L.f[8]);
+  d.ey = F(L.f[9]);
+  d.ez = F(L.f[10]);
+  d.pstart = I(L.pstart);
+  d.pcount = I(L.pcount);
+  d.sorig = I(L.sorig);
+  d.box = F(L.box);
+  TNN_HIP_CHECK(launch_block_box(d, F(L.box), st));
+  std::vector<float> box(8 * (size_t)nb);
+  if (nb > 0)
+    TNN_HIP_CHECK(hipMemcpyAsync(box.data(), F(L.box), 32 * nb, hipMemcpyDeviceToHost, st));
+  TNN_HIP_CHECK(hipStreamSynchronize(st));
+  for (int f = 0; f < 4; ++f) {
+    d.lo[f] = 0.0f;
+    d.hi[f] = 0.0f;
+    if (nb == 0) continue;
+    float lo = INFINITY, hi = -INFINITY;
+    for (int64_t b = 0; b < nb; ++b) {
+      lo = std::min(lo, box[f * nb + b]);
+      hi = std::max(hi, box[(4 + f) * nb + b]);
+    }
+    d.lo[f] = lo;
+    d.hi[f] = hi;
+  }
+  std::memset(out, 0, sizeof(*out));
+  std::memcpy(out, &d, sizeof(d));
+  return TNN_OK;
+}
+
+tnn_status tnn_index_info(const tnn_index *index, int64_t *n_points, int64_t *n_segments,
+                          int64_t *n_blocks, int32_t *seg_len) {
+  const IndexDesc *d = desc_of(index);
+  if (!d) return TNN_E_ARG;
+  if (n_points) *n_points = d->n_points;
+  if (n_segments) *n_segments = d->n_seg;
+  if (n_blocks) *n_blocks = d->n_blocks;
+  if (seg_len) *seg_len = d->seg_len;
+  return TNN_OK;
+}
+
+tnn_status tnn_query_workspace(const tnn_index *index, int64_t n_queries,
+                               const tnn_query_params *params, size_t *bytes) {
+  const IndexDesc *d = desc_of(index);
+  if (!d || !bytes || n_queries < 0) return TNN_E_ARG;
+  const tnn_status c = check_params(params);
+  if (c != TNN_OK) return c;
+  *bytes = (params->flags & TNN_BRUTE) ? 256 : prep_bytes(d->n_seg);
+  return TNN_OK;
+}
+
+tnn_status tnn_query(const tnn_index *index, tnn_points queries, const tnn_query_params *params,
+                     int32_t *d_out_idx, double *d_out_dist, void *d_scratch,
+                     size_t scratch_bytes, void *stream) {
+  const IndexDesc *d = desc_of(index);
+  if (!d || !points_ok(queries)) return TNN_E_ARG;
+  const tnn_status c = check_params(params);
+  if (c != TNN_OK) return c;
+  if (queries.n > 0 && (!d_out_idx || !d_out_dist)) return TNN_E_ARG;
+  size_t need = 0;
+  tnn_query_workspace(index, queries.n, params, &need);
+  if (scratch_bytes < need || (need > 0 && !d_scratch && !(params->flags & TNN_BRUTE)))
+    return TNN_E_WORKSPACE;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const QueryArgs a = make_args(params);
+  const int wpb = params->waves_per_block ? params->waves_per_block : 4;
+  if (params->flags & TNN_BRUTE) {
+    TNN_HIP_CHECK(launch_brute(*d, a, queries, wpb, d_out_idx, d_out_dist, st));
+    return TNN_OK;
+  }
+  const Prep pr = prep_view(d_scratch, d->n_seg);
+  TNN_HIP_CHECK(launch_prep(*d, a, pr, st));
+  TNN_HIP_CHECK(launch_query(*d, pr, a, queries, wpb, d_out_idx, d_out_dist, st));
+  return TNN_OK;
+}
+
+tnn_status tnn_debug_export_index(const tnn_index *index, float *d_seg_f32, int32_t *d_seg_i32,
+                                  int32_t *d_point_id, float *d_block_box, void *stream) {
+  const IndexDesc *d = desc_of(index);
+  if (!d) return TNN_E_ARG;
+  TNN_HIP_CHECK(launch_export(*d, d_seg_f32, d_seg_i32, d_point_id, d_block_box,
+                              static_cast<hipStream_t>(stream)));
+  return TNN_OK;
+}
+
+tnn_status tnn_debug_lower_bounds(const tnn_index *index, tnn_points queries,
+                                  const double *h_scale, double t_window, double *d_seg_lb,
+                                  float *d_block_lb, void *d_scratch, size_t scratch_bytes,
+                                  void *stream) {
+  const IndexDesc *d = desc_of(index);
+  if (!d || !points_ok(queries) || !h_scale) return TNN_E_ARG;
+  tnn_query_params p;
+  std::memset(&p, 0, sizeof(p));
+  for (int f = 0; f < 4; ++f) p.scale[f] = h_scale[f];
+  p.t_window = t_window;
+  p.k = 1;
+  const tnn_status c = check_params(&p);
+  if (c != TNN_OK) return c;
+  if (scratch_bytes < prep_bytes(d->n_seg) || (d->n_seg > 0 && !d_scratch)) return TNN_E_WORKSPACE;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const QueryArgs a = make_args(&p);
+  const Prep pr = prep_view(d_scratch, d->n_seg);
+  TNN_HIP_CHECK(launch_prep(*d, a, pr, st));
+  TNN_HIP_CHECK(launch_debug_lb(*d, pr, a, queries, d_seg_lb, d_block_lb, st));
+  return TNN_OK;
+}
+
+}  // extern "C"

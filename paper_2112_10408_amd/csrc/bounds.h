@@ -1,0 +1,106 @@
+// Lower bounds and exact distances shared by the query kernels.
+//
+// Every bound here is conservative: it never exceeds the binary64 distance
+// (the value the result reports) of any member point that passes the time
+// mask.  Rounding slack is derived in the design notes; in short:
+//  * block bound (float32): each term carries at most 7 float32 roundings of
+//    a non-negative quantity, so multiplying by (1 - 2^-18) stays below the
+//    real bound, which is below the real distance, which is within a
+//    2^-50 relative error of the reported one;
+//  * cylinder bound (binary64): the projection parameter is approximate, which
+//    can only raise the computed distance to the segment by a second-order
+//    term bounded by 2^-48 |AB|_s, covered by the 2^-30 |AB|_s slack; the
+//    residual's cancellation error (relative 2^-50 of |AP| + |AB|) is covered by
+//    the (1 - 2^-40) factors.
+#pragma once
+#include "tnn_internal.h"
+#include "wave.h"
+
+namespace tnn {
+
+// Scaled squared distance, each operation rounded once in this order (no
+// contraction): the value the result reports.
+__device__ __forceinline__ double exact_dist(const double s[4], float qx, float qy, float qz,
+                                             float qt, float px, float py, float pz, float pt) {
+#pragma clang fp contract(off)
+  const double dx = (double)qx - (double)px;
+  const double dy = (double)qy - (double)py;
+  const double dz = (double)qz - (double)pz;
+  const double dt = (double)qt - (double)pt;
+  const double a = s[0] * (dx * dx);
+  const double b = s[1] * (dy * dy);
+  const double c = s[2] * (dz * dz);
+  const double e = s[3] * (dt * dt);
+  return ((a + b) + c) + e;
+}
+
+// Per-query constants of the time mask.
+struct QueryPoint {
+  float x, y, z, t;
+  double thr;   // (double)t - t_w: a point is a candidate iff (double)t_p < thr
+  double gw;    // lower bound on t - t_p for any candidate (0 when t_w = 0)
+  float gwf;    // the same, rounded down to float32
+};
+
+__device__ __forceinline__ QueryPoint make_query(float x, float y, float z, float t, double t_window) {
+  QueryPoint q;
+  q.x = x;
+  q.y = y;
+  q.z = z;
+  q.t = t;
+  q.thr = (double)t - t_window;
+  double gw = 0.0;
+  if (t_window > 0.0) gw = fmax(t_window - 0x1p-50 * (fabs((double)t) + t_window), 0.0);
+  q.gw = gw;
+  q.gwf = __double2float_rd(gw);
+  return q;
+}
+
+// Lower bound from a query to every point of block b: scaled squared
+// distance to the block's (x, y, z, t) bounding box.  +inf when no point of
+// the block is early enough.
+__device__ __forceinline__ float block_lb(const IndexDesc &ix, int b, const QueryPoint &q,
+                                          const float sf[4]) {
+  const int nb = ix.n_blocks;
+  const float *box = ix.box;
+  const float lt = box[3 * nb + b];
+  if ((double)lt >= q.thr) return __builtin_huge_valf();
+  const float lx = box[b], ly = box[nb + b], lz = box[2 * nb + b];
+  const float hx = box[4 * nb + b], hy = box[5 * nb + b], hz = box[6 * nb + b];
+  const float ht = box[7 * nb + b];
+  const float gx = fmaxf(fmaxf(lx - q.x, q.x - hx), 0.0f);
+  const float gy = fmaxf(fmaxf(ly - q.y, q.y - hy), 0.0f);
+  const float gz = fmaxf(fmaxf(lz - q.z, q.z - hz), 0.0f);
+  const float gt = fmaxf(fmaxf(q.t - ht, q.gwf), 0.0f);
+  const float v = sf[0] * (gx * gx) + sf[1] * (gy * gy) + sf[2] * (gz * gz) + sf[3] * (gt * gt);
+  return v * (1.0f - 0x1p-18f);
+}
+
+// Cylinder lower bound (Sec. 3.4 masked distance minus approximation error,
+// Algorithm 1, corrected): +inf if t_min >= t_q - t_w; otherwise
+// max(0, D - R)^2 + s_t max(0, t_q - t_max, t_w)^2 with D the distance from
+// the query to segment AB in the scaled metric (projection in that metric).
+__device__ __forceinline__ double seg_lb(const IndexDesc &ix, const Prep &pr, int64_t s,
+                                         const QueryPoint &q, const double sc[4]) {
+  const float tmin = ix.tmin[s];
+  if ((double)tmin >= q.thr) return kInf;
+  const double ax = ix.ax[s], ay = ix.ay[s], az = ix.az[s];
+  const double abx = (double)ix.bx[s] - ax;
+  const double aby = (double)ix.by[s] - ay;
+  const double abz = (double)ix.bz[s] - az;
+  const double apx = (double)q.x - ax;
+  const double apy = (double)q.y - ay;
+  const double apz = (double)q.z - az;
+  const double dot = sc[0] * apx * abx + sc[1] * apy * aby + sc[2] * apz * abz;
+  const double del = fmin(fmax(dot * pr.inv_n2[s], 0.0), 1.0);
+  const double rx = apx - del * abx;
+  const double ry = apy - del * aby;
+  const double rz = apz - del * abz;
+  const double d2 = sc[0] * rx * rx + sc[1] * ry * ry + sc[2] * rz * rz;
+  const double dlo = sqrt(d2) * (1.0 - 0x1p-40);
+  const double g = fmax(dlo - pr.slack[s] - pr.rad[s], 0.0);
+  const double gt = fmax(fmax((double)q.t - (double)ix.tmax[s], q.gw), 0.0);
+  return (g * g + sc[3] * (gt * gt)) * (1.0 - 0x1p-40);
+}
+
+}  // namespace tnn

@@ -1,0 +1,231 @@
+// Index construction kernels (Sec. 3.4: partition into runs of K points,
+// segment from first to last point, approximation error) and the test export.
+#include "query.h"
+#include "wave.h"
+
+namespace tnn {
+
+constexpr uint32_t kBadUnsorted = 1u;
+constexpr uint32_t kBadNonFinite = 2u;
+
+// One thread per segment, trajectory order.  cnt_flags[s] = member count in
+// bits 0..15, bit 16 set when s is the first segment of its trajectory.
+__global__ void seg_stats_kernel(tnn_points pts, const int32_t *start, const int32_t *cnt_flags,
+                                 int64_t n_seg, const float *osc, float *ax, float *ay, float *az,
+                                 float *bx, float *by, float *bz, float *tmin, float *tmax,
+                                 float *ex, float *ey, float *ez, float *keys, uint32_t *status) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n_seg) return;
+  const int p0 = start[s];
+  const int c = cnt_flags[s] & 0xffff;
+  const bool first = (cnt_flags[s] >> 16) & 1;
+  const int p1 = p0 + c - 1;
+  uint32_t bad = 0;
+  if (!first && pts.t[p0 - 1] > pts.t[p0]) bad |= kBadUnsorted;
+  const double A[3] = {pts.x[p0], pts.y[p0], pts.z[p0]};
+  const double B[3] = {pts.x[p1], pts.y[p1], pts.z[p1]};
+  const double AB[3] = {B[0] - A[0], B[1] - A[1], B[2] - A[2]};
+  const double n2 = AB[0] * AB[0] + AB[1] * AB[1] + AB[2] * AB[2];
+  double e[3] = {0.0, 0.0, 0.0};
+  float tlo = pts.t[p0], thi = pts.t[p0];
+  float tprev = pts.t[p0];
+  for (int i = 0; i < c; ++i) {
+    const float fx = pts.x[p0 + i], fy = pts.y[p0 + i], fz = pts.z[p0 + i], ft = pts.t[p0 + i];
+    if (!isfinite(fx) || !isfinite(fy) || !isfinite(fz) || !isfinite(ft)) bad |= kBadNonFinite;
+    if (ft < tprev) bad |= kBadUnsorted;
+    tprev = ft;
+    tlo = fminf(tlo, ft);
+    thi = fmaxf(thi, ft);
+    const double P[3] = {fx, fy, fz};
+    double u = 0.0;
+    if (n2 > 0.0) {
+      u = ((P[0] - A[0]) * AB[0] + (P[1] - A[1]) * AB[1] + (P[2] - A[2]) * AB[2]) / n2;
+      u = fmin(fmax(u, 0.0), 1.0);
+    }
+#pragma unroll
+    for (int f = 0; f < 3; ++f) {
+      // |P - Q| for Q = A + u AB, plus room for the rounding of Q
+      const double q = A[f] + u * AB[f];
+      const double dev = fabs(P[f] - q) + 0x1p-40 * (fabs(A[f]) + fabs(B[f]) + fabs(P[f]));
+      e[f] = fmax(e[f], dev);
+    }
+  }
+  ax[s] = (float)A[0];
+  ay[s] = (float)A[1];
+  az[s] = (float)A[2];
+  bx[s] = (float)B[0];
+  by[s] = (float)B[1];
+  bz[s] = (float)B[2];
+  tmin[s] = tlo;
+  tmax[s] = thi;
+  ex[s] = __double2float_ru(e[0]);
+  ey[s] = __double2float_ru(e[1]);
+  ez[s] = __double2float_ru(e[2]);
+  if (osc) {
+    keys[4 * s + 0] = (float)(0.5 * (A[0] + B[0])) * osc[0];
+    keys[4 * s + 1] = (float)(0.5 * (A[1] + B[1])) * osc[1];
+    keys[4 * s + 2] = (float)(0.5 * (A[2] + B[2])) * osc[2];
+    keys[4 * s + 3] = (float)(0.5 * ((double)tlo + (double)thi)) * osc[3];
+  }
+  if (bad) atomicOr(status, bad);
+}
+
+struct F11 {
+  const float *p[11];
+};
+struct F11w {
+  float *p[11];
+};
+
+// One workgroup of 64 lanes per segment in index order: copies the segment's
+// fields and its member points into index order.
+__global__ void seg_scatter_kernel(tnn_points pts, int64_t n_seg, const int32_t *perm,
+                                   const int32_t *src_start, const int32_t *src_cf,
+                                   const int32_t *dst_pstart, F11 src, F11w dst,
+                                   int32_t *out_pstart, int32_t *out_pcount, int32_t *out_sorig,
+                                   float *px, float *py, float *pz, float *pt, int32_t *pid) {
+  const int64_t j = blockIdx.x;
+  if (j >= n_seg) return;
+  const int o = perm[j];
+  const int c = src_cf[o] & 0xffff;
+  const int p0 = src_start[o];
+  const int d0 = dst_pstart[j];
+  const int t = threadIdx.x;
+  if (t < c) {
+    px[d0 + t] = pts.x[p0 + t];
+    py[d0 + t] = pts.y[p0 + t];
+    pz[d0 + t] = pts.z[p0 + t];
+    pt[d0 + t] = pts.t[p0 + t];
+    pid[d0 + t] = p0 + t;
+  }
+  if (t < 11) dst.p[t][j] = src.p[t][o];
+  if (t == 0) {
+    out_pstart[j] = d0;
+    out_pcount[j] = c;
+    out_sorig[j] = o;
+  }
+}
+
+// One wavefront per block of 64 segments: bounding box of its points.
+__global__ void block_box_kernel(IndexDesc ix, float *box) {
+  const int b = blockIdx.x;
+  const int lane = threadIdx.x;
+  const int64_t s = (int64_t)b * kBlockSegs + lane;
+  float lo[4], hi[4];
+#pragma unroll
+  for (int f = 0; f < 4; ++f) {
+    lo[f] = __builtin_huge_valf();
+    hi[f] = -__builtin_huge_valf();
+  }
+  if (s < ix.n_seg) {
+    const int ps = ix.pstart[s], pc = ix.pcount[s];
+    for (int i = 0; i < pc; ++i) {
+      const float v[4] = {ix.px[ps + i], ix.py[ps + i], ix.pz[ps + i], ix.pt[ps + i]};
+#pragma unroll
+      for (int f = 0; f < 4; ++f) {
+        lo[f] = fminf(lo[f], v[f]);
+        hi[f] = fmaxf(hi[f], v[f]);
+      }
+    }
+  }
+#pragma unroll
+  for (int f = 0; f < 4; ++f) {
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) {
+      lo[f] = fminf(lo[f], __shfl_xor(lo[f], m, 64));
+      hi[f] = fmaxf(hi[f], __shfl_xor(hi[f], m, 64));
+    }
+  }
+  if (lane == 0) {
+    const int nb = ix.n_blocks;
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+      box[f * nb + b] = lo[f];
+      box[(4 + f) * nb + b] = hi[f];
+    }
+  }
+}
+
+__global__ void export_kernel(IndexDesc ix, float *seg_f32, int32_t *seg_i32, int32_t *point_id,
+                              float *block_box) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < ix.n_seg) {
+    if (seg_f32) {
+      float *o = seg_f32 + 12 * i;
+      o[0] = ix.ax[i];
+      o[1] = ix.ay[i];
+      o[2] = ix.az[i];
+      o[3] = ix.bx[i];
+      o[4] = ix.by[i];
+      o[5] = ix.bz[i];
+      o[6] = ix.tmin[i];
+      o[7] = ix.tmax[i];
+      o[8] = ix.ex[i];
+      o[9] = ix.ey[i];
+      o[10] = ix.ez[i];
+      o[11] = 0.0f;
+    }
+    if (seg_i32) {
+      int32_t *o = seg_i32 + 4 * i;
+      o[0] = ix.sorig[i];
+      o[1] = ix.pstart[i];
+      o[2] = ix.pcount[i];
+      o[3] = (int32_t)(i / kBlockSegs);
+    }
+  }
+  if (point_id && i < ix.n_points) point_id[i] = ix.pid[i];
+  if (block_box && i < ix.n_blocks) {
+    for (int f = 0; f < 8; ++f) block_box[8 * i + f] = ix.box[f * ix.n_blocks + i];
+  }
+}
+
+hipError_t launch_seg_stats(const tnn_points &pts, const int32_t *start, const int32_t *cnt_flags,
+                            int64_t n_seg, const float *osc, float *ax, float *ay, float *az,
+                            float *bx, float *by, float *bz, float *tmin, float *tmax, float *ex,
+                            float *ey, float *ez, float *keys, uint32_t *status, hipStream_t st) {
+  if (n_seg == 0) return hipSuccess;
+  const int tpb = 256;
+  hipLaunchKernelGGL(seg_stats_kernel, dim3((unsigned)((n_seg + tpb - 1) / tpb)), dim3(tpb), 0, st,
+                     pts, start, cnt_flags, n_seg, osc, ax, ay, az, bx, by, bz, tmin, tmax, ex, ey,
+                     ez, keys, status);
+  return hipGetLastError();
+}
+
+hipError_t launch_seg_scatter(const tnn_points &pts, int64_t n_seg, const int32_t *perm,
+                              const int32_t *src_start, const int32_t *src_cnt_flags,
+                              const int32_t *dst_pstart, const float *const src_f[11],
+                              float *const dst_f[11], int32_t *dst_pstart_out, int32_t *dst_pcount,
+                              int32_t *dst_sorig, float *px, float *py, float *pz, float *pt,
+                              int32_t *pid, hipStream_t st) {
+  if (n_seg == 0) return hipSuccess;
+  F11 src;
+  F11w dst;
+  for (int i = 0; i < 11; ++i) {
+    src.p[i] = src_f[i];
+    dst.p[i] = dst_f[i];
+  }
+  hipLaunchKernelGGL(seg_scatter_kernel, dim3((unsigned)n_seg), dim3(kWave), 0, st, pts, n_seg, perm,
+                     src_start, src_cnt_flags, dst_pstart, src, dst, dst_pstart_out, dst_pcount,
+                     dst_sorig, px, py, pz, pt, pid);
+  return hipGetLastError();
+}
+
+hipError_t launch_block_box(const IndexDesc &ix, float *box, hipStream_t st) {
+  if (ix.n_blocks == 0) return hipSuccess;
+  hipLaunchKernelGGL(block_box_kernel, dim3((unsigned)ix.n_blocks), dim3(kWave), 0, st, ix, box);
+  return hipGetLastError();
+}
+
+hipError_t launch_export(const IndexDesc &ix, float *seg_f32, int32_t *seg_i32, int32_t *point_id,
+                         float *block_box, hipStream_t st) {
+  int64_t n = ix.n_seg;
+  if (ix.n_points > n) n = ix.n_points;
+  if (ix.n_blocks > n) n = ix.n_blocks;
+  if (n == 0) return hipSuccess;
+  const int tpb = 256;
+  hipLaunchKernelGGL(export_kernel, dim3((unsigned)((n + tpb - 1) / tpb)), dim3(tpb), 0, st, ix,
+                     seg_f32, seg_i32, point_id, block_box);
+  return hipGetLastError();
+}
+
+}  // namespace tnn

@@ -1,0 +1,33 @@
+// Host launchers of the query kernels.
+#pragma once
+#include "tnn_internal.h"
+
+namespace tnn {
+
+hipError_t launch_prep(const IndexDesc &ix, const QueryArgs &a, const Prep &pr, hipStream_t st);
+hipError_t launch_query(const IndexDesc &ix, const Prep &pr, const QueryArgs &a,
+                        const tnn_points &qs, int waves_per_block, int32_t *out_idx,
+                        double *out_dist, hipStream_t st);
+hipError_t launch_brute(const IndexDesc &ix, const QueryArgs &a, const tnn_points &qs,
+                        int waves_per_block, int32_t *out_idx, double *out_dist, hipStream_t st);
+hipError_t launch_debug_lb(const IndexDesc &ix, const Prep &pr, const QueryArgs &a,
+                           const tnn_points &qs, double *seg_lb_out, float *block_lb_out,
+                           hipStream_t st);
+
+// Index construction (build.hip).
+hipError_t launch_seg_stats(const tnn_points &pts, const int32_t *start, const int32_t *cnt_flags,
+                            int64_t n_seg, const float *order_sqrt_scale, float *ax, float *ay,
+                            float *az, float *bx, float *by, float *bz, float *tmin, float *tmax,
+                            float *ex, float *ey, float *ez, float *keys, uint32_t *status,
+                            hipStream_t st);
+hipError_t launch_seg_scatter(const tnn_points &pts, int64_t n_seg, const int32_t *perm,
+                              const int32_t *src_start, const int32_t *src_cnt_flags,
+                              const int32_t *dst_pstart, const float *const src_f[11],
+                              float *const dst_f[11], int32_t *dst_pstart_out, int32_t *dst_pcount,
+                              int32_t *dst_sorig, float *px, float *py, float *pz, float *pt,
+                              int32_t *pid, hipStream_t st);
+hipError_t launch_block_box(const IndexDesc &ix, float *box, hipStream_t st);
+hipError_t launch_export(const IndexDesc &ix, float *seg_f32, int32_t *seg_i32, int32_t *point_id,
+                         float *block_box, hipStream_t st);
+
+}  // namespace tnn

@@ -1,0 +1,357 @@
+// Query kernels: per-call segment preparation, TNN search (plain and
+// learned-radius seeded), linear search, and the bound export for tests.
+#include "bounds.h"
+#include "query.h"
+
+namespace tnn {
+
+// ---------------------------------------------------------------------------
+// Per-call preparation (depends on the scales): 1/|AB|_s^2, the radius
+// R = sqrt(sum_f s_f e_f^2) rounded up, and the projection slack.
+// ---------------------------------------------------------------------------
+__global__ void prep_kernel(IndexDesc ix, QueryArgs a, double *inv_n2, double *rad, double *slack) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= ix.n_seg) return;
+  const double abx = (double)ix.bx[s] - (double)ix.ax[s];
+  const double aby = (double)ix.by[s] - (double)ix.ay[s];
+  const double abz = (double)ix.bz[s] - (double)ix.az[s];
+  const double n2 = a.s[0] * abx * abx + a.s[1] * aby * aby + a.s[2] * abz * abz;
+  inv_n2[s] = n2 > 0.0 ? 1.0 / n2 : 0.0;
+  const double ex = ix.ex[s], ey = ix.ey[s], ez = ix.ez[s];
+  rad[s] = sqrt(a.s[0] * ex * ex + a.s[1] * ey * ey + a.s[2] * ez * ez) * (1.0 + 0x1p-40);
+  slack[s] = 0x1p-30 * sqrt(n2);
+}
+
+// ---------------------------------------------------------------------------
+// One wavefront answers one query.
+// ---------------------------------------------------------------------------
+struct WaveStats {
+  uint32_t blocks, segs, points, merges, rounds, fallback;
+};
+
+struct Searcher {
+  const IndexDesc &ix;
+  const Prep &pr;
+  const QueryArgs &a;
+  QueryPoint q;
+  TopK tk;
+  WaveStats st;
+  int lane;
+  int spi_shift;  // log2(kpad): lanes per segment when scanning points
+
+  __device__ Searcher(const IndexDesc &ix_, const Prep &pr_, const QueryArgs &a_)
+      : ix(ix_), pr(pr_), a(a_) {}
+
+  // Scan the member points of the segments of block `bb` whose lanes are set
+  // in `cm`, feeding the top-k.  Several segments share one 64-lane pass.
+  __device__ void scan(uint64_t cm, int bb) {
+    const int kpad = 1 << spi_shift;
+    const int spi = kWave >> spi_shift;
+    const int slot = lane >> spi_shift;
+    const int off = lane & (kpad - 1);
+    while (cm) {
+      int my_l = -1;
+      for (int i = 0; i < spi && cm; ++i) {
+        const int l = __ffsll((long long)cm) - 1;
+        cm &= cm - 1;
+        if (slot == i) my_l = l;
+      }
+      const bool has = my_l >= 0;
+      const int64_t s = (int64_t)bb * kBlockSegs + (has ? my_l : 0);
+      const int ps = has ? ix.pstart[s] : 0;
+      const int pc = has ? ix.pcount[s] : 0;
+      const bool ok = has && off < pc;
+      const int p = ps + off;
+      float px = 0.f, py = 0.f, pz = 0.f, pt = 0.f;
+      int pid = kNoId;
+      if (ok) {
+        px = ix.px[p];
+        py = ix.py[p];
+        pz = ix.pz[p];
+        pt = ix.pt[p];
+        pid = ix.pid[p];
+      }
+      const double d = exact_dist(a.s, q.x, q.y, q.z, q.t, px, py, pz, pt);
+      const bool valid = ok && (double)pt < q.thr;
+      st.points += (uint32_t)__popcll(ballot(ok));
+      const bool gate = valid && tk.admits(d, pid);
+      const uint64_t gm = ballot(gate);
+      if (gm) {
+        tk.offer(gm, gate, d, pid);
+        ++st.merges;
+      }
+    }
+  }
+
+  // One expansion round.  A segment's key is the larger of its cylinder
+  // bound and its block's bound; every segment with prev < key <= min(tau,
+  // k-th) is scanned (seeded segments excluded).  Rounds use increasing tau,
+  // so a segment is scanned in the first round whose tau reaches its key, or
+  // never when its key already exceeded the k-th distance then.  Returns the largest finite
+  // block bound seen (uniform).
+  __device__ float round(double prev, double tau, int seed_block, uint64_t seed_mask) {
+    const int nb = ix.n_blocks;
+    const int64_t S = ix.n_seg;
+    float maxfin = 0.0f;
+    for (int base = 0; base < nb; base += kWave) {
+      const int b = base + lane;
+      const float lbb = b < nb ? block_lb(ix, b, q, a.sf) : __builtin_huge_valf();
+      st.blocks += (uint32_t)min(kWave, nb - base);
+      if (lbb < __builtin_huge_valf()) maxfin = fmaxf(maxfin, lbb);
+      const double tau0 = fmin(tau, tk.kd);
+      uint64_t m = ballot(lbb < __builtin_huge_valf() && (double)lbb <= tau0);
+      while (m) {
+        const int bl = __ffsll((long long)m) - 1;
+        m &= m - 1;
+        const double tau_cur = fmin(tau, tk.kd);
+        const double lbb_b = (double)readlane_f(lbb, bl);
+        if (lbb_b > tau_cur) continue;
+        const int bb = base + bl;
+        const int64_t s = (int64_t)bb * kBlockSegs + lane;
+        // both bounds hold for every member; the larger one decides the round
+        const double key = fmax(s < S ? seg_lb(ix, pr, s, q, a.s) : kInf, lbb_b);
+        st.segs += (uint32_t)min((int64_t)kBlockSegs, S - (int64_t)bb * kBlockSegs);
+        const bool seeded = bb == seed_block && ((seed_mask >> lane) & 1ull);
+        // a masked segment (infinite key) holds no candidate
+        const bool cand = s < S && key < kInf && key <= tau_cur && key > prev && !seeded;
+        const uint64_t cm = ballot(cand);
+        if (cm) scan(cm, bb);
+      }
+    }
+    return wave_max_f(maxfin);
+  }
+};
+
+__device__ __forceinline__ void flush_stats(unsigned long long *stats, const WaveStats &st) {
+  if (!stats || lane_id() != 0) return;
+  atomicAdd(stats + TNN_STAT_QUERIES, 1ull);
+  atomicAdd(stats + TNN_STAT_BLOCKS, (unsigned long long)st.blocks);
+  atomicAdd(stats + TNN_STAT_SEGMENTS, (unsigned long long)st.segs);
+  atomicAdd(stats + TNN_STAT_POINTS, (unsigned long long)st.points);
+  atomicAdd(stats + TNN_STAT_MERGES, (unsigned long long)st.merges);
+  atomicAdd(stats + TNN_STAT_ROUNDS, (unsigned long long)st.rounds);
+  atomicAdd(stats + TNN_STAT_FALLBACKS, (unsigned long long)st.fallback);
+}
+
+// Answer query `qi` with one wavefront (Algorithm 2 in radius form).
+//  plain   : seed = the F segments with the smallest bounds inside the block
+//            with the smallest block bound; then expand with tau = k-th.
+//  learned : tau = predicted k-th distance; one round settles the query when
+//            at least k candidates lie within it, otherwise expansion
+//            continues from the k-th found (or a 16x larger radius).
+// Rounds only widen tau; a segment is scanned in the first round whose
+// radius reaches its bound, so no point enters the top-k twice.
+__device__ void answer_query(const IndexDesc &ix, const Prep &pr, const QueryArgs &a,
+                             const float *qx, const float *qy, const float *qz, const float *qt,
+                             int64_t qi, int32_t *out_idx, double *out_dist) {
+  Searcher se(ix, pr, a);
+  se.lane = lane_id();
+  se.spi_shift = 31 - __clz(ix.kpad);
+  se.q = make_query(qx[qi], qy[qi], qz[qi], qt[qi], a.t_window);
+  se.tk.init(a.k, a.inf);
+  se.st = WaveStats{0, 0, 0, 0, 0, 0};
+  const int nb = ix.n_blocks;
+  const int64_t S = ix.n_seg;
+  // scale of the data, used to grow the radius when nothing is known yet
+  double diag2 = 0.0;
+  for (int f = 0; f < 4; ++f) {
+    const double e = (double)ix.hi[f] - (double)ix.lo[f];
+    diag2 += a.s[f] * e * e;
+  }
+  const double floor_tau = fmax(diag2 * 0x1p-24, 1e-300);
+
+  int seed_block = -1;
+  uint64_t seed_mask = 0;
+  double tau;
+  bool learned = (a.flags & TNN_LEARNED) != 0;
+  double r2 = learned ? (double)a.radius2[qi] : 0.0;
+  if (learned && !(r2 > 0.0 && r2 < kInf)) learned = false;  // no usable prediction
+  if (learned) {
+    tau = r2;
+  } else {
+    // nearest block by its bound
+    float best = __builtin_huge_valf();
+    int bestb = kNoId;
+    for (int b = se.lane; b < nb; b += kWave) {
+      const float v = block_lb(ix, b, se.q, a.sf);
+      if (v < best) {
+        best = v;
+        bestb = b;
+      }
+    }
+    se.st.blocks += (uint32_t)nb;
+    wave_argmin_f(best, bestb);
+    if (!(best < __builtin_huge_valf())) {  // nothing early enough anywhere
+      tau = kInf;
+      se.st.rounds = 0;
+      goto write_out;
+    }
+    seed_block = bestb;
+    {
+      const int64_t s = (int64_t)bestb * kBlockSegs + se.lane;
+      double v = s < S ? seg_lb(ix, pr, s, se.q, a.s) : kInf;
+      se.st.segs += (uint32_t)min((int64_t)kBlockSegs, S - (int64_t)bestb * kBlockSegs);
+      const int F = a.seed_segments;
+      for (int i = 0; i < F; ++i) {
+        double mv = v;
+        int ml = se.lane;
+        wave_argmin_d(mv, ml);
+        if (!(mv < kInf)) break;
+        seed_mask |= 1ull << ml;
+        if (se.lane == ml) v = kInf;
+      }
+      if (seed_mask) se.scan(seed_mask, bestb);
+    }
+    if (se.tk.kd < kInf) {
+      tau = se.tk.kd;
+    } else {
+      // fewer than k candidates so far: start from the largest distance seen
+      double far = se.tk.d < kInf ? se.tk.d : 0.0;
+      for (int m = 32; m > 0; m >>= 1) far = fmax(far, __shfl_xor(far, m, 64));
+      tau = fmax(fmax(far, (double)best) * 16.0, floor_tau);
+    }
+  }
+  {
+    double prev = -1.0;
+    for (;;) {
+      ++se.st.rounds;
+      const float maxfin = se.round(prev, tau, seed_block, seed_mask);
+      if (se.tk.kd <= tau || !(tau < kInf)) break;
+      if (learned) se.st.fallback = 1;
+      prev = tau;
+      if (se.tk.kd < kInf) {
+        tau = se.tk.kd;
+      } else {
+        tau = fmax(tau * 16.0, floor_tau);
+        if (tau >= (double)maxfin) tau = kInf;
+      }
+    }
+  }
+write_out:
+  if (se.lane < a.k) {
+    out_idx[qi * a.k + se.lane] = se.tk.id == kNoId ? -1 : se.tk.id;
+    out_dist[qi * a.k + se.lane] = se.tk.d;
+  }
+  flush_stats(a.stats, se.st);
+}
+
+__global__ __launch_bounds__(512) void tnn_query_kernel(IndexDesc ix, Prep pr, QueryArgs a,
+                                                        const float *qx, const float *qy,
+                                                        const float *qz, const float *qt,
+                                                        int64_t nq, int32_t *out_idx,
+                                                        double *out_dist) {
+  const int64_t qi = (int64_t)blockIdx.x * (blockDim.x >> 6) + uniform_i((int)(threadIdx.x >> 6));
+  if (qi >= nq) return;
+  answer_query(ix, pr, a, qx, qy, qz, qt, qi, out_idx, out_dist);
+}
+
+// ---------------------------------------------------------------------------
+// Linear search (the paper's baseline, Sec. 3.6): every point, binary64
+// distances, same top-k.  One wavefront per query.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(512) void brute_kernel(IndexDesc ix, QueryArgs a, const float *qxp,
+                                                    const float *qyp, const float *qzp,
+                                                    const float *qtp, int64_t nq,
+                                                    int32_t *out_idx, double *out_dist) {
+  const int64_t qi = (int64_t)blockIdx.x * (blockDim.x >> 6) + uniform_i((int)(threadIdx.x >> 6));
+  if (qi >= nq) return;
+  const int lane = lane_id();
+  const QueryPoint q = make_query(qxp[qi], qyp[qi], qzp[qi], qtp[qi], a.t_window);
+  TopK tk;
+  tk.init(a.k, a.inf);
+  uint32_t merges = 0;
+  const int64_t n = ix.n_points;
+  for (int64_t p0 = 0; p0 < n; p0 += kWave) {
+    const int64_t p = p0 + lane;
+    const bool ok = p < n;
+    float px = 0.f, py = 0.f, pz = 0.f, pt = 0.f;
+    int pid = kNoId;
+    if (ok) {
+      px = ix.px[p];
+      py = ix.py[p];
+      pz = ix.pz[p];
+      pt = ix.pt[p];
+      pid = ix.pid[p];
+    }
+    const double d = exact_dist(a.s, q.x, q.y, q.z, q.t, px, py, pz, pt);
+    const bool gate = ok && (double)pt < q.thr && tk.admits(d, pid);
+    const uint64_t gm = ballot(gate);
+    if (gm) {
+      tk.offer(gm, gate, d, pid);
+      ++merges;
+    }
+  }
+  if (lane < a.k) {
+    out_idx[qi * a.k + lane] = tk.id == kNoId ? -1 : tk.id;
+    out_dist[qi * a.k + lane] = tk.d;
+  }
+  if (a.stats && lane == 0) {
+    atomicAdd(a.stats + TNN_STAT_QUERIES, 1ull);
+    atomicAdd(a.stats + TNN_STAT_POINTS, (unsigned long long)n);
+    atomicAdd(a.stats + TNN_STAT_MERGES, (unsigned long long)merges);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Test export of the bounds, one thread per (query, segment) / (query, block).
+// ---------------------------------------------------------------------------
+__global__ void debug_lb_kernel(IndexDesc ix, Prep pr, QueryArgs a, const float *qx,
+                                const float *qy, const float *qz, const float *qt, int64_t nq,
+                                double *seg_lb_out, float *block_lb_out) {
+  const int64_t S = ix.n_seg, nb = ix.n_blocks;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t per_q = S + nb;
+  if (i >= nq * per_q) return;
+  const int64_t qi = i / per_q, j = i % per_q;
+  const QueryPoint q = make_query(qx[qi], qy[qi], qz[qi], qt[qi], a.t_window);
+  if (j < S) {
+    if (seg_lb_out) seg_lb_out[qi * S + j] = seg_lb(ix, pr, j, q, a.s);
+  } else if (block_lb_out) {
+    block_lb_out[qi * nb + (j - S)] = block_lb(ix, (int)(j - S), q, a.sf);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Host launchers.
+// ---------------------------------------------------------------------------
+hipError_t launch_prep(const IndexDesc &ix, const QueryArgs &a, const Prep &pr, hipStream_t st) {
+  if (ix.n_seg == 0) return hipSuccess;
+  const int tpb = 256;
+  const int64_t grid = (ix.n_seg + tpb - 1) / tpb;
+  hipLaunchKernelGGL(prep_kernel, dim3((unsigned)grid), dim3(tpb), 0, st, ix, a,
+                     const_cast<double *>(pr.inv_n2), const_cast<double *>(pr.rad),
+                     const_cast<double *>(pr.slack));
+  return hipGetLastError();
+}
+
+hipError_t launch_query(const IndexDesc &ix, const Prep &pr, const QueryArgs &a,
+                        const tnn_points &qs, int waves_per_block, int32_t *out_idx,
+                        double *out_dist, hipStream_t st) {
+  if (qs.n == 0) return hipSuccess;
+  const int64_t grid = (qs.n + waves_per_block - 1) / waves_per_block;
+  hipLaunchKernelGGL(tnn_query_kernel, dim3((unsigned)grid), dim3(waves_per_block * kWave), 0, st,
+                     ix, pr, a, qs.x, qs.y, qs.z, qs.t, qs.n, out_idx, out_dist);
+  return hipGetLastError();
+}
+
+hipError_t launch_brute(const IndexDesc &ix, const QueryArgs &a, const tnn_points &qs,
+                        int waves_per_block, int32_t *out_idx, double *out_dist, hipStream_t st) {
+  if (qs.n == 0) return hipSuccess;
+  const int64_t grid = (qs.n + waves_per_block - 1) / waves_per_block;
+  hipLaunchKernelGGL(brute_kernel, dim3((unsigned)grid), dim3(waves_per_block * kWave), 0, st, ix,
+                     a, qs.x, qs.y, qs.z, qs.t, qs.n, out_idx, out_dist);
+  return hipGetLastError();
+}
+
+hipError_t launch_debug_lb(const IndexDesc &ix, const Prep &pr, const QueryArgs &a,
+                           const tnn_points &qs, double *seg_lb_out, float *block_lb_out,
+                           hipStream_t st) {
+  const int64_t total = qs.n * (ix.n_seg + ix.n_blocks);
+  if (total == 0) return hipSuccess;
+  const int tpb = 256;
+  hipLaunchKernelGGL(debug_lb_kernel, dim3((unsigned)((total + tpb - 1) / tpb)), dim3(tpb), 0, st,
+                     ix, pr, a, qs.x, qs.y, qs.z, qs.t, qs.n, seg_lb_out, block_lb_out);
+  return hipGetLastError();
+}
+
+}  // namespace tnn

@@ -1,0 +1,63 @@
+// Internal layout shared by the host entry points and the gfx950 kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/tnn.h"
+
+namespace tnn {
+
+constexpr int kWave = 64;          // CDNA wavefront width
+constexpr int kBlockSegs = 64;     // segments per culling block (one per lane)
+constexpr int kMaxK = 64;          // top-k held one rank per lane
+constexpr int kMaxSegLen = 64;
+
+// Everything a kernel needs to read a built index.  Lives inside tnn_index.
+struct IndexDesc {
+  uint32_t magic;
+  int32_t seg_len;     // K
+  int32_t kpad;        // K rounded up to a power of two (points per lane group)
+  int32_t n_blocks;
+  int64_t n_points;
+  int64_t n_seg;
+  // sorted points (segment order), SoA
+  const float *px, *py, *pz, *pt;
+  const int32_t *pid;  // caller index of each slot
+  // segments (block order), SoA
+  const float *ax, *ay, *az, *bx, *by, *bz, *tmin, *tmax, *ex, *ey, *ez;
+  const int32_t *pstart, *pcount, *sorig;
+  // block boxes: box[f][b] for f = 0..7 (lo x y z t, hi x y z t)
+  const float *box;
+  float lo[4], hi[4];  // bounding box of all points
+};
+static_assert(sizeof(IndexDesc) <= sizeof(tnn_index), "index descriptor too large");
+constexpr uint32_t kIndexMagic = 0x544e4e31u;  // "TNN1"
+
+// Per-call prepared segment data (depends on the scales).
+struct Prep {
+  const double *inv_n2;  // 1 / |AB|_s^2, 0 for a degenerate segment
+  const double *rad;     // radius R(s) = sqrt(sum s_f e_f^2), rounded up
+  const double *slack;   // absolute slack for the projection error, 2^-30 |AB|_s
+};
+
+struct QueryArgs {
+  double inf;          // +infinity, from the host (see TopK::init)
+  double s[4];
+  float sf[4];         // scales rounded toward zero to float32 (block bounds)
+  double t_window;
+  int32_t k;
+  uint32_t flags;
+  int32_t seed_segments;
+  const float *radius2;
+  unsigned long long *stats;
+};
+
+inline size_t align_up(size_t v, size_t a = 256) { return (v + a - 1) / a * a; }
+
+}  // namespace tnn
+
+#define TNN_HIP_CHECK(expr)                   \
+  do {                                        \
+    hipError_t e_ = (expr);                   \
+    if (e_ != hipSuccess) return TNN_E_HIP;   \
+  } while (0)

@@ -1,0 +1,156 @@
+"""Python binding of the C ABI: the same entry points, taking torch device
+tensors.  Argument marshalling only -- every step runs in libtnn's kernels;
+torch supplies device memory and the current stream.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import capi
+from .capi import TnnIndex, TnnPoints, TnnQueryParams, check
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _f32(t):
+    if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
+        raise ValueError("expected a contiguous float32 CUDA tensor")
+    return t
+
+
+def points(x, y, z, t):
+    """tnn_points view of four float32 device tensors (kept alive by caller)."""
+    n = x.shape[0]
+    for a in (x, y, z, t):
+        _f32(a)
+        if a.shape[0] != n:
+            raise ValueError("x, y, z, t must have the same length")
+    return TnnPoints(_ptr(x), _ptr(y), _ptr(z), _ptr(t), n)
+
+
+def to_device(*arrays, device="cuda"):
+    return tuple(torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(device) for a in arrays)
+
+
+@dataclass
+class Index:
+    mem: torch.Tensor
+    c: TnnIndex
+    n_points: int
+    n_segments: int
+    n_blocks: int
+    seg_len: int
+
+    @property
+    def ref(self):
+        return ctypes.byref(self.c)
+
+
+def tnn_build_segments(x, y, z, t, traj_offsets, seg_len, order_scale=(1.0, 1.0, 10.0, 0.05)):
+    L = capi.lib()
+    off = np.ascontiguousarray(traj_offsets, dtype=np.int64)
+    n_traj = off.shape[0] - 1
+    nbytes = ctypes.c_size_t(0)
+    check(L.tnn_build_segments_workspace(off.ctypes.data_as(ctypes.c_void_p), n_traj, seg_len,
+                                         ctypes.byref(nbytes)), "tnn_build_segments_workspace")
+    mem = torch.empty(max(nbytes.value, 256), dtype=torch.uint8, device=x.device)
+    idx = TnnIndex()
+    osc = None
+    if order_scale is not None:
+        osc = (ctypes.c_double * 4)(*[float(v) for v in order_scale])
+    check(L.tnn_build_segments(points(x, y, z, t), off.ctypes.data_as(ctypes.c_void_p), n_traj,
+                               seg_len, osc, _ptr(mem), nbytes.value, _stream(), ctypes.byref(idx)),
+          "tnn_build_segments")
+    n_p, n_s, n_b, sl = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int32()
+    check(L.tnn_index_info(ctypes.byref(idx), ctypes.byref(n_p), ctypes.byref(n_s), ctypes.byref(n_b),
+                           ctypes.byref(sl)), "tnn_index_info")
+    return Index(mem, idx, n_p.value, n_s.value, n_b.value, sl.value)
+
+
+def make_params(scale, t_window, k, flags=0, seed_segments=0, waves_per_block=0, radius2=None,
+                stats=None):
+    p = TnnQueryParams()
+    for i in range(4):
+        p.scale[i] = float(scale[i])
+    p.t_window = float(t_window)
+    p.k = int(k)
+    p.flags = int(flags)
+    p.seed_segments = int(seed_segments)
+    p.waves_per_block = int(waves_per_block)
+    p.d_radius2 = _ptr(radius2) if radius2 is not None else None
+    p.d_stats = _ptr(stats) if stats is not None else None
+    return p
+
+
+def tnn_query_workspace(index, n_queries, params):
+    nbytes = ctypes.c_size_t(0)
+    check(capi.lib().tnn_query_workspace(index.ref, n_queries, ctypes.byref(params), ctypes.byref(nbytes)),
+          "tnn_query_workspace")
+    return nbytes.value
+
+
+def new_stats(device="cuda"):
+    return torch.zeros(capi.TNN_STAT_COUNT, dtype=torch.int64, device=device)
+
+
+def stats_dict(stats):
+    v = stats.cpu().numpy().astype(np.uint64)
+    out = {name: int(v[i]) for i, name in enumerate(capi.STAT_NAMES)}
+    out["max_err"] = float(v[8:9].view(np.float64)[0])
+    del out["max_err_bits"]
+    return out
+
+
+def tnn_query(index, qx, qy, qz, qt, scale, t_window, k, flags=0, seed_segments=0,
+              waves_per_block=0, radius2=None, stats=None, out=None, scratch=None):
+    """Returns (idx int32 [nq, k], dist float64 [nq, k]) device tensors."""
+    L = capi.lib()
+    nq = qx.shape[0]
+    params = make_params(scale, t_window, k, flags, seed_segments, waves_per_block, radius2, stats)
+    need = tnn_query_workspace(index, nq, params)
+    if scratch is None or scratch.numel() < need:
+        scratch = torch.empty(max(need, 256), dtype=torch.uint8, device=qx.device)
+    if out is None:
+        out = (torch.empty((nq, k), dtype=torch.int32, device=qx.device),
+               torch.empty((nq, k), dtype=torch.float64, device=qx.device))
+    check(L.tnn_query(index.ref, points(qx, qy, qz, qt), ctypes.byref(params), _ptr(out[0]),
+                      _ptr(out[1]), _ptr(scratch), scratch.numel(), _stream()), "tnn_query")
+    return out
+
+
+def tnn_debug_export_index(index):
+    L = capi.lib()
+    dev = index.mem.device
+    seg_f = torch.empty((index.n_segments, 12), dtype=torch.float32, device=dev)
+    seg_i = torch.empty((index.n_segments, 4), dtype=torch.int32, device=dev)
+    pid = torch.empty(index.n_points, dtype=torch.int32, device=dev)
+    box = torch.empty((index.n_blocks, 8), dtype=torch.float32, device=dev)
+    check(L.tnn_debug_export_index(index.ref, _ptr(seg_f), _ptr(seg_i), _ptr(pid), _ptr(box), _stream()),
+          "tnn_debug_export_index")
+    return dict(seg_f32=seg_f, seg_i32=seg_i, point_id=pid, block_box=box)
+
+
+def tnn_debug_lower_bounds(index, qx, qy, qz, qt, scale, t_window):
+    L = capi.lib()
+    nq = qx.shape[0]
+    dev = qx.device
+    seg_lb = torch.empty((nq, index.n_segments), dtype=torch.float64, device=dev)
+    blk_lb = torch.empty((nq, index.n_blocks), dtype=torch.float32, device=dev)
+    params = make_params(scale, t_window, 1)
+    need = tnn_query_workspace(index, nq, params)
+    scratch = torch.empty(max(need, 256), dtype=torch.uint8, device=dev)
+    sc = (ctypes.c_double * 4)(*[float(v) for v in scale])
+    check(L.tnn_debug_lower_bounds(index.ref, points(qx, qy, qz, qt), sc, float(t_window), _ptr(seg_lb),
+                                   _ptr(blk_lb), _ptr(scratch), scratch.numel(), _stream()),
+          "tnn_debug_lower_bounds")
+    return seg_lb, blk_lb

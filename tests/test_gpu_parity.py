@@ -1,0 +1,233 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle."""
+import json
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_util import assert_same, build, config_data, dev_points, gpu_query, say
+from paper_2112_10408_amd import capi, synth
+from paper_2112_10408_amd import tnn as T
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+SCALE = synth.SCALE
+
+
+def _soa(rows):
+    a = np.array([[float(Fraction(str(v))) for v in r] for r in rows], dtype=np.float64)
+    return synth.PointSet(*(a[:, i].astype(np.float32) for i in range(4)),
+                          offsets=np.array([0, a.shape[0]], dtype=np.int64))
+
+
+def _golden():
+    with open(os.path.join(GOLDEN, "knn_cases.json")) as f:
+        return json.load(f)["cases"]
+
+
+@pytest.mark.parametrize("case", _golden(), ids=lambda c: c["name"])
+@pytest.mark.parametrize("flags", [capi.TNN_PLAIN, capi.TNN_BRUTE])
+def test_golden_cases(case, flags):
+    say("golden", case["name"], flags)
+    ps = _soa(case["points"])
+    ps.offsets = np.array(case["offsets"], dtype=np.int64)
+    qs = _soa(case["queries"])
+    ix = build(ps, seg_len=2)
+    gi, gd = gpu_query(ix, qs, case["scale"], case["t_window"], case["k"], flags=flags)
+    assert gi.tolist() == case["idx"]
+    want = np.array([[math.inf if v == "inf" else float(Fraction(v)) for v in r] for r in case["dist"]])
+    assert np.array_equal(gd, want)
+
+
+@pytest.mark.parametrize("flags", [capi.TNN_PLAIN, capi.TNN_BRUTE])
+def test_c1_all_queries(flags):
+    """10k points (200 x 50), K=16, every point a query, k=8."""
+    ps, qs, _, cfg = config_data("c1")
+    say("c1", flags)
+    ix = build(ps, cfg["seg_len"])
+    gi, gd = gpu_query(ix, qs, SCALE, 0.0, cfg["k"], flags=flags)
+    oi, od = oracle.knn(ps.soa(), qs.soa(), SCALE, 0.0, cfg["k"])
+    assert_same(gi, gd, oi, od, "c1")
+
+
+def _climbing(seed, n_traj=40, n_pts=77):
+    rng = np.random.default_rng(seed)
+    ps = synth.trajectories(n_traj, n_pts, 120.0, 900.0, seed)
+    ps.z = (ps.z + np.cumsum(rng.normal(0, 0.3, ps.n))).astype(np.float32)
+    ps.y = (ps.y + rng.normal(0, 0.4, ps.n)).astype(np.float32)
+    return ps
+
+
+@pytest.mark.parametrize("seg_len", [1, 5, 16, 64])
+def test_segments_match_oracle(seg_len):
+    ps = _climbing(3)
+    say("segments", seg_len)
+    ix = build(ps, seg_len)
+    ex = T.tnn_debug_export_index(ix)
+    torch.cuda.synchronize()
+    seg = oracle.segments(ps.soa(), ps.offsets, seg_len)
+    S = seg["start"].shape[0]
+    assert ix.n_segments == S
+    f = ex["seg_f32"].cpu().numpy().astype(np.float64)
+    i = ex["seg_i32"].cpu().numpy()
+    pid = ex["point_id"].cpu().numpy()
+    order = i[:, 0]
+    assert sorted(order.tolist()) == list(range(S))
+    # integer fields bit-exact
+    assert np.array_equal(pid[i[:, 1]], seg["start"][order])
+    assert np.array_equal(i[:, 2], seg["count"][order])
+    assert np.array_equal(np.sort(pid), np.arange(ps.n))
+    for s in range(0, S, max(1, S // 50)):
+        c = i[s, 2]
+        assert np.array_equal(pid[i[s, 1]:i[s, 1] + c], np.arange(seg["start"][order[s]], seg["start"][order[s]] + c))
+    # endpoints and times are copies of float32 inputs: exact
+    assert np.array_equal(f[:, 0:3], seg["a"][order])
+    assert np.array_equal(f[:, 3:6], seg["b"][order])
+    assert np.array_equal(f[:, 6], seg["tmin"][order])
+    assert np.array_equal(f[:, 7], seg["tmax"][order])
+    # errors: rounded up, never below the oracle's, within a float32 ulp + slack
+    e_o = seg["e"][order]
+    e_g = f[:, 8:11]
+    assert np.all(e_g >= e_o)
+    mag = np.abs(seg["a"][order]) + np.abs(seg["b"][order]) + 1.0
+    assert np.all(e_g - e_o <= np.spacing(e_g.astype(np.float32)).astype(np.float64) + 1e-9 * mag)
+
+
+@pytest.mark.parametrize("scale", [SCALE, (1.0, 3.0, 100.0, 0.5), (0.2, 1.0, 1.0, 0.0)])
+@pytest.mark.parametrize("t_window", [0.0, 25.0])
+def test_lower_bounds_hold_and_are_tight(scale, t_window):
+    ps = _climbing(5)
+    ix = build(ps, 11)
+    say("lower bounds", scale, t_window)
+    rng = np.random.default_rng(8)
+    qi = rng.choice(ps.n, 64, replace=False)
+    qs = ps.take(qi)
+    qs.t = (qs.t + rng.uniform(-3, 30, qs.n)).astype(np.float32)
+    qx, qy, qz, qt = dev_points(qs)
+    seg_lb, blk_lb = T.tnn_debug_lower_bounds(ix, qx, qy, qz, qt, scale, t_window)
+    ex = T.tnn_debug_export_index(ix)
+    torch.cuda.synchronize()
+    seg_lb = seg_lb.cpu().numpy()
+    blk_lb = blk_lb.cpu().numpy().astype(np.float64)
+    i = ex["seg_i32"].cpu().numpy()
+    pid = ex["point_id"].cpu().numpy()
+    S = ix.n_segments
+    # exact distance of every (query, point) pair, oracle arithmetic
+    QQ, PP = np.meshgrid(np.arange(qs.n), np.arange(ps.n), indexing="ij")
+    d = oracle.pair_dist(ps.soa(), qs.soa(), QQ.ravel(), PP.ravel(), scale).reshape(qs.n, ps.n)
+    valid = ps.t[None, :].astype(np.float64) < (qs.t.astype(np.float64)[:, None] - t_window)
+    dm = np.where(valid, d, np.inf)
+    seg_o = oracle.segments(ps.soa(), ps.offsets, 11)
+    lb_o = oracle.lower_bound(seg_o, qs.soa(), scale, t_window)[:, i[:, 0]]
+    for s in range(S):
+        members = pid[i[s, 1]:i[s, 1] + i[s, 2]]
+        dmin = dm[:, members].min(1)
+        assert np.all(seg_lb[:, s] <= dmin), s
+        b = s // 64
+        assert np.all(blk_lb[:, b] <= dmin), s
+    # masks agree exactly with the oracle's; finite bounds within rounding slack
+    assert np.array_equal(np.isinf(seg_lb), np.isinf(lb_o))
+    fin = np.isfinite(lb_o)
+    assert np.all(seg_lb[fin] <= lb_o[fin] * (1 + 1e-9) + 1e-12)
+    assert np.all(seg_lb[fin] >= lb_o[fin] * (1 - 1e-5) - 1e-6)
+
+
+@pytest.mark.parametrize("k", [1, 7, 32, 64])
+@pytest.mark.parametrize("seg_len", [1, 3, 32, 64])
+def test_shapes_and_ragged(k, seg_len):
+    """Several blocks, ragged trajectories, k up to 64, K from 1 to 64."""
+    rng = np.random.default_rng(k * 100 + seg_len)
+    counts = rng.integers(1, 150, 60)
+    ps = synth.trajectories(60, counts, 150.0, 1200.0, seed=k + seg_len)
+    qs, _ = synth.sample_queries(ps, 300, seed=1)
+    say("shapes", k, seg_len, ps.n)
+    ix = build(ps, seg_len)
+    oi, od = oracle.knn(ps.soa(), qs.soa(), SCALE, 0.0, k)
+    for flags in (capi.TNN_PLAIN, capi.TNN_BRUTE):
+        gi, gd = gpu_query(ix, qs, SCALE, 0.0, k, flags=flags)
+        assert_same(gi, gd, oi, od, f"k={k} K={seg_len} flags={flags}")
+
+
+@pytest.mark.parametrize("scale,t_window", [((1, 1, 10, 0.05), 60.0), ((1, 1, 10, 0.0), 0.0),
+                                            ((0, 0, 0, 1), 0.0), ((1, 1, 1, 1), 0.0),
+                                            ((1, 2, 3, 4e-4), 1000.0)])
+def test_scales_windows_and_off_data_queries(scale, t_window):
+    ps = synth.trajectories(80, 60, 200.0, 1800.0, seed=21)
+    rng = np.random.default_rng(22)
+    qs = synth.PointSet(rng.uniform(-20, 220, 400).astype(np.float32),
+                        rng.uniform(-20, 220, 400).astype(np.float32),
+                        rng.uniform(7, 13, 400).astype(np.float32),
+                        rng.uniform(-100, 2300, 400).astype(np.float32), np.array([0, 400]))
+    say("scales", scale, t_window)
+    ix = build(ps, 16)
+    oi, od = oracle.knn(ps.soa(), qs.soa(), scale, t_window, 10)
+    gi, gd = gpu_query(ix, qs, scale, t_window, 10)
+    assert_same(gi, gd, oi, od, f"scale={scale} tw={t_window}")
+
+
+def test_empty_and_tiny_inputs():
+    ps = synth.trajectories(3, 4, 10.0, 100.0, seed=1)
+    ix = build(ps, 16)
+    empty = synth.PointSet(*(np.zeros(0, np.float32) for _ in range(4)), np.array([0, 0]))
+    gi, gd = gpu_query(ix, empty, SCALE, 0.0, 5)
+    assert gi.shape == (0, 5)
+    qs = ps.take(np.arange(ps.n))
+    gi, gd = gpu_query(ix, qs, SCALE, 0.0, 64)  # k far above the data
+    oi, od = oracle.knn(ps.soa(), qs.soa(), SCALE, 0.0, 64)
+    assert_same(gi, gd, oi, od, "k>N")
+
+
+@pytest.mark.parametrize("kind", ["zero", "inf", "nan", "tiny", "huge", "exact", "under", "noisy"])
+def test_learned_radius_never_changes_results(kind):
+    ps, qs, _, cfg = config_data("c1")
+    ix = build(ps, cfg["seg_len"])
+    k = cfg["k"]
+    oi, od = oracle.knn(ps.soa(), qs.soa(), SCALE, 0.0, k)
+    kth = od[:, k - 1]
+    rng = np.random.default_rng(4)
+    r2 = {"zero": np.zeros(qs.n), "inf": np.full(qs.n, np.inf), "nan": np.full(qs.n, np.nan),
+          "tiny": np.full(qs.n, 1e-30), "huge": np.full(qs.n, 1e30),
+          "exact": kth, "under": kth * 0.999,
+          "noisy": kth * np.exp(rng.normal(0, 1.0, qs.n))}[kind]
+    say("learned radius", kind)
+    r2t = torch.from_numpy(np.asarray(r2, dtype=np.float32)).cuda()
+    gi, gd = gpu_query(ix, qs, SCALE, 0.0, k, flags=capi.TNN_LEARNED, radius2=r2t)
+    assert_same(gi, gd, oi, od, f"learned {kind}")
+
+
+def test_c2_full_size_sampled_parity():
+    """1M points (5000 x 200), K=32, 100k sampled queries, k=32: every query
+    on the GPU (plain TNN and linear search agree everywhere); a seeded sample
+    of queries checked against the oracle."""
+    ps, qs, _, cfg = config_data("c2")
+    k = cfg["k"]
+    say("c2 build")
+    ix = build(ps, cfg["seg_len"])
+    stats = T.new_stats()
+    say("c2 plain")
+    gi, gd = gpu_query(ix, qs, SCALE, 0.0, k, stats=stats)
+    say("c2 stats", T.stats_dict(stats))
+    say("c2 brute")
+    bi, bd = gpu_query(ix, qs, SCALE, 0.0, k, flags=capi.TNN_BRUTE)
+    assert_same(gi, gd, bi.astype(np.int64), bd, "c2 plain vs brute")
+    rng = np.random.default_rng(2112)
+    sample = np.sort(rng.choice(qs.n, 256, replace=False))
+    sample = np.concatenate([sample, np.argsort(qs.t)[:8]])  # the earliest queries
+    oi, od = oracle.knn(ps.soa(), qs.take(sample).soa(), SCALE, 0.0, k)
+    assert_same(gi[sample], gd[sample], oi, od, "c2 sample")
+    # properties on every query: ascending keys, valid, caller indices
+    assert np.all((np.diff(gd, axis=1) >= 0) | np.isinf(gd[:, 1:]))
+    ok = gi >= 0
+    assert np.all(ps.t[np.where(ok, gi, 0)][ok] < qs.t[:, None].repeat(k, 1)[ok])
+
+
+def test_repeat_runs_are_bitwise_identical():
+    ps, qs, _, cfg = config_data("c1")
+    ix = build(ps, cfg["seg_len"])
+    a = gpu_query(ix, qs, SCALE, 0.0, cfg["k"])
+    b = gpu_query(ix, qs, SCALE, 0.0, cfg["k"])
+    assert a[0].tobytes() == b[0].tobytes() and a[1].tobytes() == b[1].tobytes()
