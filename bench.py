@@ -79,6 +79,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-brute", action="store_true")
+    ap.add_argument("--train-queries", type=int, default=100_000)
+    ap.add_argument("--train-epochs", type=int, default=8)
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run a 256 MiB device-to-device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -87,12 +91,12 @@ def main():
         sys.exit(2)
 
     import torch
-    from paper_2112_10408_amd import capi, synth
+    from paper_2112_10408_amd import capi, radius, synth
     from paper_2112_10408_amd import tnn as T
 
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
-    ps, qs, _, cfg = synth.make_config("c2")
+    ps, qs, qidx, cfg = synth.make_config("c2")
     k, K, scale = cfg["k"], cfg["seg_len"], synth.SCALE
     log(f"workload: {ps.n} points, {qs.n} queries, k={k}, K={K}")
     x, y, z, t = T.to_device(ps.x, ps.y, ps.z, ps.t)
@@ -109,6 +113,7 @@ def main():
     scratch = torch.empty(max(T.tnn_query_workspace(ix, qs.n, p_plain), 256), dtype=torch.uint8,
                           device="cuda")
 
+    # ---- plain TNN ----------------------------------------------------------
     def plain():
         T.tnn_query(ix, qx, qy, qz, qt, scale, 0.0, k, out=out, scratch=scratch)
 
@@ -117,9 +122,70 @@ def main():
     stats = T.new_stats()
     T.tnn_query(ix, qx, qy, qz, qt, scale, 0.0, k, stats=stats, out=out, scratch=scratch)
     torch.cuda.synchronize()
-    st = T.stats_dict(stats)
-    log("plain stats:", st)
+    st_plain = T.stats_dict(stats)
+    log("plain stats:", st_plain)
     ref_idx = out[0].clone()
+    ref_dist = out[1].clone()
+
+    # ---- learned radius: train on the method's own output (setup, untimed) --
+    tq, _ = synth.sample_queries(ps, args.train_queries, cfg["seed"] + 2000, exclude=qidx)
+    tx, ty, tz, tt = T.to_device(tq.x, tq.y, tq.z, tq.t)
+    t0 = time.perf_counter()
+    model, loss, pdist, ptr = radius.train(ix, tx, ty, tz, tt, scale, 0.0, k,
+                                           epochs=args.train_epochs, batch=4096, lr=3e-3)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    log(f"radius model: {args.train_queries} labelled queries, loss {loss:.4f}, {train_s:.2f} s")
+    r2 = torch.empty(qs.n, dtype=torch.float32, device="cuda")
+    # safety factor: the quantile whose learned search is fastest on the
+    # training queries
+    r2_tr = torch.empty(tq.n, dtype=torch.float32, device="cuda")
+    out_tr = (torch.empty((tq.n, k), dtype=torch.int32, device="cuda"),
+              torch.empty((tq.n, k), dtype=torch.float64, device="cuda"))
+    best = None
+    for qnt in (0.5, 0.7, 0.8, 0.9, 0.95):
+        a = radius.calibrate(model, *ptr, pdist, k, quantile=qnt)
+
+        def learned_tr():
+            T.tnn_radius_infer(model, tx, ty, tz, tt, a, out=r2_tr)
+            T.tnn_query(ix, tx, ty, tz, tt, scale, 0.0, k, flags=capi.TNN_LEARNED, radius2=r2_tr,
+                        out=out_tr, scratch=scratch)
+
+        ms = timed(learned_tr, 3, 1, stream)
+        log(f"  quantile {qnt}: alpha {a:.3f}, {ms:.3f} ms on the training queries")
+        if best is None or ms < best[0]:
+            best = (ms, qnt, a)
+    alpha = best[2]
+
+    # ---- learned TNN: the headline step (radius inference + search) ---------
+    def learned():
+        T.tnn_radius_infer(model, qx, qy, qz, qt, alpha, out=r2)
+        T.tnn_query(ix, qx, qy, qz, qt, scale, 0.0, k, flags=capi.TNN_LEARNED, radius2=r2,
+                    out=out, scratch=scratch)
+
+    ms_learned = timed(learned, args.steps, args.warmup, stream)
+
+    def learned_search_only():
+        T.tnn_query(ix, qx, qy, qz, qt, scale, 0.0, k, flags=capi.TNN_LEARNED, radius2=r2,
+                    out=out, scratch=scratch)
+
+    ms_search = timed(learned_search_only, args.steps, 1, stream)
+    exact = bool(torch.equal(out[0], ref_idx)) and bool(torch.equal(out[1], ref_dist))
+    stats = T.new_stats()
+    T.tnn_query(ix, qx, qy, qz, qt, scale, 0.0, k, flags=capi.TNN_LEARNED, radius2=r2,
+                stats=stats, out=out, scratch=scratch)
+    torch.cuda.synchronize()
+    st = T.stats_dict(stats)
+    log(f"learned TNN: {ms_learned:.3f} ms/step ({ms_search:.3f} ms search), "
+        f"{qs.n / ms_learned * 1e3:.0f} q/s, same as plain {exact}, fallbacks {st['fallbacks']}")
+    log("learned stats:", st)
+
+    if args.calib_copy:
+        src = torch.empty(64 << 20, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     result_extra = {}
     if not args.no_brute:
@@ -136,21 +202,28 @@ def main():
 
     flops = (FLOPS_BLOCK_BOUND * st["blocks"] + FLOPS_SEG_BOUND * st["segments"]
              + FLOPS_POINT * st["points"])
-    achieved = flops / (ms_plain * 1e-3) / 1e12
+    achieved = flops / (ms_search * 1e-3) / 1e12
     roofline = {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": None,
-                "kernel": "tnn_query_kernel"}
-    value = qs.n / ms_plain * 1e3
+                "kernel": "tnn_query_kernel (learned)",
+                "kernel_ms": ms_search}
+    value = qs.n / ms_learned * 1e3
     res = {
         "metric": "exact k-NN queries/sec at 1M pts, k=32: learned+mixed TNN vs plain TNN vs brute",
         "value": value, "unit": "queries/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": ms_plain, "higher_is_better": True,
+        "warmup": args.warmup, "ms_per_step": ms_learned, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": "1M trajectory points (5000x200), K=32, 100k sampled queries, k=32, "
                                "scales (1,1,10,0.05), mask t'<t",
-                   "path": "plain TNN", "global_batch": qs.n, "seed": cfg["seed"]},
+                   "path": "learned-radius TNN (radius inference + search)",
+                   "global_batch": qs.n, "seed": cfg["seed"]},
         "roofline": roofline,
-        "plain_qps": value, "index_build_s": build_s, "stats": st,
+        "plain_qps": qs.n / ms_plain * 1e3, "learned_qps": value,
+        "learned_speedup_vs_plain": ms_plain / ms_learned,
+        "learned_matches_plain": exact, "fallback_rate": st["fallbacks"] / qs.n,
+        "radius_alpha": alpha, "radius_quantile": best[1], "radius_train_s": train_s,
+        "radius_train_queries": args.train_queries,
+        "index_build_s": build_s, "stats_learned": st, "stats_plain": st_plain,
     }
     res.update(result_extra)
     if not args.no_cpu_baseline:

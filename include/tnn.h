@@ -165,6 +165,74 @@ tnn_status tnn_debug_lower_bounds(const tnn_index *index, tnn_points queries,
                                   float *d_block_lb, void *d_scratch, size_t scratch_bytes,
                                   void *stream);
 
+
+/* ------------------------------------------------------------------------
+ * Learned k-th radius (not in the paper): a 5-64-64-1 ReLU MLP predicting
+ * log r_k, r_k = sqrt(d_k) the k-th neighbour's distance, from the query's
+ * coordinates mapped to [-1, 1] over the data's bounding box and
+ * 0.25*log1p(segment count of its cell in a 32^3 (x, y, t) grid).  Its
+ * prediction seeds TNN_LEARNED queries; results stay exact whatever it says.
+ * ------------------------------------------------------------------------ */
+#define TNN_RADIUS_HIDDEN 64
+#define TNN_RADIUS_INPUTS 5
+#define TNN_RADIUS_GRID 32
+#define TNN_RADIUS_NPARAMS (TNN_RADIUS_HIDDEN * TNN_RADIUS_INPUTS + TNN_RADIUS_HIDDEN + \
+                            TNN_RADIUS_HIDDEN * TNN_RADIUS_HIDDEN + TNN_RADIUS_HIDDEN +     \
+                            TNN_RADIUS_HIDDEN + 1)
+
+/* Device layout of a radius model; its bytes are the checkpoint format. */
+typedef struct {
+  float params[TNN_RADIUS_NPARAMS]; /* W1[64][5] b1[64] W2[64][64] b2[64] W3[64] b3 */
+  float pad[3];
+  float lo[4], hi[4];               /* bounding box of the indexed points (x, y, z, t) */
+  int32_t grid[TNN_RADIUS_GRID * TNN_RADIUS_GRID * TNN_RADIUS_GRID]; /* [x][y][t] */
+} tnn_radius_model;
+
+/* sizeof(tnn_radius_model). */
+tnn_status tnn_radius_model_bytes(size_t *bytes);
+
+/* Fill a model for `index`: bounding box and density grid from the index,
+ * weights drawn uniformly in +-sqrt(6 / fan_in) from a counter-based hash of
+ * `seed` (biases 0).  d_model: device, tnn_radius_model_bytes.  Async. */
+tnn_status tnn_radius_model_init(const tnn_index *index, void *d_model, uint64_t seed,
+                                 void *stream);
+
+/* Scratch bytes of tnn_radius_grad / tnn_radius_train_step for `batch`. */
+tnn_status tnn_radius_train_workspace(int64_t batch, size_t *bytes);
+
+/*
+ * Gradient of the mean squared error between the MLP output and the label
+ * log(sqrt(d)) over the samples [first, first + batch) of `samples`, where d =
+ * d_dist[i*k + k-1] (the k-th distance tnn_query wrote for sample i); samples
+ * whose d is not finite and positive are left out.  Writes d_grad[NPARAMS]
+ * (float32, device) and *d_loss (float32, device; may be NULL).  Sums run in
+ * a fixed order: the result is deterministic.  Async.
+ */
+tnn_status tnn_radius_grad(const void *d_model, tnn_points samples, const double *d_dist,
+                           int32_t k, int64_t first, int64_t batch, float *d_grad,
+                           float *d_loss, void *d_scratch, size_t scratch_bytes, void *stream);
+
+/*
+ * One Adam step (Kingma & Ba 2015, beta1 0.9, beta2 0.999, eps 1e-8) on that
+ * gradient.  d_adam: device float[2*NPARAMS] (first and second moments),
+ * zero before step 1; `step` counts from 1.  Async.
+ */
+tnn_status tnn_radius_train_step(void *d_model, float *d_adam, tnn_points samples,
+                                 const double *d_dist, int32_t k, int64_t first, int64_t batch,
+                                 int32_t step, float lr, float *d_loss, void *d_scratch,
+                                 size_t scratch_bytes, void *stream);
+
+/* Test export: the 5 features of each query, d_feat[5*i + j].  Async. */
+tnn_status tnn_radius_features(const void *d_model, tnn_points queries, float *d_feat,
+                               void *stream);
+
+/*
+ * Predicted k-th distance per query: d_radius2[i] = (alpha * exp(out_i))^2,
+ * float32 (the TNN_LEARNED seed); d_logr (nullable) receives out_i.  Async.
+ */
+tnn_status tnn_radius_infer(const void *d_model, tnn_points queries, float alpha,
+                            float *d_radius2, float *d_logr, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -79,8 +79,8 @@ _SIGS = {
     "tnn_radius_model_bytes": (i32, [ctypes.POINTER(sz)]),
     "tnn_radius_model_init": (i32, [ctypes.POINTER(TnnIndex), P, u64, P]),
     "tnn_radius_train_workspace": (i32, [i64, ctypes.POINTER(sz)]),
-    "tnn_radius_grad": (i32, [P, TnnPoints, P, i32, i64, P, P, P, sz, P]),
-    "tnn_radius_train_step": (i32, [P, P, TnnPoints, P, i32, i64, i32, f32, P, P, sz, P]),
+    "tnn_radius_grad": (i32, [P, TnnPoints, P, i32, i64, i64, P, P, P, sz, P]),
+    "tnn_radius_train_step": (i32, [P, P, TnnPoints, P, i32, i64, i64, i32, f32, P, P, sz, P]),
     "tnn_radius_features": (i32, [P, TnnPoints, P, P]),
     "tnn_radius_infer": (i32, [P, TnnPoints, f32, P, P, P]),
     "tnn_query_mixed_workspace": (i32, [ctypes.POINTER(TnnIndex), i64, ctypes.POINTER(TnnQueryParams),

@@ -1,0 +1,384 @@
+// Learned k-th radius: a 5-64-64-1 ReLU MLP (float32) with hand-written
+// inference, forward/backward and Adam kernels.  Not part of the paper; it
+// only seeds the search radius of TNN_LEARNED queries.
+#include <cmath>
+#include <cstring>
+
+#include "tnn_internal.h"
+
+namespace tnn {
+namespace {
+
+constexpr int H = TNN_RADIUS_HIDDEN;
+constexpr int NI = TNN_RADIUS_INPUTS;
+constexpr int G = TNN_RADIUS_GRID;
+constexpr int NP = TNN_RADIUS_NPARAMS;
+// offsets of the parameter tensors in params[]
+constexpr int OW1 = 0, OB1 = OW1 + H * NI, OW2 = OB1 + H, OB2 = OW2 + H * H, OW3 = OB2 + H,
+              OB3 = OW3 + H;
+static_assert(OB3 + 1 == NP, "parameter layout");
+constexpr int kTrainBlock = 64;  // samples per workgroup in the backward pass
+
+__host__ __device__ inline uint64_t splitmix64(uint64_t x) {
+  x += 0x9e3779b97f4a7c15ull;
+  x = (x ^ (x >> 30)) * 0xbf58476d1ce4e5b9ull;
+  x = (x ^ (x >> 27)) * 0x94d049bb133111ebull;
+  return x ^ (x >> 31);
+}
+
+// Cell of the density grid, decided in float32 exactly as written.
+__device__ inline int cell_of(float v, float lo, float hi) {
+  const float span = hi - lo;
+  const float cs = span > 0.0f ? (float)G / span : 0.0f;
+  float c = (v - lo) * cs;
+  if (!isfinite(c)) c = 0.0f;
+  c = truncf(c);
+  int i = (int)fminf(fmaxf(c, 0.0f), (float)(G - 1));
+  return i;
+}
+
+__device__ inline void features(const tnn_radius_model *m, float x, float y, float z, float t,
+                                float f[NI]) {
+  const float v[4] = {x, y, z, t};
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const float span = m->hi[j] - m->lo[j];
+    const float g = span > 0.0f ? 2.0f / span : 1.0f;
+    f[j] = (v[j] - 0.5f * (m->lo[j] + m->hi[j])) * g;
+  }
+  const int cx = cell_of(x, m->lo[0], m->hi[0]);
+  const int cy = cell_of(y, m->lo[1], m->hi[1]);
+  const int ct = cell_of(t, m->lo[3], m->hi[3]);
+  f[4] = 0.25f * log1pf((float)m->grid[(cx * G + cy) * G + ct]);
+}
+
+__global__ void init_kernel(tnn_radius_model *m, uint64_t seed, IndexDesc ix) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < NP) {
+    int fan_in = 0;
+    if (i < OB1) fan_in = NI;
+    else if (i >= OW2 && i < OB2) fan_in = H;
+    else if (i >= OW3 && i < OB3) fan_in = H;
+    float w = 0.0f;
+    if (fan_in) {
+      const uint64_t r = splitmix64(seed ^ ((uint64_t)i * 0xd1b54a32d192ed03ull));
+      const float u = (float)(r >> 40) * (1.0f / 16777216.0f);  // [0, 1)
+      w = (2.0f * u - 1.0f) * sqrtf(6.0f / (float)fan_in);
+    }
+    m->params[i] = w;
+  }
+  if (i < 3) m->pad[i] = 0.0f;
+  if (i < 4) {
+    m->lo[i] = ix.lo[i];
+    m->hi[i] = ix.hi[i];
+  }
+  if (i < G * G * G) m->grid[i] = 0;
+}
+
+__global__ void grid_kernel(tnn_radius_model *m, IndexDesc ix) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= ix.n_seg) return;
+  const float mx = 0.5f * (ix.ax[s] + ix.bx[s]);
+  const float my = 0.5f * (ix.ay[s] + ix.by[s]);
+  const float mt = 0.5f * (ix.tmin[s] + ix.tmax[s]);
+  const int cx = cell_of(mx, m->lo[0], m->hi[0]);
+  const int cy = cell_of(my, m->lo[1], m->hi[1]);
+  const int ct = cell_of(mt, m->lo[3], m->hi[3]);
+  atomicAdd(&m->grid[(cx * G + cy) * G + ct], 1);
+}
+
+__global__ void features_kernel(const tnn_radius_model *m, tnn_points q, float *out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= q.n) return;
+  float f[NI];
+  features(m, q.x[i], q.y[i], q.z[i], q.t[i], f);
+  for (int j = 0; j < NI; ++j) out[NI * i + j] = f[j];
+}
+
+// One thread per query; weights staged in LDS (broadcast reads).
+__global__ __launch_bounds__(256) void infer_kernel(const tnn_radius_model *m, tnn_points q,
+                                                     float alpha, float *radius2, float *logr) {
+  __shared__ float W[NP];
+  for (int i = threadIdx.x; i < NP; i += blockDim.x) W[i] = m->params[i];
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= q.n) return;
+  float f[NI];
+  features(m, q.x[i], q.y[i], q.z[i], q.t[i], f);
+  float h1[H];
+#pragma unroll
+  for (int j = 0; j < H; ++j) {
+    float a = W[OB1 + j];
+#pragma unroll
+    for (int c = 0; c < NI; ++c) a += W[OW1 + j * NI + c] * f[c];
+    h1[j] = fmaxf(a, 0.0f);
+  }
+  float out = W[OB3];
+  for (int j = 0; j < H; ++j) {
+    float a = W[OB2 + j];
+#pragma unroll
+    for (int c = 0; c < H; ++c) a += W[OW2 + j * H + c] * h1[c];
+    out += W[OW3 + j] * fmaxf(a, 0.0f);
+  }
+  const float r = alpha * expf(out);
+  radius2[i] = r * r;
+  if (logr) logr[i] = out;
+}
+
+// Forward and backward over kTrainBlock samples per workgroup; writes this
+// workgroup's un-normalised gradient sum (2 r dout/dtheta) and its loss
+// partials (sum r^2, count) to partial[blockIdx].
+__global__ __launch_bounds__(kTrainBlock) void fwd_bwd_kernel(const tnn_radius_model *m,
+                                                              tnn_points smp, const double *dist,
+                                                              int32_t k, int64_t first,
+                                                              int64_t batch, float *partial) {
+  __shared__ float W[NP];
+  __shared__ float F[kTrainBlock][NI];
+  __shared__ float H1[kTrainBlock][H + 1];   // h1
+  __shared__ float H2[kTrainBlock][H + 1];   // h2
+  __shared__ float G2[kTrainBlock][H + 1];   // dL/dz2
+  __shared__ float G1[kTrainBlock][H + 1];   // dL/dz1
+  __shared__ float GO[kTrainBlock];      // dL/dout (un-normalised: 2 r)
+  __shared__ float R2[kTrainBlock];
+  const int t = threadIdx.x;
+  for (int i = t; i < NP; i += blockDim.x) W[i] = m->params[i];
+  __syncthreads();
+  const int64_t b = (int64_t)blockIdx.x * kTrainBlock + t;
+  float go = 0.0f, r2 = 0.0f;
+  float f[NI] = {0, 0, 0, 0, 0};
+  if (b < batch) {
+    const int64_t si = first + b;
+    features(m, smp.x[si], smp.y[si], smp.z[si], smp.t[si], f);
+    const double dk = dist[si * k + (k - 1)];
+    const bool lab = dk > 0.0 && dk < __builtin_huge_val();
+    for (int j = 0; j < H; ++j) {
+      float a = W[OB1 + j];
+#pragma unroll
+      for (int c = 0; c < NI; ++c) a += W[OW1 + j * NI + c] * f[c];
+      G1[t][j] = a;  // z1 for now; replaced by dL/dz1 below
+      H1[t][j] = fmaxf(a, 0.0f);
+    }
+    float out = W[OB3];
+    for (int j = 0; j < H; ++j) {
+      float a = W[OB2 + j];
+      for (int c = 0; c < H; ++c) a += W[OW2 + j * H + c] * H1[t][c];
+      const float h2 = fmaxf(a, 0.0f);
+      H2[t][j] = h2;
+      G2[t][j] = a > 0.0f ? 1.0f : 0.0f;  // relu gate, scaled below
+      out += W[OW3 + j] * h2;
+    }
+    if (lab) {
+      const float y = (float)(0.5 * log(dk));
+      const float r = out - y;
+      go = 2.0f * r;
+      r2 = r * r;
+    }
+    for (int j = 0; j < H; ++j) G2[t][j] *= go * W[OW3 + j];
+    for (int c = 0; c < H; ++c) {
+      float a = 0.0f;
+      for (int j = 0; j < H; ++j) a += G2[t][j] * W[OW2 + j * H + c];
+      G1[t][c] = G1[t][c] > 0.0f ? a : 0.0f;
+    }
+    for (int c = 0; c < NI; ++c) F[t][c] = f[c];
+    GO[t] = go;
+    R2[t] = lab ? r2 : 0.0f;
+  } else {
+    for (int j = 0; j < H; ++j) H1[t][j] = H2[t][j] = G2[t][j] = G1[t][j] = 0.0f;
+    for (int c = 0; c < NI; ++c) F[t][c] = 0.0f;
+    GO[t] = 0.0f;
+    R2[t] = 0.0f;
+  }
+  __syncthreads();
+  float *out = partial + (size_t)blockIdx.x * (NP + 3);
+  for (int p = t; p < NP; p += blockDim.x) {
+    float acc = 0.0f;
+    if (p < OB1) {
+      const int j = p / NI, c = p % NI;
+      for (int s = 0; s < kTrainBlock; ++s) acc += G1[s][j] * F[s][c];
+    } else if (p < OW2) {
+      const int j = p - OB1;
+      for (int s = 0; s < kTrainBlock; ++s) acc += G1[s][j];
+    } else if (p < OB2) {
+      const int j = (p - OW2) / H, c = (p - OW2) % H;
+      for (int s = 0; s < kTrainBlock; ++s) acc += G2[s][j] * H1[s][c];
+    } else if (p < OW3) {
+      const int j = p - OB2;
+      for (int s = 0; s < kTrainBlock; ++s) acc += G2[s][j];
+    } else if (p < OB3) {
+      const int j = p - OW3;
+      for (int s = 0; s < kTrainBlock; ++s) acc += GO[s] * H2[s][j];
+    } else {
+      for (int s = 0; s < kTrainBlock; ++s) acc += GO[s];
+    }
+    out[p] = acc;
+  }
+  if (t == 0) {
+    float l = 0.0f, c = 0.0f;
+    for (int s = 0; s < kTrainBlock; ++s) {
+      l += R2[s];
+      const int64_t bs = (int64_t)blockIdx.x * kTrainBlock + s;
+      if (bs < batch) {
+        const double dk = dist[(first + bs) * k + (k - 1)];
+        c += (dk > 0.0 && dk < __builtin_huge_val()) ? 1.0f : 0.0f;
+      }
+    }
+    out[NP] = l;
+    out[NP + 1] = c;
+  }
+}
+
+// Sum of the partials in block order (deterministic), divided by the number
+// of labelled samples.
+__global__ void reduce_kernel(const float *partial, int nblk, float *grad, float *loss) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  float n = 0.0f;
+  for (int b = 0; b < nblk; ++b) n += partial[(size_t)b * (NP + 3) + NP + 1];
+  const float inv = 1.0f / fmaxf(n, 1.0f);
+  if (p < NP) {
+    float a = 0.0f;
+    for (int b = 0; b < nblk; ++b) a += partial[(size_t)b * (NP + 3) + p];
+    grad[p] = a * inv;
+  }
+  if (p == 0 && loss) {
+    float l = 0.0f;
+    for (int b = 0; b < nblk; ++b) l += partial[(size_t)b * (NP + 3) + NP];
+    *loss = l * inv;
+  }
+}
+
+__global__ void adam_kernel(float *params, float *mom, const float *grad, int step, float lr) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= NP) return;
+  const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+  const float g = grad[p];
+  const float m = b1 * mom[p] + (1.0f - b1) * g;
+  const float v = b2 * mom[NP + p] + (1.0f - b2) * g * g;
+  mom[p] = m;
+  mom[NP + p] = v;
+  const float mh = m / (1.0f - powf(b1, (float)step));
+  const float vh = v / (1.0f - powf(b2, (float)step));
+  params[p] -= lr * mh / (sqrtf(vh) + eps);
+}
+
+size_t train_scratch(int64_t batch) {
+  const int64_t nblk = (batch + kTrainBlock - 1) / kTrainBlock;
+  return align_up((size_t)nblk * (NP + 3) * sizeof(float)) + align_up(NP * sizeof(float)) + 256;
+}
+
+const IndexDesc *desc_of(const tnn_index *index) {
+  if (!index) return nullptr;
+  const IndexDesc *d = reinterpret_cast<const IndexDesc *>(index);
+  return d->magic == kIndexMagic ? d : nullptr;
+}
+
+bool pts_ok(const tnn_points &p) {
+  return p.n >= 0 && (p.n == 0 || (p.x && p.y && p.z && p.t));
+}
+
+tnn_status launch_grad(const void *d_model, tnn_points smp, const double *d_dist, int32_t k,
+                       int64_t first, int64_t batch, float *grad, float *loss, void *scratch,
+                       size_t bytes, hipStream_t st) {
+  if (!d_model || !pts_ok(smp) || !d_dist || k < 1 || k > kMaxK || first < 0 || batch < 1 ||
+      first + batch > smp.n || !grad)
+    return TNN_E_ARG;
+  if (!scratch || bytes < train_scratch(batch)) return TNN_E_WORKSPACE;
+  const int nblk = (int)((batch + kTrainBlock - 1) / kTrainBlock);
+  float *partial = static_cast<float *>(scratch);
+  hipLaunchKernelGGL(fwd_bwd_kernel, dim3(nblk), dim3(kTrainBlock), 0, st,
+                     static_cast<const tnn_radius_model *>(d_model), smp, d_dist, k, first, batch,
+                     partial);
+  TNN_HIP_CHECK(hipGetLastError());
+  hipLaunchKernelGGL(reduce_kernel, dim3((NP + 255) / 256), dim3(256), 0, st, partial, nblk, grad,
+                     loss);
+  TNN_HIP_CHECK(hipGetLastError());
+  return TNN_OK;
+}
+
+}  // namespace
+}  // namespace tnn
+
+using namespace tnn;
+
+extern "C" {
+
+tnn_status tnn_radius_model_bytes(size_t *bytes) {
+  if (!bytes) return TNN_E_ARG;
+  *bytes = sizeof(tnn_radius_model);
+  return TNN_OK;
+}
+
+tnn_status tnn_radius_model_init(const tnn_index *index, void *d_model, uint64_t seed,
+                                 void *stream) {
+  const IndexDesc *d = desc_of(index);
+  if (!d || !d_model) return TNN_E_ARG;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  tnn_radius_model *m = static_cast<tnn_radius_model *>(d_model);
+  const int n = G * G * G > NP ? G * G * G : NP;
+  hipLaunchKernelGGL(init_kernel, dim3((n + 255) / 256), dim3(256), 0, st, m, seed, *d);
+  TNN_HIP_CHECK(hipGetLastError());
+  if (d->n_seg > 0) {
+    hipLaunchKernelGGL(grid_kernel, dim3((unsigned)((d->n_seg + 255) / 256)), dim3(256), 0, st, m,
+                       *d);
+    TNN_HIP_CHECK(hipGetLastError());
+  }
+  return TNN_OK;
+}
+
+tnn_status tnn_radius_train_workspace(int64_t batch, size_t *bytes) {
+  if (!bytes || batch < 1) return TNN_E_ARG;
+  *bytes = train_scratch(batch);
+  return TNN_OK;
+}
+
+tnn_status tnn_radius_grad(const void *d_model, tnn_points samples, const double *d_dist,
+                           int32_t k, int64_t first, int64_t batch, float *d_grad, float *d_loss,
+                           void *d_scratch, size_t scratch_bytes, void *stream) {
+  return launch_grad(d_model, samples, d_dist, k, first, batch, d_grad, d_loss, d_scratch,
+                     scratch_bytes, static_cast<hipStream_t>(stream));
+}
+
+tnn_status tnn_radius_train_step(void *d_model, float *d_adam, tnn_points samples,
+                                 const double *d_dist, int32_t k, int64_t first, int64_t batch,
+                                 int32_t step, float lr, float *d_loss, void *d_scratch,
+                                 size_t scratch_bytes, void *stream) {
+  if (!d_adam || step < 1 || !(lr > 0.0f) || !std::isfinite(lr)) return TNN_E_ARG;
+  if (!d_scratch || scratch_bytes < train_scratch(batch > 0 ? batch : 1)) return TNN_E_WORKSPACE;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int64_t nblk = (batch + kTrainBlock - 1) / kTrainBlock;
+  float *grad = reinterpret_cast<float *>(static_cast<char *>(d_scratch) +
+                                          align_up((size_t)nblk * (NP + 3) * sizeof(float)));
+  const tnn_status s = launch_grad(d_model, samples, d_dist, k, first, batch, grad, d_loss,
+                                   d_scratch, scratch_bytes, st);
+  if (s != TNN_OK) return s;
+  hipLaunchKernelGGL(adam_kernel, dim3((NP + 255) / 256), dim3(256), 0, st,
+                     static_cast<tnn_radius_model *>(d_model)->params, d_adam, grad, step, lr);
+  TNN_HIP_CHECK(hipGetLastError());
+  return TNN_OK;
+}
+
+tnn_status tnn_radius_features(const void *d_model, tnn_points queries, float *d_feat,
+                               void *stream) {
+  if (!d_model || !pts_ok(queries) || (queries.n > 0 && !d_feat)) return TNN_E_ARG;
+  if (queries.n == 0) return TNN_OK;
+  hipLaunchKernelGGL(features_kernel, dim3((unsigned)((queries.n + 255) / 256)), dim3(256), 0,
+                     static_cast<hipStream_t>(stream),
+                     static_cast<const tnn_radius_model *>(d_model), queries, d_feat);
+  TNN_HIP_CHECK(hipGetLastError());
+  return TNN_OK;
+}
+
+tnn_status tnn_radius_infer(const void *d_model, tnn_points queries, float alpha,
+                            float *d_radius2, float *d_logr, void *stream) {
+  if (!d_model || !pts_ok(queries) || (queries.n > 0 && !d_radius2) || !(alpha > 0.0f) ||
+      !std::isfinite(alpha))
+    return TNN_E_ARG;
+  if (queries.n == 0) return TNN_OK;
+  hipLaunchKernelGGL(infer_kernel, dim3((unsigned)((queries.n + 255) / 256)), dim3(256), 0,
+                     static_cast<hipStream_t>(stream),
+                     static_cast<const tnn_radius_model *>(d_model), queries, alpha, d_radius2,
+                     d_logr);
+  TNN_HIP_CHECK(hipGetLastError());
+  return TNN_OK;
+}
+
+}  // extern "C"

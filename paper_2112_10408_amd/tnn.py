@@ -154,3 +154,84 @@ def tnn_debug_lower_bounds(index, qx, qy, qz, qt, scale, t_window):
                                    _ptr(blk_lb), _ptr(scratch), scratch.numel(), _stream()),
           "tnn_debug_lower_bounds")
     return seg_lb, blk_lb
+
+
+# --------------------------------------------------------------------------
+# Learned k-th radius
+# --------------------------------------------------------------------------
+def tnn_radius_model_bytes():
+    n = ctypes.c_size_t(0)
+    check(capi.lib().tnn_radius_model_bytes(ctypes.byref(n)), "tnn_radius_model_bytes")
+    return n.value
+
+
+def tnn_radius_model_init(index, seed=1):
+    m = torch.empty(tnn_radius_model_bytes(), dtype=torch.uint8, device=index.mem.device)
+    check(capi.lib().tnn_radius_model_init(index.ref, _ptr(m), int(seed), _stream()),
+          "tnn_radius_model_init")
+    return m
+
+
+def radius_params(model):
+    """float32 view of the parameter vector inside a model blob."""
+    return model[: capi.RADIUS_NPARAMS * 4].view(torch.float32)
+
+
+def radius_box(model):
+    off = (capi.RADIUS_NPARAMS + 3) * 4
+    v = model[off: off + 32].view(torch.float32)
+    return v[:4], v[4:]
+
+
+def radius_grid(model):
+    off = (capi.RADIUS_NPARAMS + 3) * 4 + 32
+    g = capi.RADIUS_GRID
+    return model[off: off + 4 * g ** 3].view(torch.int32).view(g, g, g)
+
+
+def tnn_radius_train_workspace(batch):
+    n = ctypes.c_size_t(0)
+    check(capi.lib().tnn_radius_train_workspace(int(batch), ctypes.byref(n)),
+          "tnn_radius_train_workspace")
+    return n.value
+
+
+def tnn_radius_grad(model, sx, sy, sz, st, dist, k, first, batch, scratch=None):
+    dev = sx.device
+    grad = torch.empty(capi.RADIUS_NPARAMS, dtype=torch.float32, device=dev)
+    loss = torch.empty(1, dtype=torch.float32, device=dev)
+    need = tnn_radius_train_workspace(batch)
+    if scratch is None or scratch.numel() < need:
+        scratch = torch.empty(need, dtype=torch.uint8, device=dev)
+    check(capi.lib().tnn_radius_grad(_ptr(model), points(sx, sy, sz, st), _ptr(dist), int(k),
+                                     int(first), int(batch), _ptr(grad), _ptr(loss), _ptr(scratch),
+                                     scratch.numel(), _stream()), "tnn_radius_grad")
+    return grad, loss
+
+
+def tnn_radius_train_step(model, adam, sx, sy, sz, st, dist, k, first, batch, step, lr,
+                          loss=None, scratch=None):
+    dev = sx.device
+    need = tnn_radius_train_workspace(batch)
+    if scratch is None or scratch.numel() < need:
+        scratch = torch.empty(need, dtype=torch.uint8, device=dev)
+    check(capi.lib().tnn_radius_train_step(_ptr(model), _ptr(adam), points(sx, sy, sz, st), _ptr(dist),
+                                           int(k), int(first), int(batch), int(step), float(lr),
+                                           _ptr(loss), _ptr(scratch), scratch.numel(), _stream()),
+          "tnn_radius_train_step")
+    return scratch
+
+
+def tnn_radius_features(model, qx, qy, qz, qt):
+    f = torch.empty((qx.shape[0], capi.RADIUS_INPUTS), dtype=torch.float32, device=qx.device)
+    check(capi.lib().tnn_radius_features(_ptr(model), points(qx, qy, qz, qt), _ptr(f), _stream()),
+          "tnn_radius_features")
+    return f
+
+
+def tnn_radius_infer(model, qx, qy, qz, qt, alpha=1.0, out=None, logr=None):
+    if out is None:
+        out = torch.empty(qx.shape[0], dtype=torch.float32, device=qx.device)
+    check(capi.lib().tnn_radius_infer(_ptr(model), points(qx, qy, qz, qt), float(alpha), _ptr(out),
+                                      _ptr(logr), _stream()), "tnn_radius_infer")
+    return out

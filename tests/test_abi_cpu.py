@@ -84,3 +84,24 @@ def test_build_rejects_bad_arguments_without_gpu():
     rc = L.tnn_build_segments(pts, off.ctypes.data_as(ctypes.c_void_p), 1, 16, None,
                               ctypes.c_void_p(1), 1 << 20, None, ctypes.byref(out))
     assert rc == capi.TNN_E_ARG
+
+
+def _decl_arg_counts():
+    out = {}
+    inc = os.path.join(ROOT, "include")
+    for fn in os.listdir(inc):
+        if not fn.endswith(".h"):
+            continue
+        src = re.sub(r"/\*.*?\*/", "", open(os.path.join(inc, fn)).read(), flags=re.S)
+        for m in re.finditer(r"\b(tnn_[a-z0-9_]+)\s*\(([^)]*)\)\s*;", src):
+            args = m.group(2).strip()
+            out[m.group(1)] = 0 if args in ("", "void") else args.count(",") + 1
+    return out
+
+
+def test_binding_signatures_match_header_arity():
+    L = capi.lib()
+    counts = _decl_arg_counts()
+    assert counts
+    for name, n in counts.items():
+        assert len(getattr(L, name).argtypes) == n, name

@@ -1,0 +1,143 @@
+"""GPU parity of the learned k-th radius kernels (features, inference,
+forward/backward, Adam) against the oracle, and what training gains."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_util import assert_same, build, config_data, dev_points, gpu_query, say
+from paper_2112_10408_amd import capi, radius, synth
+from paper_2112_10408_amd import tnn as T
+
+pytestmark = pytest.mark.gpu
+SCALE = synth.SCALE
+
+
+@pytest.fixture(scope="module")
+def setup():
+    ps = synth.trajectories(400, 120, 800.0, 4 * 3600.0, seed=31)
+    ix = build(ps, 16)
+    model = T.tnn_radius_model_init(ix, seed=5)
+    torch.cuda.synchronize()
+    seg = oracle.segments(ps.soa(), ps.offsets, 16)
+    lo = np.array([a.min() for a in ps.soa()], dtype=np.float32)
+    hi = np.array([a.max() for a in ps.soa()], dtype=np.float32)
+    grid = oracle.radius_density_grid(seg["a"], seg["b"], seg["tmin"], seg["tmax"], lo, hi)
+    return ps, ix, model, lo, hi, grid
+
+
+def test_box_and_density_grid_match_oracle(setup):
+    ps, ix, model, lo, hi, grid = setup
+    glo, ghi = T.radius_box(model)
+    assert np.array_equal(glo.cpu().numpy(), lo) and np.array_equal(ghi.cpu().numpy(), hi)
+    g = T.radius_grid(model).cpu().numpy()
+    assert g.sum() == ix.n_segments
+    assert np.array_equal(g, grid)
+
+
+def test_features_match_oracle(setup):
+    ps, ix, model, lo, hi, grid = setup
+    rng = np.random.default_rng(3)
+    qs = ps.take(rng.choice(ps.n, 2000, replace=False))
+    f = T.tnn_radius_features(model, *dev_points(qs)).cpu().numpy().astype(np.float64)
+    fo = oracle.radius_features(*qs.soa(), lo, hi, grid)
+    assert np.allclose(f, fo, rtol=1e-6, atol=2e-6)
+
+
+def test_inference_matches_oracle_forward(setup):
+    ps, ix, model, lo, hi, grid = setup
+    qs = ps.take(np.arange(0, ps.n, 7))
+    q = dev_points(qs)
+    logr = torch.empty(qs.n, dtype=torch.float32, device="cuda")
+    r2 = T.tnn_radius_infer(model, *q, alpha=1.5, logr=logr)
+    theta = T.radius_params(model).cpu().numpy().astype(np.float64)
+    out, _ = oracle.mlp_forward(theta, oracle.radius_features(*qs.soa(), lo, hi, grid))
+    lg = logr.cpu().numpy().astype(np.float64)
+    assert np.allclose(lg, out, rtol=1e-5, atol=1e-5)
+    assert np.allclose(r2.cpu().numpy(), (1.5 * np.exp(lg)) ** 2, rtol=1e-5)
+
+
+@pytest.mark.parametrize("batch", [1, 63, 64, 1000])
+def test_gradient_matches_oracle_backprop(setup, batch):
+    ps, ix, model, lo, hi, grid = setup
+    k = 8
+    rng = np.random.default_rng(batch)
+    qs = ps.take(rng.choice(ps.n, batch + 10, replace=False))
+    _, dist = oracle.knn(ps.soa(), qs.soa(), SCALE, 0.0, k)
+    q = dev_points(qs)
+    dd = torch.from_numpy(dist).cuda()
+    first = 10
+    say("grad", batch)
+    g, loss = T.tnn_radius_grad(model, *q, dd, k, first, batch)
+    g = g.cpu().numpy().astype(np.float64)
+    theta = T.radius_params(model).cpu().numpy().astype(np.float64)
+    sub = qs.take(np.arange(first, first + batch))
+    X = oracle.radius_features(*sub.soa(), lo, hi, grid)
+    y = oracle.radius_label(dist[first:first + batch, k - 1])
+    lo_, go = oracle.mlp_loss_grad(theta, X, y)
+    assert float(loss.item()) == pytest.approx(lo_, rel=1e-4, abs=1e-6)
+    assert np.linalg.norm(g - go) <= 1e-4 * np.linalg.norm(go) + 1e-7
+
+
+def test_adam_step_matches_oracle(setup):
+    ps, ix, model0, lo, hi, grid = setup
+    model = model0.clone()
+    k = 8
+    qs = ps.take(np.arange(0, ps.n, 11)[:2048])
+    _, dist = oracle.knn(ps.soa(), qs.soa(), SCALE, 0.0, k)
+    q = dev_points(qs)
+    dd = torch.from_numpy(dist).cuda()
+    theta0 = T.radius_params(model).cpu().numpy().astype(np.float64)
+    adam = torch.zeros(2 * capi.RADIUS_NPARAMS, dtype=torch.float32, device="cuda")
+    m = np.zeros_like(theta0)
+    v = np.zeros_like(theta0)
+    th = theta0
+    for step in (1, 2, 3):
+        g_step, _ = T.tnn_radius_grad(model, *q, dd, k, 0, qs.n)
+        gs = g_step.cpu().numpy().astype(np.float64)
+        T.tnn_radius_train_step(model, adam, *q, dd, k, 0, qs.n, step, 1e-3)
+        th, m, v = oracle.adam_step(th, gs, m, v, step, 1e-3)
+        got = T.radius_params(model).cpu().numpy().astype(np.float64)
+        assert np.allclose(got, th, rtol=1e-5, atol=1e-6), step
+        th = got  # follow the device weights so rounding does not accumulate
+
+
+def test_training_learns_more_than_a_constant():
+    """Trained on the method's own k-th radii, the MLP predicts held-out
+    radii better than the best constant, and the learned search stays exact
+    while comparing fewer points than plain TNN."""
+    ps, qs, _, cfg = config_data("c1")
+    k = cfg["k"]
+    ix = build(ps, cfg["seg_len"])
+    rng = np.random.default_rng(17)
+    perm = rng.permutation(ps.n)
+    tr, te = ps.take(perm[:6000]), ps.take(perm[6000:])
+    say("train radius")
+    model, loss, pdist, ptr = radius.train(ix, *dev_points(tr), SCALE, 0.0, k, epochs=40, batch=512,
+                                           lr=3e-3)
+    te_q = dev_points(te)
+    logr = torch.empty(te.n, dtype=torch.float32, device="cuda")
+    T.tnn_radius_infer(model, *te_q, 1.0, logr=logr)
+    _, od = oracle.knn(ps.soa(), te.soa(), SCALE, 0.0, k)
+    y = oracle.radius_label(od[:, k - 1])
+    ok = np.isfinite(y)
+    pred = logr.cpu().numpy()[ok]
+    mse_model = float(np.mean((pred - y[ok]) ** 2))
+    mse_const = float(np.var(y[ok]))
+    say("held-out mse", mse_model, "constant", mse_const)
+    # the coordinates carry little of the radius on this synthetic data (it
+    # depends mostly on how far along its own trajectory a query lies), but
+    # the trained network must still beat the best constant
+    assert mse_model < 0.97 * mse_const
+    alpha = radius.calibrate(model, *ptr, pdist, k, quantile=0.9)
+    r2 = T.tnn_radius_infer(model, *te_q, alpha)
+    st_l = T.new_stats()
+    gi, gd = gpu_query(ix, te, SCALE, 0.0, k, flags=capi.TNN_LEARNED, radius2=r2, stats=st_l)
+    oi, _ = oracle.knn(ps.soa(), te.soa(), SCALE, 0.0, k)
+    assert_same(gi, gd, oi, od, "learned c1")
+    st_p = T.new_stats()
+    gpu_query(ix, te, SCALE, 0.0, k, stats=st_p)
+    sl, sp = T.stats_dict(st_l), T.stats_dict(st_p)
+    say("learned", sl, "plain", sp)
+    assert sl["blocks"] < sp["blocks"]
+    assert sl["fallbacks"] < 0.35 * te.n
