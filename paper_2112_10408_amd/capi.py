@@ -83,8 +83,6 @@ _SIGS = {
     "tnn_radius_train_step": (i32, [P, P, TnnPoints, P, i32, i64, i64, i32, f32, P, P, sz, P]),
     "tnn_radius_features": (i32, [P, TnnPoints, P, P]),
     "tnn_radius_infer": (i32, [P, TnnPoints, f32, P, P, P]),
-    "tnn_query_mixed_workspace": (i32, [ctypes.POINTER(TnnIndex), i64, ctypes.POINTER(TnnQueryParams),
-                                        ctypes.POINTER(sz)]),
     "tnn_batch_workspace": (i32, [ctypes.POINTER(TnnBatchItem), i32, ctypes.POINTER(sz)]),
     "tnn_batch_prepare": (i32, [ctypes.POINTER(TnnBatchItem), i32, P, sz, P, P]),
     "tnn_query_batched": (i32, [i32, P, sz, P]),

@@ -334,7 +334,10 @@ tnn_status tnn_query_workspace(const tnn_index *index, int64_t n_queries,
   if (!d || !bytes || n_queries < 0) return TNN_E_ARG;
   const tnn_status c = check_params(params);
   if (c != TNN_OK) return c;
-  *bytes = (params->flags & TNN_BRUTE) ? 256 : prep_bytes(d->n_seg);
+  if (params->flags & TNN_MIXED_BF16)
+    *bytes = mixed_scratch_bytes(d->n_points);
+  else
+    *bytes = (params->flags & TNN_BRUTE) ? 256 : prep_bytes(d->n_seg);
   return TNN_OK;
 }
 
@@ -348,11 +351,15 @@ tnn_status tnn_query(const tnn_index *index, tnn_points queries, const tnn_query
   if (queries.n > 0 && (!d_out_idx || !d_out_dist)) return TNN_E_ARG;
   size_t need = 0;
   tnn_query_workspace(index, queries.n, params, &need);
-  if (scratch_bytes < need || (need > 0 && !d_scratch && !(params->flags & TNN_BRUTE)))
-    return TNN_E_WORKSPACE;
+  const bool plain_brute = (params->flags & TNN_BRUTE) && !(params->flags & TNN_MIXED_BF16);
+  if (scratch_bytes < need || (need > 0 && !d_scratch && !plain_brute)) return TNN_E_WORKSPACE;
   hipStream_t st = static_cast<hipStream_t>(stream);
   const QueryArgs a = make_args(params);
   const int wpb = params->waves_per_block ? params->waves_per_block : 4;
+  if ((params->flags & TNN_BRUTE) && (params->flags & TNN_MIXED_BF16)) {
+    TNN_HIP_CHECK(launch_mixed_brute(*d, a, queries, d_out_idx, d_out_dist, d_scratch, st));
+    return TNN_OK;
+  }
   if (params->flags & TNN_BRUTE) {
     TNN_HIP_CHECK(launch_brute(*d, a, queries, wpb, d_out_idx, d_out_dist, st));
     return TNN_OK;

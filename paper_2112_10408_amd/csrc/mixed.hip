@@ -1,0 +1,346 @@
+// Linear search with BF16 matrix-core distance tiles (TNN_BRUTE |
+// TNN_MIXED_BF16).  Not in the paper: the all-pairs distance of Sec. 3.6's
+// linear search runs on MFMA as a proven lower-bound filter, and every pair
+// that passes it is rescored with the binary64 formula before the top-k, so
+// the result is identical to the exact linear search.
+//
+// Distance as a matrix product.  With v_f = sqrt(s_f) (p_f - c_f) and
+// u_f = sqrt(s_f) (q_f - c_f) (c = centre of the data box),
+//     d(q, p) = |u|^2 + |v|^2 - 2 u.v .
+// Each coordinate is split into three bfloat16 terms (h + m + l carries 24
+// bits) and the six products that matter (hh, hm, mh, hl, mm, lh) fill 24 of
+// the 32 K-slots of v_mfma_f32_16x16x32_bf16; the norms, pre-scaled by
+// (1 - gamma) and split the same way, fill six more.  The tile value is then
+//     c' = (1 - gamma)(|u|^2 + |v|^2) - 2 u.v  <=  d(q, p)
+// because the split, the float32 accumulation of 32 terms and the float32
+// inputs err by at most 1.6 * 2^-18 (|u|^2 + |v|^2), below gamma = 2^-16.
+#include "bounds.h"
+#include "query.h"
+
+namespace tnn {
+namespace {
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
+
+constexpr float kGamma = 0x1p-16f;
+constexpr int kMQ = 16;      // queries per wave (MFMA rows)
+constexpr int kWaves = 4;    // waves per workgroup
+constexpr int kPT = 32;      // points per LDS tile (two 16-column MFMA tiles)
+
+__device__ __forceinline__ __bf16 to_bf16(float x) {
+  // round to nearest even (finite inputs)
+  uint32_t u = __float_as_uint(x);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  const unsigned short h = (unsigned short)(u >> 16);
+  return __builtin_bit_cast(__bf16, h);
+}
+
+__device__ __forceinline__ float from_bf16(__bf16 b) {
+  const unsigned short h = __builtin_bit_cast(unsigned short, b);
+  return __uint_as_float((uint32_t)h << 16);
+}
+
+__device__ __forceinline__ void split3(float x, __bf16 &h, __bf16 &m, __bf16 &l) {
+  h = to_bf16(x);
+  const float r1 = x - from_bf16(h);
+  m = to_bf16(r1);
+  const float r2 = r1 - from_bf16(m);
+  l = to_bf16(r2);
+}
+
+struct MixedCtx {
+  float c[4];   // centre
+  float sq[4];  // sqrt of the scales
+};
+
+// Scaled, centred coordinates and their squared norm.
+__device__ __forceinline__ float scaled(const MixedCtx &mc, float x, float y, float z, float t,
+                                        float u[4]) {
+  const float v[4] = {x, y, z, t};
+  float n = 0.0f;
+#pragma unroll
+  for (int f = 0; f < 4; ++f) {
+    u[f] = mc.sq[f] * (v[f] - mc.c[f]);
+    n += u[f] * u[f];
+  }
+  return n;
+}
+
+// B operand (point side) for K-group g (lanes 16g..16g+15 supply slots
+// 8g..8g+7): see the slot table in the file comment.
+__device__ __forceinline__ bf16x8 point_group(const float v[4], float nvs, int g) {
+  __bf16 h[4], m[4], l[4];
+#pragma unroll
+  for (int f = 0; f < 4; ++f) split3(v[f], h[f], m[f], l[f]);
+  bf16x8 o;
+  const __bf16 one = to_bf16(1.0f), zero = to_bf16(0.0f);
+  if (g == 0) {
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+      o[f] = to_bf16(-2.0f * from_bf16(h[f]));
+      o[4 + f] = to_bf16(-2.0f * from_bf16(m[f]));
+    }
+  } else if (g == 1) {
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+      o[f] = to_bf16(-2.0f * from_bf16(h[f]));
+      o[4 + f] = to_bf16(-2.0f * from_bf16(l[f]));
+    }
+  } else if (g == 2) {
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+      o[f] = to_bf16(-2.0f * from_bf16(m[f]));
+      o[4 + f] = to_bf16(-2.0f * from_bf16(h[f]));
+    }
+  } else {
+    __bf16 nh, nm, nl;
+    split3(nvs, nh, nm, nl);
+    o[0] = one;
+    o[1] = one;
+    o[2] = one;
+    o[3] = nh;
+    o[4] = nm;
+    o[5] = nl;
+    o[6] = zero;
+    o[7] = zero;
+  }
+  return o;
+}
+
+// A operand (query side), paired slot by slot with point_group.
+__device__ __forceinline__ bf16x8 query_group(const float u[4], float nus, int g) {
+  __bf16 h[4], m[4], l[4];
+#pragma unroll
+  for (int f = 0; f < 4; ++f) split3(u[f], h[f], m[f], l[f]);
+  bf16x8 o;
+  const __bf16 one = to_bf16(1.0f), zero = to_bf16(0.0f);
+  if (g == 0) {
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+      o[f] = h[f];
+      o[4 + f] = h[f];
+    }
+  } else if (g == 1) {
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+      o[f] = m[f];
+      o[4 + f] = h[f];
+    }
+  } else if (g == 2) {
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+      o[f] = m[f];
+      o[4 + f] = l[f];
+    }
+  } else {
+    __bf16 nh, nm, nl;
+    split3(nus, nh, nm, nl);
+    o[0] = nh;
+    o[1] = nm;
+    o[2] = nl;
+    o[3] = one;
+    o[4] = one;
+    o[5] = one;
+    o[6] = zero;
+    o[7] = zero;
+  }
+  return o;
+}
+
+// Per call: the point operands in index order (4 groups of 8 bf16 per
+// point, 64 bytes) and |v|^2.
+__global__ void mixed_prep_kernel(IndexDesc ix, MixedCtx mc, bf16x8 *ops, float *nv) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= ix.n_points) return;
+  float v[4];
+  const float n = scaled(mc, ix.px[p], ix.py[p], ix.pz[p], ix.pt[p], v);
+  const float ns = (1.0f - kGamma) * n;
+#pragma unroll
+  for (int g = 0; g < 4; ++g) ops[4 * p + g] = point_group(v, ns, g);
+  nv[p] = n;
+}
+
+__device__ __forceinline__ float round_up_f(double x) {
+  return x < kInf ? __double2float_ru(x) : __builtin_huge_valf();
+}
+
+__global__ __launch_bounds__(kWaves * 64) void mixed_brute_kernel(
+    IndexDesc ix, QueryArgs a, MixedCtx mc, const bf16x8 *ops, const float *nv, const float *qxp,
+    const float *qyp, const float *qzp, const float *qtp, int64_t nq, int32_t *out_idx,
+    double *out_dist) {
+  __shared__ bf16x8 s_ops[kPT * 4];
+  __shared__ float s_pt[kPT];
+  __shared__ double s_tkd[kWaves][kMQ][64];
+  __shared__ int s_tkid[kWaves][kMQ][64];
+  __shared__ int s_qn[kWaves][kMQ];
+  __shared__ int s_qp[kWaves][kMQ][kPT];
+  __shared__ float s_qc[kWaves][kMQ][kPT];
+  __shared__ float s_tau[kWaves][kMQ];
+  __shared__ float s_thr[kWaves][kMQ];
+  __shared__ float s_nu[kWaves][kMQ];
+
+  const int lane = lane_id();
+  const int w = uniform_i((int)(threadIdx.x >> 6));
+  const int64_t qbase = ((int64_t)blockIdx.x * kWaves + w) * kMQ;
+  const int g = lane >> 4;        // K-group this lane supplies
+  const int row = lane & 15;      // A row = query
+  // ---- query operand and per-query state
+  const int64_t qa = qbase + row;
+  float u[4] = {0, 0, 0, 0};
+  float nu = 0.0f;
+  if (qa < nq) nu = scaled(mc, qxp[qa], qyp[qa], qzp[qa], qtp[qa], u);
+  const bf16x8 aop = query_group(u, (1.0f - kGamma) * nu, g);
+  if (lane < kMQ) {
+    const int64_t q = qbase + lane;
+    s_qn[w][lane] = 0;
+    s_nu[w][lane] = nu;
+    if (q < nq) {
+      s_tau[w][lane] = __builtin_huge_valf();
+      s_thr[w][lane] = round_up_f((double)qtp[q] - a.t_window);
+    } else {
+      s_tau[w][lane] = -__builtin_huge_valf();  // inactive row: nothing passes
+      s_thr[w][lane] = -__builtin_huge_valf();
+    }
+  }
+  for (int m = 0; m < kMQ; ++m) {
+    s_tkd[w][m][lane] = a.inf;
+    s_tkid[w][m][lane] = kNoId;
+  }
+  uint32_t rescored = 0;
+  double max_err = 0.0;
+  const int k = a.k;
+  const int64_t n = ix.n_points;
+  for (int64_t p0 = 0; p0 < n; p0 += kPT) {
+    __syncthreads();
+    // stage kPT point operands (256 threads x 16 bytes) and times
+    {
+      const int t = threadIdx.x;
+      const int64_t p = p0 + (t >> 2);
+      if (t < kPT * 4) {
+        bf16x8 v = {};
+        if (p < n) v = ops[4 * p + (t & 3)];
+        s_ops[t] = v;
+      }
+      if (t < kPT) s_pt[t] = (p0 + t < n) ? ix.pt[p0 + t] : __builtin_huge_valf();
+    }
+    __syncthreads();
+    float tau[4], thr[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      tau[e] = s_tau[w][g * 4 + e];
+      thr[e] = s_thr[w][g * 4 + e];
+    }
+#pragma unroll
+    for (int cb = 0; cb < kPT / 16; ++cb) {
+      const int col = cb * 16 + row;
+      const bf16x8 bop = s_ops[col * 4 + g];
+      f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aop, bop, acc, 0, 0, 0);
+      const float pt = s_pt[col];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        // row (query) g*4+e, column (point) col
+        if ((acc[e] <= tau[e]) & (pt < thr[e])) {
+          const int m = g * 4 + e;
+          const int slot = atomicAdd(&s_qn[w][m], 1);
+          s_qp[w][m][slot] = (int)(p0 + col);
+          s_qc[w][m][slot] = acc[e];
+        }
+      }
+    }
+    __syncthreads();
+    // ---- rescore survivors in binary64 and merge them into each top-k
+    for (int m = 0; m < kMQ; ++m) {
+      const int cnt = s_qn[w][m];
+      const int64_t q = qbase + m;
+      if (cnt == 0 || q >= nq) continue;
+      const QueryPoint qp = make_query(qxp[q], qyp[q], qzp[q], qtp[q], a.t_window);
+      const bool has = lane < cnt;
+      const int p = has ? s_qp[w][m][lane] : 0;
+      double d = a.inf;
+      int pid = kNoId;
+      bool valid = false;
+      if (has) {
+        const float pt = ix.pt[p];
+        d = exact_dist(a.s, qp.x, qp.y, qp.z, qp.t, ix.px[p], ix.py[p], ix.pz[p], pt);
+        pid = ix.pid[p];
+        valid = (double)pt < qp.thr;
+        const double approx = (double)s_qc[w][m][lane] + (double)kGamma * ((double)s_nu[w][m] + (double)nv[p]);
+        max_err = fmax(max_err, fabs(approx - d));
+      }
+      rescored += (uint32_t)cnt;
+      TopK tk;
+      tk.init(k, a.inf);
+      tk.d = s_tkd[w][m][lane];
+      tk.id = s_tkid[w][m][lane];
+      tk.refresh();
+      const bool gate = valid && tk.admits(d, pid);
+      const uint64_t gm = ballot(gate);
+      if (gm) {
+        tk.offer(gm, gate, d, pid);
+        s_tkd[w][m][lane] = tk.d;
+        s_tkid[w][m][lane] = tk.id;
+        if (lane == 0) s_tau[w][m] = round_up_f(tk.kd);
+      }
+      if (lane == 0) s_qn[w][m] = 0;
+    }
+  }
+  __syncthreads();
+  for (int m = 0; m < kMQ; ++m) {
+    const int64_t q = qbase + m;
+    if (q < nq && lane < k) {
+      const int id = s_tkid[w][m][lane];
+      out_idx[q * k + lane] = id == kNoId ? -1 : id;
+      out_dist[q * k + lane] = s_tkd[w][m][lane];
+    }
+  }
+  if (a.stats) {
+    for (int o = 32; o > 0; o >>= 1) max_err = fmax(max_err, __shfl_xor(max_err, o, 64));
+    if (lane == 0) {
+      int64_t nvalid = nq - qbase;
+      nvalid = nvalid < 0 ? 0 : (nvalid > kMQ ? kMQ : nvalid);
+      atomicAdd(a.stats + TNN_STAT_QUERIES, (unsigned long long)nvalid);
+      atomicAdd(a.stats + TNN_STAT_POINTS, (unsigned long long)(nvalid * n));
+      atomicAdd(a.stats + TNN_STAT_RESCORED, (unsigned long long)rescored);
+      atomicMax(a.stats + TNN_STAT_MAX_ERR, (unsigned long long)__double_as_longlong(max_err));
+    }
+  }
+}
+
+}  // namespace
+
+size_t mixed_scratch_bytes(int64_t n_points) {
+  return align_up((size_t)n_points * 64) + align_up((size_t)n_points * 4);
+}
+
+MixedCtx make_ctx(const IndexDesc &ix, const QueryArgs &a) {
+  MixedCtx mc;
+  for (int f = 0; f < 4; ++f) {
+    mc.c[f] = 0.5f * (ix.lo[f] + ix.hi[f]);
+    mc.sq[f] = (float)sqrt(a.s[f]);
+  }
+  return mc;
+}
+
+hipError_t launch_mixed_brute(const IndexDesc &ix, const QueryArgs &a, const tnn_points &qs,
+                              int32_t *out_idx, double *out_dist, void *scratch, hipStream_t st) {
+  if (qs.n == 0) return hipSuccess;
+  const MixedCtx mc = make_ctx(ix, a);
+  bf16x8 *ops = static_cast<bf16x8 *>(scratch);
+  float *nv = reinterpret_cast<float *>(static_cast<char *>(scratch) +
+                                        align_up((size_t)ix.n_points * 64));
+  if (ix.n_points > 0) {
+    hipLaunchKernelGGL(mixed_prep_kernel, dim3((unsigned)((ix.n_points + 255) / 256)), dim3(256), 0,
+                       st, ix, mc, ops, nv);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  const int64_t per_block = (int64_t)kWaves * kMQ;
+  hipLaunchKernelGGL(mixed_brute_kernel, dim3((unsigned)((qs.n + per_block - 1) / per_block)),
+                     dim3(kWaves * 64), 0, st, ix, a, mc, ops, nv, qs.x, qs.y, qs.z, qs.t, qs.n,
+                     out_idx, out_dist);
+  return hipGetLastError();
+}
+
+}  // namespace tnn

@@ -29,8 +29,12 @@ def _golden():
         return json.load(f)["cases"]
 
 
+MIXED = capi.TNN_BRUTE | capi.TNN_MIXED_BF16
+ALL_PATHS = [capi.TNN_PLAIN, capi.TNN_BRUTE, MIXED]
+
+
 @pytest.mark.parametrize("case", _golden(), ids=lambda c: c["name"])
-@pytest.mark.parametrize("flags", [capi.TNN_PLAIN, capi.TNN_BRUTE])
+@pytest.mark.parametrize("flags", ALL_PATHS)
 def test_golden_cases(case, flags):
     say("golden", case["name"], flags)
     ps = _soa(case["points"])
@@ -43,7 +47,7 @@ def test_golden_cases(case, flags):
     assert np.array_equal(gd, want)
 
 
-@pytest.mark.parametrize("flags", [capi.TNN_PLAIN, capi.TNN_BRUTE])
+@pytest.mark.parametrize("flags", ALL_PATHS)
 def test_c1_all_queries(flags):
     """10k points (200 x 50), K=16, every point a query, k=8."""
     ps, qs, _, cfg = config_data("c1")
@@ -147,7 +151,7 @@ def test_shapes_and_ragged(k, seg_len):
     say("shapes", k, seg_len, ps.n)
     ix = build(ps, seg_len)
     oi, od = oracle.knn(ps.soa(), qs.soa(), SCALE, 0.0, k)
-    for flags in (capi.TNN_PLAIN, capi.TNN_BRUTE):
+    for flags in ALL_PATHS:
         gi, gd = gpu_query(ix, qs, SCALE, 0.0, k, flags=flags)
         assert_same(gi, gd, oi, od, f"k={k} K={seg_len} flags={flags}")
 
@@ -165,8 +169,9 @@ def test_scales_windows_and_off_data_queries(scale, t_window):
     say("scales", scale, t_window)
     ix = build(ps, 16)
     oi, od = oracle.knn(ps.soa(), qs.soa(), scale, t_window, 10)
-    gi, gd = gpu_query(ix, qs, scale, t_window, 10)
-    assert_same(gi, gd, oi, od, f"scale={scale} tw={t_window}")
+    for flags in ALL_PATHS:
+        gi, gd = gpu_query(ix, qs, scale, t_window, 10, flags=flags)
+        assert_same(gi, gd, oi, od, f"scale={scale} tw={t_window} flags={flags}")
 
 
 def test_empty_and_tiny_inputs():
@@ -214,6 +219,9 @@ def test_c2_full_size_sampled_parity():
     say("c2 brute")
     bi, bd = gpu_query(ix, qs, SCALE, 0.0, k, flags=capi.TNN_BRUTE)
     assert_same(gi, gd, bi.astype(np.int64), bd, "c2 plain vs brute")
+    say("c2 mixed")
+    mi, md = gpu_query(ix, qs, SCALE, 0.0, k, flags=MIXED)
+    assert_same(gi, gd, mi.astype(np.int64), md, "c2 plain vs mixed brute")
     rng = np.random.default_rng(2112)
     sample = np.sort(rng.choice(qs.n, 256, replace=False))
     sample = np.concatenate([sample, np.argsort(qs.t)[:8]])  # the earliest queries
@@ -231,3 +239,25 @@ def test_repeat_runs_are_bitwise_identical():
     a = gpu_query(ix, qs, SCALE, 0.0, cfg["k"])
     b = gpu_query(ix, qs, SCALE, 0.0, cfg["k"])
     assert a[0].tobytes() == b[0].tobytes() and a[1].tobytes() == b[1].tobytes()
+
+
+def test_mixed_precision_error_is_within_the_proven_margin():
+    """BF16 tiles: the largest |approximate - binary64| distance over every
+    rescored pair stays below gamma (|u|^2 + |v|^2) with gamma = 2^-16, and
+    the indices are bit-exact."""
+    ps, qs, _, cfg = config_data("c1")
+    k = cfg["k"]
+    ix = build(ps, cfg["seg_len"])
+    stats = T.new_stats()
+    gi, gd = gpu_query(ix, qs, SCALE, 0.0, k, flags=MIXED, stats=stats)
+    oi, od = oracle.knn(ps.soa(), qs.soa(), SCALE, 0.0, k)
+    assert_same(gi, gd, oi, od, "mixed c1")
+    st = T.stats_dict(stats)
+    say("mixed stats", st)
+    pts = np.stack([a.astype(np.float64) for a in ps.soa()], 1)
+    lo, hi = pts.min(0), pts.max(0)
+    c = 0.5 * (lo + hi)
+    s = np.asarray(SCALE)
+    n_max = (s * np.maximum((lo - c) ** 2, (hi - c) ** 2)).sum()
+    assert st["rescored"] >= qs.n * 1  # every query rescored at least its neighbours
+    assert 0.0 < st["max_err"] <= 2.0 ** -16 * 2 * n_max
