@@ -233,6 +233,75 @@ tnn_status tnn_radius_features(const void *d_model, tnn_points queries, float *d
 tnn_status tnn_radius_infer(const void *d_model, tnn_points queries, float alpha,
                             float *d_radius2, float *d_logr, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Batched ragged serving: many independent indexes ("airspaces"), each with
+ * its own queries, k, scales and flags, answered by one persistent launch.
+ * Waves pull chunks of queries from a device work counter, heaviest airspace
+ * first (longest-processing-time order by estimated cost), so a whole batch
+ * is one kernel and can be captured in a HIP graph and replayed.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+  const tnn_index *index;   /* host pointer to a built index */
+  tnn_points queries;       /* device SoA */
+  tnn_query_params params;  /* TNN_PLAIN or TNN_LEARNED only; k 1..64 */
+  int32_t *d_out_idx;       /* device [queries.n * k] */
+  double *d_out_dist;       /* device [queries.n * k] */
+} tnn_batch_item;
+
+/* Launch shape of the persistent kernel (0 fields = defaults). */
+typedef struct {
+  int32_t chunk;            /* queries per pull from the work counter (1..64; 0 = 8) */
+  int32_t waves_per_block;  /* 1, 2, 4 or 8 (0 = 4) */
+  int32_t blocks_per_cu;    /* resident workgroups per compute unit (1..16; 0 = 4) */
+  int32_t reserved;
+} tnn_batch_config;
+
+/* Plan of a prepared batch: plain data describing device buffers that live in
+ * the scratch given to tnn_batch_prepare. */
+typedef struct {
+  uint64_t opaque[16];
+} tnn_batch_plan;
+
+#define TNN_MAX_BATCH_ITEMS 1024
+
+/* Scratch bytes of tnn_batch_prepare for these items (1..TNN_MAX_BATCH_ITEMS). */
+tnn_status tnn_batch_workspace(const tnn_batch_item *items, int32_t n_items, size_t *bytes);
+
+/*
+ * Validate the items, order them by estimated cost and upload the descriptor
+ * table into d_scratch (synchronous: not for graph capture).  The items'
+ * buffers must outlive every tnn_query_batched call on the plan.
+ */
+tnn_status tnn_batch_prepare(const tnn_batch_item *items, int32_t n_items,
+                             const tnn_batch_config *config, void *d_scratch, size_t bytes,
+                             void *stream, tnn_batch_plan *plan);
+
+/*
+ * Answer every item's queries (same results as one tnn_query per item).
+ * Queues only kernels (per-item preparation, a counter reset, the persistent
+ * search): safe inside HIP graph capture and replay.  Also records device
+ * wall-clock ticks: ticks[0] at the start, ticks[1 + i] when item i's last
+ * query is written (see tnn_batch_ticks, tnn_wall_clock_rate_khz).  Async.
+ */
+tnn_status tnn_query_batched(const tnn_batch_plan *plan, void *stream);
+
+/* Device pointer to the plan's uint64 tick array [n_items + 1]. */
+tnn_status tnn_batch_ticks(const tnn_batch_plan *plan, const uint64_t **d_ticks);
+
+/* Frequency of the device wall clock used for the ticks, in kHz. */
+tnn_status tnn_wall_clock_rate_khz(int64_t *khz);
+
+/*
+ * Autotuner: times the candidate launch shapes of the persistent kernel on
+ * these items (each candidate prepared and run on `stream`) and returns the
+ * fastest in *best.  With cache_path (nullable) the choice is read from / added
+ * to a small text cache keyed by device, item count, total queries and points,
+ * so later runs skip the search.  Synchronous.
+ */
+tnn_status tnn_autotune_batched(const tnn_batch_item *items, int32_t n_items, void *d_scratch,
+                                size_t bytes, void *stream, const char *cache_path,
+                                tnn_batch_config *best);
+
 #ifdef __cplusplus
 }
 #endif

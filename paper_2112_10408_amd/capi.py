@@ -64,6 +64,14 @@ class TnnBatchItem(ctypes.Structure):
                 ("params", TnnQueryParams), ("d_out_idx", P), ("d_out_dist", P)]
 
 
+class TnnBatchConfig(ctypes.Structure):
+    _fields_ = [("chunk", i32), ("waves_per_block", i32), ("blocks_per_cu", i32), ("reserved", i32)]
+
+
+class TnnBatchPlan(ctypes.Structure):
+    _fields_ = [("opaque", u64 * 16)]
+
+
 _SIGS = {
     "tnn_status_string": (ctypes.c_char_p, [i32]),
     "tnn_build_segments_workspace": (i32, [P, i64, i32, ctypes.POINTER(sz)]),
@@ -84,9 +92,13 @@ _SIGS = {
     "tnn_radius_features": (i32, [P, TnnPoints, P, P]),
     "tnn_radius_infer": (i32, [P, TnnPoints, f32, P, P, P]),
     "tnn_batch_workspace": (i32, [ctypes.POINTER(TnnBatchItem), i32, ctypes.POINTER(sz)]),
-    "tnn_batch_prepare": (i32, [ctypes.POINTER(TnnBatchItem), i32, P, sz, P, P]),
-    "tnn_query_batched": (i32, [i32, P, sz, P]),
+    "tnn_batch_prepare": (i32, [ctypes.POINTER(TnnBatchItem), i32, ctypes.POINTER(TnnBatchConfig),
+                                P, sz, P, ctypes.POINTER(TnnBatchPlan)]),
+    "tnn_query_batched": (i32, [ctypes.POINTER(TnnBatchPlan), P]),
+    "tnn_batch_ticks": (i32, [ctypes.POINTER(TnnBatchPlan), ctypes.POINTER(ctypes.c_void_p)]),
     "tnn_wall_clock_rate_khz": (i32, [ctypes.POINTER(i64)]),
+    "tnn_autotune_batched": (i32, [ctypes.POINTER(TnnBatchItem), i32, P, sz, P, ctypes.c_char_p,
+                                   ctypes.POINTER(TnnBatchConfig)]),
 }
 
 _lib = None

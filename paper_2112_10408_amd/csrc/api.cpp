@@ -1,6 +1,7 @@
 // C ABI of the trajectory nearest-neighbour library (declared in tnn.h):
 // argument checks, buffer layouts and kernel launches.  No allocation.
 #include <algorithm>
+#include <cstdio>
 #include <cmath>
 #include <cstring>
 #include <numeric>
@@ -103,14 +104,14 @@ bool points_ok(const tnn_points &p) {
   return p.x && p.y && p.z && p.t && p.n <= INT32_MAX;
 }
 
-tnn_status check_params(const tnn_query_params *p) {
+tnn_status check_params(const tnn_query_params *p, int64_t n_queries = 1) {
   if (!p) return TNN_E_ARG;
   for (int f = 0; f < 4; ++f)
     if (!(p->scale[f] >= 0.0) || !std::isfinite(p->scale[f])) return TNN_E_ARG;
   if (!(p->t_window >= 0.0) || !std::isfinite(p->t_window)) return TNN_E_ARG;
   if (p->k < 1 || p->k > kMaxK) return TNN_E_ARG;
   if (p->flags & ~(TNN_BRUTE | TNN_MIXED_BF16 | TNN_LEARNED)) return TNN_E_ARG;
-  if ((p->flags & TNN_LEARNED) && !p->d_radius2) return TNN_E_ARG;
+  if ((p->flags & TNN_LEARNED) && !p->d_radius2 && n_queries > 0) return TNN_E_ARG;
   if ((p->flags & TNN_MIXED_BF16) && !(p->flags & TNN_BRUTE)) return TNN_E_UNSUPPORTED;
   if (p->seed_segments < 0 || p->seed_segments > 64) return TNN_E_ARG;
   const int w = p->waves_per_block;
@@ -332,7 +333,7 @@ tnn_status tnn_query_workspace(const tnn_index *index, int64_t n_queries,
                                const tnn_query_params *params, size_t *bytes) {
   const IndexDesc *d = desc_of(index);
   if (!d || !bytes || n_queries < 0) return TNN_E_ARG;
-  const tnn_status c = check_params(params);
+  const tnn_status c = check_params(params, n_queries);
   if (c != TNN_OK) return c;
   if (params->flags & TNN_MIXED_BF16)
     *bytes = mixed_scratch_bytes(d->n_points);
@@ -346,7 +347,7 @@ tnn_status tnn_query(const tnn_index *index, tnn_points queries, const tnn_query
                      size_t scratch_bytes, void *stream) {
   const IndexDesc *d = desc_of(index);
   if (!d || !points_ok(queries)) return TNN_E_ARG;
-  const tnn_status c = check_params(params);
+  const tnn_status c = check_params(params, queries.n);
   if (c != TNN_OK) return c;
   if (queries.n > 0 && (!d_out_idx || !d_out_dist)) return TNN_E_ARG;
   size_t need = 0;
@@ -399,6 +400,254 @@ tnn_status tnn_debug_lower_bounds(const tnn_index *index, tnn_points queries,
   TNN_HIP_CHECK(launch_prep(*d, a, pr, st));
   TNN_HIP_CHECK(launch_debug_lb(*d, pr, a, queries, d_seg_lb, d_block_lb, st));
   return TNN_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Batched ragged serving.
+// ---------------------------------------------------------------------------
+namespace {
+
+struct BatchLayout {
+  size_t items, qprefix, order, seg_prefix, counter, done, ticks, prep0, total;
+  std::vector<size_t> prep;  // per item
+};
+
+BatchLayout batch_layout(const tnn_batch_item *items, int32_t n) {
+  BatchLayout L;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t r = o;
+    o = align_up(o + bytes);
+    return r;
+  };
+  L.items = take(sizeof(BatchItemDev) * (size_t)n);
+  L.qprefix = take(8 * (size_t)(n + 1));
+  L.order = take(4 * (size_t)n);
+  L.seg_prefix = take(8 * (size_t)(n + 1));
+  L.counter = take(8);
+  L.done = take(4 * (size_t)n);
+  L.ticks = take(8 * (size_t)(n + 1));
+  L.prep0 = o;
+  L.prep.resize(n);
+  for (int32_t i = 0; i < n; ++i) {
+    const IndexDesc *d = desc_of(items[i].index);
+    L.prep[i] = take(prep_bytes(d ? d->n_seg : 0));
+  }
+  L.total = o;
+  return L;
+}
+
+tnn_status check_items(const tnn_batch_item *items, int32_t n) {
+  if (!items || n < 1 || n > TNN_MAX_BATCH_ITEMS) return TNN_E_ARG;
+  for (int32_t i = 0; i < n; ++i) {
+    const tnn_batch_item &it = items[i];
+    if (!desc_of(it.index) || !points_ok(it.queries)) return TNN_E_ARG;
+    const tnn_status c = check_params(&it.params, it.queries.n);
+    if (c != TNN_OK) return c;
+    if (it.params.flags & (TNN_BRUTE | TNN_MIXED_BF16)) return TNN_E_UNSUPPORTED;
+    if (it.queries.n > 0 && (!it.d_out_idx || !it.d_out_dist)) return TNN_E_ARG;
+  }
+  return TNN_OK;
+}
+
+int device_cus() {
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  return cus;
+}
+
+}  // namespace
+
+extern "C" {
+
+tnn_status tnn_batch_workspace(const tnn_batch_item *items, int32_t n_items, size_t *bytes) {
+  if (!bytes) return TNN_E_ARG;
+  const tnn_status c = check_items(items, n_items);
+  if (c != TNN_OK) return c;
+  *bytes = batch_layout(items, n_items).total;
+  return TNN_OK;
+}
+
+tnn_status tnn_batch_prepare(const tnn_batch_item *items, int32_t n_items,
+                             const tnn_batch_config *config, void *d_scratch, size_t bytes,
+                             void *stream, tnn_batch_plan *plan) {
+  if (!plan || !d_scratch) return TNN_E_ARG;
+  const tnn_status c = check_items(items, n_items);
+  if (c != TNN_OK) return c;
+  tnn_batch_config cfg = {8, 4, 4, 0};
+  if (config) {
+    if (config->chunk) cfg.chunk = config->chunk;
+    if (config->waves_per_block) cfg.waves_per_block = config->waves_per_block;
+    if (config->blocks_per_cu) cfg.blocks_per_cu = config->blocks_per_cu;
+  }
+  const int w = cfg.waves_per_block;
+  if (cfg.chunk < 1 || cfg.chunk > 64 || !(w == 1 || w == 2 || w == 4 || w == 8) ||
+      cfg.blocks_per_cu < 1 || cfg.blocks_per_cu > 16)
+    return TNN_E_ARG;
+  const BatchLayout L = batch_layout(items, n_items);
+  if (bytes < L.total) return TNN_E_WORKSPACE;
+  const int cus = device_cus();
+  if (cus <= 0) return TNN_E_HIP;
+  char *m = static_cast<char *>(d_scratch);
+  const int32_t n = n_items;
+  std::vector<BatchItemDev> dev(n);
+  std::vector<int64_t> seg_prefix(n + 1, 0), qprefix(n + 1, 0);
+  std::vector<double> cost(n);
+  for (int32_t i = 0; i < n; ++i) {
+    const tnn_batch_item &it = items[i];
+    const IndexDesc *d = desc_of(it.index);
+    BatchItemDev &b = dev[i];
+    b.ix = *d;
+    b.a = make_args(&it.params);
+    b.pr = prep_view(m + L.prep[i], d->n_seg);
+    b.qx = it.queries.x;
+    b.qy = it.queries.y;
+    b.qz = it.queries.z;
+    b.qt = it.queries.t;
+    b.nq = it.queries.n;
+    b.out_idx = it.d_out_idx;
+    b.out_dist = it.d_out_dist;
+    seg_prefix[i + 1] = seg_prefix[i] + d->n_seg;
+    // per-query work grows with the blocks every round visits
+    cost[i] = (double)it.queries.n * (double)(d->n_blocks + kBlockSegs);
+  }
+  std::vector<int32_t> order(n);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return cost[a] > cost[b]; });
+  for (int32_t p = 0; p < n; ++p) qprefix[p + 1] = qprefix[p] + dev[order[p]].nq;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  TNN_HIP_CHECK(hipMemcpyAsync(m + L.items, dev.data(), sizeof(BatchItemDev) * n, hipMemcpyHostToDevice, st));
+  TNN_HIP_CHECK(hipMemcpyAsync(m + L.qprefix, qprefix.data(), 8 * (n + 1), hipMemcpyHostToDevice, st));
+  TNN_HIP_CHECK(hipMemcpyAsync(m + L.order, order.data(), 4 * n, hipMemcpyHostToDevice, st));
+  TNN_HIP_CHECK(hipMemcpyAsync(m + L.seg_prefix, seg_prefix.data(), 8 * (n + 1), hipMemcpyHostToDevice, st));
+  TNN_HIP_CHECK(hipStreamSynchronize(st));
+  BatchLaunch bl;
+  std::memset(&bl, 0, sizeof(bl));
+  bl.magic = kBatchMagic;
+  bl.n = n;
+  bl.chunk = cfg.chunk;
+  bl.waves_per_block = w;
+  bl.grid = (int64_t)cus * cfg.blocks_per_cu;
+  bl.total_q = qprefix[n];
+  bl.total_seg = seg_prefix[n];
+  bl.items = reinterpret_cast<const BatchItemDev *>(m + L.items);
+  bl.qprefix = reinterpret_cast<const int64_t *>(m + L.qprefix);
+  bl.order = reinterpret_cast<const int32_t *>(m + L.order);
+  bl.seg_prefix = reinterpret_cast<const int64_t *>(m + L.seg_prefix);
+  bl.counter = reinterpret_cast<unsigned long long *>(m + L.counter);
+  bl.done = reinterpret_cast<unsigned *>(m + L.done);
+  bl.ticks = reinterpret_cast<unsigned long long *>(m + L.ticks);
+  std::memset(plan, 0, sizeof(*plan));
+  std::memcpy(plan, &bl, sizeof(bl));
+  return TNN_OK;
+}
+
+tnn_status tnn_query_batched(const tnn_batch_plan *plan, void *stream) {
+  if (!plan) return TNN_E_ARG;
+  const BatchLaunch *bl = reinterpret_cast<const BatchLaunch *>(plan);
+  if (bl->magic != kBatchMagic) return TNN_E_ARG;
+  TNN_HIP_CHECK(launch_batch(*bl, static_cast<hipStream_t>(stream)));
+  return TNN_OK;
+}
+
+tnn_status tnn_batch_ticks(const tnn_batch_plan *plan, const uint64_t **d_ticks) {
+  if (!plan || !d_ticks) return TNN_E_ARG;
+  const BatchLaunch *bl = reinterpret_cast<const BatchLaunch *>(plan);
+  if (bl->magic != kBatchMagic) return TNN_E_ARG;
+  *d_ticks = reinterpret_cast<const uint64_t *>(bl->ticks);
+  return TNN_OK;
+}
+
+tnn_status tnn_wall_clock_rate_khz(int64_t *khz) {
+  if (!khz) return TNN_E_ARG;
+  int dev = 0, rate = 0;
+  TNN_HIP_CHECK(hipGetDevice(&dev));
+  TNN_HIP_CHECK(hipDeviceGetAttribute(&rate, hipDeviceAttributeWallClockRate, dev));
+  *khz = rate;
+  return TNN_OK;
+}
+
+tnn_status tnn_autotune_batched(const tnn_batch_item *items, int32_t n_items, void *d_scratch,
+                                size_t bytes, void *stream, const char *cache_path,
+                                tnn_batch_config *best) {
+  if (!best) return TNN_E_ARG;
+  const tnn_status c = check_items(items, n_items);
+  if (c != TNN_OK) return c;
+  int64_t total_q = 0, total_p = 0;
+  for (int32_t i = 0; i < n_items; ++i) {
+    total_q += items[i].queries.n;
+    total_p += desc_of(items[i].index)->n_points;
+  }
+  int dev = 0;
+  TNN_HIP_CHECK(hipGetDevice(&dev));
+  hipDeviceProp_t prop;
+  TNN_HIP_CHECK(hipGetDeviceProperties(&prop, dev));
+  char key[256];
+  std::snprintf(key, sizeof(key), "batch %s %d %lld %lld", prop.gcnArchName, n_items,
+                (long long)total_q, (long long)total_p);
+  for (char *p = key; *p; ++p)
+    if (*p == ':') *p = '_';
+  if (cache_path) {
+    if (FILE *f = std::fopen(cache_path, "r")) {
+      char line[512];
+      while (std::fgets(line, sizeof(line), f)) {
+        const size_t kl = std::strlen(key);
+        tnn_batch_config cfg = {0, 0, 0, 0};
+        if (std::strncmp(line, key, kl) == 0 && line[kl] == ' ' &&
+            std::sscanf(line + kl, "%d %d %d", &cfg.chunk, &cfg.waves_per_block,
+                        &cfg.blocks_per_cu) == 3) {
+          std::fclose(f);
+          *best = cfg;
+          return TNN_OK;
+        }
+      }
+      std::fclose(f);
+    }
+  }
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipEvent_t e0, e1;
+  TNN_HIP_CHECK(hipEventCreate(&e0));
+  TNN_HIP_CHECK(hipEventCreate(&e1));
+  float best_ms = INFINITY;
+  tnn_status rc = TNN_OK;
+  for (int chunk : {1, 4, 16})
+    for (int w : {2, 4, 8})
+      for (int bpc : {2, 4, 8}) {
+        tnn_batch_config cfg = {chunk, w, bpc, 0};
+        tnn_batch_plan plan;
+        rc = tnn_batch_prepare(items, n_items, &cfg, d_scratch, bytes, stream, &plan);
+        if (rc != TNN_OK) goto done;
+        rc = tnn_query_batched(&plan, stream);  // warm-up
+        if (rc != TNN_OK) goto done;
+        if (hipEventRecord(e0, st) != hipSuccess) { rc = TNN_E_HIP; goto done; }
+        for (int r = 0; r < 3; ++r) {
+          rc = tnn_query_batched(&plan, stream);
+          if (rc != TNN_OK) goto done;
+        }
+        if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+          rc = TNN_E_HIP;
+          goto done;
+        }
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { rc = TNN_E_HIP; goto done; }
+        if (ms < best_ms) {
+          best_ms = ms;
+          *best = cfg;
+        }
+      }
+  if (cache_path) {
+    if (FILE *f = std::fopen(cache_path, "a")) {
+      std::fprintf(f, "%s %d %d %d\n", key, best->chunk, best->waves_per_block, best->blocks_per_cu);
+      std::fclose(f);
+    }
+  }
+done:
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return rc;
 }
 
 }  // extern "C"

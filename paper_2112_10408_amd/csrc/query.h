@@ -4,6 +4,39 @@
 
 namespace tnn {
 
+// One airspace of a batch, as the persistent kernel reads it.
+struct BatchItemDev {
+  IndexDesc ix;
+  Prep pr;
+  QueryArgs a;
+  const float *qx, *qy, *qz, *qt;
+  int64_t nq;
+  int32_t *out_idx;
+  double *out_dist;
+};
+
+// Everything tnn_query_batched launches with (lives in tnn_batch_plan).
+struct BatchLaunch {
+  uint32_t magic;
+  int32_t n;
+  int32_t chunk;
+  int32_t waves_per_block;
+  int64_t grid;
+  int64_t total_q;
+  int64_t total_seg;
+  const BatchItemDev *items;
+  const int64_t *qprefix;
+  const int32_t *order;
+  const int64_t *seg_prefix;
+  unsigned long long *counter;
+  unsigned *done;
+  unsigned long long *ticks;
+};
+static_assert(sizeof(BatchLaunch) <= sizeof(tnn_batch_plan), "batch plan too large");
+constexpr uint32_t kBatchMagic = 0x544e4e42u;  // "TNNB"
+
+hipError_t launch_batch(const BatchLaunch &bl, hipStream_t st);
+
 hipError_t launch_prep(const IndexDesc &ix, const QueryArgs &a, const Prep &pr, hipStream_t st);
 hipError_t launch_query(const IndexDesc &ix, const Prep &pr, const QueryArgs &a,
                         const tnn_points &qs, int waves_per_block, int32_t *out_idx,

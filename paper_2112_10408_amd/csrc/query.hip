@@ -9,9 +9,8 @@ namespace tnn {
 // Per-call preparation (depends on the scales): 1/|AB|_s^2, the radius
 // R = sqrt(sum_f s_f e_f^2) rounded up, and the projection slack.
 // ---------------------------------------------------------------------------
-__global__ void prep_kernel(IndexDesc ix, QueryArgs a, double *inv_n2, double *rad, double *slack) {
-  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= ix.n_seg) return;
+__device__ __forceinline__ void prep_one(const IndexDesc &ix, const QueryArgs &a, double *inv_n2,
+                                         double *rad, double *slack, int64_t s) {
   const double abx = (double)ix.bx[s] - (double)ix.ax[s];
   const double aby = (double)ix.by[s] - (double)ix.ay[s];
   const double abz = (double)ix.bz[s] - (double)ix.az[s];
@@ -20,6 +19,12 @@ __global__ void prep_kernel(IndexDesc ix, QueryArgs a, double *inv_n2, double *r
   const double ex = ix.ex[s], ey = ix.ey[s], ez = ix.ez[s];
   rad[s] = sqrt(a.s[0] * ex * ex + a.s[1] * ey * ey + a.s[2] * ez * ez) * (1.0 + 0x1p-40);
   slack[s] = 0x1p-30 * sqrt(n2);
+}
+
+__global__ void prep_kernel(IndexDesc ix, QueryArgs a, double *inv_n2, double *rad, double *slack) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= ix.n_seg) return;
+  prep_one(ix, a, inv_n2, rad, slack, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -309,6 +314,96 @@ __global__ void debug_lb_kernel(IndexDesc ix, Prep pr, QueryArgs a, const float 
   } else if (block_lb_out) {
     block_lb_out[qi * nb + (j - S)] = block_lb(ix, (int)(j - S), q, a.sf);
   }
+}
+
+// ---------------------------------------------------------------------------
+// Batched ragged serving: one persistent launch over many indexes.
+// ---------------------------------------------------------------------------
+__global__ void batch_reset_kernel(unsigned long long *counter, unsigned *done, int n,
+                                   unsigned long long *ticks) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) {
+    *counter = 0;
+    ticks[0] = wall_clock64();
+  }
+  if (i < n) {
+    done[i] = 0;
+    ticks[i + 1] = 0;
+  }
+}
+
+// Largest position p in [0, n) with prefix[p] <= g (prefix non-decreasing,
+// prefix[0] = 0 <= g < prefix[n]).
+__device__ __forceinline__ int find_item(const int64_t *prefix, int n, int64_t g) {
+  int lo = 0, hi = n;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (prefix[mid] <= g) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+__global__ void batch_prep_kernel(const BatchItemDev *items, const int64_t *seg_prefix, int n) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= seg_prefix[n]) return;
+  const int i = find_item(seg_prefix, n, g);
+  const BatchItemDev &it = items[i];
+  prep_one(it.ix, it.a, const_cast<double *>(it.pr.inv_n2), const_cast<double *>(it.pr.rad),
+           const_cast<double *>(it.pr.slack), g - seg_prefix[i]);
+}
+
+// Waves pull `chunk` queries at a time from a global counter over the
+// queries of all items laid end to end in the order given by `order`
+// (longest first); each query is answered exactly as by tnn_query_kernel.
+// Every wave leaves once the counter passes the total.
+__global__ __launch_bounds__(512) void batch_kernel(const BatchItemDev *items,
+                                                    const int64_t *qprefix, const int32_t *order,
+                                                    int n, int chunk,
+                                                    unsigned long long *counter, unsigned *done,
+                                                    unsigned long long *ticks) {
+  const int lane = lane_id();
+  const int64_t total = qprefix[n];
+  for (;;) {
+    unsigned long long b = 0;
+    if (lane == 0) b = atomicAdd(counter, (unsigned long long)chunk);
+    const int64_t base = (int64_t)(((unsigned long long)(unsigned)uniform_i((int)(b >> 32)) << 32) |
+                                   (unsigned)uniform_i((int)(b & 0xffffffffull)));
+    if (base >= total) break;
+    for (int j = 0; j < chunk; ++j) {
+      const int64_t gq = base + j;
+      if (gq >= total) break;
+      const int pos = find_item(qprefix, n, gq);
+      const int item = order[pos];
+      const BatchItemDev &it = items[item];
+      answer_query(it.ix, it.pr, it.a, it.qx, it.qy, it.qz, it.qt, gq - qprefix[pos], it.out_idx,
+                   it.out_dist);
+      if (lane == 0) {
+        const unsigned d = atomicAdd(&done[item], 1u) + 1u;
+        if ((int64_t)d == it.nq) ticks[item + 1] = wall_clock64();
+      }
+    }
+  }
+}
+
+hipError_t launch_batch(const BatchLaunch &bl, hipStream_t st) {
+  hipLaunchKernelGGL(batch_reset_kernel, dim3((unsigned)((bl.n + 1 + 255) / 256)), dim3(256), 0, st,
+                     bl.counter, bl.done, bl.n, bl.ticks);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (bl.total_seg > 0) {
+    hipLaunchKernelGGL(batch_prep_kernel, dim3((unsigned)((bl.total_seg + 255) / 256)), dim3(256),
+                       0, st, bl.items, bl.seg_prefix, bl.n);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  if (bl.total_q > 0) {
+    hipLaunchKernelGGL(batch_kernel, dim3((unsigned)bl.grid), dim3(bl.waves_per_block * kWave), 0,
+                       st, bl.items, bl.qprefix, bl.order, bl.n, bl.chunk, bl.counter, bl.done,
+                       bl.ticks);
+    e = hipGetLastError();
+  }
+  return e;
 }
 
 // ---------------------------------------------------------------------------

@@ -235,3 +235,99 @@ def tnn_radius_infer(model, qx, qy, qz, qt, alpha=1.0, out=None, logr=None):
     check(capi.lib().tnn_radius_infer(_ptr(model), points(qx, qy, qz, qt), float(alpha), _ptr(out),
                                       _ptr(logr), _stream()), "tnn_radius_infer")
     return out
+
+
+# --------------------------------------------------------------------------
+# Batched ragged serving
+# --------------------------------------------------------------------------
+class Batch:
+    """A prepared batch: the C item array, its plan and every tensor the
+    device descriptors point to (kept alive here)."""
+
+    def __init__(self, items, keep, scratch, plan):
+        self.items = items
+        self.keep = keep
+        self.scratch = scratch
+        self.plan = plan
+
+
+def _batch_items(entries):
+    """entries: list of dicts with index, q (x, y, z, t tensors), scale,
+    t_window, k, flags, radius2 (opt), stats (opt), out (opt)."""
+    n = len(entries)
+    arr = (capi.TnnBatchItem * n)()
+    keep = []
+    outs = []
+    for i, e in enumerate(entries):
+        qx, qy, qz, qt = e["q"]
+        k = int(e["k"])
+        out = e.get("out")
+        if out is None:
+            out = (torch.empty((qx.shape[0], k), dtype=torch.int32, device=qx.device),
+                   torch.empty((qx.shape[0], k), dtype=torch.float64, device=qx.device))
+        arr[i].index = ctypes.pointer(e["index"].c)
+        arr[i].queries = points(qx, qy, qz, qt)
+        arr[i].params = make_params(e["scale"], e.get("t_window", 0.0), k, e.get("flags", 0),
+                                    e.get("seed_segments", 0), 0, e.get("radius2"), e.get("stats"))
+        arr[i].d_out_idx = _ptr(out[0])
+        arr[i].d_out_dist = _ptr(out[1])
+        keep.append((e, out))
+        outs.append(out)
+    return arr, keep, outs
+
+
+def tnn_batch_workspace(items, n):
+    b = ctypes.c_size_t(0)
+    check(capi.lib().tnn_batch_workspace(items, n, ctypes.byref(b)), "tnn_batch_workspace")
+    return b.value
+
+
+def tnn_batch_prepare(entries, config=None, scratch=None):
+    arr, keep, outs = _batch_items(entries)
+    n = len(entries)
+    need = tnn_batch_workspace(arr, n)
+    dev = entries[0]["q"][0].device
+    if scratch is None or scratch.numel() < need:
+        scratch = torch.empty(need, dtype=torch.uint8, device=dev)
+    plan = capi.TnnBatchPlan()
+    cfg = None
+    if config is not None:
+        cfg = capi.TnnBatchConfig(*[int(v) for v in config], 0) if not isinstance(config, capi.TnnBatchConfig) else config
+    check(capi.lib().tnn_batch_prepare(arr, n, ctypes.byref(cfg) if cfg is not None else None,
+                                       _ptr(scratch), scratch.numel(), _stream(), ctypes.byref(plan)),
+          "tnn_batch_prepare")
+    b = Batch(arr, keep, scratch, plan)
+    b.outs = outs
+    return b
+
+
+def tnn_query_batched(batch):
+    check(capi.lib().tnn_query_batched(ctypes.byref(batch.plan), _stream()), "tnn_query_batched")
+    return batch.outs
+
+
+def tnn_batch_ticks(batch):
+    """int64 view (device) of the tick array [n_items + 1] inside the scratch."""
+    p = ctypes.c_void_p(0)
+    check(capi.lib().tnn_batch_ticks(ctypes.byref(batch.plan), ctypes.byref(p)), "tnn_batch_ticks")
+    off = p.value - batch.scratch.data_ptr()
+    n = len(batch.outs)
+    return batch.scratch[off: off + 8 * (n + 1)].view(torch.int64)
+
+
+def tnn_wall_clock_rate_khz():
+    v = ctypes.c_int64(0)
+    check(capi.lib().tnn_wall_clock_rate_khz(ctypes.byref(v)), "tnn_wall_clock_rate_khz")
+    return v.value
+
+
+def tnn_autotune_batched(entries, cache_path=None):
+    arr, keep, outs = _batch_items(entries)
+    n = len(entries)
+    need = tnn_batch_workspace(arr, n)
+    scratch = torch.empty(need, dtype=torch.uint8, device=entries[0]["q"][0].device)
+    best = capi.TnnBatchConfig()
+    check(capi.lib().tnn_autotune_batched(arr, n, _ptr(scratch), scratch.numel(), _stream(),
+                                          cache_path.encode() if cache_path else None, ctypes.byref(best)),
+          "tnn_autotune_batched")
+    return (best.chunk, best.waves_per_block, best.blocks_per_cu)
