@@ -72,6 +72,75 @@ def cpu_baseline(ps, qs, k, scale, budget_s=15.0):
                       f"{dt:.1f} s wall"}
 
 
+def run_batched(args, T, capi, radius, synth, torch, stream):
+    """64 independent airspaces (log-uniform sizes, k in {8, 32, 64}), each
+    with its own index and learned radius; the step (per-airspace radius
+    inference + one persistent batched search) is captured in a HIP graph."""
+    scale = synth.SCALE
+    t0 = time.perf_counter()
+    airs = synth.airspaces(args.airspaces)
+    entries, models = [], []
+    total_q = total_p = 0
+    fallback_guess = []
+    for a in airs:
+        ps, qs = a["points"], a["queries"]
+        x, y, z, t = T.to_device(ps.x, ps.y, ps.z, ps.t)
+        ix = T.tnn_build_segments(x, y, z, t, ps.offsets, a["seg_len"], scale)
+        ix._keep = (x, y, z, t)
+        n_tr = min(20000, ps.n // 2)
+        excl = a["qidx"] if ps.n - qs.n >= n_tr else None  # small airspace: queries cover it
+        tq, _ = synth.sample_queries(ps, n_tr, 77, exclude=excl)
+        tx = T.to_device(tq.x, tq.y, tq.z, tq.t)
+        model, _, pdist, ptr = radius.train(ix, *tx, scale, 0.0, a["k"], epochs=4, batch=2048)
+        alpha = radius.calibrate(model, *ptr, pdist, a["k"], quantile=0.8)
+        q = T.to_device(qs.x, qs.y, qs.z, qs.t)
+        r2 = torch.empty(qs.n, dtype=torch.float32, device="cuda")
+        entries.append(dict(index=ix, q=q, scale=scale, k=a["k"], flags=capi.TNN_LEARNED, radius2=r2))
+        models.append((model, alpha, q, r2))
+        total_q += qs.n
+        total_p += ps.n
+    setup_s = time.perf_counter() - t0
+    best = T.tnn_autotune_batched(entries, None)
+    b = T.tnn_batch_prepare(entries, best)
+
+    def step():
+        for model, alpha, q, r2 in models:
+            T.tnn_radius_infer(model, *q, alpha, out=r2)
+        T.tnn_query_batched(b)
+
+    step()
+    torch.cuda.synchronize()
+    # exactness: every airspace against its own plain TNN search
+    exact = True
+    for e, out in zip(entries, b.outs):
+        pi, pd = T.tnn_query(e["index"], *e["q"], scale, 0.0, e["k"])
+        exact &= bool(torch.equal(pi, out[0])) and bool(torch.equal(pd, out[1]))
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        step()
+    torch.cuda.current_stream().wait_stream(side)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        step()
+    ms = timed(g.replay, args.steps, args.warmup, stream)
+    g.replay()
+    torch.cuda.synchronize()
+    ticks = T.tnn_batch_ticks(b).cpu().numpy().astype(np.float64)
+    khz = T.tnn_wall_clock_rate_khz()
+    lat_ms = [(ticks[i + 1] - ticks[0]) / khz for i in range(len(entries)) if entries[i]["q"][0].shape[0]]
+    lat_ms = np.array(lat_ms)
+    out = {"workload": f"{len(entries)} airspaces, {total_p} points, {total_q} queries, "
+                       "k in {8,32,64}, learned radius, one persistent graph-captured launch",
+           "queries_per_s": total_q / ms * 1e3, "ms_per_step": ms,
+           "airspace_latency_ms_p50": float(np.percentile(lat_ms, 50)),
+           "airspace_latency_ms_p99": float(np.percentile(lat_ms, 99)),
+           "autotuned_chunk_waves_blocks": list(best), "exact_vs_plain": exact,
+           "setup_s": setup_s}
+    log("batched:", out)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -80,6 +149,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-brute", action="store_true")
     ap.add_argument("--train-queries", type=int, default=100_000)
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--airspaces", type=int, default=64)
     ap.add_argument("--train-epochs", type=int, default=8)
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a 256 MiB device-to-device copy (counter calibration)")
@@ -200,6 +271,27 @@ def main():
         result_extra["brute_qps"] = qs.n / ms_brute * 1e3
         result_extra["brute_matches_tnn"] = same
 
+        def mixed():
+            T.tnn_query(ix, qx, qy, qz, qt, scale, 0.0, k, flags=capi.TNN_BRUTE | capi.TNN_MIXED_BF16,
+                        out=out, scratch=mscratch)
+
+        mp = T.make_params(scale, 0.0, k, capi.TNN_BRUTE | capi.TNN_MIXED_BF16)
+        mscratch = torch.empty(T.tnn_query_workspace(ix, qs.n, mp), dtype=torch.uint8, device="cuda")
+        ms_mixed = timed(mixed, bsteps, 1, stream)
+        same_m = bool(torch.equal(out[0], ref_idx)) and bool(torch.equal(out[1], ref_dist))
+        mstats = T.new_stats()
+        T.tnn_query(ix, qx, qy, qz, qt, scale, 0.0, k, flags=capi.TNN_BRUTE | capi.TNN_MIXED_BF16,
+                    out=out, scratch=mscratch, stats=mstats)
+        torch.cuda.synchronize()
+        mst = T.stats_dict(mstats)
+        log(f"mixed brute (BF16 MFMA + binary64 rescoring): {ms_mixed:.3f} ms/step, "
+            f"{qs.n / ms_mixed * 1e3:.0f} q/s, exact {same_m}, rescored {mst['rescored']}, "
+            f"max |approx - exact| {mst['max_err']:.3g}")
+        result_extra["mixed_brute_qps"] = qs.n / ms_mixed * 1e3
+        result_extra["mixed_brute_exact"] = same_m
+        result_extra["mixed_brute_rescored_per_query"] = mst["rescored"] / qs.n
+        result_extra["mixed_max_abs_dist_err"] = mst["max_err"]
+
     flops = (FLOPS_BLOCK_BOUND * st["blocks"] + FLOPS_SEG_BOUND * st["segments"]
              + FLOPS_POINT * st["points"])
     achieved = flops / (ms_search * 1e-3) / 1e12
@@ -226,6 +318,8 @@ def main():
         "index_build_s": build_s, "stats_learned": st, "stats_plain": st_plain,
     }
     res.update(result_extra)
+    if not args.no_batched:
+        res["batched"] = run_batched(args, T, capi, radius, synth, torch, stream)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(ps, qs, k, scale)
         log("cpu baseline:", res["cpu_baseline"])

@@ -16,7 +16,7 @@ namespace {
 struct BuildLayout {
   size_t px, py, pz, pt, pid;                  // index-order points
   size_t f[11], pstart, pcount, sorig;          // index-order segments
-  size_t box;                                   // block boxes
+  size_t box, sbox;                             // block and superblock boxes
   size_t tf[11], tstart, tcf, keys, perm, dpstart, status;  // build temporaries
   size_t total;
 };
@@ -40,6 +40,7 @@ BuildLayout build_layout(int64_t n, int64_t S) {
   L.pcount = take(4 * S);
   L.sorig = take(4 * S);
   L.box = take(4 * 8 * nb);
+  L.sbox = take(4 * 8 * ((nb + kSuperBlocks - 1) / kSuperBlocks));
   for (int i = 0; i < 11; ++i) L.tf[i] = take(4 * S);
   L.tstart = take(4 * S);
   L.tcf = take(4 * S);
@@ -301,6 +302,24 @@ tnn_status tnn_build_segments(tnn_points pts, const int64_t *h_traj_offsets, int
   if (nb > 0)
     TNN_HIP_CHECK(hipMemcpyAsync(box.data(), F(L.box), 32 * nb, hipMemcpyDeviceToHost, st));
   TNN_HIP_CHECK(hipStreamSynchronize(st));
+  const int64_t ns = (nb + kSuperBlocks - 1) / kSuperBlocks;
+  std::vector<float> sbox(8 * (size_t)ns);
+  for (int64_t sb = 0; sb < ns; ++sb)
+    for (int f = 0; f < 4; ++f) {
+      float lo = INFINITY, hi = -INFINITY;
+      for (int64_t b = sb * kSuperBlocks; b < std::min<int64_t>(nb, (sb + 1) * kSuperBlocks); ++b) {
+        lo = std::min(lo, box[f * nb + b]);
+        hi = std::max(hi, box[(4 + f) * nb + b]);
+      }
+      sbox[f * ns + sb] = lo;
+      sbox[(4 + f) * ns + sb] = hi;
+    }
+  if (ns > 0) {
+    TNN_HIP_CHECK(hipMemcpyAsync(F(L.sbox), sbox.data(), 32 * ns, hipMemcpyHostToDevice, st));
+    TNN_HIP_CHECK(hipStreamSynchronize(st));
+  }
+  d.sbox = F(L.sbox);
+  d.n_super = (int32_t)ns;
   for (int f = 0; f < 4; ++f) {
     d.lo[f] = 0.0f;
     d.hi[f] = 0.0f;

@@ -59,10 +59,10 @@ __device__ __forceinline__ QueryPoint make_query(float x, float y, float z, floa
 // Lower bound from a query to every point of block b: scaled squared
 // distance to the block's (x, y, z, t) bounding box.  +inf when no point of
 // the block is early enough.
-__device__ __forceinline__ float block_lb(const IndexDesc &ix, int b, const QueryPoint &q,
+// `box` is the index's box array box[f * nb + b] in global memory or a copy
+// of it in LDS.
+__device__ __forceinline__ float block_lb(const float *box, int nb, int b, const QueryPoint &q,
                                           const float sf[4]) {
-  const int nb = ix.n_blocks;
-  const float *box = ix.box;
   const float lt = box[3 * nb + b];
   if ((double)lt >= q.thr) return __builtin_huge_valf();
   const float lx = box[b], ly = box[nb + b], lz = box[2 * nb + b];
@@ -74,6 +74,11 @@ __device__ __forceinline__ float block_lb(const IndexDesc &ix, int b, const Quer
   const float gt = fmaxf(fmaxf(q.t - ht, q.gwf), 0.0f);
   const float v = sf[0] * (gx * gx) + sf[1] * (gy * gy) + sf[2] * (gz * gz) + sf[3] * (gt * gt);
   return v * (1.0f - 0x1p-18f);
+}
+
+__device__ __forceinline__ float block_lb(const IndexDesc &ix, int b, const QueryPoint &q,
+                                          const float sf[4]) {
+  return block_lb(ix.box, ix.n_blocks, b, q, sf);
 }
 
 // Cylinder lower bound (Sec. 3.4 masked distance minus approximation error,

@@ -25,8 +25,7 @@ typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
 
 constexpr float kGamma = 0x1p-16f;
 constexpr int kMQ = 16;      // queries per wave (MFMA rows)
-constexpr int kWaves = 4;    // waves per workgroup
-constexpr int kPT = 32;      // points per LDS tile (two 16-column MFMA tiles)
+constexpr int kStep = 64;    // points per step (four 16-column MFMA tiles)
 
 __device__ __forceinline__ __bf16 to_bf16(float x) {
   // round to nearest even (finite inputs)
@@ -165,27 +164,29 @@ __device__ __forceinline__ float round_up_f(double x) {
   return x < kInf ? __double2float_ru(x) : __builtin_huge_valf();
 }
 
-__global__ __launch_bounds__(kWaves * 64) void mixed_brute_kernel(
+// One wavefront = one workgroup answers 16 queries (the MFMA rows).  Point
+// operands stream straight from global memory (64 points per step, four
+// 16-column MFMA tiles); no workgroup barrier is needed.  Per-query state in
+// LDS: the top-k (k entries) and a candidate queue of one step's points.
+__global__ __launch_bounds__(64) void mixed_brute_kernel(
     IndexDesc ix, QueryArgs a, MixedCtx mc, const bf16x8 *ops, const float *nv, const float *qxp,
     const float *qyp, const float *qzp, const float *qtp, int64_t nq, int32_t *out_idx,
-    double *out_dist) {
-  __shared__ bf16x8 s_ops[kPT * 4];
-  __shared__ float s_pt[kPT];
-  __shared__ double s_tkd[kWaves][kMQ][64];
-  __shared__ int s_tkid[kWaves][kMQ][64];
-  __shared__ int s_qn[kWaves][kMQ];
-  __shared__ int s_qp[kWaves][kMQ][kPT];
-  __shared__ float s_qc[kWaves][kMQ][kPT];
-  __shared__ float s_tau[kWaves][kMQ];
-  __shared__ float s_thr[kWaves][kMQ];
-  __shared__ float s_nu[kWaves][kMQ];
+    double *out_dist, int64_t tile_stride) {
+  extern __shared__ double s_dyn[];
+  const int k = a.k;
+  double *s_tkd = s_dyn;                                            // [kMQ][k]
+  int *s_tkid = reinterpret_cast<int *>(s_tkd + kMQ * k);           // [kMQ][k]
+  int *s_qp = s_tkid + kMQ * k;                                     // [kMQ][kStep]
+  float *s_qc = reinterpret_cast<float *>(s_qp + kMQ * kStep);      // [kMQ][kStep]
+  int *s_qn = reinterpret_cast<int *>(s_qc + kMQ * kStep);          // [kMQ]
+  float *s_tau = reinterpret_cast<float *>(s_qn + kMQ);             // [kMQ]
+  float *s_thr = s_tau + kMQ;                                       // [kMQ]
+  float *s_nu = s_thr + kMQ;                                        // [kMQ]
 
   const int lane = lane_id();
-  const int w = uniform_i((int)(threadIdx.x >> 6));
-  const int64_t qbase = ((int64_t)blockIdx.x * kWaves + w) * kMQ;
-  const int g = lane >> 4;        // K-group this lane supplies
-  const int row = lane & 15;      // A row = query
-  // ---- query operand and per-query state
+  const int64_t qbase = (int64_t)blockIdx.x * kMQ;
+  const int g = lane >> 4;    // K-group this lane supplies
+  const int row = lane & 15;  // A row (query) / C column (point)
   const int64_t qa = qbase + row;
   float u[4] = {0, 0, 0, 0};
   float nu = 0.0f;
@@ -193,71 +194,79 @@ __global__ __launch_bounds__(kWaves * 64) void mixed_brute_kernel(
   const bf16x8 aop = query_group(u, (1.0f - kGamma) * nu, g);
   if (lane < kMQ) {
     const int64_t q = qbase + lane;
-    s_qn[w][lane] = 0;
-    s_nu[w][lane] = nu;
+    s_qn[lane] = 0;
+    s_nu[lane] = nu;
     if (q < nq) {
-      s_tau[w][lane] = __builtin_huge_valf();
-      s_thr[w][lane] = round_up_f((double)qtp[q] - a.t_window);
+      s_tau[lane] = __builtin_huge_valf();
+      s_thr[lane] = round_up_f((double)qtp[q] - a.t_window);
     } else {
-      s_tau[w][lane] = -__builtin_huge_valf();  // inactive row: nothing passes
-      s_thr[w][lane] = -__builtin_huge_valf();
+      s_tau[lane] = -__builtin_huge_valf();  // inactive row: nothing passes
+      s_thr[lane] = -__builtin_huge_valf();
     }
   }
-  for (int m = 0; m < kMQ; ++m) {
-    s_tkd[w][m][lane] = a.inf;
-    s_tkid[w][m][lane] = kNoId;
+  for (int i = lane; i < kMQ * k; i += 64) {
+    s_tkd[i] = a.inf;
+    s_tkid[i] = kNoId;
   }
+  __syncthreads();
   uint32_t rescored = 0;
   double max_err = 0.0;
-  const int k = a.k;
   const int64_t n = ix.n_points;
-  for (int64_t p0 = 0; p0 < n; p0 += kPT) {
-    __syncthreads();
-    // stage kPT point operands (256 threads x 16 bytes) and times
-    {
-      const int t = threadIdx.x;
-      const int64_t p = p0 + (t >> 2);
-      if (t < kPT * 4) {
-        bf16x8 v = {};
-        if (p < n) v = ops[4 * p + (t & 3)];
-        s_ops[t] = v;
+  const int64_t n_steps = (n + kStep - 1) / kStep;
+  float tau[4], thr[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    tau[e] = s_tau[g * 4 + e];
+    thr[e] = s_thr[g * 4 + e];
+  }
+  for (int64_t si = 0; si < n_steps; ++si) {
+    // Steps in a scattered order: index order is spatially sorted, and a
+    // scan that approaches the query gradually would improve the k-th
+    // distance at almost every point, sending nearly all of them to the
+    // binary64 rescoring.  tile_stride is coprime with n_steps.
+    const int64_t p0 = (int64_t)(((unsigned long long)si * (unsigned long long)tile_stride) %
+                                 (unsigned long long)n_steps) * kStep;
+    bf16x8 bop[kStep / 16];
+    float pts[kStep / 16];
+#pragma unroll
+    for (int cb = 0; cb < kStep / 16; ++cb) {
+      const int64_t p = p0 + cb * 16 + row;
+      bf16x8 v = {};
+      float t = __builtin_huge_valf();
+      if (p < n) {
+        v = ops[4 * p + g];
+        t = ix.pt[p];
       }
-      if (t < kPT) s_pt[t] = (p0 + t < n) ? ix.pt[p0 + t] : __builtin_huge_valf();
+      bop[cb] = v;
+      pts[cb] = t;
     }
-    __syncthreads();
-    float tau[4], thr[4];
+    bool any = false;
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      tau[e] = s_tau[w][g * 4 + e];
-      thr[e] = s_thr[w][g * 4 + e];
-    }
-#pragma unroll
-    for (int cb = 0; cb < kPT / 16; ++cb) {
-      const int col = cb * 16 + row;
-      const bf16x8 bop = s_ops[col * 4 + g];
+    for (int cb = 0; cb < kStep / 16; ++cb) {
       f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aop, bop, acc, 0, 0, 0);
-      const float pt = s_pt[col];
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aop, bop[cb], acc, 0, 0, 0);
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        // row (query) g*4+e, column (point) col
-        if ((acc[e] <= tau[e]) & (pt < thr[e])) {
+        // row (query) g*4+e, column (point) cb*16 + row; the point's time is
+        // held by the lane that loaded column `row`, i.e. this lane
+        if ((acc[e] <= tau[e]) & (pts[cb] < thr[e])) {
           const int m = g * 4 + e;
-          const int slot = atomicAdd(&s_qn[w][m], 1);
-          s_qp[w][m][slot] = (int)(p0 + col);
-          s_qc[w][m][slot] = acc[e];
+          const int slot = atomicAdd(&s_qn[m], 1);
+          s_qp[m * kStep + slot] = (int)(p0 + cb * 16 + row);
+          s_qc[m * kStep + slot] = acc[e];
+          any = true;
         }
       }
     }
-    __syncthreads();
+    if (!ballot(any)) continue;
     // ---- rescore survivors in binary64 and merge them into each top-k
     for (int m = 0; m < kMQ; ++m) {
-      const int cnt = s_qn[w][m];
+      const int cnt = s_qn[m];
       const int64_t q = qbase + m;
       if (cnt == 0 || q >= nq) continue;
       const QueryPoint qp = make_query(qxp[q], qyp[q], qzp[q], qtp[q], a.t_window);
       const bool has = lane < cnt;
-      const int p = has ? s_qp[w][m][lane] : 0;
+      const int p = has ? s_qp[m * kStep + lane] : 0;
       double d = a.inf;
       int pid = kNoId;
       bool valid = false;
@@ -266,33 +275,39 @@ __global__ __launch_bounds__(kWaves * 64) void mixed_brute_kernel(
         d = exact_dist(a.s, qp.x, qp.y, qp.z, qp.t, ix.px[p], ix.py[p], ix.pz[p], pt);
         pid = ix.pid[p];
         valid = (double)pt < qp.thr;
-        const double approx = (double)s_qc[w][m][lane] + (double)kGamma * ((double)s_nu[w][m] + (double)nv[p]);
+        const double approx = (double)s_qc[m * kStep + lane] +
+                              (double)kGamma * ((double)s_nu[m] + (double)nv[p]);
         max_err = fmax(max_err, fabs(approx - d));
       }
       rescored += (uint32_t)cnt;
       TopK tk;
       tk.init(k, a.inf);
-      tk.d = s_tkd[w][m][lane];
-      tk.id = s_tkid[w][m][lane];
+      if (lane < k) {
+        tk.d = s_tkd[m * k + lane];
+        tk.id = s_tkid[m * k + lane];
+      }
       tk.refresh();
       const bool gate = valid && tk.admits(d, pid);
       const uint64_t gm = ballot(gate);
       if (gm) {
         tk.offer(gm, gate, d, pid);
-        s_tkd[w][m][lane] = tk.d;
-        s_tkid[w][m][lane] = tk.id;
-        if (lane == 0) s_tau[w][m] = round_up_f(tk.kd);
+        if (lane < k) {
+          s_tkd[m * k + lane] = tk.d;
+          s_tkid[m * k + lane] = tk.id;
+        }
+        if (lane == 0) s_tau[m] = round_up_f(tk.kd);
       }
-      if (lane == 0) s_qn[w][m] = 0;
+      if (lane == 0) s_qn[m] = 0;
     }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) tau[e] = s_tau[g * 4 + e];
   }
-  __syncthreads();
   for (int m = 0; m < kMQ; ++m) {
     const int64_t q = qbase + m;
     if (q < nq && lane < k) {
-      const int id = s_tkid[w][m][lane];
+      const int id = s_tkid[m * k + lane];
       out_idx[q * k + lane] = id == kNoId ? -1 : id;
-      out_dist[q * k + lane] = s_tkd[w][m][lane];
+      out_dist[q * k + lane] = s_tkd[m * k + lane];
     }
   }
   if (a.stats) {
@@ -336,10 +351,24 @@ hipError_t launch_mixed_brute(const IndexDesc &ix, const QueryArgs &a, const tnn
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  const int64_t per_block = (int64_t)kWaves * kMQ;
-  hipLaunchKernelGGL(mixed_brute_kernel, dim3((unsigned)((qs.n + per_block - 1) / per_block)),
-                     dim3(kWaves * 64), 0, st, ix, a, mc, ops, nv, qs.x, qs.y, qs.z, qs.t, qs.n,
-                     out_idx, out_dist);
+  const int64_t n_steps = (ix.n_points + kStep - 1) / kStep;
+  int64_t stride = 1;
+  if (n_steps > 2) {
+    auto gcd = [](int64_t x, int64_t y) {
+      while (y) {
+        const int64_t r = x % y;
+        x = y;
+        y = r;
+      }
+      return x;
+    };
+    stride = (int64_t)(0.6180339887 * (double)n_steps) | 1;
+    while (gcd(stride, n_steps) != 1) stride += 2;
+  }
+  const size_t lds = (size_t)kMQ * a.k * 12 + (size_t)kMQ * kStep * 8 + (size_t)kMQ * 16;
+  hipLaunchKernelGGL(mixed_brute_kernel, dim3((unsigned)((qs.n + kMQ - 1) / kMQ)), dim3(64), lds,
+                     st, ix, a, mc, ops, nv, qs.x, qs.y, qs.z, qs.t, qs.n, out_idx, out_dist,
+                     stride);
   return hipGetLastError();
 }
 

@@ -5,6 +5,8 @@
 
 namespace tnn {
 
+constexpr size_t kLdsBoxBytes = 48 * 1024;  // stage block boxes in LDS up to this size
+
 // ---------------------------------------------------------------------------
 // Per-call preparation (depends on the scales): 1/|AB|_s^2, the radius
 // R = sqrt(sum_f s_f e_f^2) rounded up, and the projection slack.
@@ -43,6 +45,8 @@ struct Searcher {
   WaveStats st;
   int lane;
   int spi_shift;  // log2(kpad): lanes per segment when scanning points
+  const float *box;   // block boxes (global memory or an LDS copy)
+  const float *sbox;  // superblock boxes (global memory or an LDS copy)
 
   __device__ Searcher(const IndexDesc &ix_, const Prep &pr_, const QueryArgs &a_)
       : ix(ix_), pr(pr_), a(a_) {}
@@ -96,31 +100,45 @@ struct Searcher {
   // block bound seen (uniform).
   __device__ float round(double prev, double tau, int seed_block, uint64_t seed_mask) {
     const int nb = ix.n_blocks;
+    const int ns = ix.n_super;
     const int64_t S = ix.n_seg;
+    const float finf = __builtin_huge_valf();
     float maxfin = 0.0f;
-    for (int base = 0; base < nb; base += kWave) {
-      const int b = base + lane;
-      const float lbb = b < nb ? block_lb(ix, b, q, a.sf) : __builtin_huge_valf();
-      st.blocks += (uint32_t)min(kWave, nb - base);
-      if (lbb < __builtin_huge_valf()) maxfin = fmaxf(maxfin, lbb);
-      const double tau0 = fmin(tau, tk.kd);
-      uint64_t m = ballot(lbb < __builtin_huge_valf() && (double)lbb <= tau0);
-      while (m) {
-        const int bl = __ffsll((long long)m) - 1;
-        m &= m - 1;
-        const double tau_cur = fmin(tau, tk.kd);
-        const double lbb_b = (double)readlane_f(lbb, bl);
-        if (lbb_b > tau_cur) continue;
-        const int bb = base + bl;
-        const int64_t s = (int64_t)bb * kBlockSegs + lane;
-        // both bounds hold for every member; the larger one decides the round
-        const double key = fmax(s < S ? seg_lb(ix, pr, s, q, a.s) : kInf, lbb_b);
-        st.segs += (uint32_t)min((int64_t)kBlockSegs, S - (int64_t)bb * kBlockSegs);
-        const bool seeded = bb == seed_block && ((seed_mask >> lane) & 1ull);
-        // a masked segment (infinite key) holds no candidate
-        const bool cand = s < S && key < kInf && key <= tau_cur && key > prev && !seeded;
-        const uint64_t cm = ballot(cand);
-        if (cm) scan(cm, bb);
+    // superblock level: 64 superblock bounds per pass
+    for (int sbase = 0; sbase < ns; sbase += kWave) {
+      const int sb = sbase + lane;
+      const float lbs = sb < ns ? block_lb(sbox, ns, sb, q, a.sf) : finf;
+      st.blocks += (uint32_t)min(kWave, ns - sbase);
+      if (lbs < finf) maxfin = fmaxf(maxfin, lbs);
+      uint64_t ms = ballot(lbs < finf && (double)lbs <= fmin(tau, tk.kd));
+      while (ms) {
+        const int sl = __ffsll((long long)ms) - 1;
+        ms &= ms - 1;
+        if ((double)readlane_f(lbs, sl) > fmin(tau, tk.kd)) continue;
+        // block level: the superblock's 64 blocks, one per lane
+        const int b0 = (sbase + sl) * kSuperBlocks;
+        const int b = b0 + lane;
+        const float lbb = b < nb ? block_lb(box, nb, b, q, a.sf) : finf;
+        st.blocks += (uint32_t)min(kSuperBlocks, nb - b0);
+        if (lbb < finf) maxfin = fmaxf(maxfin, lbb);
+        uint64_t m = ballot(lbb < finf && (double)lbb <= fmin(tau, tk.kd));
+        while (m) {
+          const int bl = __ffsll((long long)m) - 1;
+          m &= m - 1;
+          const double tau_cur = fmin(tau, tk.kd);
+          const double lbb_b = (double)readlane_f(lbb, bl);
+          if (lbb_b > tau_cur) continue;
+          const int bb = b0 + bl;
+          const int64_t s = (int64_t)bb * kBlockSegs + lane;
+          // both bounds hold for every member; the larger one decides the round
+          const double key = fmax(s < S ? seg_lb(ix, pr, s, q, a.s) : kInf, lbb_b);
+          st.segs += (uint32_t)min((int64_t)kBlockSegs, S - (int64_t)bb * kBlockSegs);
+          const bool seeded = bb == seed_block && ((seed_mask >> lane) & 1ull);
+          // a masked segment (infinite key) holds no candidate
+          const bool cand = s < S && key < kInf && key <= tau_cur && key > prev && !seeded;
+          const uint64_t cm = ballot(cand);
+          if (cm) scan(cm, bb);
+        }
       }
     }
     return wave_max_f(maxfin);
@@ -146,11 +164,15 @@ __device__ __forceinline__ void flush_stats(unsigned long long *stats, const Wav
 //            continues from the k-th found (or a 16x larger radius).
 // Rounds only widen tau; a segment is scanned in the first round whose
 // radius reaches its bound, so no point enters the top-k twice.
-__device__ void answer_query(const IndexDesc &ix, const Prep &pr, const QueryArgs &a,
-                             const float *qx, const float *qy, const float *qz, const float *qt,
-                             int64_t qi, int32_t *out_idx, double *out_dist) {
+__device__ __forceinline__ void answer_query(const IndexDesc &ix, const Prep &pr,
+                                             const QueryArgs &a, const float *qx, const float *qy,
+                                             const float *qz, const float *qt, int64_t qi,
+                                             int32_t *out_idx, double *out_dist,
+                                             const float *box, const float *sbox) {
   Searcher se(ix, pr, a);
   se.lane = lane_id();
+  se.box = box;
+  se.sbox = sbox;
   se.spi_shift = 31 - __clz(ix.kpad);
   se.q = make_query(qx[qi], qy[qi], qz[qi], qt[qi], a.t_window);
   se.tk.init(a.k, a.inf);
@@ -174,18 +196,37 @@ __device__ void answer_query(const IndexDesc &ix, const Prep &pr, const QueryArg
   if (learned) {
     tau = r2;
   } else {
-    // nearest block by its bound
+    // nearest block by its bound: best-first over superblocks (a superblock
+    // bound never exceeds the bounds of its blocks, so once the nearest
+    // unvisited superblock is no closer than the best block the argmin is
+    // exact)
     float best = __builtin_huge_valf();
     int bestb = kNoId;
-    for (int b = se.lane; b < nb; b += kWave) {
-      const float v = block_lb(ix, b, se.q, a.sf);
-      if (v < best) {
-        best = v;
-        bestb = b;
+    {
+      const int ns = ix.n_super;
+      for (int sbase = 0; sbase < ns; sbase += kWave) {
+        const int sb = sbase + se.lane;
+        float lbs = sb < ns ? block_lb(se.sbox, ns, sb, se.q, a.sf) : __builtin_huge_valf();
+        se.st.blocks += (uint32_t)min(kWave, ns - sbase);
+        for (;;) {
+          float v = lbs;
+          int vl = se.lane;
+          wave_argmin_f(v, vl);
+          if (!(v < best)) break;
+          if (se.lane == vl) lbs = __builtin_huge_valf();
+          const int b0 = (sbase + vl) * kSuperBlocks;
+          const int b = b0 + se.lane;
+          float bv = b < nb ? block_lb(se.box, nb, b, se.q, a.sf) : __builtin_huge_valf();
+          int bi = b < nb ? b : kNoId;
+          se.st.blocks += (uint32_t)min(kSuperBlocks, nb - b0);
+          wave_argmin_f(bv, bi);
+          if (bv < best || (bv == best && bi < bestb)) {
+            best = bv;
+            bestb = bi;
+          }
+        }
       }
     }
-    se.st.blocks += (uint32_t)nb;
-    wave_argmin_f(best, bestb);
     if (!(best < __builtin_huge_valf())) {  // nothing early enough anywhere
       tau = kInf;
       se.st.rounds = 0;
@@ -247,7 +288,30 @@ __global__ __launch_bounds__(512) void tnn_query_kernel(IndexDesc ix, Prep pr, Q
                                                         double *out_dist) {
   const int64_t qi = (int64_t)blockIdx.x * (blockDim.x >> 6) + uniform_i((int)(threadIdx.x >> 6));
   if (qi >= nq) return;
-  answer_query(ix, pr, a, qx, qy, qz, qt, qi, out_idx, out_dist);
+  answer_query(ix, pr, a, qx, qy, qz, qt, qi, out_idx, out_dist, ix.box, ix.sbox);
+}
+
+// Same search with the block boxes staged once per workgroup in LDS (small
+// indexes): the workgroup stays resident and its waves walk the queries with
+// a grid stride.
+__global__ __launch_bounds__(512) void tnn_query_lds_kernel(IndexDesc ix, Prep pr, QueryArgs a,
+                                                            const float *qx, const float *qy,
+                                                            const float *qz, const float *qt,
+                                                            int64_t nq, int32_t *out_idx,
+                                                            double *out_dist, int boxes_in_lds) {
+  extern __shared__ float s_box[];
+  // superblock boxes first, then (when they fit) the block boxes
+  const int nsbox = 8 * ix.n_super;
+  for (int i = threadIdx.x; i < nsbox; i += blockDim.x) s_box[i] = ix.sbox[i];
+  const int nbox = boxes_in_lds ? 8 * ix.n_blocks : 0;
+  for (int i = threadIdx.x; i < nbox; i += blockDim.x) s_box[nsbox + i] = ix.box[i];
+  __syncthreads();
+  const float *box = boxes_in_lds ? s_box + nsbox : ix.box;
+  const int wpb = blockDim.x >> 6;
+  const int64_t stride = (int64_t)gridDim.x * wpb;
+  for (int64_t qi = (int64_t)blockIdx.x * wpb + uniform_i((int)(threadIdx.x >> 6)); qi < nq;
+       qi += stride)
+    answer_query(ix, pr, a, qx, qy, qz, qt, qi, out_idx, out_dist, box, s_box);
 }
 
 // ---------------------------------------------------------------------------
@@ -377,7 +441,7 @@ __global__ __launch_bounds__(512) void batch_kernel(const BatchItemDev *items,
       const int item = order[pos];
       const BatchItemDev &it = items[item];
       answer_query(it.ix, it.pr, it.a, it.qx, it.qy, it.qz, it.qt, gq - qprefix[pos], it.out_idx,
-                   it.out_dist);
+                   it.out_dist, it.ix.box, it.ix.sbox);
       if (lane == 0) {
         const unsigned d = atomicAdd(&done[item], 1u) + 1u;
         if ((int64_t)d == it.nq) ticks[item + 1] = wall_clock64();
@@ -419,11 +483,35 @@ hipError_t launch_prep(const IndexDesc &ix, const QueryArgs &a, const Prep &pr, 
   return hipGetLastError();
 }
 
+static int cu_count() {
+  static int cached[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (!cached[dev]) {
+    int c = 0;
+    if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || c <= 0)
+      c = 256;
+    cached[dev] = c;
+  }
+  return cached[dev];
+}
+
 hipError_t launch_query(const IndexDesc &ix, const Prep &pr, const QueryArgs &a,
                         const tnn_points &qs, int waves_per_block, int32_t *out_idx,
                         double *out_dist, hipStream_t st) {
   if (qs.n == 0) return hipSuccess;
   const int64_t grid = (qs.n + waves_per_block - 1) / waves_per_block;
+  const size_t sl = (size_t)ix.n_super * 8 * sizeof(float);
+  const size_t bl = (size_t)ix.n_blocks * 8 * sizeof(float);
+  if (sl <= kLdsBoxBytes) {
+    const int in_lds = sl + bl <= kLdsBoxBytes ? 1 : 0;
+    const size_t lds = in_lds ? sl + bl : sl;
+    const int64_t resident = (int64_t)cu_count() * (32 / waves_per_block);
+    const int64_t g = grid < resident ? grid : resident;
+    hipLaunchKernelGGL(tnn_query_lds_kernel, dim3((unsigned)g), dim3(waves_per_block * kWave), lds,
+                       st, ix, pr, a, qs.x, qs.y, qs.z, qs.t, qs.n, out_idx, out_dist, in_lds);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(tnn_query_kernel, dim3((unsigned)grid), dim3(waves_per_block * kWave), 0, st,
                      ix, pr, a, qs.x, qs.y, qs.z, qs.t, qs.n, out_idx, out_dist);
   return hipGetLastError();

@@ -9,6 +9,7 @@ namespace tnn {
 
 constexpr int kWave = 64;          // CDNA wavefront width
 constexpr int kBlockSegs = 64;     // segments per culling block (one per lane)
+constexpr int kSuperBlocks = 64;   // blocks per superblock (one per lane)
 constexpr int kMaxK = 64;          // top-k held one rank per lane
 constexpr int kMaxSegLen = 64;
 
@@ -28,6 +29,10 @@ struct IndexDesc {
   const int32_t *pstart, *pcount, *sorig;
   // block boxes: box[f][b] for f = 0..7 (lo x y z t, hi x y z t)
   const float *box;
+  // superblock boxes (64 consecutive blocks each): sbox[f][s]
+  const float *sbox;
+  int32_t n_super;
+  int32_t pad_;
   float lo[4], hi[4];  // bounding box of all points
 };
 static_assert(sizeof(IndexDesc) <= sizeof(tnn_index), "index descriptor too large");

@@ -30,12 +30,12 @@ def train(index, sx, sy, sz, st, scale, t_window, k, epochs=20, batch=4096, lr=3
     loss = torch.zeros(1, dtype=torch.float32, device=dev)
     scratch = None
     step = 0
-    nb = max(1, n // batch)
+    nb = max(1, n // batch) if n > 0 else 0
     for ep in range(epochs):
         for b in range(nb):
             step += 1
             first = b * batch
-            size = min(batch, n - first)
+            size = min(batch, n - first) if b < nb - 1 else n - first
             scratch = T.tnn_radius_train_step(model, adam, px, py, pz, pt, pdist, k, first, size,
                                               step, lr, loss=loss, scratch=scratch)
         if log is not None:

@@ -308,3 +308,25 @@ def test_generator_is_seeded_and_sorted():
         assert np.all(np.diff(tt) > 0)
         step = np.hypot(np.diff(a.x[a.offsets[j]:a.offsets[j + 1]]), np.diff(a.y[a.offsets[j]:a.offsets[j + 1]]))
         assert np.all((step > 0.6) & (step < 1.3))  # ~230 m/s over 4 s
+
+
+def test_radius_density_grid_and_features_hand_case():
+    """Three segments with hand-placed midpoints in a box [0, 32]^2 x [0, 320]:
+    cell width 1 in x and y, 10 in t."""
+    lo = np.array([0.0, 0.0, 8.0, 0.0], np.float32)
+    hi = np.array([32.0, 32.0, 12.0, 320.0], np.float32)
+    a = np.array([[0.0, 0.0, 9.0], [3.0, 4.0, 9.0], [3.0, 4.0, 9.0]])
+    b = np.array([[1.0, 1.0, 9.0], [4.0, 5.0, 9.0], [4.0, 5.0, 9.0]])
+    tmin = np.array([0.0, 100.0, 104.0])
+    tmax = np.array([10.0, 110.0, 114.0])
+    g = oracle.radius_density_grid(a, b, tmin, tmax, lo, hi)
+    # midpoints (0.5, 0.5, 5) -> cell (0, 0, 0); (3.5, 4.5, 105) and (3.5, 4.5, 109) -> (3, 4, 10)
+    assert g.sum() == 3 and g[0, 0, 0] == 1 and g[3, 4, 10] == 2
+    f = oracle.radius_features(np.array([16.0, 3.9], np.float32), np.array([0.0, 4.2], np.float32),
+                               np.array([10.0, 12.0], np.float32), np.array([160.0, 107.0], np.float32),
+                               lo, hi, g)
+    # centre maps to 0, edges to -1 / +1; density feature 0.25 log1p(count)
+    assert np.allclose(f[0, :4], [0.0, -1.0, 0.0, 0.0])
+    assert f[0, 4] == 0.0
+    assert f[1, 4] == pytest.approx(0.25 * math.log(3.0))
+    assert f[1, 2] == pytest.approx(1.0)
