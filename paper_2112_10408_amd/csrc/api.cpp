@@ -138,15 +138,15 @@ QueryArgs make_args(const tnn_query_params *p) {
   return a;
 }
 
-size_t prep_bytes(int64_t S) { return 3 * align_up(8 * (size_t)S); }
+size_t prep_bytes(int64_t S) { return 3 * align_up(4 * (size_t)S); }
 
 Prep prep_view(void *scratch, int64_t S) {
   char *b = static_cast<char *>(scratch);
-  const size_t one = align_up(8 * (size_t)S);
+  const size_t one = align_up(4 * (size_t)S);
   Prep p;
-  p.inv_n2 = reinterpret_cast<const double *>(b);
-  p.rad = reinterpret_cast<const double *>(b + one);
-  p.slack = reinterpret_cast<const double *>(b + 2 * one);
+  p.inv_n2 = reinterpret_cast<const float *>(b);
+  p.rad = reinterpret_cast<const float *>(b + one);
+  p.slack = reinterpret_cast<const float *>(b + 2 * one);
   return p;
 }
 

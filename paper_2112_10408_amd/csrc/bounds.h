@@ -7,11 +7,7 @@
 //    a non-negative quantity, so multiplying by (1 - 2^-18) stays below the
 //    real bound, which is below the real distance, which is within a
 //    2^-50 relative error of the reported one;
-//  * cylinder bound (binary64): the projection parameter is approximate, which
-//    can only raise the computed distance to the segment by a second-order
-//    term bounded by 2^-48 |AB|_s, covered by the 2^-30 |AB|_s slack; the
-//    residual's cancellation error (relative 2^-50 of |AP| + |AB|) is covered by
-//    the (1 - 2^-40) factors.
+//  * cylinder bound (float32): see seg_lb.
 #pragma once
 #include "tnn_internal.h"
 #include "wave.h"
@@ -85,27 +81,27 @@ __device__ __forceinline__ float block_lb(const IndexDesc &ix, int b, const Quer
 // Algorithm 1, corrected): +inf if t_min >= t_q - t_w; otherwise
 // max(0, D - R)^2 + s_t max(0, t_q - t_max, t_w)^2 with D the distance from
 // the query to segment AB in the scaled metric (projection in that metric).
-__device__ __forceinline__ double seg_lb(const IndexDesc &ix, const Prep &pr, int64_t s,
-                                         const QueryPoint &q, const double sc[4]) {
+// Float32 with a proven margin: the computed distance to the segment exceeds
+// the true one by at most 7u D + 14u |AB|_s (u = 2^-24; rounding of the
+// differences, the projection parameter's second-order effect, sqrt), which
+// the (1 - 2^-18) factor and the 2^-17 |AB|_s slack remove; the scales are
+// rounded toward zero, R is rounded up, and the final (1 - 2^-20) factor
+// covers the remaining float32 roundings.
+__device__ __forceinline__ float seg_lb(const IndexDesc &ix, const Prep &pr, int64_t s,
+                                        const QueryPoint &q, const float sf[4]) {
   const float tmin = ix.tmin[s];
-  if ((double)tmin >= q.thr) return kInf;
-  const double ax = ix.ax[s], ay = ix.ay[s], az = ix.az[s];
-  const double abx = (double)ix.bx[s] - ax;
-  const double aby = (double)ix.by[s] - ay;
-  const double abz = (double)ix.bz[s] - az;
-  const double apx = (double)q.x - ax;
-  const double apy = (double)q.y - ay;
-  const double apz = (double)q.z - az;
-  const double dot = sc[0] * apx * abx + sc[1] * apy * aby + sc[2] * apz * abz;
-  const double del = fmin(fmax(dot * pr.inv_n2[s], 0.0), 1.0);
-  const double rx = apx - del * abx;
-  const double ry = apy - del * aby;
-  const double rz = apz - del * abz;
-  const double d2 = sc[0] * rx * rx + sc[1] * ry * ry + sc[2] * rz * rz;
-  const double dlo = sqrt(d2) * (1.0 - 0x1p-40);
-  const double g = fmax(dlo - pr.slack[s] - pr.rad[s], 0.0);
-  const double gt = fmax(fmax((double)q.t - (double)ix.tmax[s], q.gw), 0.0);
-  return (g * g + sc[3] * (gt * gt)) * (1.0 - 0x1p-40);
+  if ((double)tmin >= q.thr) return __builtin_huge_valf();
+  const float ax = ix.ax[s], ay = ix.ay[s], az = ix.az[s];
+  const float abx = ix.bx[s] - ax, aby = ix.by[s] - ay, abz = ix.bz[s] - az;
+  const float apx = q.x - ax, apy = q.y - ay, apz = q.z - az;
+  const float dot = sf[0] * (apx * abx) + sf[1] * (apy * aby) + sf[2] * (apz * abz);
+  const float del = fminf(fmaxf(dot * pr.inv_n2[s], 0.0f), 1.0f);
+  const float rx = apx - del * abx, ry = apy - del * aby, rz = apz - del * abz;
+  const float d2 = sf[0] * (rx * rx) + sf[1] * (ry * ry) + sf[2] * (rz * rz);
+  const float dlo = sqrtf(d2) * (1.0f - 0x1p-18f) - pr.slack[s];
+  const float g = fmaxf(dlo - pr.rad[s], 0.0f);
+  const float gt = fmaxf(fmaxf(q.t - ix.tmax[s], q.gwf), 0.0f);
+  return (g * g + sf[3] * (gt * gt)) * (1.0f - 0x1p-20f);
 }
 
 }  // namespace tnn

@@ -7,23 +7,35 @@ namespace tnn {
 
 constexpr size_t kLdsBoxBytes = 48 * 1024;  // stage block boxes in LDS up to this size
 
+// Minimum resident waves per SIMD the search kernels are compiled for.
+#ifndef TNN_QUERY_MIN_WAVES
+#define TNN_QUERY_MIN_WAVES 1
+#endif
+
 // ---------------------------------------------------------------------------
 // Per-call preparation (depends on the scales): 1/|AB|_s^2, the radius
 // R = sqrt(sum_f s_f e_f^2) rounded up, and the projection slack.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void prep_one(const IndexDesc &ix, const QueryArgs &a, double *inv_n2,
-                                         double *rad, double *slack, int64_t s) {
-  const double abx = (double)ix.bx[s] - (double)ix.ax[s];
-  const double aby = (double)ix.by[s] - (double)ix.ay[s];
-  const double abz = (double)ix.bz[s] - (double)ix.az[s];
+__device__ __forceinline__ void prep_one(const IndexDesc &ix, const QueryArgs &a, float *inv_n2,
+                                         float *rad, float *slack, int64_t s) {
+  // AB as the bound computes it (float32 differences), norms in binary64
+  const double abx = (double)(ix.bx[s] - ix.ax[s]);
+  const double aby = (double)(ix.by[s] - ix.ay[s]);
+  const double abz = (double)(ix.bz[s] - ix.az[s]);
   const double n2 = a.s[0] * abx * abx + a.s[1] * aby * aby + a.s[2] * abz * abz;
-  inv_n2[s] = n2 > 0.0 ? 1.0 / n2 : 0.0;
+  inv_n2[s] = n2 > 0.0 ? (float)(1.0 / n2) : 0.0f;
   const double ex = ix.ex[s], ey = ix.ey[s], ez = ix.ez[s];
-  rad[s] = sqrt(a.s[0] * ex * ex + a.s[1] * ey * ey + a.s[2] * ez * ez) * (1.0 + 0x1p-40);
-  slack[s] = 0x1p-30 * sqrt(n2);
+  rad[s] = __double2float_ru(sqrt(a.s[0] * ex * ex + a.s[1] * ey * ey + a.s[2] * ez * ez) *
+                             (1.0 + 0x1p-40));
+  // exact AB and its norm bound the float32 errors of the bound
+  const double tx = (double)ix.bx[s] - (double)ix.ax[s];
+  const double ty = (double)ix.by[s] - (double)ix.ay[s];
+  const double tz = (double)ix.bz[s] - (double)ix.az[s];
+  const double nt = sqrt(a.s[0] * tx * tx + a.s[1] * ty * ty + a.s[2] * tz * tz);
+  slack[s] = __double2float_ru(0x1p-17 * (nt + sqrt(n2)) * 0.5 * (1.0 + 0x1p-30));
 }
 
-__global__ void prep_kernel(IndexDesc ix, QueryArgs a, double *inv_n2, double *rad, double *slack) {
+__global__ void prep_kernel(IndexDesc ix, QueryArgs a, float *inv_n2, float *rad, float *slack) {
   const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= ix.n_seg) return;
   prep_one(ix, a, inv_n2, rad, slack, s);
@@ -53,7 +65,8 @@ struct Searcher {
 
   // Scan the member points of the segments of block `bb` whose lanes are set
   // in `cm`, feeding the top-k.  Several segments share one 64-lane pass.
-  __device__ void scan(uint64_t cm, int bb) {
+  // (ps_l, pc_l): this lane's segment's first point slot and member count.
+  __device__ void scan(uint64_t cm, int bb, int ps_l, int pc_l) {
     const int kpad = 1 << spi_shift;
     const int spi = kWave >> spi_shift;
     const int slot = lane >> spi_shift;
@@ -66,9 +79,12 @@ struct Searcher {
         if (slot == i) my_l = l;
       }
       const bool has = my_l >= 0;
-      const int64_t s = (int64_t)bb * kBlockSegs + (has ? my_l : 0);
-      const int ps = has ? ix.pstart[s] : 0;
-      const int pc = has ? ix.pcount[s] : 0;
+      // every lane must take part in the cross-lane reads: a lane that is
+      // switched off does not supply its register
+      const int src = has ? my_l : 0;
+      const int ps = __shfl(ps_l, src, 64);
+      const int pc_src = __shfl(pc_l, src, 64);
+      const int pc = has ? pc_src : 0;
       const bool ok = has && off < pc;
       const int p = ps + off;
       float px = 0.f, py = 0.f, pz = 0.f, pt = 0.f;
@@ -130,14 +146,16 @@ struct Searcher {
           if (lbb_b > tau_cur) continue;
           const int bb = b0 + bl;
           const int64_t s = (int64_t)bb * kBlockSegs + lane;
+          const int ps_l = s < S ? ix.pstart[s] : 0;
+          const int pc_l = s < S ? ix.pcount[s] : 0;
           // both bounds hold for every member; the larger one decides the round
-          const double key = fmax(s < S ? seg_lb(ix, pr, s, q, a.s) : kInf, lbb_b);
+          const double key = fmax(s < S ? (double)seg_lb(ix, pr, s, q, a.sf) : kInf, lbb_b);
           st.segs += (uint32_t)min((int64_t)kBlockSegs, S - (int64_t)bb * kBlockSegs);
           const bool seeded = bb == seed_block && ((seed_mask >> lane) & 1ull);
           // a masked segment (infinite key) holds no candidate
           const bool cand = s < S && key < kInf && key <= tau_cur && key > prev && !seeded;
           const uint64_t cm = ballot(cand);
-          if (cm) scan(cm, bb);
+          if (cm) scan(cm, bb, ps_l, pc_l);
         }
       }
     }
@@ -235,7 +253,9 @@ __device__ __forceinline__ void answer_query(const IndexDesc &ix, const Prep &pr
     seed_block = bestb;
     {
       const int64_t s = (int64_t)bestb * kBlockSegs + se.lane;
-      double v = s < S ? seg_lb(ix, pr, s, se.q, a.s) : kInf;
+      const int ps_l = s < S ? ix.pstart[s] : 0;
+      const int pc_l = s < S ? ix.pcount[s] : 0;
+      double v = s < S ? (double)seg_lb(ix, pr, s, se.q, a.sf) : kInf;
       se.st.segs += (uint32_t)min((int64_t)kBlockSegs, S - (int64_t)bestb * kBlockSegs);
       const int F = a.seed_segments;
       for (int i = 0; i < F; ++i) {
@@ -246,7 +266,7 @@ __device__ __forceinline__ void answer_query(const IndexDesc &ix, const Prep &pr
         seed_mask |= 1ull << ml;
         if (se.lane == ml) v = kInf;
       }
-      if (seed_mask) se.scan(seed_mask, bestb);
+      if (seed_mask) se.scan(seed_mask, bestb, ps_l, pc_l);
     }
     if (se.tk.kd < kInf) {
       tau = se.tk.kd;
@@ -294,7 +314,7 @@ __global__ __launch_bounds__(512) void tnn_query_kernel(IndexDesc ix, Prep pr, Q
 // Same search with the block boxes staged once per workgroup in LDS (small
 // indexes): the workgroup stays resident and its waves walk the queries with
 // a grid stride.
-__global__ __launch_bounds__(512) void tnn_query_lds_kernel(IndexDesc ix, Prep pr, QueryArgs a,
+__global__ __launch_bounds__(512, TNN_QUERY_MIN_WAVES) void tnn_query_lds_kernel(IndexDesc ix, Prep pr, QueryArgs a,
                                                             const float *qx, const float *qy,
                                                             const float *qz, const float *qt,
                                                             int64_t nq, int32_t *out_idx,
@@ -374,7 +394,7 @@ __global__ void debug_lb_kernel(IndexDesc ix, Prep pr, QueryArgs a, const float 
   const int64_t qi = i / per_q, j = i % per_q;
   const QueryPoint q = make_query(qx[qi], qy[qi], qz[qi], qt[qi], a.t_window);
   if (j < S) {
-    if (seg_lb_out) seg_lb_out[qi * S + j] = seg_lb(ix, pr, j, q, a.s);
+    if (seg_lb_out) seg_lb_out[qi * S + j] = (double)seg_lb(ix, pr, j, q, a.sf);
   } else if (block_lb_out) {
     block_lb_out[qi * nb + (j - S)] = block_lb(ix, (int)(j - S), q, a.sf);
   }
@@ -413,8 +433,8 @@ __global__ void batch_prep_kernel(const BatchItemDev *items, const int64_t *seg_
   if (g >= seg_prefix[n]) return;
   const int i = find_item(seg_prefix, n, g);
   const BatchItemDev &it = items[i];
-  prep_one(it.ix, it.a, const_cast<double *>(it.pr.inv_n2), const_cast<double *>(it.pr.rad),
-           const_cast<double *>(it.pr.slack), g - seg_prefix[i]);
+  prep_one(it.ix, it.a, const_cast<float *>(it.pr.inv_n2), const_cast<float *>(it.pr.rad),
+           const_cast<float *>(it.pr.slack), g - seg_prefix[i]);
 }
 
 // Waves pull `chunk` queries at a time from a global counter over the
@@ -478,8 +498,8 @@ hipError_t launch_prep(const IndexDesc &ix, const QueryArgs &a, const Prep &pr, 
   const int tpb = 256;
   const int64_t grid = (ix.n_seg + tpb - 1) / tpb;
   hipLaunchKernelGGL(prep_kernel, dim3((unsigned)grid), dim3(tpb), 0, st, ix, a,
-                     const_cast<double *>(pr.inv_n2), const_cast<double *>(pr.rad),
-                     const_cast<double *>(pr.slack));
+                     const_cast<float *>(pr.inv_n2), const_cast<float *>(pr.rad),
+                     const_cast<float *>(pr.slack));
   return hipGetLastError();
 }
 

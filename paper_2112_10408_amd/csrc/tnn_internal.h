@@ -40,9 +40,9 @@ constexpr uint32_t kIndexMagic = 0x544e4e31u;  // "TNN1"
 
 // Per-call prepared segment data (depends on the scales).
 struct Prep {
-  const double *inv_n2;  // 1 / |AB|_s^2, 0 for a degenerate segment
-  const double *rad;     // radius R(s) = sqrt(sum s_f e_f^2), rounded up
-  const double *slack;   // absolute slack for the projection error, 2^-30 |AB|_s
+  const float *inv_n2;  // 1 / |AB|_s^2, 0 for a degenerate segment
+  const float *rad;     // radius R(s) = sqrt(sum s_f e_f^2), rounded up
+  const float *slack;   // absolute slack for the float32 bound, 2^-17 |AB|_s rounded up
 };
 
 struct QueryArgs {

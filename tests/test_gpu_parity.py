@@ -137,7 +137,8 @@ def test_lower_bounds_hold_and_are_tight(scale, t_window):
     assert np.array_equal(np.isinf(seg_lb), np.isinf(lb_o))
     fin = np.isfinite(lb_o)
     assert np.all(seg_lb[fin] <= lb_o[fin] * (1 + 1e-9) + 1e-12)
-    assert np.all(seg_lb[fin] >= lb_o[fin] * (1 - 1e-5) - 1e-6)
+    # float32 bound: within its proven slack of the binary64 definition
+    assert np.all(np.sqrt(seg_lb[fin]) >= np.sqrt(lb_o[fin]) * (1 - 1e-5) - 1e-3)
 
 
 @pytest.mark.parametrize("k", [1, 7, 32, 64])
