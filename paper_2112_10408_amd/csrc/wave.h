@@ -8,6 +8,9 @@ namespace tnn {
 
 constexpr double kInf = __builtin_huge_val();
 constexpr int kNoId = 0x7fffffff;
+// Newcomers up to this count are inserted one by one; more are sorted and
+// merged with a bitonic network.
+constexpr int kInsertMax = 12;
 
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63u); }
 
@@ -67,10 +70,28 @@ __device__ __forceinline__ float wave_max_f(float v) {
   return v;
 }
 
+// Value of lane ^ j (j a power of two known after unrolling): DPP quad
+// permutes for 1 and 2, LDS swizzle for 4..16, a permute for 32.
+__device__ __forceinline__ int xor_lane(int v, int j) {
+  if (j == 1) return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false);  // quad_perm [1,0,3,2]
+  if (j == 2) return __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false);  // quad_perm [2,3,0,1]
+  if (j == 4) return __builtin_amdgcn_ds_swizzle(v, 0x1F | (4 << 10));
+  if (j == 8) return __builtin_amdgcn_ds_swizzle(v, 0x1F | (8 << 10));
+  if (j == 16) return __builtin_amdgcn_ds_swizzle(v, 0x1F | (16 << 10));
+  return __shfl_xor(v, j, 64);
+}
+
+__device__ __forceinline__ double xor_lane_d(double v, int j) {
+  const long long b = __double_as_longlong(v);
+  const int lo = xor_lane((int)(b & 0xffffffffll), j);
+  const int hi = xor_lane((int)(b >> 32), j);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
 // Compare-exchange with lane ^ j: keep the smaller key if `keep_min`.
 __device__ __forceinline__ void cmpx(double &d, int &id, int j, bool keep_min) {
-  const double od = __shfl_xor(d, j, 64);
-  const int oid = __shfl_xor(id, j, 64);
+  const double od = xor_lane_d(d, j);
+  const int oid = xor_lane(id, j);
   const bool other_lt = key_lt(od, oid, d, id);
   const bool other_gt = key_lt(d, id, od, oid);
   if (keep_min ? other_lt : other_gt) {
@@ -154,7 +175,8 @@ struct TopK {
   // Offer one key per lane; lanes with gate=false offer nothing.  `gm` is the
   // ballot of gate.  Returns nothing; updates the threshold.
   __device__ __forceinline__ void offer(uint64_t gm, bool gate, double nd, int nid) {
-    if (__popcll(gm) <= 6) {
+    const int n = __popcll(gm);
+    if (n <= kInsertMax) {
       while (gm) {
         const int l = __ffsll((long long)gm) - 1;
         gm &= gm - 1;
@@ -164,6 +186,12 @@ struct TopK {
       double cd = gate ? nd : inf_;
       int cid = gate ? nid : kNoId;
       sort64(cd, cid);
+      if (!(readlane_d(d, 0) < inf_)) {  // empty top-k: the sorted batch is the result
+        d = cd;
+        id = cid;
+        refresh();
+        return;
+      }
       const int rl = 63 - lane_id();
       const double rd = __shfl(cd, rl, 64);
       const int rid = __shfl(cid, rl, 64);
