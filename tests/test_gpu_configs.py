@@ -1,0 +1,72 @@
+"""Full-size workloads: 1M points with every point a query (k=32) and 8M points
+with 1M held-out queries (k=64, learned radius trained on 200k).  Every path
+is compared on every query; a seeded sample is checked against the oracle."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_util import assert_same, build, config_data, dev_points, gpu_query, say
+from paper_2112_10408_amd import capi, radius, synth
+from paper_2112_10408_amd import tnn as T
+
+pytestmark = pytest.mark.gpu
+SCALE = synth.SCALE
+
+
+def _sample_check(ps, qs, gi, gd, k, n=192, seed=7):
+    rng = np.random.default_rng(seed)
+    sample = np.sort(rng.choice(qs.n, n, replace=False))
+    sample = np.concatenate([sample, np.argsort(qs.t)[:8]])
+    oi, od = oracle.knn(ps.soa(), qs.take(sample).soa(), SCALE, 0.0, k)
+    assert_same(gi[sample], gd[sample], oi, od, "sample")
+
+
+def test_1m_points_every_point_a_query():
+    ps, qs, _, cfg = config_data("c3")
+    k = cfg["k"]
+    ix = build(ps, cfg["seg_len"])
+    q = dev_points(qs)
+    say("c3 plain")
+    pi, pd = T.tnn_query(ix, *q, SCALE, 0.0, k)
+    say("c3 mixed brute")
+    st = T.new_stats()
+    mi, md = T.tnn_query(ix, *q, SCALE, 0.0, k, flags=capi.TNN_BRUTE | capi.TNN_MIXED_BF16, stats=st)
+    torch.cuda.synchronize()
+    assert torch.equal(pi, mi) and torch.equal(pd, md)
+    s = T.stats_dict(st)
+    say("c3 mixed stats", s)
+    assert s["max_err"] > 0
+    say("c3 learned")
+    tq, _ = synth.sample_queries(ps, 100_000, 99)
+    model, _, pdist, ptr = radius.train(ix, *dev_points(tq), SCALE, 0.0, k, epochs=4, batch=4096)
+    alpha = radius.calibrate(model, *ptr, pdist, k, quantile=0.8)
+    r2 = T.tnn_radius_infer(model, *q, alpha)
+    li, ld = T.tnn_query(ix, *q, SCALE, 0.0, k, flags=capi.TNN_LEARNED, radius2=r2)
+    torch.cuda.synchronize()
+    assert torch.equal(pi, li) and torch.equal(pd, ld)
+    _sample_check(ps, qs, pi.cpu().numpy(), pd.cpu().numpy(), k)
+
+
+def test_8m_points_learned_radius_k64():
+    ps, qs, _, cfg = config_data("c4")
+    k = cfg["k"]
+    say("c4 build", ps.n)
+    ix = build(ps, cfg["seg_len"])
+    tr = ps.take(cfg["train_idx"])
+    say("c4 train")
+    model, loss, pdist, ptr = radius.train(ix, *dev_points(tr), SCALE, 0.0, k, epochs=4, batch=4096)
+    alpha = radius.calibrate(model, *ptr, pdist, k, quantile=0.8)
+    q = dev_points(qs)
+    r2 = T.tnn_radius_infer(model, *q, alpha)
+    st = T.new_stats()
+    say("c4 learned")
+    li, ld = T.tnn_query(ix, *q, SCALE, 0.0, k, flags=capi.TNN_LEARNED, radius2=r2, stats=st)
+    say("c4 plain")
+    pi, pd = T.tnn_query(ix, *q, SCALE, 0.0, k)
+    torch.cuda.synchronize()
+    assert torch.equal(pi, li) and torch.equal(pd, ld)
+    s = T.stats_dict(st)
+    say("c4 learned stats", s, "fallback rate", s["fallbacks"] / qs.n)
+    assert s["fallbacks"] < 0.5 * qs.n
+    _sample_check(ps, qs, li.cpu().numpy(), ld.cpu().numpy(), k, n=96)
