@@ -20,12 +20,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP64_VECTOR_PEAK_TFLOPS = 78.6   # MI355X: 256 CU x 64 lanes x 2.4 GHz x 2 (FMA)
+FP32_VECTOR_PEAK_TFLOPS = 157.3  # twice the binary64 rate
 HBM_PEAK_GBS = 8000.0
 
 # Algorithmic floating-point work per unit of the TNN query kernel (counted
 # from the source; FMA = 2): see the design notes.
 FLOPS_BLOCK_BOUND = 20     # float32 box distance
-FLOPS_SEG_BOUND = 39       # binary64 cylinder bound
+FLOPS_SEG_BOUND = 39       # float32 cylinder bound
 FLOPS_POINT = 15           # binary64 exact distance
 
 
@@ -141,6 +142,114 @@ def run_batched(args, T, capi, radius, synth, torch, stream):
     return out
 
 
+def run_config(name, args, T, capi, radius, synth, torch, stream):
+    """One of the other synthetic workloads: plain TNN, learned-radius TNN
+    (trained on queries disjoint from the test queries where the data allow),
+    BF16 MFMA brute force with binary64 rescoring and, where it finishes in
+    seconds, binary64 brute force.  Every path is checked against plain TNN."""
+    scale = synth.SCALE
+    ps, qs, qidx, cfg = synth.make_config(name)
+    k, K = cfg["k"], cfg["seg_len"]
+    x, y, z, t = T.to_device(ps.x, ps.y, ps.z, ps.t)
+    q = T.to_device(qs.x, qs.y, qs.z, qs.t)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ix = T.tnn_build_segments(x, y, z, t, ps.offsets, K, scale)
+    build_s = time.perf_counter() - t0
+    n = qs.n
+    out = (torch.empty((n, k), dtype=torch.int32, device="cuda"),
+           torch.empty((n, k), dtype=torch.float64, device="cuda"))
+    scratch = torch.empty(max(T.tnn_query_workspace(ix, n, T.make_params(scale, 0.0, k)), 256),
+                          dtype=torch.uint8, device="cuda")
+    steps = max(1, min(args.steps, 5))
+    res = {"points": ps.n, "queries": n, "k": k, "seg_len": K, "index_build_s": build_s}
+
+    def plain():
+        T.tnn_query(ix, *q, scale, 0.0, k, out=out, scratch=scratch)
+
+    ms = timed(plain, steps, 1, stream)
+    ref = (out[0].clone(), out[1].clone())
+    res["plain_qps"] = n / ms * 1e3
+    # learned radius
+    if "train_idx" in cfg:
+        tq = ps.take(cfg["train_idx"])
+    else:
+        n_tr = min(100_000, ps.n // 2)
+        tq, _ = synth.sample_queries(ps, n_tr, cfg["seed"] + 2000,
+                                     exclude=qidx if ps.n - n >= n_tr else None)
+    tx = T.to_device(tq.x, tq.y, tq.z, tq.t)
+    t0 = time.perf_counter()
+    model, loss, pdist, ptr = radius.train(ix, *tx, scale, 0.0, k, epochs=args.train_epochs,
+                                           batch=4096, lr=3e-3)
+    torch.cuda.synchronize()
+    res["radius_train_s"] = time.perf_counter() - t0
+    res["radius_train_queries"] = tq.n
+    r2 = torch.empty(n, dtype=torch.float32, device="cuda")
+    r2_tr = torch.empty(tq.n, dtype=torch.float32, device="cuda")
+    out_tr = (torch.empty((tq.n, k), dtype=torch.int32, device="cuda"),
+              torch.empty((tq.n, k), dtype=torch.float64, device="cuda"))
+    scr_tr = torch.empty(max(T.tnn_query_workspace(ix, tq.n, T.make_params(scale, 0.0, k)), 256),
+                         dtype=torch.uint8, device="cuda")
+    best = None
+    for qnt in (0.7, 0.8, 0.9):
+        a = radius.calibrate(model, *ptr, pdist, k, quantile=qnt)
+
+        def learned_tr():
+            T.tnn_radius_infer(model, *tx, a, out=r2_tr)
+            T.tnn_query(ix, *tx, scale, 0.0, k, flags=capi.TNN_LEARNED, radius2=r2_tr,
+                        out=out_tr, scratch=scr_tr)
+
+        m = timed(learned_tr, 2, 1, stream)
+        if best is None or m < best[0]:
+            best = (m, qnt, a)
+    alpha = best[2]
+
+    def learned():
+        T.tnn_radius_infer(model, *q, alpha, out=r2)
+        T.tnn_query(ix, *q, scale, 0.0, k, flags=capi.TNN_LEARNED, radius2=r2, out=out,
+                    scratch=scratch)
+
+    ms_l = timed(learned, steps, 1, stream)
+    st = T.new_stats()
+    T.tnn_query(ix, *q, scale, 0.0, k, flags=capi.TNN_LEARNED, radius2=r2, out=out,
+                scratch=scratch, stats=st)
+    torch.cuda.synchronize()
+    st = T.stats_dict(st)
+    res.update(learned_qps=n / ms_l * 1e3, learned_speedup_vs_plain=ms / ms_l,
+               learned_matches_plain=bool(torch.equal(out[0], ref[0])) and bool(torch.equal(out[1], ref[1])),
+               fallback_rate=st["fallbacks"] / max(n, 1), radius_quantile=best[1], radius_alpha=alpha)
+    del out_tr, scr_tr, r2_tr
+    if not args.no_brute:
+        mf = capi.TNN_BRUTE | capi.TNN_MIXED_BF16
+        mscr = torch.empty(T.tnn_query_workspace(ix, n, T.make_params(scale, 0.0, k, mf)),
+                           dtype=torch.uint8, device="cuda")
+
+        def mixed():
+            T.tnn_query(ix, *q, scale, 0.0, k, flags=mf, out=out, scratch=mscr)
+
+        ms_m = timed(mixed, 1, 1, stream)
+        mst = T.new_stats()
+        T.tnn_query(ix, *q, scale, 0.0, k, flags=mf, out=out, scratch=mscr, stats=mst)
+        torch.cuda.synchronize()
+        mst = T.stats_dict(mst)
+        res.update(mixed_brute_qps=n / ms_m * 1e3,
+                   mixed_brute_exact=bool(torch.equal(out[0], ref[0])) and bool(torch.equal(out[1], ref[1])),
+                   mixed_brute_rescored_per_query=mst["rescored"] / max(n, 1),
+                   mixed_max_abs_dist_err=mst["max_err"])
+        del mscr
+        if float(ps.n) * n <= 2e12:
+            def brute():
+                T.tnn_query(ix, *q, scale, 0.0, k, flags=capi.TNN_BRUTE, out=out, scratch=scratch)
+
+            ms_b = timed(brute, 1, 1, stream)
+            res.update(brute_qps=n / ms_b * 1e3,
+                       brute_matches_tnn=bool(torch.equal(out[0], ref[0])))
+            res["learned_speedup_vs_brute"] = ms_b / ms_l
+        res["learned_speedup_vs_mixed_brute"] = ms_m / ms_l
+    log(f"{name}:", res)
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -151,6 +260,8 @@ def main():
     ap.add_argument("--train-queries", type=int, default=100_000)
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--airspaces", type=int, default=64)
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the 10k-point, 1M-query and 8M-point workloads")
     ap.add_argument("--train-epochs", type=int, default=8)
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a 256 MiB device-to-device copy (counter calibration)")
@@ -292,12 +403,16 @@ def main():
         result_extra["mixed_brute_rescored_per_query"] = mst["rescored"] / qs.n
         result_extra["mixed_max_abs_dist_err"] = mst["max_err"]
 
-    flops = (FLOPS_BLOCK_BOUND * st["blocks"] + FLOPS_SEG_BOUND * st["segments"]
-             + FLOPS_POINT * st["points"])
+    f32 = FLOPS_BLOCK_BOUND * st["blocks"] + FLOPS_SEG_BOUND * st["segments"]
+    f64 = FLOPS_POINT * st["points"]
+    flops = f32 + f64
     achieved = flops / (ms_search * 1e-3) / 1e12
-    roofline = {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": None,
-                "kernel": "tnn_query_kernel (learned)",
+    # ALU roof of this float32/binary64 mix: the time the flops take at the
+    # two vector peaks, expressed as one rate
+    peak = flops / (f32 / FP32_VECTOR_PEAK_TFLOPS + f64 / FP64_VECTOR_PEAK_TFLOPS)
+    roofline = {"bound": "alu", "achieved": achieved, "peak": peak,
+                "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
+                "kernel": "tnn_query_lds_kernel (learned radius; the timed call also runs the per-call prep_kernel)",
                 "kernel_ms": ms_search}
     value = qs.n / ms_learned * 1e3
     res = {
@@ -318,6 +433,12 @@ def main():
         "index_build_s": build_s, "stats_learned": st, "stats_plain": st_plain,
     }
     res.update(result_extra)
+    if not args.no_configs:
+        res["configs"] = {}
+        for name, label in (("c1", "10k_points_k8"), ("c3", "1M_points_1M_queries_k32"),
+                            ("c4", "8M_points_1M_queries_k64")):
+            res["configs"][label] = run_config(name, args, T, capi, radius, synth, torch, stream)
+            torch.cuda.empty_cache()
     if not args.no_batched:
         res["batched"] = run_batched(args, T, capi, radius, synth, torch, stream)
     if not args.no_cpu_baseline:
