@@ -263,6 +263,8 @@ def main():
     ap.add_argument("--no-configs", action="store_true",
                     help="skip the 10k-point, 1M-query and 8M-point workloads")
     ap.add_argument("--train-epochs", type=int, default=8)
+    ap.add_argument("--radius-quantile", type=float, default=None,
+                    help="fixed calibration quantile (default: the fastest on the training queries)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a 256 MiB device-to-device copy (counter calibration)")
     args = ap.parse_args()
@@ -325,7 +327,8 @@ def main():
     out_tr = (torch.empty((tq.n, k), dtype=torch.int32, device="cuda"),
               torch.empty((tq.n, k), dtype=torch.float64, device="cuda"))
     best = None
-    for qnt in (0.5, 0.7, 0.8, 0.9, 0.95):
+    sweep = (0.5, 0.7, 0.8, 0.9, 0.95) if args.radius_quantile is None else (args.radius_quantile,)
+    for qnt in sweep:
         a = radius.calibrate(model, *ptr, pdist, k, quantile=qnt)
 
         def learned_tr():

@@ -129,7 +129,11 @@ tnn_status tnn_build_segments(tnn_points pts, const int64_t *h_traj_offsets, int
 tnn_status tnn_index_info(const tnn_index *index, int64_t *n_points, int64_t *n_segments,
                           int64_t *n_blocks, int32_t *seg_len);
 
-/* Scratch bytes tnn_query needs for n_queries queries with these params. */
+/* Scratch bytes tnn_query needs for n_queries queries with these params:
+ * the per-call segment constants that depend on the scales, and the
+ * counters of the search's work queues (both written by tnn_query itself, so
+ * the buffer needs no initialisation, but two calls in flight at once must
+ * not share it). */
 tnn_status tnn_query_workspace(const tnn_index *index, int64_t n_queries,
                                const tnn_query_params *params, size_t *bytes);
 

@@ -138,7 +138,8 @@ QueryArgs make_args(const tnn_query_params *p) {
   return a;
 }
 
-size_t prep_bytes(int64_t S) { return 3 * align_up(4 * (size_t)S); }
+// three float arrays of S, then 16 work-queue counters 256 bytes apart
+size_t prep_bytes(int64_t S) { return 3 * align_up(4 * (size_t)S) + 16 * 256; }
 
 Prep prep_view(void *scratch, int64_t S) {
   char *b = static_cast<char *>(scratch);
@@ -147,6 +148,7 @@ Prep prep_view(void *scratch, int64_t S) {
   p.inv_n2 = reinterpret_cast<const float *>(b);
   p.rad = reinterpret_cast<const float *>(b + one);
   p.slack = reinterpret_cast<const float *>(b + 2 * one);
+  p.ticket = reinterpret_cast<unsigned long long *>(b + 3 * one);
   return p;
 }
 

@@ -11,6 +11,20 @@ constexpr size_t kLdsBoxBytes = 48 * 1024;  // stage block boxes in LDS up to th
 #ifndef TNN_QUERY_MIN_WAVES
 #define TNN_QUERY_MIN_WAVES 1
 #endif
+#ifndef TNN_QUERY_QUEUES
+#define TNN_QUERY_QUEUES 8
+#endif
+// Queries a wave takes from a work queue at a time (0: fixed grid stride).
+#ifndef TNN_QUERY_CHUNK
+#define TNN_QUERY_CHUNK 2
+#endif
+// The queries are split into kQueues contiguous slices with one counter
+// each (one counter for all would serialise the atomics); a workgroup starts
+// on the slice of its accelerator die (dispatch is round-robin over the 8
+// dies) and moves on to the next slice once its own is used up.
+constexpr int kQueues = TNN_QUERY_QUEUES;
+constexpr int kTicketStride = 32;  // counters 256 bytes apart
+static_assert(kQueues >= 1 && kQueues <= 16, "the query workspace holds 16 counters");
 
 // ---------------------------------------------------------------------------
 // Per-call preparation (depends on the scales): 1/|AB|_s^2, the radius
@@ -35,8 +49,11 @@ __device__ __forceinline__ void prep_one(const IndexDesc &ix, const QueryArgs &a
   slack[s] = __double2float_ru(0x1p-17 * (nt + sqrt(n2)) * 0.5 * (1.0 + 0x1p-30));
 }
 
-__global__ void prep_kernel(IndexDesc ix, QueryArgs a, float *inv_n2, float *rad, float *slack) {
+__global__ void prep_kernel(IndexDesc ix, QueryArgs a, float *inv_n2, float *rad, float *slack,
+                            unsigned long long *ticket) {
   const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  // the search kernel that follows starts its queues at 0
+  if (s < kQueues && ticket) ticket[s * kTicketStride] = 0;
   if (s >= ix.n_seg) return;
   prep_one(ix, a, inv_n2, rad, slack, s);
 }
@@ -312,8 +329,9 @@ __global__ __launch_bounds__(512) void tnn_query_kernel(IndexDesc ix, Prep pr, Q
 }
 
 // Same search with the block boxes staged once per workgroup in LDS (small
-// indexes): the workgroup stays resident and its waves walk the queries with
-// a grid stride.
+// indexes): the grid is exactly what stays resident, and each wave takes
+// TNN_QUERY_CHUNK queries at a time from a counter (query costs vary by
+// orders of magnitude, so a fixed share per wave leaves a long tail).
 __global__ __launch_bounds__(512, TNN_QUERY_MIN_WAVES) void tnn_query_lds_kernel(IndexDesc ix, Prep pr, QueryArgs a,
                                                             const float *qx, const float *qy,
                                                             const float *qz, const float *qt,
@@ -327,11 +345,30 @@ __global__ __launch_bounds__(512, TNN_QUERY_MIN_WAVES) void tnn_query_lds_kernel
   for (int i = threadIdx.x; i < nbox; i += blockDim.x) s_box[nsbox + i] = ix.box[i];
   __syncthreads();
   const float *box = boxes_in_lds ? s_box + nsbox : ix.box;
+#if TNN_QUERY_CHUNK > 0
+  const int lane = lane_id();
+  const int first = (int)(blockIdx.x % kQueues);
+  for (int j = 0; j < kQueues; ++j) {
+    const int qn = (first + j) % kQueues;
+    const int64_t lo = nq * qn / kQueues, hi = nq * (qn + 1) / kQueues;
+    unsigned long long *ctr = pr.ticket + qn * kTicketStride;
+    for (;;) {
+      unsigned long long b = 0;
+      if (lane == 0) b = atomicAdd(ctr, (unsigned long long)TNN_QUERY_CHUNK);
+      const int64_t base = lo + (int64_t)uniform_u64(b);
+      if (base >= hi) break;
+      const int64_t end = base + TNN_QUERY_CHUNK < hi ? base + TNN_QUERY_CHUNK : hi;
+      for (int64_t qi = base; qi < end; ++qi)
+        answer_query(ix, pr, a, qx, qy, qz, qt, qi, out_idx, out_dist, box, s_box);
+    }
+  }
+#else
   const int wpb = blockDim.x >> 6;
   const int64_t stride = (int64_t)gridDim.x * wpb;
   for (int64_t qi = (int64_t)blockIdx.x * wpb + uniform_i((int)(threadIdx.x >> 6)); qi < nq;
        qi += stride)
     answer_query(ix, pr, a, qx, qy, qz, qt, qi, out_idx, out_dist, box, s_box);
+#endif
 }
 
 // ---------------------------------------------------------------------------
@@ -494,12 +531,11 @@ hipError_t launch_batch(const BatchLaunch &bl, hipStream_t st) {
 // Host launchers.
 // ---------------------------------------------------------------------------
 hipError_t launch_prep(const IndexDesc &ix, const QueryArgs &a, const Prep &pr, hipStream_t st) {
-  if (ix.n_seg == 0) return hipSuccess;
   const int tpb = 256;
-  const int64_t grid = (ix.n_seg + tpb - 1) / tpb;
+  const int64_t grid = ix.n_seg > 0 ? (ix.n_seg + tpb - 1) / tpb : 1;
   hipLaunchKernelGGL(prep_kernel, dim3((unsigned)grid), dim3(tpb), 0, st, ix, a,
                      const_cast<float *>(pr.inv_n2), const_cast<float *>(pr.rad),
-                     const_cast<float *>(pr.slack));
+                     const_cast<float *>(pr.slack), pr.ticket);
   return hipGetLastError();
 }
 
@@ -526,7 +562,12 @@ hipError_t launch_query(const IndexDesc &ix, const Prep &pr, const QueryArgs &a,
   if (sl <= kLdsBoxBytes) {
     const int in_lds = sl + bl <= kLdsBoxBytes ? 1 : 0;
     const size_t lds = in_lds ? sl + bl : sl;
-    const int64_t resident = (int64_t)cu_count() * (32 / waves_per_block);
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, tnn_query_lds_kernel,
+                                                     waves_per_block * kWave, lds) != hipSuccess ||
+        per_cu <= 0)
+      per_cu = 1;
+    const int64_t resident = (int64_t)cu_count() * per_cu;
     const int64_t g = grid < resident ? grid : resident;
     hipLaunchKernelGGL(tnn_query_lds_kernel, dim3((unsigned)g), dim3(waves_per_block * kWave), lds,
                        st, ix, pr, a, qs.x, qs.y, qs.z, qs.t, qs.n, out_idx, out_dist, in_lds);

@@ -43,6 +43,7 @@ struct Prep {
   const float *inv_n2;  // 1 / |AB|_s^2, 0 for a degenerate segment
   const float *rad;     // radius R(s) = sqrt(sum s_f e_f^2), rounded up
   const float *slack;   // absolute slack for the float32 bound, 2^-17 |AB|_s rounded up
+  unsigned long long *ticket;  // work-queue counter of the resident search kernel
 };
 
 struct QueryArgs {
