@@ -14,7 +14,7 @@ using namespace tnn;
 namespace {
 
 struct BuildLayout {
-  size_t px, py, pz, pt, pid;                  // index-order points
+  size_t pt4, pid;                             // index-order points
   size_t f[11], pstart, pcount, sorig;          // index-order segments
   size_t box, sbox;                             // block and superblock boxes
   size_t tf[11], tstart, tcf, keys, perm, dpstart, status;  // build temporaries
@@ -30,10 +30,7 @@ BuildLayout build_layout(int64_t n, int64_t S) {
     return r;
   };
   const int64_t nb = (S + kBlockSegs - 1) / kBlockSegs;
-  L.px = take(4 * n);
-  L.py = take(4 * n);
-  L.pz = take(4 * n);
-  L.pt = take(4 * n);
+  L.pt4 = take(16 * n);
   L.pid = take(4 * n);
   for (int i = 0; i < 11; ++i) L.f[i] = take(4 * S);
   L.pstart = take(4 * S);
@@ -138,17 +135,14 @@ QueryArgs make_args(const tnn_query_params *p) {
   return a;
 }
 
-// three float arrays of S, then 16 work-queue counters 256 bytes apart
-size_t prep_bytes(int64_t S) { return 3 * align_up(4 * (size_t)S) + 16 * 256; }
+// kSegRec float4 per segment, then 16 work-queue counters 256 bytes apart
+size_t prep_bytes(int64_t S) { return align_up(16 * kSegRec * (size_t)S) + 16 * 256; }
 
 Prep prep_view(void *scratch, int64_t S) {
   char *b = static_cast<char *>(scratch);
-  const size_t one = align_up(4 * (size_t)S);
   Prep p;
-  p.inv_n2 = reinterpret_cast<const float *>(b);
-  p.rad = reinterpret_cast<const float *>(b + one);
-  p.slack = reinterpret_cast<const float *>(b + 2 * one);
-  p.ticket = reinterpret_cast<unsigned long long *>(b + 3 * one);
+  p.rec = reinterpret_cast<float4 *>(b);
+  p.ticket = reinterpret_cast<unsigned long long *>(b + align_up(16 * kSegRec * (size_t)S));
   return p;
 }
 
@@ -266,8 +260,8 @@ tnn_status tnn_build_segments(tnn_points pts, const int64_t *h_traj_offsets, int
     dst_f[i] = F(L.f[i]);
   }
   TNN_HIP_CHECK(launch_seg_scatter(pts, S, I(L.perm), I(L.tstart), I(L.tcf), I(L.dpstart), src_f,
-                                   dst_f, I(L.pstart), I(L.pcount), I(L.sorig), F(L.px), F(L.py),
-                                   F(L.pz), F(L.pt), I(L.pid), st));
+                                   dst_f, I(L.pstart), I(L.pcount), I(L.sorig),
+                                   reinterpret_cast<float4 *>(F(L.pt4)), I(L.pid), st));
 
   IndexDesc d;
   std::memset(&d, 0, sizeof(d));
@@ -279,10 +273,7 @@ tnn_status tnn_build_segments(tnn_points pts, const int64_t *h_traj_offsets, int
   d.n_blocks = (int32_t)nb;
   d.n_points = n;
   d.n_seg = S;
-  d.px = F(L.px);
-  d.py = F(L.py);
-  d.pz = F(L.pz);
-  d.pt = F(L.pt);
+  d.pt4 = reinterpret_cast<const float4 *>(F(L.pt4));
   d.pid = I(L.pid);
   d.ax = F(L.f[0]);
   d.ay = F(L.f[1]);
@@ -310,11 +301,11 @@ tnn_status tnn_build_segments(tnn_points pts, const int64_t *h_traj_offsets, int
     for (int f = 0; f < 4; ++f) {
       float lo = INFINITY, hi = -INFINITY;
       for (int64_t b = sb * kSuperBlocks; b < std::min<int64_t>(nb, (sb + 1) * kSuperBlocks); ++b) {
-        lo = std::min(lo, box[f * nb + b]);
-        hi = std::max(hi, box[(4 + f) * nb + b]);
+        lo = std::min(lo, box[8 * b + f]);
+        hi = std::max(hi, box[8 * b + 4 + f]);
       }
-      sbox[f * ns + sb] = lo;
-      sbox[(4 + f) * ns + sb] = hi;
+      sbox[8 * sb + f] = lo;
+      sbox[8 * sb + 4 + f] = hi;
     }
   if (ns > 0) {
     TNN_HIP_CHECK(hipMemcpyAsync(F(L.sbox), sbox.data(), 32 * ns, hipMemcpyHostToDevice, st));
@@ -328,8 +319,8 @@ tnn_status tnn_build_segments(tnn_points pts, const int64_t *h_traj_offsets, int
     if (nb == 0) continue;
     float lo = INFINITY, hi = -INFINITY;
     for (int64_t b = 0; b < nb; ++b) {
-      lo = std::min(lo, box[f * nb + b]);
-      hi = std::max(hi, box[(4 + f) * nb + b]);
+      lo = std::min(lo, box[8 * b + f]);
+      hi = std::max(hi, box[8 * b + 4 + f]);
     }
     d.lo[f] = lo;
     d.hi[f] = hi;

@@ -55,26 +55,37 @@ __device__ __forceinline__ QueryPoint make_query(float x, float y, float z, floa
 // Lower bound from a query to every point of block b: scaled squared
 // distance to the block's (x, y, z, t) bounding box.  +inf when no point of
 // the block is early enough.
-// `box` is the index's box array box[f * nb + b] in global memory or a copy
-// of it in LDS.
-__device__ __forceinline__ float block_lb(const float *box, int nb, int b, const QueryPoint &q,
+// `box` is the index's box array (box[8 b + f]) in global memory or a copy of
+// it in LDS.
+__device__ __forceinline__ float block_lb(const float *box, int b, const QueryPoint &q,
                                           const float sf[4]) {
-  const float lt = box[3 * nb + b];
-  if ((double)lt >= q.thr) return __builtin_huge_valf();
-  const float lx = box[b], ly = box[nb + b], lz = box[2 * nb + b];
-  const float hx = box[4 * nb + b], hy = box[5 * nb + b], hz = box[6 * nb + b];
-  const float ht = box[7 * nb + b];
-  const float gx = fmaxf(fmaxf(lx - q.x, q.x - hx), 0.0f);
-  const float gy = fmaxf(fmaxf(ly - q.y, q.y - hy), 0.0f);
-  const float gz = fmaxf(fmaxf(lz - q.z, q.z - hz), 0.0f);
-  const float gt = fmaxf(fmaxf(q.t - ht, q.gwf), 0.0f);
+  const float4 lo = reinterpret_cast<const float4 *>(box)[2 * b];
+  const float4 hi = reinterpret_cast<const float4 *>(box)[2 * b + 1];
+  if ((double)lo.w >= q.thr) return __builtin_huge_valf();
+  const float gx = fmaxf(fmaxf(lo.x - q.x, q.x - hi.x), 0.0f);
+  const float gy = fmaxf(fmaxf(lo.y - q.y, q.y - hi.y), 0.0f);
+  const float gz = fmaxf(fmaxf(lo.z - q.z, q.z - hi.z), 0.0f);
+  const float gt = fmaxf(fmaxf(q.t - hi.w, q.gwf), 0.0f);
   const float v = sf[0] * (gx * gx) + sf[1] * (gy * gy) + sf[2] * (gz * gz) + sf[3] * (gt * gt);
   return v * (1.0f - 0x1p-18f);
 }
 
-__device__ __forceinline__ float block_lb(const IndexDesc &ix, int b, const QueryPoint &q,
-                                          const float sf[4]) {
-  return block_lb(ix.box, ix.n_blocks, b, q, sf);
+// A segment's record as the search reads it.
+struct SegView {
+  float4 r0, r1, r2;
+  int ps, pc;  // first point slot, member count
+};
+
+__device__ __forceinline__ SegView load_seg(const Prep &pr, int64_t s) {
+  const float4 *r = pr.rec + kSegRec * s;
+  SegView v;
+  v.r0 = r[0];
+  v.r1 = r[1];
+  v.r2 = r[2];
+  const float4 r3 = r[3];
+  v.ps = __float_as_int(r3.x);
+  v.pc = __float_as_int(r3.y);
+  return v;
 }
 
 // Cylinder lower bound (Sec. 3.4 masked distance minus approximation error,
@@ -87,20 +98,17 @@ __device__ __forceinline__ float block_lb(const IndexDesc &ix, int b, const Quer
 // the (1 - 2^-18) factor and the 2^-17 |AB|_s slack remove; the scales are
 // rounded toward zero, R is rounded up, and the final (1 - 2^-20) factor
 // covers the remaining float32 roundings.
-__device__ __forceinline__ float seg_lb(const IndexDesc &ix, const Prep &pr, int64_t s,
-                                        const QueryPoint &q, const float sf[4]) {
-  const float tmin = ix.tmin[s];
-  if ((double)tmin >= q.thr) return __builtin_huge_valf();
-  const float ax = ix.ax[s], ay = ix.ay[s], az = ix.az[s];
-  const float abx = ix.bx[s] - ax, aby = ix.by[s] - ay, abz = ix.bz[s] - az;
-  const float apx = q.x - ax, apy = q.y - ay, apz = q.z - az;
+__device__ __forceinline__ float seg_lb(const SegView &v, const QueryPoint &q, const float sf[4]) {
+  if ((double)v.r0.w >= q.thr) return __builtin_huge_valf();
+  const float abx = v.r1.x, aby = v.r1.y, abz = v.r1.z;
+  const float apx = q.x - v.r0.x, apy = q.y - v.r0.y, apz = q.z - v.r0.z;
   const float dot = sf[0] * (apx * abx) + sf[1] * (apy * aby) + sf[2] * (apz * abz);
-  const float del = fminf(fmaxf(dot * pr.inv_n2[s], 0.0f), 1.0f);
+  const float del = fminf(fmaxf(dot * v.r2.x, 0.0f), 1.0f);
   const float rx = apx - del * abx, ry = apy - del * aby, rz = apz - del * abz;
   const float d2 = sf[0] * (rx * rx) + sf[1] * (ry * ry) + sf[2] * (rz * rz);
-  const float dlo = sqrtf(d2) * (1.0f - 0x1p-18f) - pr.slack[s];
-  const float g = fmaxf(dlo - pr.rad[s], 0.0f);
-  const float gt = fmaxf(fmaxf(q.t - ix.tmax[s], q.gwf), 0.0f);
+  const float dlo = sqrtf(d2) * (1.0f - 0x1p-18f) - v.r2.z;
+  const float g = fmaxf(dlo - v.r2.y, 0.0f);
+  const float gt = fmaxf(fmaxf(q.t - v.r1.w, q.gwf), 0.0f);
   return (g * g + sf[3] * (gt * gt)) * (1.0f - 0x1p-20f);
 }
 

@@ -83,7 +83,7 @@ __global__ void seg_scatter_kernel(tnn_points pts, int64_t n_seg, const int32_t 
                                    const int32_t *src_start, const int32_t *src_cf,
                                    const int32_t *dst_pstart, F11 src, F11w dst,
                                    int32_t *out_pstart, int32_t *out_pcount, int32_t *out_sorig,
-                                   float *px, float *py, float *pz, float *pt, int32_t *pid) {
+                                   float4 *pt4, int32_t *pid) {
   const int64_t j = blockIdx.x;
   if (j >= n_seg) return;
   const int o = perm[j];
@@ -92,10 +92,7 @@ __global__ void seg_scatter_kernel(tnn_points pts, int64_t n_seg, const int32_t 
   const int d0 = dst_pstart[j];
   const int t = threadIdx.x;
   if (t < c) {
-    px[d0 + t] = pts.x[p0 + t];
-    py[d0 + t] = pts.y[p0 + t];
-    pz[d0 + t] = pts.z[p0 + t];
-    pt[d0 + t] = pts.t[p0 + t];
+    pt4[d0 + t] = make_float4(pts.x[p0 + t], pts.y[p0 + t], pts.z[p0 + t], pts.t[p0 + t]);
     pid[d0 + t] = p0 + t;
   }
   if (t < 11) dst.p[t][j] = src.p[t][o];
@@ -120,7 +117,8 @@ __global__ void block_box_kernel(IndexDesc ix, float *box) {
   if (s < ix.n_seg) {
     const int ps = ix.pstart[s], pc = ix.pcount[s];
     for (int i = 0; i < pc; ++i) {
-      const float v[4] = {ix.px[ps + i], ix.py[ps + i], ix.pz[ps + i], ix.pt[ps + i]};
+      const float4 p = ix.pt4[ps + i];
+      const float v[4] = {p.x, p.y, p.z, p.w};
 #pragma unroll
       for (int f = 0; f < 4; ++f) {
         lo[f] = fminf(lo[f], v[f]);
@@ -137,11 +135,10 @@ __global__ void block_box_kernel(IndexDesc ix, float *box) {
     }
   }
   if (lane == 0) {
-    const int nb = ix.n_blocks;
 #pragma unroll
     for (int f = 0; f < 4; ++f) {
-      box[f * nb + b] = lo[f];
-      box[(4 + f) * nb + b] = hi[f];
+      box[8 * b + f] = lo[f];
+      box[8 * b + 4 + f] = hi[f];
     }
   }
 }
@@ -175,7 +172,7 @@ __global__ void export_kernel(IndexDesc ix, float *seg_f32, int32_t *seg_i32, in
   }
   if (point_id && i < ix.n_points) point_id[i] = ix.pid[i];
   if (block_box && i < ix.n_blocks) {
-    for (int f = 0; f < 8; ++f) block_box[8 * i + f] = ix.box[f * ix.n_blocks + i];
+    for (int f = 0; f < 8; ++f) block_box[8 * i + f] = ix.box[8 * i + f];
   }
 }
 
@@ -195,8 +192,7 @@ hipError_t launch_seg_scatter(const tnn_points &pts, int64_t n_seg, const int32_
                               const int32_t *src_start, const int32_t *src_cnt_flags,
                               const int32_t *dst_pstart, const float *const src_f[11],
                               float *const dst_f[11], int32_t *dst_pstart_out, int32_t *dst_pcount,
-                              int32_t *dst_sorig, float *px, float *py, float *pz, float *pt,
-                              int32_t *pid, hipStream_t st) {
+                              int32_t *dst_sorig, float4 *pt4, int32_t *pid, hipStream_t st) {
   if (n_seg == 0) return hipSuccess;
   F11 src;
   F11w dst;
@@ -206,7 +202,7 @@ hipError_t launch_seg_scatter(const tnn_points &pts, int64_t n_seg, const int32_
   }
   hipLaunchKernelGGL(seg_scatter_kernel, dim3((unsigned)n_seg), dim3(kWave), 0, st, pts, n_seg, perm,
                      src_start, src_cnt_flags, dst_pstart, src, dst, dst_pstart_out, dst_pcount,
-                     dst_sorig, px, py, pz, pt, pid);
+                     dst_sorig, pt4, pid);
   return hipGetLastError();
 }
 

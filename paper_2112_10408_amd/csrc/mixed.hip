@@ -148,12 +148,15 @@ __device__ __forceinline__ bf16x8 query_group(const float u[4], float nus, int g
 }
 
 // Per call: the point operands in index order (4 groups of 8 bf16 per
-// point, 64 bytes) and |v|^2.
-__global__ void mixed_prep_kernel(IndexDesc ix, MixedCtx mc, bf16x8 *ops, float *nv) {
+// point, 64 bytes), |v|^2 and a copy of the times (read densely by the
+// distance tiles).
+__global__ void mixed_prep_kernel(IndexDesc ix, MixedCtx mc, bf16x8 *ops, float *nv, float *tv) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= ix.n_points) return;
   float v[4];
-  const float n = scaled(mc, ix.px[p], ix.py[p], ix.pz[p], ix.pt[p], v);
+  const float4 pv = ix.pt4[p];
+  tv[p] = pv.w;
+  const float n = scaled(mc, pv.x, pv.y, pv.z, pv.w, v);
   const float ns = (1.0f - kGamma) * n;
 #pragma unroll
   for (int g = 0; g < 4; ++g) ops[4 * p + g] = point_group(v, ns, g);
@@ -169,7 +172,8 @@ __device__ __forceinline__ float round_up_f(double x) {
 // 16-column MFMA tiles); no workgroup barrier is needed.  Per-query state in
 // LDS: the top-k (k entries) and a candidate queue of one step's points.
 __global__ __launch_bounds__(64) void mixed_brute_kernel(
-    IndexDesc ix, QueryArgs a, MixedCtx mc, const bf16x8 *ops, const float *nv, const float *qxp,
+    IndexDesc ix, QueryArgs a, MixedCtx mc, const bf16x8 *ops, const float *nv, const float *tv,
+    const float *qxp,
     const float *qyp, const float *qzp, const float *qtp, int64_t nq, int32_t *out_idx,
     double *out_dist, int64_t tile_stride) {
   extern __shared__ double s_dyn[];
@@ -235,7 +239,7 @@ __global__ __launch_bounds__(64) void mixed_brute_kernel(
       float t = __builtin_huge_valf();
       if (p < n) {
         v = ops[4 * p + g];
-        t = ix.pt[p];
+        t = tv[p];
       }
       bop[cb] = v;
       pts[cb] = t;
@@ -271,8 +275,9 @@ __global__ __launch_bounds__(64) void mixed_brute_kernel(
       int pid = kNoId;
       bool valid = false;
       if (has) {
-        const float pt = ix.pt[p];
-        d = exact_dist(a.s, qp.x, qp.y, qp.z, qp.t, ix.px[p], ix.py[p], ix.pz[p], pt);
+        const float4 pv = ix.pt4[p];
+        const float pt = pv.w;
+        d = exact_dist(a.s, qp.x, qp.y, qp.z, qp.t, pv.x, pv.y, pv.z, pt);
         pid = ix.pid[p];
         valid = (double)pt < qp.thr;
         const double approx = (double)s_qc[m * kStep + lane] +
@@ -326,7 +331,7 @@ __global__ __launch_bounds__(64) void mixed_brute_kernel(
 }  // namespace
 
 size_t mixed_scratch_bytes(int64_t n_points) {
-  return align_up((size_t)n_points * 64) + align_up((size_t)n_points * 4);
+  return align_up((size_t)n_points * 64) + 2 * align_up((size_t)n_points * 4);
 }
 
 MixedCtx make_ctx(const IndexDesc &ix, const QueryArgs &a) {
@@ -345,9 +350,11 @@ hipError_t launch_mixed_brute(const IndexDesc &ix, const QueryArgs &a, const tnn
   bf16x8 *ops = static_cast<bf16x8 *>(scratch);
   float *nv = reinterpret_cast<float *>(static_cast<char *>(scratch) +
                                         align_up((size_t)ix.n_points * 64));
+  float *tv = reinterpret_cast<float *>(reinterpret_cast<char *>(nv) +
+                                        align_up((size_t)ix.n_points * 4));
   if (ix.n_points > 0) {
     hipLaunchKernelGGL(mixed_prep_kernel, dim3((unsigned)((ix.n_points + 255) / 256)), dim3(256), 0,
-                       st, ix, mc, ops, nv);
+                       st, ix, mc, ops, nv, tv);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -367,7 +374,7 @@ hipError_t launch_mixed_brute(const IndexDesc &ix, const QueryArgs &a, const tnn
   }
   const size_t lds = (size_t)kMQ * a.k * 12 + (size_t)kMQ * kStep * 8 + (size_t)kMQ * 16;
   hipLaunchKernelGGL(mixed_brute_kernel, dim3((unsigned)((qs.n + kMQ - 1) / kMQ)), dim3(64), lds,
-                     st, ix, a, mc, ops, nv, qs.x, qs.y, qs.z, qs.t, qs.n, out_idx, out_dist,
+                     st, ix, a, mc, ops, nv, tv, qs.x, qs.y, qs.z, qs.t, qs.n, out_idx, out_dist,
                      stride);
   return hipGetLastError();
 }

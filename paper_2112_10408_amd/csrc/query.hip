@@ -27,35 +27,41 @@ constexpr int kTicketStride = 32;  // counters 256 bytes apart
 static_assert(kQueues >= 1 && kQueues <= 16, "the query workspace holds 16 counters");
 
 // ---------------------------------------------------------------------------
-// Per-call preparation (depends on the scales): 1/|AB|_s^2, the radius
-// R = sqrt(sum_f s_f e_f^2) rounded up, and the projection slack.
+// Per-call preparation (depends on the scales): the segment records the
+// search reads, with 1/|AB|_s^2, the radius R = sqrt(sum_f s_f e_f^2) rounded
+// up, and the projection slack.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void prep_one(const IndexDesc &ix, const QueryArgs &a, float *inv_n2,
-                                         float *rad, float *slack, int64_t s) {
+__device__ __forceinline__ void prep_one(const IndexDesc &ix, const QueryArgs &a, float4 *rec,
+                                         int64_t s) {
+  const float ax = ix.ax[s], ay = ix.ay[s], az = ix.az[s];
+  const float bx = ix.bx[s], by = ix.by[s], bz = ix.bz[s];
   // AB as the bound computes it (float32 differences), norms in binary64
-  const double abx = (double)(ix.bx[s] - ix.ax[s]);
-  const double aby = (double)(ix.by[s] - ix.ay[s]);
-  const double abz = (double)(ix.bz[s] - ix.az[s]);
+  const float fx = bx - ax, fy = by - ay, fz = bz - az;
+  const double abx = (double)fx, aby = (double)fy, abz = (double)fz;
   const double n2 = a.s[0] * abx * abx + a.s[1] * aby * aby + a.s[2] * abz * abz;
-  inv_n2[s] = n2 > 0.0 ? (float)(1.0 / n2) : 0.0f;
+  const float inv_n2 = n2 > 0.0 ? (float)(1.0 / n2) : 0.0f;
   const double ex = ix.ex[s], ey = ix.ey[s], ez = ix.ez[s];
-  rad[s] = __double2float_ru(sqrt(a.s[0] * ex * ex + a.s[1] * ey * ey + a.s[2] * ez * ez) *
-                             (1.0 + 0x1p-40));
+  const float rad = __double2float_ru(sqrt(a.s[0] * ex * ex + a.s[1] * ey * ey + a.s[2] * ez * ez) *
+                                      (1.0 + 0x1p-40));
   // exact AB and its norm bound the float32 errors of the bound
-  const double tx = (double)ix.bx[s] - (double)ix.ax[s];
-  const double ty = (double)ix.by[s] - (double)ix.ay[s];
-  const double tz = (double)ix.bz[s] - (double)ix.az[s];
+  const double tx = (double)bx - (double)ax;
+  const double ty = (double)by - (double)ay;
+  const double tz = (double)bz - (double)az;
   const double nt = sqrt(a.s[0] * tx * tx + a.s[1] * ty * ty + a.s[2] * tz * tz);
-  slack[s] = __double2float_ru(0x1p-17 * (nt + sqrt(n2)) * 0.5 * (1.0 + 0x1p-30));
+  const float slack = __double2float_ru(0x1p-17 * (nt + sqrt(n2)) * 0.5 * (1.0 + 0x1p-30));
+  float4 *r = rec + kSegRec * s;
+  r[0] = make_float4(ax, ay, az, ix.tmin[s]);
+  r[1] = make_float4(fx, fy, fz, ix.tmax[s]);
+  r[2] = make_float4(inv_n2, rad, slack, 0.0f);
+  r[3] = make_float4(__int_as_float(ix.pstart[s]), __int_as_float(ix.pcount[s]), 0.0f, 0.0f);
 }
 
-__global__ void prep_kernel(IndexDesc ix, QueryArgs a, float *inv_n2, float *rad, float *slack,
-                            unsigned long long *ticket) {
+__global__ void prep_kernel(IndexDesc ix, QueryArgs a, float4 *rec, unsigned long long *ticket) {
   const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   // the search kernel that follows starts its queues at 0
   if (s < kQueues && ticket) ticket[s * kTicketStride] = 0;
   if (s >= ix.n_seg) return;
-  prep_one(ix, a, inv_n2, rad, slack, s);
+  prep_one(ix, a, rec, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -104,17 +110,14 @@ struct Searcher {
       const int pc = has ? pc_src : 0;
       const bool ok = has && off < pc;
       const int p = ps + off;
-      float px = 0.f, py = 0.f, pz = 0.f, pt = 0.f;
+      float4 pv = make_float4(0.f, 0.f, 0.f, 0.f);
       int pid = kNoId;
       if (ok) {
-        px = ix.px[p];
-        py = ix.py[p];
-        pz = ix.pz[p];
-        pt = ix.pt[p];
+        pv = ix.pt4[p];
         pid = ix.pid[p];
       }
-      const double d = exact_dist(a.s, q.x, q.y, q.z, q.t, px, py, pz, pt);
-      const bool valid = ok && (double)pt < q.thr;
+      const double d = exact_dist(a.s, q.x, q.y, q.z, q.t, pv.x, pv.y, pv.z, pv.w);
+      const bool valid = ok && (double)pv.w < q.thr;
       st.points += (uint32_t)__popcll(ballot(ok));
       const bool gate = valid && tk.admits(d, pid);
       const uint64_t gm = ballot(gate);
@@ -140,7 +143,7 @@ struct Searcher {
     // superblock level: 64 superblock bounds per pass
     for (int sbase = 0; sbase < ns; sbase += kWave) {
       const int sb = sbase + lane;
-      const float lbs = sb < ns ? block_lb(sbox, ns, sb, q, a.sf) : finf;
+      const float lbs = sb < ns ? block_lb(sbox, sb, q, a.sf) : finf;
       st.blocks += (uint32_t)min(kWave, ns - sbase);
       if (lbs < finf) maxfin = fmaxf(maxfin, lbs);
       uint64_t ms = ballot(lbs < finf && (double)lbs <= fmin(tau, tk.kd));
@@ -151,7 +154,7 @@ struct Searcher {
         // block level: the superblock's 64 blocks, one per lane
         const int b0 = (sbase + sl) * kSuperBlocks;
         const int b = b0 + lane;
-        const float lbb = b < nb ? block_lb(box, nb, b, q, a.sf) : finf;
+        const float lbb = b < nb ? block_lb(box, b, q, a.sf) : finf;
         st.blocks += (uint32_t)min(kSuperBlocks, nb - b0);
         if (lbb < finf) maxfin = fmaxf(maxfin, lbb);
         uint64_t m = ballot(lbb < finf && (double)lbb <= fmin(tau, tk.kd));
@@ -163,10 +166,11 @@ struct Searcher {
           if (lbb_b > tau_cur) continue;
           const int bb = b0 + bl;
           const int64_t s = (int64_t)bb * kBlockSegs + lane;
-          const int ps_l = s < S ? ix.pstart[s] : 0;
-          const int pc_l = s < S ? ix.pcount[s] : 0;
+          SegView sv{};
+          if (s < S) sv = load_seg(pr, s);
+          const int ps_l = sv.ps, pc_l = sv.pc;
           // both bounds hold for every member; the larger one decides the round
-          const double key = fmax(s < S ? (double)seg_lb(ix, pr, s, q, a.sf) : kInf, lbb_b);
+          const double key = fmax(s < S ? (double)seg_lb(sv, q, a.sf) : kInf, lbb_b);
           st.segs += (uint32_t)min((int64_t)kBlockSegs, S - (int64_t)bb * kBlockSegs);
           const bool seeded = bb == seed_block && ((seed_mask >> lane) & 1ull);
           // a masked segment (infinite key) holds no candidate
@@ -241,7 +245,7 @@ __device__ __forceinline__ void answer_query(const IndexDesc &ix, const Prep &pr
       const int ns = ix.n_super;
       for (int sbase = 0; sbase < ns; sbase += kWave) {
         const int sb = sbase + se.lane;
-        float lbs = sb < ns ? block_lb(se.sbox, ns, sb, se.q, a.sf) : __builtin_huge_valf();
+        float lbs = sb < ns ? block_lb(se.sbox, sb, se.q, a.sf) : __builtin_huge_valf();
         se.st.blocks += (uint32_t)min(kWave, ns - sbase);
         for (;;) {
           float v = lbs;
@@ -251,7 +255,7 @@ __device__ __forceinline__ void answer_query(const IndexDesc &ix, const Prep &pr
           if (se.lane == vl) lbs = __builtin_huge_valf();
           const int b0 = (sbase + vl) * kSuperBlocks;
           const int b = b0 + se.lane;
-          float bv = b < nb ? block_lb(se.box, nb, b, se.q, a.sf) : __builtin_huge_valf();
+          float bv = b < nb ? block_lb(se.box, b, se.q, a.sf) : __builtin_huge_valf();
           int bi = b < nb ? b : kNoId;
           se.st.blocks += (uint32_t)min(kSuperBlocks, nb - b0);
           wave_argmin_f(bv, bi);
@@ -270,9 +274,10 @@ __device__ __forceinline__ void answer_query(const IndexDesc &ix, const Prep &pr
     seed_block = bestb;
     {
       const int64_t s = (int64_t)bestb * kBlockSegs + se.lane;
-      const int ps_l = s < S ? ix.pstart[s] : 0;
-      const int pc_l = s < S ? ix.pcount[s] : 0;
-      double v = s < S ? (double)seg_lb(ix, pr, s, se.q, a.sf) : kInf;
+      SegView sv{};
+      if (s < S) sv = load_seg(pr, s);
+      const int ps_l = sv.ps, pc_l = sv.pc;
+      double v = s < S ? (double)seg_lb(sv, se.q, a.sf) : kInf;
       se.st.segs += (uint32_t)min((int64_t)kBlockSegs, S - (int64_t)bestb * kBlockSegs);
       const int F = a.seed_segments;
       for (int i = 0; i < F; ++i) {
@@ -337,14 +342,17 @@ __global__ __launch_bounds__(512, TNN_QUERY_MIN_WAVES) void tnn_query_lds_kernel
                                                             const float *qz, const float *qt,
                                                             int64_t nq, int32_t *out_idx,
                                                             double *out_dist, int boxes_in_lds) {
-  extern __shared__ float s_box[];
+  extern __shared__ float4 s_box4[];
   // superblock boxes first, then (when they fit) the block boxes
-  const int nsbox = 8 * ix.n_super;
-  for (int i = threadIdx.x; i < nsbox; i += blockDim.x) s_box[i] = ix.sbox[i];
-  const int nbox = boxes_in_lds ? 8 * ix.n_blocks : 0;
-  for (int i = threadIdx.x; i < nbox; i += blockDim.x) s_box[nsbox + i] = ix.box[i];
+  const int nsbox = 2 * ix.n_super;
+  const float4 *g_sbox = reinterpret_cast<const float4 *>(ix.sbox);
+  const float4 *g_box = reinterpret_cast<const float4 *>(ix.box);
+  for (int i = threadIdx.x; i < nsbox; i += blockDim.x) s_box4[i] = g_sbox[i];
+  const int nbox = boxes_in_lds ? 2 * ix.n_blocks : 0;
+  for (int i = threadIdx.x; i < nbox; i += blockDim.x) s_box4[nsbox + i] = g_box[i];
   __syncthreads();
-  const float *box = boxes_in_lds ? s_box + nsbox : ix.box;
+  const float *s_box = reinterpret_cast<const float *>(s_box4);
+  const float *box = boxes_in_lds ? reinterpret_cast<const float *>(s_box4 + nsbox) : ix.box;
 #if TNN_QUERY_CHUNK > 0
   const int lane = lane_id();
   const int first = (int)(blockIdx.x % kQueues);
@@ -390,17 +398,14 @@ __global__ __launch_bounds__(512) void brute_kernel(IndexDesc ix, QueryArgs a, c
   for (int64_t p0 = 0; p0 < n; p0 += kWave) {
     const int64_t p = p0 + lane;
     const bool ok = p < n;
-    float px = 0.f, py = 0.f, pz = 0.f, pt = 0.f;
+    float4 pv = make_float4(0.f, 0.f, 0.f, 0.f);
     int pid = kNoId;
     if (ok) {
-      px = ix.px[p];
-      py = ix.py[p];
-      pz = ix.pz[p];
-      pt = ix.pt[p];
+      pv = ix.pt4[p];
       pid = ix.pid[p];
     }
-    const double d = exact_dist(a.s, q.x, q.y, q.z, q.t, px, py, pz, pt);
-    const bool gate = ok && (double)pt < q.thr && tk.admits(d, pid);
+    const double d = exact_dist(a.s, q.x, q.y, q.z, q.t, pv.x, pv.y, pv.z, pv.w);
+    const bool gate = ok && (double)pv.w < q.thr && tk.admits(d, pid);
     const uint64_t gm = ballot(gate);
     if (gm) {
       tk.offer(gm, gate, d, pid);
@@ -431,9 +436,9 @@ __global__ void debug_lb_kernel(IndexDesc ix, Prep pr, QueryArgs a, const float 
   const int64_t qi = i / per_q, j = i % per_q;
   const QueryPoint q = make_query(qx[qi], qy[qi], qz[qi], qt[qi], a.t_window);
   if (j < S) {
-    if (seg_lb_out) seg_lb_out[qi * S + j] = (double)seg_lb(ix, pr, j, q, a.sf);
+    if (seg_lb_out) seg_lb_out[qi * S + j] = (double)seg_lb(load_seg(pr, j), q, a.sf);
   } else if (block_lb_out) {
-    block_lb_out[qi * nb + (j - S)] = block_lb(ix, (int)(j - S), q, a.sf);
+    block_lb_out[qi * nb + (j - S)] = block_lb(ix.box, (int)(j - S), q, a.sf);
   }
 }
 
@@ -470,8 +475,7 @@ __global__ void batch_prep_kernel(const BatchItemDev *items, const int64_t *seg_
   if (g >= seg_prefix[n]) return;
   const int i = find_item(seg_prefix, n, g);
   const BatchItemDev &it = items[i];
-  prep_one(it.ix, it.a, const_cast<float *>(it.pr.inv_n2), const_cast<float *>(it.pr.rad),
-           const_cast<float *>(it.pr.slack), g - seg_prefix[i]);
+  prep_one(it.ix, it.a, it.pr.rec, g - seg_prefix[i]);
 }
 
 // Waves pull `chunk` queries at a time from a global counter over the
@@ -533,9 +537,8 @@ hipError_t launch_batch(const BatchLaunch &bl, hipStream_t st) {
 hipError_t launch_prep(const IndexDesc &ix, const QueryArgs &a, const Prep &pr, hipStream_t st) {
   const int tpb = 256;
   const int64_t grid = ix.n_seg > 0 ? (ix.n_seg + tpb - 1) / tpb : 1;
-  hipLaunchKernelGGL(prep_kernel, dim3((unsigned)grid), dim3(tpb), 0, st, ix, a,
-                     const_cast<float *>(pr.inv_n2), const_cast<float *>(pr.rad),
-                     const_cast<float *>(pr.slack), pr.ticket);
+  hipLaunchKernelGGL(prep_kernel, dim3((unsigned)grid), dim3(tpb), 0, st, ix, a, pr.rec,
+                     pr.ticket);
   return hipGetLastError();
 }
 

@@ -21,15 +21,15 @@ struct IndexDesc {
   int32_t n_blocks;
   int64_t n_points;
   int64_t n_seg;
-  // sorted points (segment order), SoA
-  const float *px, *py, *pz, *pt;
+  // sorted points (segment order): (x, y, z, t) of slot p in pt4[p]
+  const float4 *pt4;
   const int32_t *pid;  // caller index of each slot
   // segments (block order), SoA
   const float *ax, *ay, *az, *bx, *by, *bz, *tmin, *tmax, *ex, *ey, *ez;
   const int32_t *pstart, *pcount, *sorig;
-  // block boxes: box[f][b] for f = 0..7 (lo x y z t, hi x y z t)
+  // block boxes: box[8 b + f] for f = 0..7 (lo x y z t, hi x y z t)
   const float *box;
-  // superblock boxes (64 consecutive blocks each): sbox[f][s]
+  // superblock boxes (64 consecutive blocks each), same layout
   const float *sbox;
   int32_t n_super;
   int32_t pad_;
@@ -38,12 +38,17 @@ struct IndexDesc {
 static_assert(sizeof(IndexDesc) <= sizeof(tnn_index), "index descriptor too large");
 constexpr uint32_t kIndexMagic = 0x544e4e31u;  // "TNN1"
 
-// Per-call prepared segment data (depends on the scales).
+// Per-call segment records (the radius and projection constants depend on
+// the scales), kSegRec float4 per segment in index order:
+//   [0] A.x, A.y, A.z, t_min
+//   [1] (B - A).x, .y, .z (float32 differences), t_max
+//   [2] 1 / |AB|_s^2 (0 for a degenerate segment), radius R = sqrt(sum s_f
+//       e_f^2) rounded up, absolute slack 2^-17 |AB|_s rounded up, 0
+//   [3] first point slot, member count (int32 bits), 0, 0
+constexpr int kSegRec = 4;
 struct Prep {
-  const float *inv_n2;  // 1 / |AB|_s^2, 0 for a degenerate segment
-  const float *rad;     // radius R(s) = sqrt(sum s_f e_f^2), rounded up
-  const float *slack;   // absolute slack for the float32 bound, 2^-17 |AB|_s rounded up
-  unsigned long long *ticket;  // work-queue counter of the resident search kernel
+  float4 *rec;
+  unsigned long long *ticket;  // work-queue counters of the resident search kernel
 };
 
 struct QueryArgs {
