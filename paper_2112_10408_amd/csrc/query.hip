@@ -180,7 +180,7 @@ struct Searcher {
         }
       }
     }
-    return wave_max_f(maxfin);
+    return wave_max_nonneg(maxfin);
   }
 };
 
@@ -248,17 +248,17 @@ __device__ __forceinline__ void answer_query(const IndexDesc &ix, const Prep &pr
         float lbs = sb < ns ? block_lb(se.sbox, sb, se.q, a.sf) : __builtin_huge_valf();
         se.st.blocks += (uint32_t)min(kWave, ns - sbase);
         for (;;) {
-          float v = lbs;
-          int vl = se.lane;
-          wave_argmin_f(v, vl);
+          float v;
+          const int vl = wave_argmin_lane(lbs, v);
           if (!(v < best)) break;
           if (se.lane == vl) lbs = __builtin_huge_valf();
           const int b0 = (sbase + vl) * kSuperBlocks;
           const int b = b0 + se.lane;
-          float bv = b < nb ? block_lb(se.box, b, se.q, a.sf) : __builtin_huge_valf();
-          int bi = b < nb ? b : kNoId;
+          const float bv_l = b < nb ? block_lb(se.box, b, se.q, a.sf) : __builtin_huge_valf();
           se.st.blocks += (uint32_t)min(kSuperBlocks, nb - b0);
-          wave_argmin_f(bv, bi);
+          float bv;
+          const int bl = wave_argmin_lane(bv_l, bv);
+          const int bi = b0 + bl;
           if (bv < best || (bv == best && bi < bestb)) {
             best = bv;
             bestb = bi;
@@ -277,16 +277,15 @@ __device__ __forceinline__ void answer_query(const IndexDesc &ix, const Prep &pr
       SegView sv{};
       if (s < S) sv = load_seg(pr, s);
       const int ps_l = sv.ps, pc_l = sv.pc;
-      double v = s < S ? (double)seg_lb(sv, se.q, a.sf) : kInf;
+      float v = s < S ? seg_lb(sv, se.q, a.sf) : __builtin_huge_valf();
       se.st.segs += (uint32_t)min((int64_t)kBlockSegs, S - (int64_t)bestb * kBlockSegs);
       const int F = a.seed_segments;
       for (int i = 0; i < F; ++i) {
-        double mv = v;
-        int ml = se.lane;
-        wave_argmin_d(mv, ml);
-        if (!(mv < kInf)) break;
+        float mv;
+        const int ml = wave_argmin_lane(v, mv);
+        if (!(mv < __builtin_huge_valf())) break;
         seed_mask |= 1ull << ml;
-        if (se.lane == ml) v = kInf;
+        if (se.lane == ml) v = __builtin_huge_valf();
       }
       if (seed_mask) se.scan(seed_mask, bestb, ps_l, pc_l);
     }
@@ -337,22 +336,24 @@ __global__ __launch_bounds__(512) void tnn_query_kernel(IndexDesc ix, Prep pr, Q
 // indexes): the grid is exactly what stays resident, and each wave takes
 // TNN_QUERY_CHUNK queries at a time from a counter (query costs vary by
 // orders of magnitude, so a fixed share per wave leaves a long tail).
-__global__ __launch_bounds__(512, TNN_QUERY_MIN_WAVES) void tnn_query_lds_kernel(IndexDesc ix, Prep pr, QueryArgs a,
-                                                            const float *qx, const float *qy,
-                                                            const float *qz, const float *qt,
-                                                            int64_t nq, int32_t *out_idx,
-                                                            double *out_dist, int boxes_in_lds) {
+// BoxesInLds: the block boxes fit in LDS too (the superblock boxes always
+// do); a template argument so that every box read is a plain LDS or global
+// access rather than a generic one.
+template <bool BoxesInLds>
+__global__ __launch_bounds__(512, TNN_QUERY_MIN_WAVES) void tnn_query_lds_kernel(
+    IndexDesc ix, Prep pr, QueryArgs a, const float *qx, const float *qy, const float *qz,
+    const float *qt, int64_t nq, int32_t *out_idx, double *out_dist) {
   extern __shared__ float4 s_box4[];
   // superblock boxes first, then (when they fit) the block boxes
   const int nsbox = 2 * ix.n_super;
   const float4 *g_sbox = reinterpret_cast<const float4 *>(ix.sbox);
   const float4 *g_box = reinterpret_cast<const float4 *>(ix.box);
   for (int i = threadIdx.x; i < nsbox; i += blockDim.x) s_box4[i] = g_sbox[i];
-  const int nbox = boxes_in_lds ? 2 * ix.n_blocks : 0;
+  const int nbox = BoxesInLds ? 2 * ix.n_blocks : 0;
   for (int i = threadIdx.x; i < nbox; i += blockDim.x) s_box4[nsbox + i] = g_box[i];
   __syncthreads();
   const float *s_box = reinterpret_cast<const float *>(s_box4);
-  const float *box = boxes_in_lds ? reinterpret_cast<const float *>(s_box4 + nsbox) : ix.box;
+  const float *box = BoxesInLds ? reinterpret_cast<const float *>(s_box4 + nsbox) : ix.box;
 #if TNN_QUERY_CHUNK > 0
   const int lane = lane_id();
   const int first = (int)(blockIdx.x % kQueues);
@@ -565,15 +566,16 @@ hipError_t launch_query(const IndexDesc &ix, const Prep &pr, const QueryArgs &a,
   if (sl <= kLdsBoxBytes) {
     const int in_lds = sl + bl <= kLdsBoxBytes ? 1 : 0;
     const size_t lds = in_lds ? sl + bl : sl;
+    const auto kern = in_lds ? tnn_query_lds_kernel<true> : tnn_query_lds_kernel<false>;
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, tnn_query_lds_kernel,
-                                                     waves_per_block * kWave, lds) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, waves_per_block * kWave, lds) !=
+            hipSuccess ||
         per_cu <= 0)
       per_cu = 1;
     const int64_t resident = (int64_t)cu_count() * per_cu;
     const int64_t g = grid < resident ? grid : resident;
-    hipLaunchKernelGGL(tnn_query_lds_kernel, dim3((unsigned)g), dim3(waves_per_block * kWave), lds,
-                       st, ix, pr, a, qs.x, qs.y, qs.z, qs.t, qs.n, out_idx, out_dist, in_lds);
+    hipLaunchKernelGGL(kern, dim3((unsigned)g), dim3(waves_per_block * kWave), lds, st, ix, pr, a,
+                       qs.x, qs.y, qs.z, qs.t, qs.n, out_idx, out_dist);
     return hipGetLastError();
   }
   hipLaunchKernelGGL(tnn_query_kernel, dim3((unsigned)grid), dim3(waves_per_block * kWave), 0, st,

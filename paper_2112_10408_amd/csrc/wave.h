@@ -43,88 +43,143 @@ __device__ __forceinline__ bool key_lt(double a, int ia, double b, int ib) {
   return (a < b) | ((a == b) & (ia < ib));
 }
 
-// Wave-wide argmin; every lane returns the same (value, index); ties take the
-// smaller index.
-__device__ __forceinline__ void wave_argmin_f(float &v, int &i) {
-#pragma unroll
-  for (int m = 32; m > 0; m >>= 1) {
-    const float ov = __shfl_xor(v, m, 64);
-    const int oi = __shfl_xor(i, m, 64);
-    if (ov < v || (ov == v && oi < i)) {
-      v = ov;
-      i = oi;
-    }
+// DPP controls (gfx9 encoding) used below.
+constexpr int kDppQuadXor1 = 0xB1;  // quad_perm [1,0,3,2]: lane ^ 1
+constexpr int kDppQuadXor2 = 0x4E;  // quad_perm [2,3,0,1]: lane ^ 2
+constexpr int kDppRowRor4 = 0x124;  // lane (l - 4) mod 16 within its row of 16
+constexpr int kDppRowRor8 = 0x128;  // lane (l + 8) mod 16 = lane ^ 8
+constexpr int kDppWaveShr1 = 0x138; // lane l - 1
+
+template <int Ctrl>
+__device__ __forceinline__ int dpp_i(int v) {
+  return __builtin_amdgcn_mov_dpp(v, Ctrl, 0xF, 0xF, false);
+}
+template <int Ctrl>
+__device__ __forceinline__ float dpp_f(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), Ctrl, 0xF, 0xF, false));
+}
+
+// Both values of each lane pair (l, l ^ J), J = 16 or 32, in every lane:
+// `lo` from the lane whose bit J is clear, `hi` from the lane whose bit J is
+// set (gfx950 permlane swaps: no LDS round trip).
+template <int J>
+__device__ __forceinline__ void lane_pair(int v, int &lo, int &hi) {
+  static_assert(J == 16 || J == 32, "pair exchange spans 16 or 32 lanes");
+  if constexpr (J == 16) {
+    const auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+    lo = (int)r[0];
+    hi = (int)r[1];
+  } else {
+    const auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+    lo = (int)r[0];
+    hi = (int)r[1];
   }
 }
 
-__device__ __forceinline__ void wave_argmin_d(double &v, int &i) {
-#pragma unroll
-  for (int m = 32; m > 0; m >>= 1) {
-    const double ov = __shfl_xor(v, m, 64);
-    const int oi = __shfl_xor(i, m, 64);
-    if (ov < v || (ov == v && oi < i)) {
-      v = ov;
-      i = oi;
-    }
-  }
+// Wave-wide minimum / maximum of non-negative floats (or +inf), the result in
+// every lane: quad and row steps by DPP, row pairs and wave halves by
+// permlane swaps.  Non-negative floats order like their bit patterns as
+// int32, so integer min / max does the comparisons.
+template <bool Max>
+__device__ __forceinline__ int wave_ext_bits(int v) {
+  auto f = [](int a, int b) { return Max ? max(a, b) : min(a, b); };
+  v = f(v, dpp_i<kDppQuadXor1>(v));
+  v = f(v, dpp_i<kDppQuadXor2>(v));
+  v = f(v, dpp_i<kDppRowRor4>(v));
+  v = f(v, dpp_i<kDppRowRor8>(v));
+  int a, b;
+  lane_pair<16>(v, a, b);
+  v = f(a, b);
+  lane_pair<32>(v, a, b);
+  return f(a, b);
 }
 
-__device__ __forceinline__ float wave_max_f(float v) {
-#pragma unroll
-  for (int m = 32; m > 0; m >>= 1) v = fmaxf(v, __shfl_xor(v, m, 64));
-  return v;
+__device__ __forceinline__ float wave_min_nonneg(float v) {
+  return __int_as_float(wave_ext_bits<false>(__float_as_int(v)));
 }
 
-// Value of lane ^ j (j a power of two known after unrolling): DPP quad
-// permutes for 1 and 2, LDS swizzle for 4..16, a permute for 32.
-__device__ __forceinline__ int xor_lane(int v, int j) {
-  if (j == 1) return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false);  // quad_perm [1,0,3,2]
-  if (j == 2) return __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false);  // quad_perm [2,3,0,1]
-  if (j == 4) return __builtin_amdgcn_ds_swizzle(v, 0x1F | (4 << 10));
-  if (j == 8) return __builtin_amdgcn_ds_swizzle(v, 0x1F | (8 << 10));
-  if (j == 16) return __builtin_amdgcn_ds_swizzle(v, 0x1F | (16 << 10));
-  return __shfl_xor(v, j, 64);
+__device__ __forceinline__ float wave_max_nonneg(float v) {
+  return __int_as_float(wave_ext_bits<true>(__float_as_int(v)));
 }
 
-__device__ __forceinline__ double xor_lane_d(double v, int j) {
-  const long long b = __double_as_longlong(v);
-  const int lo = xor_lane((int)(b & 0xffffffffll), j);
-  const int hi = xor_lane((int)(b >> 32), j);
+// Wave-wide argmin of a non-negative float (or +inf): the minimum and the
+// lowest lane that holds it, in every lane.
+__device__ __forceinline__ int wave_argmin_lane(float v, float &vmin) {
+  vmin = wave_min_nonneg(v);
+  return __ffsll((long long)ballot(v == vmin)) - 1;
+}
+
+// Value of lane ^ J for J = 1, 2, 4, 8 (DPP quad permutes and row rotation;
+// an LDS swizzle for 4).
+template <int J>
+__device__ __forceinline__ int xor_lane(int v) {
+  static_assert(J == 1 || J == 2 || J == 4 || J == 8, "xor_lane spans a row");
+  if constexpr (J == 1) return dpp_i<kDppQuadXor1>(v);
+  else if constexpr (J == 2) return dpp_i<kDppQuadXor2>(v);
+  else if constexpr (J == 4) return __builtin_amdgcn_ds_swizzle(v, 0x1F | (4 << 10));
+  else return dpp_i<kDppRowRor8>(v);
+}
+
+__device__ __forceinline__ int lo32(double v) { return (int)(__double_as_longlong(v) & 0xffffffffll); }
+__device__ __forceinline__ int hi32(double v) { return (int)(__double_as_longlong(v) >> 32); }
+__device__ __forceinline__ double mk_double(int lo, int hi) {
   return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
 }
 
-// Compare-exchange with lane ^ j: keep the smaller key if `keep_min`.
-__device__ __forceinline__ void cmpx(double &d, int &id, int j, bool keep_min) {
-  const double od = xor_lane_d(d, j);
-  const int oid = xor_lane(id, j);
-  const bool other_lt = key_lt(od, oid, d, id);
-  const bool other_gt = key_lt(d, id, od, oid);
-  if (keep_min ? other_lt : other_gt) {
-    d = od;
-    id = oid;
-  }
-}
-
-// Bitonic sort of 64 keys, ascending by lane.
-__device__ __forceinline__ void sort64(double &d, int &id) {
-  const int l = lane_id();
-#pragma unroll
-  for (int size = 2; size <= 64; size <<= 1) {
-#pragma unroll
-    for (int j = size >> 1; j > 0; j >>= 1) {
-      const bool asc = (l & size) == 0;
-      const bool lower = (l & j) == 0;
-      cmpx(d, id, j, lower == asc);
+// Compare-exchange of the keys of lanes l and l ^ J: lanes with `keep_min`
+// keep the smaller key, the others the larger.  One comparison decides both
+// sides (equal keys are identical, so taking either is the same).
+template <int J>
+__device__ __forceinline__ void cmpx(double &d, int &id, bool keep_min) {
+  if constexpr (J >= 16) {
+    int al, bl, ah, bh, ai, bi;
+    lane_pair<J>(lo32(d), al, bl);
+    lane_pair<J>(hi32(d), ah, bh);
+    lane_pair<J>(id, ai, bi);
+    const double ad = mk_double(al, ah), bd = mk_double(bl, bh);
+    const bool b_lt = key_lt(bd, bi, ad, ai);  // the upper lane's key is the smaller
+    const bool take_b = keep_min == b_lt;
+    d = take_b ? bd : ad;
+    id = take_b ? bi : ai;
+  } else {
+    const double od = mk_double(xor_lane<J>(lo32(d)), xor_lane<J>(hi32(d)));
+    const int oid = xor_lane<J>(id);
+    const bool o_lt = key_lt(od, oid, d, id);
+    if (keep_min == o_lt) {
+      d = od;
+      id = oid;
     }
   }
 }
 
-// Sort a bitonic sequence of 64 keys ascending.
-__device__ __forceinline__ void merge64(double &d, int &id) {
-  const int l = lane_id();
-#pragma unroll
-  for (int j = 32; j > 0; j >>= 1) cmpx(d, id, j, (l & j) == 0);
+template <bool Desc, int Size, int J>
+__device__ __forceinline__ void sort_stage(double &d, int &id, int l) {
+  const bool asc = ((l & Size) == 0) != Desc;
+  const bool lower = (l & J) == 0;
+  cmpx<J>(d, id, lower == asc);
+  if constexpr (J > 1) sort_stage<Desc, Size, J / 2>(d, id, l);
 }
+
+template <bool Desc, int Size>
+__device__ __forceinline__ void sort_upto(double &d, int &id, int l) {
+  if constexpr (Size > 2) sort_upto<Desc, Size / 2>(d, id, l);
+  sort_stage<Desc, Size, Size / 2>(d, id, l);
+}
+
+// Bitonic sort of 64 keys by lane, ascending (Desc = false) or descending.
+template <bool Desc = false>
+__device__ __forceinline__ void sort64(double &d, int &id) {
+  sort_upto<Desc, 64>(d, id, lane_id());
+}
+
+template <int J>
+__device__ __forceinline__ void merge_stage(double &d, int &id, int l) {
+  cmpx<J>(d, id, (l & J) == 0);
+  if constexpr (J > 1) merge_stage<J / 2>(d, id, l);
+}
+
+// Sort a bitonic sequence of 64 keys ascending.
+__device__ __forceinline__ void merge64(double &d, int &id) { merge_stage<32>(d, id, lane_id()); }
 
 // Top-k over (distance, index): lane r holds the r-th smallest key seen so
 // far (r < 64; ranks >= k are kept but never reported).  kd/kid mirror rank
@@ -162,10 +217,10 @@ struct TopK {
   __device__ __forceinline__ void insert_one(double c, int cid) {
     const int l = lane_id();
     const bool before = key_lt(c, cid, d, id);  // candidate ranks ahead of my key
-    const int src = l > 0 ? l - 1 : 0;
-    const double up = __shfl(d, src, 64);
-    const int upid = __shfl(id, src, 64);
-    const bool prev_before = __shfl((int)before, src, 64) != 0 && l > 0;
+    // keys of lane l - 1 (whole-wave shift; lane 0 reads nothing useful)
+    const double up = mk_double(dpp_i<kDppWaveShr1>(lo32(d)), dpp_i<kDppWaveShr1>(hi32(d)));
+    const int upid = dpp_i<kDppWaveShr1>(id);
+    const bool prev_before = dpp_i<kDppWaveShr1>((int)before) != 0 && l > 0;
     if (before) {
       if (prev_before) {
         d = up;
@@ -190,21 +245,20 @@ struct TopK {
     } else {
       double cd = gate ? nd : inf_;
       int cid = gate ? nid : kNoId;
-      sort64(cd, cid);
       if (!(readlane_d(d, 0) < inf_)) {  // empty top-k: the sorted batch is the result
+        sort64<false>(cd, cid);
         d = cd;
         id = cid;
-        refresh();
-        return;
+      } else {
+        // descending batch against the ascending top-k: the lane-wise
+        // smaller keys form a bitonic sequence holding the 64 smallest
+        sort64<true>(cd, cid);
+        if (key_lt(cd, cid, d, id)) {
+          d = cd;
+          id = cid;
+        }
+        merge64(d, id);
       }
-      const int rl = 63 - lane_id();
-      const double rd = __shfl(cd, rl, 64);
-      const int rid = __shfl(cid, rl, 64);
-      if (key_lt(rd, rid, d, id)) {
-        d = rd;
-        id = rid;
-      }
-      merge64(d, id);
     }
     refresh();
   }
