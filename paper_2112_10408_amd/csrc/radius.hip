@@ -5,6 +5,7 @@
 #include <cstring>
 
 #include "tnn_internal.h"
+#include "wave.h"
 
 namespace tnn {
 namespace {
@@ -95,34 +96,92 @@ __global__ void features_kernel(const tnn_radius_model *m, tnn_points q, float *
   for (int j = 0; j < NI; ++j) out[NI * i + j] = f[j];
 }
 
-// One thread per query; weights staged in LDS (broadcast reads).
-__global__ __launch_bounds__(256) void infer_kernel(const tnn_radius_model *m, tnn_points q,
-                                                     float alpha, float *radius2, float *logr) {
-  __shared__ float W[NP];
-  for (int i = threadIdx.x; i < NP; i += blockDim.x) W[i] = m->params[i];
+// Inference, one wave per tile of 32 queries.  The hidden-to-hidden layer
+// (the only dense contraction: 32 queries x 64 inputs x 64 units) runs on
+// the matrix cores with float32 operands, v_mfma_f32_32x32x2f32:
+//   A (32 x 2): lane l holds A[l % 32][l / 32]   (query l % 32, input 2s + l / 32)
+//   B (2 x 32): lane l holds B[l / 32][l % 32]   (input 2s + l / 32, unit l % 32)
+//   D (32 x 32): element e of lane l is D[(e / 4) 8 + (l / 32) 4 + e % 4][l % 32]
+// Two output blocks cover units 0..31 and 32..63; 32 K-steps of 2 cover the
+// 64 inputs.  The first layer (5 -> 64) and the output layer run on the
+// vector units; the output layer's sum over units goes through LDS.
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+constexpr int kInferTile = 32;
+constexpr int kInferWaves = 4;  // waves per workgroup; the weights are staged once per workgroup
+
+__global__ __launch_bounds__(64 * kInferWaves) void infer_kernel(
+    const tnn_radius_model *__restrict__ m, tnn_points q, float alpha, float *__restrict__ radius2,
+    float *__restrict__ logr) {
+  __shared__ float w2s[H][H + 1];  // hidden-to-hidden weights, padded rows
+  __shared__ float4 w1s[H][2];     // first layer, per unit: weights 0..3 | weight 4, bias
+  __shared__ float part[kInferWaves][kInferTile][kInferTile + 1];
+  const float *__restrict__ W = m->params;
+  for (int i = threadIdx.x; i < H * H; i += blockDim.x) w2s[i / H][i % H] = W[OW2 + i];
+  for (int k = threadIdx.x; k < H; k += blockDim.x) {
+    w1s[k][0] = make_float4(W[OW1 + k * NI], W[OW1 + k * NI + 1], W[OW1 + k * NI + 2],
+                            W[OW1 + k * NI + 3]);
+    w1s[k][1] = make_float4(W[OW1 + k * NI + 4], W[OB1 + k], 0.0f, 0.0f);
+  }
   __syncthreads();
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= q.n) return;
-  float f[NI];
-  features(m, q.x[i], q.y[i], q.z[i], q.t[i], f);
-  float h1[H];
+  const int wv = threadIdx.x >> 6;
+  const int l = threadIdx.x & 63;
+  const int col = l & 31;   // unit within an output block / query within the tile
+  const int half = l >> 5;  // which of the two inputs of a K-step
+  // B operands for all 32 K-steps of both blocks: W2[unit][input]
+  float wb0[H / 2], wb1[H / 2];
 #pragma unroll
-  for (int j = 0; j < H; ++j) {
-    float a = W[OB1 + j];
-#pragma unroll
-    for (int c = 0; c < NI; ++c) a += W[OW1 + j * NI + c] * f[c];
-    h1[j] = fmaxf(a, 0.0f);
+  for (int st = 0; st < H / 2; ++st) {
+    wb0[st] = w2s[col][2 * st + half];
+    wb1[st] = w2s[32 + col][2 * st + half];
   }
-  float out = W[OB3];
-  for (int j = 0; j < H; ++j) {
-    float a = W[OB2 + j];
+  const float b2_0 = W[OB2 + col], b2_1 = W[OB2 + 32 + col];
+  const float w3_0 = W[OW3 + col], w3_1 = W[OW3 + 32 + col];
+  const float b3 = W[OB3];
+  float(*pw)[kInferTile + 1] = part[wv];
+  const int64_t n_tiles = (q.n + kInferTile - 1) / kInferTile;
+  for (int64_t tile = (int64_t)blockIdx.x * kInferWaves + wv; tile < n_tiles;
+       tile += (int64_t)gridDim.x * kInferWaves) {
+    const int64_t qi = tile * kInferTile + col;
+    const bool ok = qi < q.n;
+    float f[NI] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+    if (ok) features(m, q.x[qi], q.y[qi], q.z[qi], q.t[qi], f);
+    // first layer, the inputs this lane feeds to the matrix cores
+    float h1[H / 2];
 #pragma unroll
-    for (int c = 0; c < H; ++c) a += W[OW2 + j * H + c] * h1[c];
-    out += W[OW3 + j] * fmaxf(a, 0.0f);
+    for (int st = 0; st < H / 2; ++st) {
+      const float4 wa = w1s[2 * st + half][0], wb = w1s[2 * st + half][1];
+      const float a = wb.y + wa.x * f[0] + wa.y * f[1] + wa.z * f[2] + wa.w * f[3] + wb.x * f[4];
+      h1[st] = fmaxf(a, 0.0f);
+    }
+    f32x16 c0, c1;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      c0[e] = b2_0;
+      c1[e] = b2_1;
+    }
+#pragma unroll
+    for (int st = 0; st < H / 2; ++st) {
+      c0 = __builtin_amdgcn_mfma_f32_32x32x2f32(h1[st], wb0[st], c0, 0, 0, 0);
+      c1 = __builtin_amdgcn_mfma_f32_32x32x2f32(h1[st], wb1[st], c1, 0, 0, 0);
+    }
+    // output layer: per (query row, unit) terms, summed over units through
+    // this wave's LDS rows
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const int row = (e >> 2) * 8 + half * 4 + (e & 3);
+      pw[row][col] = w3_0 * fmaxf(c0[e], 0.0f) + w3_1 * fmaxf(c1[e], 0.0f);
+    }
+    wave_sync();
+    if (l < kInferTile && ok) {
+      float out = b3;
+#pragma unroll
+      for (int u = 0; u < kInferTile; ++u) out += pw[l][u];
+      const float r = alpha * expf(out);
+      radius2[qi] = r * r;
+      if (logr) logr[qi] = out;
+    }
+    wave_sync();
   }
-  const float r = alpha * expf(out);
-  radius2[i] = r * r;
-  if (logr) logr[i] = out;
 }
 
 // Forward and backward over kTrainBlock samples per workgroup; writes this
@@ -373,7 +432,9 @@ tnn_status tnn_radius_infer(const void *d_model, tnn_points queries, float alpha
       !std::isfinite(alpha))
     return TNN_E_ARG;
   if (queries.n == 0) return TNN_OK;
-  hipLaunchKernelGGL(infer_kernel, dim3((unsigned)((queries.n + 255) / 256)), dim3(256), 0,
+  const int64_t groups = (queries.n + kInferTile * kInferWaves - 1) / (kInferTile * kInferWaves);
+  const int64_t grid = groups < 1024 ? groups : 1024;
+  hipLaunchKernelGGL(infer_kernel, dim3((unsigned)grid), dim3(64 * kInferWaves), 0,
                      static_cast<hipStream_t>(stream),
                      static_cast<const tnn_radius_model *>(d_model), queries, alpha, d_radius2,
                      d_logr);

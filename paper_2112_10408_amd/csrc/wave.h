@@ -36,6 +36,15 @@ __device__ __forceinline__ double readlane_d(double v, int l) {
   return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
 }
 
+// Orders a wave's own LDS writes before its later reads of other lanes'
+// entries (the lanes of a wave run in lockstep; this only stops the compiler
+// from moving memory operations across the point).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Lexicographic (distance, caller index) order of the result.
 // Branch-free on purpose: short-circuit forms turn every compare-exchange of
 // the sorting network into divergent branches.
