@@ -30,6 +30,28 @@ FLOPS_SEG_BOUND = 39       # float32 cylinder bound
 FLOPS_POINT = 15           # binary64 exact distance
 
 
+# HBM traffic of one learned-radius search launch on this workload, from two
+# rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE, KiB per dispatch), each
+# scaled by what the counter reads for a 256 MiB device-to-device copy
+# (FETCH_SIZE x 2.00, WRITE_SIZE x 1.00): 187,000 KiB fetched and 40,598 KiB
+# written.  It describes the kernel built from the sources with this SHA-256
+# only; after any change to them the figure is reported as null.
+KERNEL_SOURCES = ("query.hip", "bounds.h", "wave.h", "tnn_internal.h")
+MEASURED_TRAFFIC = {
+    "sha256": "2a029f906a3b032d34e3b3db11de2af1e4fbd2d5899f8d5fd4b179aa7ef45173",
+    "bytes_per_launch": 424.55e6,
+}
+
+
+def measured_traffic():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2112_10408_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return MEASURED_TRAFFIC["bytes_per_launch"] if h.hexdigest() == MEASURED_TRAFFIC["sha256"] else None
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -414,7 +436,7 @@ def main():
     # two vector peaks, expressed as one rate
     peak = flops / (f32 / FP32_VECTOR_PEAK_TFLOPS + f64 / FP64_VECTOR_PEAK_TFLOPS)
     roofline = {"bound": "alu", "achieved": achieved, "peak": peak,
-                "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
+                "unit": "TFLOP/s", "frac": achieved / peak, "traffic": measured_traffic(),
                 "kernel": "tnn_query_lds_kernel (learned radius; the timed call also runs the per-call prep_kernel)",
                 "kernel_ms": ms_search}
     value = qs.n / ms_learned * 1e3
