@@ -213,7 +213,7 @@ def run_config(name, args, T, capi, radius, synth, torch, stream):
     scr_tr = torch.empty(max(T.tnn_query_workspace(ix, tq.n, T.make_params(scale, 0.0, k)), 256),
                          dtype=torch.uint8, device="cuda")
     best = None
-    for qnt in (0.7, 0.8, 0.9):
+    for qnt in ((0.7, 0.8, 0.9) if not args.radius_quantile else (args.radius_quantile,)):
         a = radius.calibrate(model, *ptr, pdist, k, quantile=qnt)
 
         def learned_tr():
@@ -285,8 +285,9 @@ def main():
     ap.add_argument("--no-configs", action="store_true",
                     help="skip the 10k-point, 1M-query and 8M-point workloads")
     ap.add_argument("--train-epochs", type=int, default=8)
-    ap.add_argument("--radius-quantile", type=float, default=None,
-                    help="fixed calibration quantile (default: the fastest on the training queries)")
+    ap.add_argument("--radius-quantile", type=float, default=0.8,
+                    help="calibration quantile of the radius safety factor; 0 sweeps "
+                         "0.5-0.95 and keeps the fastest on the training queries")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a 256 MiB device-to-device copy (counter calibration)")
     args = ap.parse_args()
@@ -349,7 +350,7 @@ def main():
     out_tr = (torch.empty((tq.n, k), dtype=torch.int32, device="cuda"),
               torch.empty((tq.n, k), dtype=torch.float64, device="cuda"))
     best = None
-    sweep = (0.5, 0.7, 0.8, 0.9, 0.95) if args.radius_quantile is None else (args.radius_quantile,)
+    sweep = (0.5, 0.7, 0.8, 0.9, 0.95) if not args.radius_quantile else (args.radius_quantile,)
     for qnt in sweep:
         a = radius.calibrate(model, *ptr, pdist, k, quantile=qnt)
 

@@ -1,5 +1,7 @@
 // Query kernels: per-call segment preparation, TNN search (plain and
 // learned-radius seeded), linear search, and the bound export for tests.
+#include <mutex>
+
 #include "bounds.h"
 #include "query.h"
 
@@ -556,6 +558,32 @@ static int cu_count() {
   return cached[dev];
 }
 
+// Workgroups of the resident search kernel that fit on one CU, cached per
+// (device, variant, waves per workgroup, LDS bytes): the occupancy query costs
+// host time comparable to a small search.
+template <class Query>
+static int resident_per_cu(int variant, int wpb, size_t lds, Query query) {
+  struct Entry {
+    int dev, variant, wpb;
+    size_t lds;
+    int per_cu;
+  };
+  static Entry cache[32];
+  static int used = 0;
+  static std::mutex mu;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) dev = -1;
+  std::lock_guard<std::mutex> lock(mu);
+  for (int i = 0; i < used; ++i)
+    if (cache[i].dev == dev && cache[i].variant == variant && cache[i].wpb == wpb &&
+        cache[i].lds == lds)
+      return cache[i].per_cu;
+  int n = 0;
+  if (query(&n) != hipSuccess || n <= 0) n = 1;
+  if (used < 32) cache[used++] = Entry{dev, variant, wpb, lds, n};
+  return n;
+}
+
 hipError_t launch_query(const IndexDesc &ix, const Prep &pr, const QueryArgs &a,
                         const tnn_points &qs, int waves_per_block, int32_t *out_idx,
                         double *out_dist, hipStream_t st) {
@@ -567,11 +595,9 @@ hipError_t launch_query(const IndexDesc &ix, const Prep &pr, const QueryArgs &a,
     const int in_lds = sl + bl <= kLdsBoxBytes ? 1 : 0;
     const size_t lds = in_lds ? sl + bl : sl;
     const auto kern = in_lds ? tnn_query_lds_kernel<true> : tnn_query_lds_kernel<false>;
-    int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, waves_per_block * kWave, lds) !=
-            hipSuccess ||
-        per_cu <= 0)
-      per_cu = 1;
+    const int per_cu = resident_per_cu(in_lds, waves_per_block, lds, [&](int *n) {
+      return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, kern, waves_per_block * kWave, lds);
+    });
     const int64_t resident = (int64_t)cu_count() * per_cu;
     const int64_t g = grid < resident ? grid : resident;
     hipLaunchKernelGGL(kern, dim3((unsigned)g), dim3(waves_per_block * kWave), lds, st, ix, pr, a,
