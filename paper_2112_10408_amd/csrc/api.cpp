@@ -438,7 +438,7 @@ BatchLayout batch_layout(const tnn_batch_item *items, int32_t n) {
   L.qprefix = take(8 * (size_t)(n + 1));
   L.order = take(4 * (size_t)n);
   L.seg_prefix = take(8 * (size_t)(n + 1));
-  L.counter = take(8);
+  L.counter = take(16 * 256);  // work-queue counters, 256 bytes apart
   L.done = take(4 * (size_t)n);
   L.ticks = take(8 * (size_t)(n + 1));
   L.prep0 = o;

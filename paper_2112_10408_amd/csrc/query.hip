@@ -451,10 +451,8 @@ __global__ void debug_lb_kernel(IndexDesc ix, Prep pr, QueryArgs a, const float 
 __global__ void batch_reset_kernel(unsigned long long *counter, unsigned *done, int n,
                                    unsigned long long *ticks) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i == 0) {
-    *counter = 0;
-    ticks[0] = wall_clock64();
-  }
+  if (i < kQueues) counter[i * kTicketStride] = 0;
+  if (i == 0) ticks[0] = wall_clock64();
   if (i < n) {
     done[i] = 0;
     ticks[i + 1] = 0;
@@ -481,10 +479,12 @@ __global__ void batch_prep_kernel(const BatchItemDev *items, const int64_t *seg_
   prep_one(it.ix, it.a, it.pr.rec, g - seg_prefix[i]);
 }
 
-// Waves pull `chunk` queries at a time from a global counter over the
+// Waves pull `chunk` queries at a time from work-queue counters over the
 // queries of all items laid end to end in the order given by `order`
-// (longest first); each query is answered exactly as by tnn_query_kernel.
-// Every wave leaves once the counter passes the total.
+// (longest first), split into kQueues contiguous slices as in the
+// single-index search; each query is answered exactly as by tnn_query.
+// Completion is counted once per item run of a chunk; the wave that completes
+// an item stamps its tick.  Every wave leaves once every slice is used up.
 __global__ __launch_bounds__(512) void batch_kernel(const BatchItemDev *items,
                                                     const int64_t *qprefix, const int32_t *order,
                                                     int n, int chunk,
@@ -492,23 +492,31 @@ __global__ __launch_bounds__(512) void batch_kernel(const BatchItemDev *items,
                                                     unsigned long long *ticks) {
   const int lane = lane_id();
   const int64_t total = qprefix[n];
-  for (;;) {
-    unsigned long long b = 0;
-    if (lane == 0) b = atomicAdd(counter, (unsigned long long)chunk);
-    const int64_t base = (int64_t)(((unsigned long long)(unsigned)uniform_i((int)(b >> 32)) << 32) |
-                                   (unsigned)uniform_i((int)(b & 0xffffffffull)));
-    if (base >= total) break;
-    for (int j = 0; j < chunk; ++j) {
-      const int64_t gq = base + j;
-      if (gq >= total) break;
-      const int pos = find_item(qprefix, n, gq);
-      const int item = order[pos];
-      const BatchItemDev &it = items[item];
-      answer_query(it.ix, it.pr, it.a, it.qx, it.qy, it.qz, it.qt, gq - qprefix[pos], it.out_idx,
-                   it.out_dist, it.ix.box, it.ix.sbox);
-      if (lane == 0) {
-        const unsigned d = atomicAdd(&done[item], 1u) + 1u;
-        if ((int64_t)d == it.nq) ticks[item + 1] = wall_clock64();
+  const int first = (int)(blockIdx.x % kQueues);
+  for (int j = 0; j < kQueues; ++j) {
+    const int qn = (first + j) % kQueues;
+    const int64_t lo = total * qn / kQueues, hi = total * (qn + 1) / kQueues;
+    unsigned long long *ctr = counter + qn * kTicketStride;
+    for (;;) {
+      unsigned long long b = 0;
+      if (lane == 0) b = atomicAdd(ctr, (unsigned long long)chunk);
+      const int64_t base = lo + (int64_t)uniform_u64(b);
+      if (base >= hi) break;
+      const int64_t end = base + chunk < hi ? base + chunk : hi;
+      int64_t gq = base;
+      while (gq < end) {
+        const int pos = find_item(qprefix, n, gq);
+        const int64_t item_end = qprefix[pos + 1] < end ? qprefix[pos + 1] : end;
+        const int item = order[pos];
+        const BatchItemDev &it = items[item];
+        const int64_t run = item_end - gq;
+        for (; gq < item_end; ++gq)
+          answer_query(it.ix, it.pr, it.a, it.qx, it.qy, it.qz, it.qt, gq - qprefix[pos],
+                       it.out_idx, it.out_dist, it.ix.box, it.ix.sbox);
+        if (lane == 0) {
+          const unsigned d = atomicAdd(&done[item], (unsigned)run) + (unsigned)run;
+          if ((int64_t)d == it.nq) ticks[item + 1] = wall_clock64();
+        }
       }
     }
   }
