@@ -126,9 +126,19 @@ def run_batched(args, T, capi, radius, synth, torch, stream):
     best = T.tnn_autotune_batched(entries, None)
     b = T.tnn_batch_prepare(entries, best)
 
+    # the per-airspace radius inferences are independent: spread them over a
+    # few streams forked from the launch stream (parallel graph branches)
+    infer_streams = [torch.cuda.Stream() for _ in range(4)]
+
     def step():
-        for model, alpha, q, r2 in models:
-            T.tnn_radius_infer(model, *q, alpha, out=r2)
+        main = torch.cuda.current_stream()
+        for s in infer_streams:
+            s.wait_stream(main)
+        for i, (model, alpha, q, r2) in enumerate(models):
+            with torch.cuda.stream(infer_streams[i % len(infer_streams)]):
+                T.tnn_radius_infer(model, *q, alpha, out=r2)
+        for s in infer_streams:
+            main.wait_stream(s)
         T.tnn_query_batched(b)
 
     step()
