@@ -157,9 +157,11 @@ def lower_bound(seg, queries, scale, t_window: float):
 # Learned k-th radius (not in the paper).
 # ----------------------------------------------------------------------------
 HIDDEN = 64
-N_IN = 5
+N_IN = 6
 GRID = 32
-# parameter vector order: W1[64x5] b1[64] W2[64x64] b2[64] W3[64] b3[1]
+START_XY = 128   # trajectory-start grid: cells along x and y
+START_T = 512    # ... and along t
+# parameter vector order: W1[64x6] b1[64] W2[64x64] b2[64] W3[64] b3[1]
 PARAM_SHAPES = [("W1", (HIDDEN, N_IN)), ("b1", (HIDDEN,)), ("W2", (HIDDEN, HIDDEN)),
                 ("b2", (HIDDEN,)), ("W3", (HIDDEN,)), ("b3", (1,))]
 N_PARAMS = sum(int(np.prod(sh)) for _, sh in PARAM_SHAPES)
@@ -179,20 +181,54 @@ def pack_params(p):
     return np.concatenate([np.asarray(p[name], dtype=np.float64).ravel() for name, _ in PARAM_SHAPES])
 
 
+def _cell(v, l, h, g):
+    """min(g-1, max(0, trunc((v - l) * (g / (h - l))))) evaluated in float32
+    exactly as written (0 for an empty span or a non-finite product)."""
+    v = np.asarray(v, dtype=np.float32)
+    l32, h32 = np.float32(l), np.float32(h)
+    span = h32 - l32
+    cs = np.float32(g) / span if span > 0 else np.float32(0.0)
+    c = ((v - l32) * cs).astype(np.float32)
+    c = np.where(np.isfinite(c), c, np.float32(0.0))
+    return np.clip(np.trunc(c), 0, g - 1).astype(np.int64)
+
+
 def radius_cells(px, py, pt, lo, hi):
     """Cell of the (x, y, t) density grid, decided in float32 exactly as
     written: c = min(G-1, max(0, trunc((v - lo) * (G / (hi - lo)))))."""
-    out = []
-    for v, l, h in ((px, lo[0], hi[0]), (py, lo[1], hi[1]), (pt, lo[3], hi[3])):
-        v = np.asarray(v, dtype=np.float32)
-        l32, h32 = np.float32(l), np.float32(h)
-        span = h32 - l32
-        cs = np.float32(GRID) / span if span > 0 else np.float32(0.0)
-        c = ((v - l32) * cs).astype(np.float32)
-        c = np.where(np.isfinite(c), c, np.float32(0.0))
-        c = np.clip(np.trunc(c), 0, GRID - 1).astype(np.int64)
-        out.append(c)
-    return out
+    return [_cell(v, l, h, GRID) for v, l, h in ((px, lo[0], hi[0]), (py, lo[1], hi[1]),
+                                                (pt, lo[3], hi[3]))]
+
+
+def radius_start_cells(px, py, pt, lo, hi):
+    """Cell of the finer trajectory-start grid (START_XY x START_XY x START_T)."""
+    return (_cell(px, lo[0], hi[0], START_XY), _cell(py, lo[1], hi[1], START_XY),
+            _cell(pt, lo[3], hi[3], START_T))
+
+
+def radius_start_grid(first_x, first_y, first_t, lo, hi):
+    """Number of trajectories whose first point falls in each cell."""
+    cx, cy, ct = radius_start_cells(first_x, first_y, first_t, lo, hi)
+    grid = np.zeros((START_XY, START_XY, START_T), dtype=np.int64)
+    np.add.at(grid, (cx, cy, ct), 1)
+    return grid
+
+
+def radius_start_count(qx, qy, qt, lo, hi, starts):
+    """Trajectory starts in the query's start-grid cell, its eight spatial
+    neighbours, and the same nine cells one time step earlier (cells outside
+    the grid contribute nothing)."""
+    cx, cy, ct = radius_start_cells(qx, qy, qt, lo, hi)
+    total = np.zeros(cx.shape, dtype=np.int64)
+    for dx in (-1, 0, 1):
+        for dy in (-1, 0, 1):
+            for dt in (-1, 0):
+                x, y, t = cx + dx, cy + dy, ct + dt
+                inside = (x >= 0) & (x < START_XY) & (y >= 0) & (y < START_XY) & (t >= 0)
+                total += np.where(inside, starts[np.clip(x, 0, START_XY - 1),
+                                                 np.clip(y, 0, START_XY - 1),
+                                                 np.clip(t, 0, START_T - 1)], 0)
+    return total
 
 
 def radius_density_grid(seg_a, seg_b, seg_tmin, seg_tmax, lo, hi):
@@ -209,9 +245,12 @@ def radius_density_grid(seg_a, seg_b, seg_tmin, seg_tmax, lo, hi):
     return grid
 
 
-def radius_features(qx, qy, qz, qt, lo, hi, grid):
+def radius_features(qx, qy, qz, qt, lo, hi, grid, starts):
     """Feature map: the four coordinates mapped to [-1, 1] over the data's
-    bounding box, and log1p of the segment count of the query's grid cell."""
+    bounding box, 0.25 log1p of the segment count of the query's grid cell,
+    and 0.5 log1p of the trajectory starts around the query in space and
+    recent time (radius_start_count): a query near the start of its own
+    trajectory has few earlier points of it, so its k-th distance is larger."""
     cols = []
     for v, l, h in zip((qx, qy, qz, qt), lo, hi):
         v = np.asarray(v, dtype=np.float64)
@@ -220,6 +259,7 @@ def radius_features(qx, qy, qz, qt, lo, hi, grid):
         cols.append((v - 0.5 * (float(l) + float(h))) * g)
     cx, cy, ct = radius_cells(qx, qy, qt, lo, hi)
     cols.append(0.25 * np.log1p(grid[cx, cy, ct].astype(np.float64)))
+    cols.append(0.5 * np.log1p(radius_start_count(qx, qy, qt, lo, hi, starts).astype(np.float64)))
     return np.stack(cols, axis=1)
 
 

@@ -322,11 +322,42 @@ def test_radius_density_grid_and_features_hand_case():
     g = oracle.radius_density_grid(a, b, tmin, tmax, lo, hi)
     # midpoints (0.5, 0.5, 5) -> cell (0, 0, 0); (3.5, 4.5, 105) and (3.5, 4.5, 109) -> (3, 4, 10)
     assert g.sum() == 3 and g[0, 0, 0] == 1 and g[3, 4, 10] == 2
+    no_starts = np.zeros((oracle.START_XY, oracle.START_XY, oracle.START_T), np.int64)
     f = oracle.radius_features(np.array([16.0, 3.9], np.float32), np.array([0.0, 4.2], np.float32),
                                np.array([10.0, 12.0], np.float32), np.array([160.0, 107.0], np.float32),
-                               lo, hi, g)
+                               lo, hi, g, no_starts)
     # centre maps to 0, edges to -1 / +1; density feature 0.25 log1p(count)
     assert np.allclose(f[0, :4], [0.0, -1.0, 0.0, 0.0])
     assert f[0, 4] == 0.0
     assert f[1, 4] == pytest.approx(0.25 * math.log(3.0))
     assert f[1, 2] == pytest.approx(1.0)
+
+
+def test_radius_start_grid_and_feature_hand_case():
+    """Trajectory starts in a box [0, 128]^2 x [0, 5120]: start-grid cells are
+    1 wide in x and y and 10 in t.  The feature counts starts in the query's
+    cell, its 8 spatial neighbours, and those 9 cells one time step earlier."""
+    lo = np.array([0.0, 0.0, 8.0, 0.0], np.float32)
+    hi = np.array([128.0, 128.0, 12.0, 5120.0], np.float32)
+    fx = np.array([5.5, 6.5, 0.2, 127.9, 8.0, 5.7], np.float32)
+    fy = np.array([5.5, 4.2, 0.7, 127.9, 5.0, 5.2], np.float32)
+    ft = np.array([105.0, 99.0, 3.0, 5119.0, 105.0, 109.9], np.float32)
+    st = oracle.radius_start_grid(fx, fy, ft, lo, hi)
+    # (5, 5, 10) twice, (6, 4, 9), (0, 0, 0), (127, 127, 511), (8, 5, 10)
+    assert st.sum() == 6 and st[5, 5, 10] == 2 and st[6, 4, 9] == 1 and st[0, 0, 0] == 1
+    assert st[127, 127, 511] == 1 and st[8, 5, 10] == 1
+    qx = np.array([5.1, 0.1, 5.1, 127.5, 5.1, 128.0], np.float32)
+    qy = np.array([5.9, 0.1, 5.9, 127.5, 5.9, 128.0], np.float32)
+    qt = np.array([101.0, 1.0, 89.0, 5119.0, 115.0, 5120.0], np.float32)
+    cnt = oracle.radius_start_count(qx, qy, qt, lo, hi, st)
+    # q0 cell (5,5,10): (5,5,10) x2 and (6,4,9); (8,5,10) is two cells away
+    # q1 cell (0,0,0): only (0,0,0) (neighbours below 0 do not exist)
+    # q2 cell (5,5,8): the starts at t-cells 9 and 10 lie in its future
+    # q3 cell (127,127,511): (127,127,511)
+    # q4 cell (5,5,11): (5,5,10) x2; (6,4,9) is two time cells back
+    # q5 on the upper edge: clamped into cell (127,127,511)
+    assert cnt.tolist() == [3, 1, 0, 1, 2, 1]
+    g = np.zeros((oracle.GRID,) * 3, np.int64)
+    f = oracle.radius_features(qx, qy, np.full(6, 10.0, np.float32), qt, lo, hi, g, st)
+    assert np.allclose(f[:, 5], 0.5 * np.log1p(np.array([3, 1, 0, 1, 2, 1], np.float64)))
+    assert np.all(f[:, 4] == 0.0)
