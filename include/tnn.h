@@ -173,23 +173,31 @@ tnn_status tnn_debug_lower_bounds(const tnn_index *index, tnn_points queries,
 /* ------------------------------------------------------------------------
  * Learned k-th radius (not in the paper): a 5-64-64-1 ReLU MLP predicting
  * log r_k, r_k = sqrt(d_k) the k-th neighbour's distance, from the query's
- * coordinates mapped to [-1, 1] over the data's bounding box and
- * 0.25*log1p(segment count of its cell in a 32^3 (x, y, t) grid).  Its
- * prediction seeds TNN_LEARNED queries; results stay exact whatever it says.
+ * coordinates mapped to [-1, 1] over the data's bounding box,
+ * 0.25*log1p(segment count of its cell in a 32^3 (x, y, t) grid), and
+ * 0.5*log1p(trajectory starts in its cell of a finer 128 x 128 x 512 grid,
+ * the 8 spatial neighbours, and those 9 cells one time step earlier; cells
+ * outside the grid add nothing).  Its prediction seeds TNN_LEARNED queries;
+ * results stay exact whatever it says.
  * ------------------------------------------------------------------------ */
 #define TNN_RADIUS_HIDDEN 64
-#define TNN_RADIUS_INPUTS 5
+#define TNN_RADIUS_INPUTS 6
 #define TNN_RADIUS_GRID 32
+#define TNN_RADIUS_START_XY 128
+#define TNN_RADIUS_START_T 512
 #define TNN_RADIUS_NPARAMS (TNN_RADIUS_HIDDEN * TNN_RADIUS_INPUTS + TNN_RADIUS_HIDDEN + \
                             TNN_RADIUS_HIDDEN * TNN_RADIUS_HIDDEN + TNN_RADIUS_HIDDEN +     \
                             TNN_RADIUS_HIDDEN + 1)
 
 /* Device layout of a radius model; its bytes are the checkpoint format. */
 typedef struct {
-  float params[TNN_RADIUS_NPARAMS]; /* W1[64][5] b1[64] W2[64][64] b2[64] W3[64] b3 */
+  float params[TNN_RADIUS_NPARAMS]; /* W1[64][6] b1[64] W2[64][64] b2[64] W3[64] b3 */
   float pad[3];
   float lo[4], hi[4];               /* bounding box of the indexed points (x, y, z, t) */
   int32_t grid[TNN_RADIUS_GRID * TNN_RADIUS_GRID * TNN_RADIUS_GRID]; /* [x][y][t] */
+  /* per cell [x][y][t]: trajectories whose first point falls in the cell, its
+   * 8 spatial neighbours, or those 9 cells one time step earlier (saturating) */
+  uint16_t starts[TNN_RADIUS_START_XY * TNN_RADIUS_START_XY * TNN_RADIUS_START_T];
 } tnn_radius_model;
 
 /* sizeof(tnn_radius_model). */

@@ -30,8 +30,10 @@ TNN_STAT_COUNT = 16
 
 # Radius model (layout of the device blob, see tnn.h)
 RADIUS_HIDDEN = 64
-RADIUS_INPUTS = 5
+RADIUS_INPUTS = 6
 RADIUS_GRID = 32
+RADIUS_START_XY = 128
+RADIUS_START_T = 512
 RADIUS_NPARAMS = RADIUS_HIDDEN * RADIUS_INPUTS + RADIUS_HIDDEN + RADIUS_HIDDEN * RADIUS_HIDDEN \
     + RADIUS_HIDDEN + RADIUS_HIDDEN + 1
 

@@ -15,7 +15,7 @@ namespace {
 
 struct BuildLayout {
   size_t pt4, pid;                             // index-order points
-  size_t f[11], pstart, pcount, sorig;          // index-order segments
+  size_t f[11], pstart, pcount, sorig, sfirst;  // index-order segments
   size_t box, sbox;                             // block and superblock boxes
   size_t tf[11], tstart, tcf, keys, perm, dpstart, status;  // build temporaries
   size_t total;
@@ -36,6 +36,7 @@ BuildLayout build_layout(int64_t n, int64_t S) {
   L.pstart = take(4 * S);
   L.pcount = take(4 * S);
   L.sorig = take(4 * S);
+  L.sfirst = take(4 * S);
   L.box = take(4 * 8 * nb);
   L.sbox = take(4 * 8 * ((nb + kSuperBlocks - 1) / kSuperBlocks));
   for (int i = 0; i < 11; ++i) L.tf[i] = take(4 * S);
@@ -260,7 +261,7 @@ tnn_status tnn_build_segments(tnn_points pts, const int64_t *h_traj_offsets, int
     dst_f[i] = F(L.f[i]);
   }
   TNN_HIP_CHECK(launch_seg_scatter(pts, S, I(L.perm), I(L.tstart), I(L.tcf), I(L.dpstart), src_f,
-                                   dst_f, I(L.pstart), I(L.pcount), I(L.sorig),
+                                   dst_f, I(L.pstart), I(L.pcount), I(L.sorig), I(L.sfirst),
                                    reinterpret_cast<float4 *>(F(L.pt4)), I(L.pid), st));
 
   IndexDesc d;
@@ -289,6 +290,7 @@ tnn_status tnn_build_segments(tnn_points pts, const int64_t *h_traj_offsets, int
   d.pstart = I(L.pstart);
   d.pcount = I(L.pcount);
   d.sorig = I(L.sorig);
+  d.sfirst = I(L.sfirst);
   d.box = F(L.box);
   TNN_HIP_CHECK(launch_block_box(d, F(L.box), st));
   std::vector<float> box(8 * (size_t)nb);

@@ -83,7 +83,7 @@ __global__ void seg_scatter_kernel(tnn_points pts, int64_t n_seg, const int32_t 
                                    const int32_t *src_start, const int32_t *src_cf,
                                    const int32_t *dst_pstart, F11 src, F11w dst,
                                    int32_t *out_pstart, int32_t *out_pcount, int32_t *out_sorig,
-                                   float4 *pt4, int32_t *pid) {
+                                   int32_t *out_first, float4 *pt4, int32_t *pid) {
   const int64_t j = blockIdx.x;
   if (j >= n_seg) return;
   const int o = perm[j];
@@ -100,6 +100,7 @@ __global__ void seg_scatter_kernel(tnn_points pts, int64_t n_seg, const int32_t 
     out_pstart[j] = d0;
     out_pcount[j] = c;
     out_sorig[j] = o;
+    out_first[j] = (src_cf[o] >> 16) & 1;
   }
 }
 
@@ -192,7 +193,8 @@ hipError_t launch_seg_scatter(const tnn_points &pts, int64_t n_seg, const int32_
                               const int32_t *src_start, const int32_t *src_cnt_flags,
                               const int32_t *dst_pstart, const float *const src_f[11],
                               float *const dst_f[11], int32_t *dst_pstart_out, int32_t *dst_pcount,
-                              int32_t *dst_sorig, float4 *pt4, int32_t *pid, hipStream_t st) {
+                              int32_t *dst_sorig, int32_t *dst_first, float4 *pt4, int32_t *pid,
+                              hipStream_t st) {
   if (n_seg == 0) return hipSuccess;
   F11 src;
   F11w dst;
@@ -202,7 +204,7 @@ hipError_t launch_seg_scatter(const tnn_points &pts, int64_t n_seg, const int32_
   }
   hipLaunchKernelGGL(seg_scatter_kernel, dim3((unsigned)n_seg), dim3(kWave), 0, st, pts, n_seg, perm,
                      src_start, src_cnt_flags, dst_pstart, src, dst, dst_pstart_out, dst_pcount,
-                     dst_sorig, pt4, pid);
+                     dst_sorig, dst_first, pt4, pid);
   return hipGetLastError();
 }
 

@@ -60,7 +60,8 @@ hipError_t launch_seg_scatter(const tnn_points &pts, int64_t n_seg, const int32_
                               const int32_t *src_start, const int32_t *src_cnt_flags,
                               const int32_t *dst_pstart, const float *const src_f[11],
                               float *const dst_f[11], int32_t *dst_pstart_out, int32_t *dst_pcount,
-                              int32_t *dst_sorig, float4 *pt4, int32_t *pid, hipStream_t st);
+                              int32_t *dst_sorig, int32_t *dst_first, float4 *pt4, int32_t *pid,
+                              hipStream_t st);
 hipError_t launch_block_box(const IndexDesc &ix, float *box, hipStream_t st);
 hipError_t launch_export(const IndexDesc &ix, float *seg_f32, int32_t *seg_i32, int32_t *point_id,
                          float *block_box, hipStream_t st);

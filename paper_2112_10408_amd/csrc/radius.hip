@@ -13,6 +13,9 @@ namespace {
 constexpr int H = TNN_RADIUS_HIDDEN;
 constexpr int NI = TNN_RADIUS_INPUTS;
 constexpr int G = TNN_RADIUS_GRID;
+constexpr int SXY = TNN_RADIUS_START_XY;
+constexpr int ST = TNN_RADIUS_START_T;
+constexpr int64_t kStartCells = (int64_t)SXY * SXY * ST;
 constexpr int NP = TNN_RADIUS_NPARAMS;
 // offsets of the parameter tensors in params[]
 constexpr int OW1 = 0, OB1 = OW1 + H * NI, OW2 = OB1 + H, OB2 = OW2 + H * H, OW3 = OB2 + H,
@@ -27,16 +30,19 @@ __host__ __device__ inline uint64_t splitmix64(uint64_t x) {
   return x ^ (x >> 31);
 }
 
-// Cell of the density grid, decided in float32 exactly as written.
-__device__ inline int cell_of(float v, float lo, float hi) {
+// Cell along one axis of a grid of n cells over [lo, hi], decided in float32
+// exactly as written: min(n-1, max(0, trunc((v - lo) * (n / (hi - lo))))).
+__device__ inline int cell_n(float v, float lo, float hi, int n) {
   const float span = hi - lo;
-  const float cs = span > 0.0f ? (float)G / span : 0.0f;
+  const float cs = span > 0.0f ? (float)n / span : 0.0f;
   float c = (v - lo) * cs;
   if (!isfinite(c)) c = 0.0f;
   c = truncf(c);
-  int i = (int)fminf(fmaxf(c, 0.0f), (float)(G - 1));
+  int i = (int)fminf(fmaxf(c, 0.0f), (float)(n - 1));
   return i;
 }
+
+__device__ inline int cell_of(float v, float lo, float hi) { return cell_n(v, lo, hi, G); }
 
 __device__ inline void features(const tnn_radius_model *m, float x, float y, float z, float t,
                                 float f[NI]) {
@@ -51,6 +57,12 @@ __device__ inline void features(const tnn_radius_model *m, float x, float y, flo
   const int cy = cell_of(y, m->lo[1], m->hi[1]);
   const int ct = cell_of(t, m->lo[3], m->hi[3]);
   f[4] = 0.25f * log1pf((float)m->grid[(cx * G + cy) * G + ct]);
+  // trajectory starts in the start-grid cell, its 8 spatial neighbours and
+  // those 9 cells one time step earlier: summed into each cell at init
+  const int sx = cell_n(x, m->lo[0], m->hi[0], SXY);
+  const int sy = cell_n(y, m->lo[1], m->hi[1], SXY);
+  const int stc = cell_n(t, m->lo[3], m->hi[3], ST);
+  f[5] = 0.5f * log1pf((float)m->starts[((int64_t)sx * SXY + sy) * ST + stc]);
 }
 
 __global__ void init_kernel(tnn_radius_model *m, uint64_t seed, IndexDesc ix) {
@@ -76,9 +88,44 @@ __global__ void init_kernel(tnn_radius_model *m, uint64_t seed, IndexDesc ix) {
   if (i < G * G * G) m->grid[i] = 0;
 }
 
+__global__ void starts_zero_kernel(tnn_radius_model *m) {
+  uint32_t *w = reinterpret_cast<uint32_t *>(m->starts);
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < kStartCells / 2;
+       i += (int64_t)gridDim.x * blockDim.x)
+    w[i] = 0u;
+}
+
+// Saturating increment of a 16-bit count inside its aligned 32-bit word.
+__device__ inline void add_start(tnn_radius_model *m, int64_t cell) {
+  uint32_t *w = reinterpret_cast<uint32_t *>(m->starts) + (cell >> 1);
+  const int shift = (int)(cell & 1) * 16;
+  uint32_t old = *w;
+  for (;;) {
+    if (((old >> shift) & 0xffffu) == 0xffffu) return;
+    const uint32_t seen = atomicCAS(w, old, old + (1u << shift));
+    if (seen == old) return;
+    old = seen;
+  }
+}
+
 __global__ void grid_kernel(tnn_radius_model *m, IndexDesc ix) {
   const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= ix.n_seg) return;
+  if (ix.sfirst[s]) {
+    // the trajectory's first point (A and t_min of its first segment) counts
+    // for every cell whose neighbourhood holds it: the 3 x 3 spatial block
+    // around its cell, at its time cell and the next
+    const int sx = cell_n(ix.ax[s], m->lo[0], m->hi[0], SXY);
+    const int sy = cell_n(ix.ay[s], m->lo[1], m->hi[1], SXY);
+    const int stc = cell_n(ix.tmin[s], m->lo[3], m->hi[3], ST);
+    for (int dx = -1; dx <= 1; ++dx)
+      for (int dy = -1; dy <= 1; ++dy)
+        for (int dt = 0; dt <= 1; ++dt) {
+          const int cx2 = sx + dx, cy2 = sy + dy, ct2 = stc + dt;
+          if (cx2 >= 0 && cx2 < SXY && cy2 >= 0 && cy2 < SXY && ct2 < ST)
+            add_start(m, ((int64_t)cx2 * SXY + cy2) * ST + ct2);
+        }
+  }
   const float mx = 0.5f * (ix.ax[s] + ix.bx[s]);
   const float my = 0.5f * (ix.ay[s] + ix.by[s]);
   const float mt = 0.5f * (ix.tmin[s] + ix.tmax[s]);
@@ -113,14 +160,15 @@ __global__ __launch_bounds__(64 * kInferWaves) void infer_kernel(
     const tnn_radius_model *__restrict__ m, tnn_points q, float alpha, float *__restrict__ radius2,
     float *__restrict__ logr) {
   __shared__ float w2s[H][H + 1];  // hidden-to-hidden weights, padded rows
-  __shared__ float4 w1s[H][2];     // first layer, per unit: weights 0..3 | weight 4, bias
+  __shared__ float4 w1s[H][2];     // first layer, per unit: weights 0..3 | weights 4, 5, bias
+  static_assert(NI == 6, "the first layer's LDS layout holds six weights and a bias per unit");
   __shared__ float part[kInferWaves][kInferTile][kInferTile + 1];
   const float *__restrict__ W = m->params;
   for (int i = threadIdx.x; i < H * H; i += blockDim.x) w2s[i / H][i % H] = W[OW2 + i];
   for (int k = threadIdx.x; k < H; k += blockDim.x) {
     w1s[k][0] = make_float4(W[OW1 + k * NI], W[OW1 + k * NI + 1], W[OW1 + k * NI + 2],
                             W[OW1 + k * NI + 3]);
-    w1s[k][1] = make_float4(W[OW1 + k * NI + 4], W[OB1 + k], 0.0f, 0.0f);
+    w1s[k][1] = make_float4(W[OW1 + k * NI + 4], W[OW1 + k * NI + 5], W[OB1 + k], 0.0f);
   }
   __syncthreads();
   const int wv = threadIdx.x >> 6;
@@ -143,14 +191,15 @@ __global__ __launch_bounds__(64 * kInferWaves) void infer_kernel(
        tile += (int64_t)gridDim.x * kInferWaves) {
     const int64_t qi = tile * kInferTile + col;
     const bool ok = qi < q.n;
-    float f[NI] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+    float f[NI] = {};
     if (ok) features(m, q.x[qi], q.y[qi], q.z[qi], q.t[qi], f);
     // first layer, the inputs this lane feeds to the matrix cores
     float h1[H / 2];
 #pragma unroll
     for (int st = 0; st < H / 2; ++st) {
       const float4 wa = w1s[2 * st + half][0], wb = w1s[2 * st + half][1];
-      const float a = wb.y + wa.x * f[0] + wa.y * f[1] + wa.z * f[2] + wa.w * f[3] + wb.x * f[4];
+      const float a =
+          wb.z + wa.x * f[0] + wa.y * f[1] + wa.z * f[2] + wa.w * f[3] + wb.x * f[4] + wb.y * f[5];
       h1[st] = fmaxf(a, 0.0f);
     }
     f32x16 c0, c1;
@@ -204,7 +253,7 @@ __global__ __launch_bounds__(kTrainBlock) void fwd_bwd_kernel(const tnn_radius_m
   __syncthreads();
   const int64_t b = (int64_t)blockIdx.x * kTrainBlock + t;
   float go = 0.0f, r2 = 0.0f;
-  float f[NI] = {0, 0, 0, 0, 0};
+  float f[NI] = {};
   if (b < batch) {
     const int64_t si = first + b;
     features(m, smp.x[si], smp.y[si], smp.z[si], smp.t[si], f);
@@ -374,6 +423,8 @@ tnn_status tnn_radius_model_init(const tnn_index *index, void *d_model, uint64_t
   tnn_radius_model *m = static_cast<tnn_radius_model *>(d_model);
   const int n = G * G * G > NP ? G * G * G : NP;
   hipLaunchKernelGGL(init_kernel, dim3((n + 255) / 256), dim3(256), 0, st, m, seed, *d);
+  TNN_HIP_CHECK(hipGetLastError());
+  hipLaunchKernelGGL(starts_zero_kernel, dim3(2048), dim3(256), 0, st, m);
   TNN_HIP_CHECK(hipGetLastError());
   if (d->n_seg > 0) {
     hipLaunchKernelGGL(grid_kernel, dim3((unsigned)((d->n_seg + 255) / 256)), dim3(256), 0, st, m,

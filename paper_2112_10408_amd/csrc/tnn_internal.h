@@ -27,6 +27,7 @@ struct IndexDesc {
   // segments (block order), SoA
   const float *ax, *ay, *az, *bx, *by, *bz, *tmin, *tmax, *ex, *ey, *ez;
   const int32_t *pstart, *pcount, *sorig;
+  const int32_t *sfirst;  // 1 for the first segment of its trajectory
   // block boxes: box[8 b + f] for f = 0..7 (lo x y z t, hi x y z t)
   const float *box;
   // superblock boxes (64 consecutive blocks each), same layout

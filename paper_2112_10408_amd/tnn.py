@@ -189,6 +189,15 @@ def radius_grid(model):
     return model[off: off + 4 * g ** 3].view(torch.int32).view(g, g, g)
 
 
+def radius_starts(model):
+    """Trajectory starts around each start-grid cell [x][y][t] (the feature's
+    neighbourhood sum; uint16 values, widened to int32)."""
+    off = (capi.RADIUS_NPARAMS + 3) * 4 + 32 + 4 * capi.RADIUS_GRID ** 3
+    sxy, st = capi.RADIUS_START_XY, capi.RADIUS_START_T
+    raw = model[off: off + 2 * sxy * sxy * st].view(torch.int16).to(torch.int32) & 0xFFFF
+    return raw.view(sxy, sxy, st)
+
+
 def tnn_radius_train_workspace(batch):
     n = ctypes.c_size_t(0)
     check(capi.lib().tnn_radius_train_workspace(int(batch), ctypes.byref(n)),
