@@ -149,10 +149,14 @@ struct Searcher {
       st.blocks += (uint32_t)min(kWave, ns - sbase);
       if (lbs < finf) maxfin = fmaxf(maxfin, lbs);
       uint64_t ms = ballot(lbs < finf && (double)lbs <= fmin(tau, tk.kd));
+      // superblocks, then blocks, in ascending order of their bounds: the
+      // nearest points arrive first, so the k-th distance prunes the rest
+      // early; once the next bound exceeds min(tau, k-th) so do all later ones
       while (ms) {
-        const int sl = __ffsll((long long)ms) - 1;
-        ms &= ms - 1;
-        if ((double)readlane_f(lbs, sl) > fmin(tau, tk.kd)) continue;
+        float smin;
+        const int sl = wave_argmin_lane(((ms >> lane) & 1ull) ? lbs : finf, smin);
+        ms &= ~(1ull << sl);
+        if ((double)smin > fmin(tau, tk.kd)) break;
         // block level: the superblock's 64 blocks, one per lane
         const int b0 = (sbase + sl) * kSuperBlocks;
         const int b = b0 + lane;
@@ -161,11 +165,12 @@ struct Searcher {
         if (lbb < finf) maxfin = fmaxf(maxfin, lbb);
         uint64_t m = ballot(lbb < finf && (double)lbb <= fmin(tau, tk.kd));
         while (m) {
-          const int bl = __ffsll((long long)m) - 1;
-          m &= m - 1;
+          float bmin;
+          const int bl = wave_argmin_lane(((m >> lane) & 1ull) ? lbb : finf, bmin);
+          m &= ~(1ull << bl);
           const double tau_cur = fmin(tau, tk.kd);
-          const double lbb_b = (double)readlane_f(lbb, bl);
-          if (lbb_b > tau_cur) continue;
+          const double lbb_b = (double)bmin;
+          if (lbb_b > tau_cur) break;
           const int bb = b0 + bl;
           const int64_t s = (int64_t)bb * kBlockSegs + lane;
           SegView sv{};
