@@ -89,9 +89,11 @@ struct Searcher {
       : ix(ix_), pr(pr_), a(a_) {}
 
   // Scan the member points of the segments of block `bb` whose lanes are set
-  // in `cm`, feeding the top-k.  Several segments share one 64-lane pass.
-  // (ps_l, pc_l): this lane's segment's first point slot and member count.
-  __device__ void scan(uint64_t cm, int bb, int ps_l, int pc_l) {
+  // in `cm`, feeding the top-k, nearest key first.  Several segments share one
+  // 64-lane pass; after each pass the segments whose key now exceeds the k-th
+  // distance are dropped.  (ps_l, pc_l, key_l): this lane's segment's first
+  // point slot, member count and key (non-negative float).
+  __device__ void scan(uint64_t cm, int bb, int ps_l, int pc_l, float key_l) {
     const int kpad = 1 << spi_shift;
     const int spi = kWave >> spi_shift;
     const int slot = lane >> spi_shift;
@@ -99,8 +101,9 @@ struct Searcher {
     while (cm) {
       int my_l = -1;
       for (int i = 0; i < spi && cm; ++i) {
-        const int l = __ffsll((long long)cm) - 1;
-        cm &= cm - 1;
+        float kmin;
+        const int l = wave_argmin_lane(((cm >> lane) & 1ull) ? key_l : __builtin_huge_valf(), kmin);
+        cm &= ~(1ull << l);
         if (slot == i) my_l = l;
       }
       const bool has = my_l >= 0;
@@ -126,6 +129,7 @@ struct Searcher {
       if (gm) {
         tk.offer(gm, gate, d, pid);
         ++st.merges;
+        cm &= ballot((double)key_l <= tk.kd);
       }
     }
   }
@@ -177,13 +181,14 @@ struct Searcher {
           if (s < S) sv = load_seg(pr, s);
           const int ps_l = sv.ps, pc_l = sv.pc;
           // both bounds hold for every member; the larger one decides the round
-          const double key = fmax(s < S ? (double)seg_lb(sv, q, a.sf) : kInf, lbb_b);
+          const float key_f = fmaxf(s < S ? seg_lb(sv, q, a.sf) : finf, bmin);
+          const double key = (double)key_f;
           st.segs += (uint32_t)min((int64_t)kBlockSegs, S - (int64_t)bb * kBlockSegs);
           const bool seeded = bb == seed_block && ((seed_mask >> lane) & 1ull);
           // a masked segment (infinite key) holds no candidate
           const bool cand = s < S && key < kInf && key <= tau_cur && key > prev && !seeded;
           const uint64_t cm = ballot(cand);
-          if (cm) scan(cm, bb, ps_l, pc_l);
+          if (cm) scan(cm, bb, ps_l, pc_l, key_f);
         }
       }
     }
@@ -284,7 +289,8 @@ __device__ __forceinline__ void answer_query(const IndexDesc &ix, const Prep &pr
       SegView sv{};
       if (s < S) sv = load_seg(pr, s);
       const int ps_l = sv.ps, pc_l = sv.pc;
-      float v = s < S ? seg_lb(sv, se.q, a.sf) : __builtin_huge_valf();
+      const float v0 = s < S ? seg_lb(sv, se.q, a.sf) : __builtin_huge_valf();
+      float v = v0;
       se.st.segs += (uint32_t)min((int64_t)kBlockSegs, S - (int64_t)bestb * kBlockSegs);
       const int F = a.seed_segments;
       for (int i = 0; i < F; ++i) {
@@ -294,7 +300,7 @@ __device__ __forceinline__ void answer_query(const IndexDesc &ix, const Prep &pr
         seed_mask |= 1ull << ml;
         if (se.lane == ml) v = __builtin_huge_valf();
       }
-      if (seed_mask) se.scan(seed_mask, bestb, ps_l, pc_l);
+      if (seed_mask) se.scan(seed_mask, bestb, ps_l, pc_l, fmaxf(v0, best));
     }
     if (se.tk.kd < kInf) {
       tau = se.tk.kd;
