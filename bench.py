@@ -181,7 +181,7 @@ def run_config(name, args, T, capi, radius, synth, torch, stream):
     seconds, binary64 brute force.  Every path is checked against plain TNN."""
     scale = synth.SCALE
     ps, qs, qidx, cfg = synth.make_config(name)
-    k, K = cfg["k"], cfg["seg_len"]
+    k, K, tw = cfg["k"], cfg["seg_len"], cfg["t_window"]
     x, y, z, t = T.to_device(ps.x, ps.y, ps.z, ps.t)
     q = T.to_device(qs.x, qs.y, qs.z, qs.t)
     torch.cuda.synchronize()
@@ -191,13 +191,14 @@ def run_config(name, args, T, capi, radius, synth, torch, stream):
     n = qs.n
     out = (torch.empty((n, k), dtype=torch.int32, device="cuda"),
            torch.empty((n, k), dtype=torch.float64, device="cuda"))
-    scratch = torch.empty(max(T.tnn_query_workspace(ix, n, T.make_params(scale, 0.0, k)), 256),
+    scratch = torch.empty(max(T.tnn_query_workspace(ix, n, T.make_params(scale, tw, k)), 256),
                           dtype=torch.uint8, device="cuda")
     steps = max(1, min(args.steps, 5))
-    res = {"points": ps.n, "queries": n, "k": k, "seg_len": K, "index_build_s": build_s}
+    res = {"points": ps.n, "queries": n, "k": k, "seg_len": K, "t_window": tw,
+           "index_build_s": build_s}
 
     def plain():
-        T.tnn_query(ix, *q, scale, 0.0, k, out=out, scratch=scratch)
+        T.tnn_query(ix, *q, scale, tw, k, out=out, scratch=scratch)
 
     ms = timed(plain, steps, 1, stream)
     ref = (out[0].clone(), out[1].clone())
@@ -211,7 +212,7 @@ def run_config(name, args, T, capi, radius, synth, torch, stream):
                                      exclude=qidx if ps.n - n >= n_tr else None)
     tx = T.to_device(tq.x, tq.y, tq.z, tq.t)
     t0 = time.perf_counter()
-    model, loss, pdist, ptr = radius.train(ix, *tx, scale, 0.0, k, epochs=args.train_epochs,
+    model, loss, pdist, ptr = radius.train(ix, *tx, scale, tw, k, epochs=args.train_epochs,
                                            batch=4096, lr=3e-3)
     torch.cuda.synchronize()
     res["radius_train_s"] = time.perf_counter() - t0
@@ -220,7 +221,7 @@ def run_config(name, args, T, capi, radius, synth, torch, stream):
     r2_tr = torch.empty(tq.n, dtype=torch.float32, device="cuda")
     out_tr = (torch.empty((tq.n, k), dtype=torch.int32, device="cuda"),
               torch.empty((tq.n, k), dtype=torch.float64, device="cuda"))
-    scr_tr = torch.empty(max(T.tnn_query_workspace(ix, tq.n, T.make_params(scale, 0.0, k)), 256),
+    scr_tr = torch.empty(max(T.tnn_query_workspace(ix, tq.n, T.make_params(scale, tw, k)), 256),
                          dtype=torch.uint8, device="cuda")
     best = None
     for qnt in ((0.7, 0.8, 0.9) if not args.radius_quantile else (args.radius_quantile,)):
@@ -228,7 +229,7 @@ def run_config(name, args, T, capi, radius, synth, torch, stream):
 
         def learned_tr():
             T.tnn_radius_infer(model, *tx, a, out=r2_tr)
-            T.tnn_query(ix, *tx, scale, 0.0, k, flags=capi.TNN_LEARNED, radius2=r2_tr,
+            T.tnn_query(ix, *tx, scale, tw, k, flags=capi.TNN_LEARNED, radius2=r2_tr,
                         out=out_tr, scratch=scr_tr)
 
         m = timed(learned_tr, 2, 1, stream)
@@ -238,12 +239,12 @@ def run_config(name, args, T, capi, radius, synth, torch, stream):
 
     def learned():
         T.tnn_radius_infer(model, *q, alpha, out=r2)
-        T.tnn_query(ix, *q, scale, 0.0, k, flags=capi.TNN_LEARNED, radius2=r2, out=out,
+        T.tnn_query(ix, *q, scale, tw, k, flags=capi.TNN_LEARNED, radius2=r2, out=out,
                     scratch=scratch)
 
     ms_l = timed(learned, steps, 1, stream)
     st = T.new_stats()
-    T.tnn_query(ix, *q, scale, 0.0, k, flags=capi.TNN_LEARNED, radius2=r2, out=out,
+    T.tnn_query(ix, *q, scale, tw, k, flags=capi.TNN_LEARNED, radius2=r2, out=out,
                 scratch=scratch, stats=st)
     torch.cuda.synchronize()
     st = T.stats_dict(st)
@@ -253,15 +254,15 @@ def run_config(name, args, T, capi, radius, synth, torch, stream):
     del out_tr, scr_tr, r2_tr
     if not args.no_brute:
         mf = capi.TNN_BRUTE | capi.TNN_MIXED_BF16
-        mscr = torch.empty(T.tnn_query_workspace(ix, n, T.make_params(scale, 0.0, k, mf)),
+        mscr = torch.empty(T.tnn_query_workspace(ix, n, T.make_params(scale, tw, k, mf)),
                            dtype=torch.uint8, device="cuda")
 
         def mixed():
-            T.tnn_query(ix, *q, scale, 0.0, k, flags=mf, out=out, scratch=mscr)
+            T.tnn_query(ix, *q, scale, tw, k, flags=mf, out=out, scratch=mscr)
 
         ms_m = timed(mixed, 1, 1, stream)
         mst = T.new_stats()
-        T.tnn_query(ix, *q, scale, 0.0, k, flags=mf, out=out, scratch=mscr, stats=mst)
+        T.tnn_query(ix, *q, scale, tw, k, flags=mf, out=out, scratch=mscr, stats=mst)
         torch.cuda.synchronize()
         mst = T.stats_dict(mst)
         res.update(mixed_brute_qps=n / ms_m * 1e3,
@@ -271,7 +272,7 @@ def run_config(name, args, T, capi, radius, synth, torch, stream):
         del mscr
         if float(ps.n) * n <= 2e12:
             def brute():
-                T.tnn_query(ix, *q, scale, 0.0, k, flags=capi.TNN_BRUTE, out=out, scratch=scratch)
+                T.tnn_query(ix, *q, scale, tw, k, flags=capi.TNN_BRUTE, out=out, scratch=scratch)
 
             ms_b = timed(brute, 1, 1, stream)
             res.update(brute_qps=n / ms_b * 1e3,
@@ -293,7 +294,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--airspaces", type=int, default=64)
     ap.add_argument("--no-configs", action="store_true",
-                    help="skip the 10k-point, 1M-query and 8M-point workloads")
+                    help="skip the other workloads (10k points, 1M queries, 8M points, "
+                         "30-min window, airways, random points)")
     ap.add_argument("--train-epochs", type=int, default=8)
     ap.add_argument("--radius-quantile", type=float, default=0.8,
                     help="calibration quantile of the radius safety factor; 0 sweeps "
@@ -472,7 +474,10 @@ def main():
     if not args.no_configs:
         res["configs"] = {}
         for name, label in (("c1", "10k_points_k8"), ("c3", "1M_points_1M_queries_k32"),
-                            ("c4", "8M_points_1M_queries_k64")):
+                            ("c4", "8M_points_1M_queries_k64"),
+                            ("c2w", "1M_points_100k_queries_k32_window_30min"),
+                            ("routes", "1M_points_40_airways_100k_queries_k32"),
+                            ("rand", "1M_random_points_100k_queries_k32")):
             res["configs"][label] = run_config(name, args, T, capi, radius, synth, torch, stream)
             torch.cuda.empty_cache()
     if not args.no_batched:

@@ -118,6 +118,44 @@ def random_points(n: int, box_km: float, span_s: float, seg_len: int,
     return PointSet(x.astype(f), y.astype(f), z.astype(f), t.astype(f), offsets)
 
 
+def routes(n_traj: int, n_pts: int, box_km: float, span_s: float, n_routes: int,
+           seed: int) -> PointSet:
+    """Route-clustered traffic, closer to recorded flights than uniform
+    headings: ``n_routes`` straight airways cross the box (a random point and
+    direction each); every trajectory follows one of them in either
+    direction, starting at a uniform position along it, with a lateral offset
+    ~ N(0, 5) km, a flight level in {9, 10, 11, 12} km plus N(0, 0.02) km,
+    speed ~ N(230, 15) m/s and heading drift ~ N(0, 0.1 deg) per 4 s step.
+    Start times ~ U[0, T] s."""
+    rng = np.random.default_rng(seed)
+    rx = rng.uniform(0.0, box_km, n_routes)
+    ry = rng.uniform(0.0, box_km, n_routes)
+    rh = rng.uniform(0.0, math.pi, n_routes)
+    r = rng.integers(0, n_routes, n_traj)
+    back = rng.random(n_traj) < 0.5
+    along = rng.uniform(-0.5 * box_km, 0.5 * box_km, n_traj)
+    lateral = rng.normal(0.0, 5.0, n_traj)
+    h0 = rh[r] + np.where(back, math.pi, 0.0)
+    x0 = rx[r] + along * np.cos(rh[r]) - lateral * np.sin(rh[r])
+    y0 = ry[r] + along * np.sin(rh[r]) + lateral * np.cos(rh[r])
+    z0 = rng.integers(9, 13, n_traj) + rng.normal(0.0, 0.02, n_traj)
+    t0 = rng.uniform(0.0, span_s, n_traj)
+    v = rng.normal(230.0, 15.0, n_traj)
+    dh = rng.normal(0.0, math.radians(0.1), (n_traj, n_pts - 1))
+    h = h0[:, None] + np.concatenate([np.zeros((n_traj, 1)), np.cumsum(dh, axis=1)], axis=1)
+    step = 4.0 * v[:, None] / 1000.0
+    dx = np.concatenate([np.zeros((n_traj, 1)), (step * np.cos(h))[:, :-1]], axis=1)
+    dy = np.concatenate([np.zeros((n_traj, 1)), (step * np.sin(h))[:, :-1]], axis=1)
+    x = x0[:, None] + np.cumsum(dx, axis=1)
+    y = y0[:, None] + np.cumsum(dy, axis=1)
+    z = np.repeat(z0[:, None], n_pts, axis=1)
+    t = t0[:, None] + 4.0 * np.arange(n_pts)[None, :]
+    offsets = np.arange(n_traj + 1, dtype=np.int64) * n_pts
+    f = np.float32
+    return PointSet(x.ravel().astype(f), y.ravel().astype(f), z.ravel().astype(f),
+                    t.ravel().astype(f), offsets)
+
+
 def sample_queries(ps: PointSet, n_queries: int | None, seed: int,
                    exclude: np.ndarray | None = None) -> tuple[PointSet, np.ndarray]:
     """Queries are data points, sampled uniformly without replacement
@@ -149,13 +187,30 @@ CONFIGS = {
     "c4": dict(n_traj=20000, n_pts=400, box_km=6000.0, span_s=24 * 3600.0,
                seg_len=32, k=64, n_queries=1_000_000, n_train=200_000,
                seed=SEED_BASE + 4),
+    # the paper's production setting: only points at least 30 min old
+    "c2w": dict(n_traj=5000, n_pts=200, box_km=3000.0, span_s=12 * 3600.0,
+                seg_len=32, k=32, n_queries=100_000, seed=SEED_BASE + 2, t_window=1800.0),
+    # Sec. 4.2's random points: TNN cannot prune, results must stay exact
+    "rand": dict(kind="random", n=1_000_000, box_km=3000.0, span_s=12 * 3600.0,
+                 seg_len=32, k=32, n_queries=100_000, seed=SEED_BASE + 6),
+    # traffic along 40 airways
+    "routes": dict(kind="routes", n_traj=5000, n_pts=200, box_km=3000.0, span_s=12 * 3600.0,
+                   n_routes=40, seg_len=32, k=32, n_queries=100_000, seed=SEED_BASE + 7),
 }
 
 
 def make_config(name: str):
     """Return (points, queries, query point indices, cfg dict)."""
     cfg = dict(CONFIGS[name])
-    ps = trajectories(cfg["n_traj"], cfg["n_pts"], cfg["box_km"], cfg["span_s"], cfg["seed"])
+    cfg.setdefault("t_window", 0.0)
+    kind = cfg.get("kind", "trajectories")
+    if kind == "random":
+        ps = random_points(cfg["n"], cfg["box_km"], cfg["span_s"], cfg["seg_len"], cfg["seed"])
+    elif kind == "routes":
+        ps = routes(cfg["n_traj"], cfg["n_pts"], cfg["box_km"], cfg["span_s"], cfg["n_routes"],
+                    cfg["seed"])
+    else:
+        ps = trajectories(cfg["n_traj"], cfg["n_pts"], cfg["box_km"], cfg["span_s"], cfg["seed"])
     if name == "c4":
         rng = np.random.default_rng(cfg["seed"] + 1000)
         perm = rng.permutation(ps.n)

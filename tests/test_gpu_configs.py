@@ -70,3 +70,29 @@ def test_8m_points_learned_radius_k64():
     say("c4 learned stats", s, "fallback rate", s["fallbacks"] / qs.n)
     assert s["fallbacks"] < 0.5 * qs.n
     _sample_check(ps, qs, li.cpu().numpy(), ld.cpu().numpy(), k, n=96)
+
+
+@pytest.mark.parametrize("name", ["c2w", "routes", "rand"])
+def test_window_airways_random_full_size(name):
+    """1M points, 100k queries, k = 32: the 30-minute window, 40 airways and
+    random points.  Learned and BF16 paths equal plain TNN on every query; a
+    sample is checked against the oracle."""
+    ps, qs, qidx, cfg = config_data(name)
+    k, tw = cfg["k"], cfg["t_window"]
+    say(name, "build")
+    ix = build(ps, cfg["seg_len"])
+    q = dev_points(qs)
+    pi, pd = T.tnn_query(ix, *q, SCALE, tw, k)
+    tq, _ = synth.sample_queries(ps, 20_000, 99, exclude=qidx)
+    model, _, pdist, ptr = radius.train(ix, *dev_points(tq), SCALE, tw, k, epochs=4, batch=4096)
+    alpha = radius.calibrate(model, *ptr, pdist, k, quantile=0.8)
+    r2 = T.tnn_radius_infer(model, *q, alpha)
+    li, ld = T.tnn_query(ix, *q, SCALE, tw, k, flags=capi.TNN_LEARNED, radius2=r2)
+    mi, md = T.tnn_query(ix, *q, SCALE, tw, k, flags=capi.TNN_BRUTE | capi.TNN_MIXED_BF16)
+    torch.cuda.synchronize()
+    assert torch.equal(pi, li) and torch.equal(pd, ld)
+    assert torch.equal(pi, mi) and torch.equal(pd, md)
+    rng = np.random.default_rng(11)
+    sample = np.sort(rng.choice(qs.n, 128, replace=False))
+    oi, od = oracle.knn(ps.soa(), qs.take(sample).soa(), SCALE, tw, k)
+    assert_same(pi.cpu().numpy()[sample], pd.cpu().numpy()[sample], oi, od, name)

@@ -262,3 +262,32 @@ def test_mixed_precision_error_is_within_the_proven_margin():
     n_max = (s * np.maximum((lo - c) ** 2, (hi - c) ** 2)).sum()
     assert st["rescored"] >= qs.n * 1  # every query rescored at least its neighbours
     assert 0.0 < st["max_err"] <= 2.0 ** -16 * 2 * n_max
+
+
+def _workload(kind):
+    if kind == "random":
+        ps = synth.random_points(20_000, 300.0, 3600.0, 32, seed=41)
+    elif kind == "routes":
+        ps = synth.routes(100, 200, 300.0, 3600.0, 6, seed=42)
+    else:
+        ps = synth.trajectories(100, 200, 300.0, 3600.0, seed=43)
+    qs, _ = synth.sample_queries(ps, 1500, seed=44)
+    return ps, qs
+
+
+@pytest.mark.parametrize("kind", ["random", "routes", "trajectories"])
+@pytest.mark.parametrize("t_window", [0.0, 1800.0])
+@pytest.mark.parametrize("flags", ALL_PATHS + [capi.TNN_LEARNED])
+def test_second_workloads_and_window(kind, t_window, flags):
+    """Random points (Sec. 4.2: no structure to prune with), traffic along a few
+    airways, and the 30-minute context window, every query against the oracle."""
+    ps, qs = _workload(kind)
+    say("workload", kind, t_window, flags)
+    ix = build(ps, 32)
+    kw = {}
+    if flags == capi.TNN_LEARNED:
+        rng = np.random.default_rng(7)
+        kw["radius2"] = torch.from_numpy(np.exp(rng.normal(6, 2, qs.n)).astype(np.float32)).cuda()
+    gi, gd = gpu_query(ix, qs, SCALE, t_window, 32, flags=flags, **kw)
+    oi, od = oracle.knn(ps.soa(), qs.soa(), SCALE, t_window, 32)
+    assert_same(gi, gd, oi, od, f"{kind} tw={t_window}")
