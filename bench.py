@@ -33,13 +33,13 @@ FLOPS_POINT = 15           # binary64 exact distance
 # HBM traffic of one learned-radius search launch on this workload, from two
 # rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE, KiB per dispatch), each
 # scaled by what the counter reads for a 256 MiB device-to-device copy
-# (FETCH_SIZE x 2.00, WRITE_SIZE x 1.00): 187,000 KiB fetched and 40,598 KiB
+# (FETCH_SIZE x 2.00, WRITE_SIZE x 1.00): 102,500 KiB fetched and 40,598 KiB
 # written.  It describes the kernel built from the sources with this SHA-256
 # only; after any change to them the figure is reported as null.
 KERNEL_SOURCES = ("query.hip", "bounds.h", "wave.h", "tnn_internal.h")
 MEASURED_TRAFFIC = {
-    "sha256": "2a029f906a3b032d34e3b3db11de2af1e4fbd2d5899f8d5fd4b179aa7ef45173",
-    "bytes_per_launch": 424.55e6,
+    "sha256": "d0c720dcd476f5c270d4c8811f89ad31d3de7ac4317aea90f0b972471123b3cc",
+    "bytes_per_launch": 251.5e6,
 }
 
 
