@@ -16,8 +16,12 @@ Pieces and the passage each follows:
                         non-squared units, masked time gap (Sec. 3.4 masked
                         distance and pruning criterion, Algorithm 1), in the
                         corrected reading (printed form is not a lower bound).
+* ``gka_average``    -- Gaussian kernel averaging of measured values over the
+                        context of each query (Sec. 3.2, Eq. gka), the context
+                        being the k nearest past points; the exponent read as
+                        decaying, exp(-d) with d the scaled squared distance.
 * ``radius_*``/``mlp_*``/``adam_step`` -- the learned k-th radius predictor
-                        (not in the paper): feature map, a 5-64-64-1 ReLU MLP,
+                        (not in the paper): feature map, a 6-64-64-1 ReLU MLP,
                         squared-error loss on log r_k, its gradient by
                         backpropagation, and Adam (Kingma & Ba 2015, Alg. 1).
 """
@@ -335,3 +339,36 @@ def finite_difference_grad(params, X, y, h=1e-6, which=None):
         tm[i] -= h
         g[i] = (mlp_loss(tp, X, y) - mlp_loss(tm, X, y)) / (2.0 * h)
     return g
+
+
+# ----------------------------------------------------------------------------
+# Gaussian kernel averaging over the k-NN context (Sec. 3.2, Eq. gka).
+# ----------------------------------------------------------------------------
+def gka_average(idx, dist, values):
+    """Forecast per query: sum_c w_c v_c / sum_c w_c over the context slots c
+    with idx >= 0, w_c = exp(-d_c) where d_c = sum_f s_f (q_f - p_f)^2 is the
+    scaled squared distance the k-NN search returns (the printed exponent
+    carries no minus sign; only a decaying kernel gives an average weighted
+    towards the nearer measurements, Sec. 3.2).  The weights are taken
+    relative to the nearest slot, exp(-(d_c - d_0)), which leaves the ratio
+    unchanged and keeps far contexts from underflowing to 0/0.  A query
+    without context gets NaN.  idx [Q, k], dist [Q, k], values [N, C] ->
+    [Q, C] binary64."""
+    idx = np.asarray(idx, dtype=np.int64)
+    dist = np.asarray(dist, dtype=np.float64)
+    values = np.asarray(values, dtype=np.float64).reshape(len(values), -1)
+    nq, k = idx.shape
+    out = np.full((nq, values.shape[1]), np.nan)
+    for q in range(nq):
+        used = [r for r in range(k) if idx[q, r] >= 0 and math.isfinite(dist[q, r])]
+        if not used:
+            continue
+        d0 = dist[q, used[0]]
+        num = np.zeros(values.shape[1])
+        den = 0.0
+        for r in used:
+            w = math.exp(-(dist[q, r] - d0))
+            num += w * values[idx[q, r]]
+            den += w
+        out[q] = num / den
+    return out

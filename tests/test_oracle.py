@@ -361,3 +361,34 @@ def test_radius_start_grid_and_feature_hand_case():
     f = oracle.radius_features(qx, qy, np.full(6, 10.0, np.float32), qt, lo, hi, g, st)
     assert np.allclose(f[:, 5], 0.5 * np.log1p(np.array([3, 1, 0, 1, 2, 1], np.float64)))
     assert np.all(f[:, 4] == 0.0)
+
+
+def test_gka_average_closed_forms():
+    """Gaussian kernel averaging over the k-NN context (Sec. 3.2, Eq. gka):
+    closed-form cases of exp(-d) weights."""
+    vals = np.array([[1.0, -2.0], [3.0, 5.0], [10.0, 0.5], [7.0, 7.0]])
+    # one neighbour: its value
+    out = oracle.gka_average(np.array([[2, -1]]), np.array([[4.0, np.inf]]), vals)
+    assert np.array_equal(out, [[10.0, 0.5]])
+    # d1 - d0 = ln 2: weights 1 and 1/2
+    d0 = 3.0
+    out = oracle.gka_average(np.array([[0, 1]]), np.array([[d0, d0 + math.log(2.0)]]), vals)
+    want = (vals[0] + 0.5 * vals[1]) / 1.5
+    assert np.allclose(out[0], want, rtol=1e-15)
+    # equal distances: the plain mean, whatever the distance (no underflow)
+    out = oracle.gka_average(np.array([[0, 1, 3]]), np.array([[1e6, 1e6, 1e6]]), vals)
+    assert np.allclose(out[0], vals[[0, 1, 3]].mean(axis=0), rtol=1e-15)
+    # no context: NaN
+    out = oracle.gka_average(np.array([[-1, -1]]), np.array([[np.inf, np.inf]]), vals)
+    assert np.all(np.isnan(out))
+    # constant values stay constant; a common shift of the distances changes nothing
+    c = np.full((4, 2), 2.5)
+    d = np.array([[0.3, 1.7, 2.2, 9.0]])
+    i4 = np.array([[3, 0, 2, 1]])
+    assert np.allclose(oracle.gka_average(i4, d, c), 2.5, rtol=1e-15)
+    a = oracle.gka_average(i4, d, vals)
+    b = oracle.gka_average(i4, d + 123.0, vals)
+    assert np.allclose(a, b, rtol=1e-14)
+    # far neighbours barely count: exp(-50) relative weight
+    out = oracle.gka_average(np.array([[1, 2]]), np.array([[0.0, 50.0]]), vals)
+    assert np.allclose(out[0], vals[1], rtol=1e-20, atol=1e-19 * 10)
