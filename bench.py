@@ -400,6 +400,24 @@ def main():
         f"{qs.n / ms_learned * 1e3:.0f} q/s, same as plain {exact}, fallbacks {st['fallbacks']}")
     log("learned stats:", st)
 
+    # ---- Gaussian kernel averaging over the context (Sec. 3.2, Eq. gka) ----
+    # synthetic 2-component wind measurements, one per point
+    wind = torch.from_numpy(np.random.default_rng(cfg["seed"] + 3000)
+                            .normal(0.0, 15.0, (ps.n, 2)).astype(np.float32)).cuda()
+    gka_out = torch.empty((qs.n, 2), dtype=torch.float64, device="cuda")
+    T.tnn_radius_infer(model, qx, qy, qz, qt, alpha, out=r2)
+    T.tnn_query(ix, qx, qy, qz, qt, scale, 0.0, k, flags=capi.TNN_LEARNED, radius2=r2,
+                out=out, scratch=scratch)
+    ms_gka = timed(lambda: T.tnn_gka_average(out[0], out[1], wind, out=gka_out), args.steps, 1,
+                   stream)
+
+    def learned_gka():
+        learned()
+        T.tnn_gka_average(out[0], out[1], wind, out=gka_out)
+
+    ms_learned_gka = timed(learned_gka, args.steps, 1, stream)
+    log(f"GKA average: {ms_gka:.3f} ms; learned TNN + GKA {ms_learned_gka:.3f} ms/step")
+
     if args.calib_copy:
         src = torch.empty(64 << 20, dtype=torch.float32, device="cuda").fill_(1.0)
         dst = torch.empty_like(src)
@@ -466,6 +484,7 @@ def main():
         "plain_qps": qs.n / ms_plain * 1e3, "learned_qps": value,
         "learned_speedup_vs_plain": ms_plain / ms_learned,
         "learned_matches_plain": exact, "fallback_rate": st["fallbacks"] / qs.n,
+        "gka_average_ms": ms_gka, "learned_plus_gka_qps": qs.n / ms_learned_gka * 1e3,
         "radius_alpha": alpha, "radius_quantile": best[1], "radius_train_s": train_s,
         "radius_train_queries": args.train_queries,
         "index_build_s": build_s, "stats_learned": st, "stats_plain": st_plain,

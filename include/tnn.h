@@ -314,6 +314,31 @@ tnn_status tnn_autotune_batched(const tnn_batch_item *items, int32_t n_items, vo
                                 size_t bytes, void *stream, const char *cache_path,
                                 tnn_batch_config *best);
 
+/* ------------------------------------------------------------------------
+ * Gaussian kernel averaging over the k-NN context (Sec. 3.2, Eq. gka): the
+ * forecast at each query is sum_c w_c v_c / sum_c w_c over its context slots
+ * c (the k neighbours tnn_query returned, slots with index -1 skipped), with
+ * w_c = exp(-d_c) and d_c the returned scaled squared distance, i.e. the
+ * kernel's (sigma_xy, sigma_xy, sigma_z, sigma_t) are the search scales.  The
+ * printed exponent has no minus sign; only a decaying kernel weights nearer
+ * measurements more.  Weights are computed relative to the nearest slot,
+ * exp(-(d_c - d_0)), which leaves the ratio unchanged and avoids 0/0 for far
+ * contexts.  Binary64 throughout.
+ * ------------------------------------------------------------------------ */
+
+/*
+ * d_idx, d_dist: device [n_queries * k], as tnn_query wrote them.
+ * d_values: device float32 [n_points * n_comp], row p = the measurement at
+ * caller point p (n_comp 1..8 components, e.g. a wind vector).
+ * d_out: device binary64 [n_queries * n_comp]; NaN rows for queries without
+ * context.  Indices outside [0, n_points) count as empty slots.  Async; no
+ * scratch.  Errors: TNN_E_ARG for null pointers (with n_queries > 0), k outside
+ * 1..64, n_comp outside 1..8, negative sizes.
+ */
+tnn_status tnn_gka_average(const int32_t *d_idx, const double *d_dist, int64_t n_queries,
+                           int32_t k, const float *d_values, int32_t n_comp, int64_t n_points,
+                           double *d_out, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -93,6 +93,7 @@ _SIGS = {
     "tnn_radius_train_step": (i32, [P, P, TnnPoints, P, i32, i64, i64, i32, f32, P, P, sz, P]),
     "tnn_radius_features": (i32, [P, TnnPoints, P, P]),
     "tnn_radius_infer": (i32, [P, TnnPoints, f32, P, P, P]),
+    "tnn_gka_average": (i32, [P, P, i64, i32, P, i32, i64, P, P]),
     "tnn_batch_workspace": (i32, [ctypes.POINTER(TnnBatchItem), i32, ctypes.POINTER(sz)]),
     "tnn_batch_prepare": (i32, [ctypes.POINTER(TnnBatchItem), i32, ctypes.POINTER(TnnBatchConfig),
                                 P, sz, P, ctypes.POINTER(TnnBatchPlan)]),

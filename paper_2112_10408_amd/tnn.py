@@ -246,6 +246,20 @@ def tnn_radius_infer(model, qx, qy, qz, qt, alpha=1.0, out=None, logr=None):
     return out
 
 
+def tnn_gka_average(idx, dist, values, out=None):
+    """Gaussian kernel averaging of `values` (float32 [n_points, n_comp] on the
+    device, caller point order) over each query's context (idx, dist from
+    tnn_query).  Returns binary64 [n_queries, n_comp]."""
+    nq, k = idx.shape
+    vals = values if values.dim() == 2 else values.view(-1, 1)
+    n_comp = vals.shape[1]
+    if out is None:
+        out = torch.empty((nq, n_comp), dtype=torch.float64, device=idx.device)
+    check(capi.lib().tnn_gka_average(_ptr(idx), _ptr(dist), nq, k, _ptr(vals), n_comp,
+                                     vals.shape[0], _ptr(out), _stream()), "tnn_gka_average")
+    return out
+
+
 # --------------------------------------------------------------------------
 # Batched ragged serving
 # --------------------------------------------------------------------------

@@ -105,3 +105,15 @@ def test_binding_signatures_match_header_arity():
     assert counts
     for name, n in counts.items():
         assert len(getattr(L, name).argtypes) == n, name
+
+
+def test_gka_rejects_bad_arguments_without_gpu():
+    L = capi.lib()
+    E = capi.TNN_E_ARG
+    assert L.tnn_gka_average(None, None, 10, 0, None, 2, 100, None, None) == E    # k = 0
+    assert L.tnn_gka_average(None, None, 10, 65, None, 2, 100, None, None) == E   # k > 64
+    assert L.tnn_gka_average(None, None, 10, 8, None, 0, 100, None, None) == E    # no component
+    assert L.tnn_gka_average(None, None, 10, 8, None, 9, 100, None, None) == E    # too many
+    assert L.tnn_gka_average(None, None, -1, 8, None, 2, 100, None, None) == E    # negative count
+    assert L.tnn_gka_average(None, None, 10, 8, None, 2, 100, None, None) == E    # null buffers
+    assert L.tnn_gka_average(None, None, 0, 8, None, 2, 100, None, None) == capi.TNN_OK  # nothing to do

@@ -291,3 +291,27 @@ def test_second_workloads_and_window(kind, t_window, flags):
     gi, gd = gpu_query(ix, qs, SCALE, t_window, 32, flags=flags, **kw)
     oi, od = oracle.knn(ps.soa(), qs.soa(), SCALE, t_window, 32)
     assert_same(gi, gd, oi, od, f"{kind} tw={t_window}")
+
+
+@pytest.mark.parametrize("k,n_comp", [(1, 1), (8, 2), (32, 3), (64, 8)])
+def test_gka_average_matches_oracle(k, n_comp):
+    """Gaussian kernel averaging (Sec. 3.2, Eq. gka) over the context the
+    search returns, against the oracle on the same context; queries early in
+    the data have empty or short contexts."""
+    ps = synth.trajectories(60, 90, 40.0, 900.0, seed=21)
+    _, qi = synth.sample_queries(ps, 700, seed=22)
+    qs = ps.take(np.concatenate([qi, np.argsort(ps.t)[:3]]))  # the earliest have no past
+    ix = build(ps, 16)
+    scale = (0.5, 0.5, 4.0, 0.02)
+    q = dev_points(qs)
+    gi, gd = T.tnn_query(ix, *q, scale, 0.0, k)
+    rng = np.random.default_rng(k)
+    vals = rng.normal(0.0, 10.0, (ps.n, n_comp)).astype(np.float32)
+    out = T.tnn_gka_average(gi, gd, torch.from_numpy(vals).cuda())
+    torch.cuda.synchronize()
+    want = oracle.gka_average(gi.cpu().numpy(), gd.cpu().numpy(), vals)
+    got = out.cpu().numpy()
+    assert np.array_equal(np.isnan(got), np.isnan(want))
+    assert np.isnan(want).any() and not np.isnan(want).all()
+    ok = ~np.isnan(want)
+    assert np.allclose(got[ok], want[ok], rtol=1e-12, atol=1e-12)
