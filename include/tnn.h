@@ -171,7 +171,7 @@ tnn_status tnn_debug_lower_bounds(const tnn_index *index, tnn_points queries,
 
 
 /* ------------------------------------------------------------------------
- * Learned k-th radius (not in the paper): a 5-64-64-1 ReLU MLP predicting
+ * Learned k-th radius (not in the paper): a 6-64-64-1 ReLU MLP predicting
  * log r_k, r_k = sqrt(d_k) the k-th neighbour's distance, from the query's
  * coordinates mapped to [-1, 1] over the data's bounding box,
  * 0.25*log1p(segment count of its cell in a 32^3 (x, y, t) grid), and

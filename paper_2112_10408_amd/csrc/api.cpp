@@ -350,7 +350,7 @@ tnn_status tnn_query_workspace(const tnn_index *index, int64_t n_queries,
   const tnn_status c = check_params(params, n_queries);
   if (c != TNN_OK) return c;
   if (params->flags & TNN_MIXED_BF16)
-    *bytes = mixed_scratch_bytes(d->n_points);
+    *bytes = mixed_scratch_bytes(d->n_points, n_queries, params->k);
   else
     *bytes = (params->flags & TNN_BRUTE) ? 256 : prep_bytes(d->n_seg);
   return TNN_OK;

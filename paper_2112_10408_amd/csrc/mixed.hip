@@ -14,6 +14,8 @@
 //     c' = (1 - gamma)(|u|^2 + |v|^2) - 2 u.v  <=  d(q, p)
 // because the split, the float32 accumulation of 32 terms and the float32
 // inputs err by at most 1.6 * 2^-18 (|u|^2 + |v|^2), below gamma = 2^-16.
+#include <mutex>
+
 #include "bounds.h"
 #include "query.h"
 
@@ -24,8 +26,17 @@ typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
 
 constexpr float kGamma = 0x1p-16f;
-constexpr int kMQ = 16;      // queries per wave (MFMA rows)
-constexpr int kStep = 64;    // points per step (four 16-column MFMA tiles)
+constexpr int kWaves = 4;                 // waves per workgroup
+constexpr int kMQ = 16;                   // queries per wave (the MFMA rows)
+constexpr int kTileQ = kWaves * kMQ;      // queries per work item
+constexpr int kStage = 128;               // points per LDS stage
+constexpr int kStageTiles = kStage / 16;  // 16-column MFMA tiles per stage
+constexpr int kQCap = 64;                 // queued survivors per wave (one row of a tile)
+constexpr int kMaxChunks = 8;             // point chunks per query tile
+// Workgroups resident on a full chip, nominally (256 CUs x 3): only sets
+// how finely the points are chunked, so the workspace size does not depend
+// on the device.
+constexpr int64_t kNominalSlots = 768;
 
 __device__ __forceinline__ __bf16 to_bf16(float x) {
   // round to nearest even (finite inputs)
@@ -147,191 +158,458 @@ __device__ __forceinline__ bf16x8 query_group(const float u[4], float nus, int g
   return o;
 }
 
-// Per call: the point operands in index order (4 groups of 8 bf16 per
-// point, 64 bytes), |v|^2 and a copy of the times (read densely by the
-// distance tiles).
-__global__ void mixed_prep_kernel(IndexDesc ix, MixedCtx mc, bf16x8 *ops, float *nv, float *tv) {
+// Per call: the point operands and |v|^2.  Operands are stored tile-major:
+// the 16-byte group g of point p sits at unit (p / 16 * 4 + g) * 16 + p % 16,
+// so a 16-point MFMA tile is 1 KB laid out lane by lane and a stage is one
+// contiguous block.  Operands are padded to whole stages with zeros.
+__global__ void mixed_prep_kernel(IndexDesc ix, MixedCtx mc, bf16x8 *ops, float *nv,
+                                  int64_t n_pad) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= ix.n_points) return;
+  if (p >= n_pad) return;
+  const int64_t unit0 = (p >> 4) * 64 + (p & 15);
+  if (p >= ix.n_points) {
+#pragma unroll
+    for (int g = 0; g < 4; ++g) ops[unit0 + 16 * g] = bf16x8{};
+    return;
+  }
   float v[4];
   const float4 pv = ix.pt4[p];
-  tv[p] = pv.w;
   const float n = scaled(mc, pv.x, pv.y, pv.z, pv.w, v);
   const float ns = (1.0f - kGamma) * n;
 #pragma unroll
-  for (int g = 0; g < 4; ++g) ops[4 * p + g] = point_group(v, ns, g);
+  for (int g = 0; g < 4; ++g) ops[unit0 + 16 * g] = point_group(v, ns, g);
   nv[p] = n;
+}
+
+// Per call: no chunk has a k-th distance yet; the work counter starts at 0.
+__global__ void mixed_reset_kernel(float *part_kd, int64_t n, unsigned long long *counter) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) part_kd[i] = __builtin_huge_valf();
+  if (i == 0) *counter = 0;
 }
 
 __device__ __forceinline__ float round_up_f(double x) {
   return x < kInf ? __double2float_ru(x) : __builtin_huge_valf();
 }
 
-// One wavefront = one workgroup answers 16 queries (the MFMA rows).  Point
-// operands stream straight from global memory (64 points per step, four
-// 16-column MFMA tiles); no workgroup barrier is needed.  Per-query state in
-// LDS: the top-k (k entries) and a candidate queue of one step's points.
-__global__ __launch_bounds__(64) void mixed_brute_kernel(
-    IndexDesc ix, QueryArgs a, MixedCtx mc, const bf16x8 *ops, const float *nv, const float *tv,
-    const float *qxp,
-    const float *qyp, const float *qzp, const float *qtp, int64_t nq, int32_t *out_idx,
-    double *out_dist, int64_t tile_stride) {
-  extern __shared__ double s_dyn[];
-  const int k = a.k;
-  double *s_tkd = s_dyn;                                            // [kMQ][k]
-  int *s_tkid = reinterpret_cast<int *>(s_tkd + kMQ * k);           // [kMQ][k]
-  int *s_qp = s_tkid + kMQ * k;                                     // [kMQ][kStep]
-  float *s_qc = reinterpret_cast<float *>(s_qp + kMQ * kStep);      // [kMQ][kStep]
-  int *s_qn = reinterpret_cast<int *>(s_qc + kMQ * kStep);          // [kMQ]
-  float *s_tau = reinterpret_cast<float *>(s_qn + kMQ);             // [kMQ]
-  float *s_thr = s_tau + kMQ;                                       // [kMQ]
-  float *s_nu = s_thr + kMQ;                                        // [kMQ]
+// What only the rescoring needs, parked in LDS so that the scan loop keeps
+// few scalar registers live.
+struct SlowArgs {
+  double s[4];
+  double t_window;
+  double inf;
+  const float *nv;
+  unsigned long long *stats;
+  int k;
+};
 
+// LDS stage buffer: the operands of kStage points (tile-major), their
+// coordinates and their caller indices.
+struct Stage {
+  bf16x8 op[kStage * 4];
+  float4 pt[kStage];
+  int pid[kStage];
+};
+
+// Work item = (query tile of kTileQ queries, chunk of the point stages).
+// A persistent grid of 4-wave workgroups takes items from a counter, chunk
+// by chunk.  The workgroup streams the chunk's stages through two LDS
+// buffers (loaded by all 256 lanes, one stage ahead), and each wave answers
+// its 16 queries against every stage: a tile whose values all exceed their
+// queries' bounds costs one LDS read, one MFMA and four compares per lane.
+// For the others the survivors (bound and time mask passed) go to the wave's
+// queue (slots from ballots), which is rescored in binary64 from the staged
+// coordinates (one lane per survivor) and merged into each query's top-k in
+// LDS.  A query's bound starts at the least k-th distance among the chunks
+// of its tile already finished (each is an upper bound on the final k-th
+// distance), and each chunk's top-k goes to a partial list that
+// mixed_merge_kernel combines.
+__global__ __launch_bounds__(kWaves * 64) void mixed_brute_kernel(
+    IndexDesc ix, QueryArgs a, MixedCtx mc, const bf16x8 *ops, const float *nv, const float *qxp,
+    const float *qyp, const float *qzp, const float *qtp, int64_t nq, double *part_d,
+    int32_t *part_i, float *part_kd, unsigned long long *counter, int64_t n_tiles, int n_chunks,
+    int64_t n_steps, int64_t tile_stride) {
+  // 16-byte aligned: the stage buffers are read with 16-byte LDS loads
+  extern __shared__ float4 s_dyn4[];
+  __shared__ SlowArgs s_a;
+  __shared__ long long s_item;
+  __shared__ float4 s_q[kWaves][kMQ];   // query coordinates (x, y, z, t)
+  __shared__ float s_tau[kWaves][kMQ];  // bound on the top-k's k-th distance, rounded up
+  __shared__ float s_nu[kWaves][kMQ];   // |u|^2 of each query
+  __shared__ int s_qp[kWaves][kQCap];   // queued survivor: index in the stage
+  __shared__ float s_qc[kWaves][kQCap];  //                 its tile value
+  __shared__ unsigned char s_qm[kWaves][kQCap];  //         its query row
+  const int k = a.k;
   const int lane = lane_id();
-  const int64_t qbase = (int64_t)blockIdx.x * kMQ;
+  const int wave = (int)(threadIdx.x >> 6);
+  const int tid = (int)threadIdx.x;
   const int g = lane >> 4;    // K-group this lane supplies
   const int row = lane & 15;  // A row (query) / C column (point)
-  const int64_t qa = qbase + row;
-  float u[4] = {0, 0, 0, 0};
-  float nu = 0.0f;
-  if (qa < nq) nu = scaled(mc, qxp[qa], qyp[qa], qzp[qa], qtp[qa], u);
-  const bf16x8 aop = query_group(u, (1.0f - kGamma) * nu, g);
-  if (lane < kMQ) {
-    const int64_t q = qbase + lane;
-    s_qn[lane] = 0;
-    s_nu[lane] = nu;
-    if (q < nq) {
-      s_tau[lane] = __builtin_huge_valf();
-      s_thr[lane] = round_up_f((double)qtp[q] - a.t_window);
-    } else {
-      s_tau[lane] = -__builtin_huge_valf();  // inactive row: nothing passes
-      s_thr[lane] = -__builtin_huge_valf();
-    }
+  // dynamic LDS: the two stages, then per wave the top-k of its queries
+  Stage *s_stage = reinterpret_cast<Stage *>(s_dyn4);
+  double *s_tkd = reinterpret_cast<double *>(s_stage + 2) + (size_t)wave * kMQ * k;   // [kMQ][k]
+  int *s_tkid = reinterpret_cast<int *>(reinterpret_cast<double *>(s_stage + 2) +
+                                        (size_t)kWaves * kMQ * k) +
+                (size_t)wave * kMQ * k;  // [kMQ][k]
+  if (tid == 0) {
+    for (int f = 0; f < 4; ++f) s_a.s[f] = a.s[f];
+    s_a.t_window = a.t_window;
+    s_a.inf = a.inf;
+    s_a.nv = nv;
+    s_a.stats = a.stats;
+    s_a.k = k;
   }
-  for (int i = lane; i < kMQ * k; i += 64) {
-    s_tkd[i] = a.inf;
-    s_tkid[i] = kNoId;
-  }
-  __syncthreads();
+  const int64_t n_real = ix.n_points;
   uint32_t rescored = 0;
   double max_err = 0.0;
-  const int64_t n = ix.n_points;
-  const int64_t n_steps = (n + kStep - 1) / kStep;
-  float tau[4], thr[4];
+  int64_t queries_done = 0;
+
+  // Rescore the wave's queued survivors (stage `st`, first point p0) in
+  // binary64, one lane each, and merge them query by query.
+  auto flush = [&](int queued, const Stage *st, int64_t p0) {
+    const int kk = __builtin_amdgcn_readfirstlane(s_a.k);
+    double sc[4];
 #pragma unroll
-  for (int e = 0; e < 4; ++e) {
-    tau[e] = s_tau[g * 4 + e];
-    thr[e] = s_thr[g * 4 + e];
-  }
-  for (int64_t si = 0; si < n_steps; ++si) {
-    // Steps in a scattered order: index order is spatially sorted, and a
-    // scan that approaches the query gradually would improve the k-th
-    // distance at almost every point, sending nearly all of them to the
-    // binary64 rescoring.  tile_stride is coprime with n_steps.
-    const int64_t p0 = (int64_t)(((unsigned long long)si * (unsigned long long)tile_stride) %
-                                 (unsigned long long)n_steps) * kStep;
-    bf16x8 bop[kStep / 16];
-    float pts[kStep / 16];
-#pragma unroll
-    for (int cb = 0; cb < kStep / 16; ++cb) {
-      const int64_t p = p0 + cb * 16 + row;
-      bf16x8 v = {};
-      float t = __builtin_huge_valf();
-      if (p < n) {
-        v = ops[4 * p + g];
-        t = tv[p];
-      }
-      bop[cb] = v;
-      pts[cb] = t;
-    }
-    bool any = false;
-#pragma unroll
-    for (int cb = 0; cb < kStep / 16; ++cb) {
-      f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aop, bop[cb], acc, 0, 0, 0);
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        // row (query) g*4+e, column (point) cb*16 + row; the point's time is
-        // held by the lane that loaded column `row`, i.e. this lane
-        if ((acc[e] <= tau[e]) & (pts[cb] < thr[e])) {
-          const int m = g * 4 + e;
-          const int slot = atomicAdd(&s_qn[m], 1);
-          s_qp[m * kStep + slot] = (int)(p0 + cb * 16 + row);
-          s_qc[m * kStep + slot] = acc[e];
-          any = true;
-        }
-      }
-    }
-    if (!ballot(any)) continue;
-    // ---- rescore survivors in binary64 and merge them into each top-k
-    for (int m = 0; m < kMQ; ++m) {
-      const int cnt = s_qn[m];
-      const int64_t q = qbase + m;
-      if (cnt == 0 || q >= nq) continue;
-      const QueryPoint qp = make_query(qxp[q], qyp[q], qzp[q], qtp[q], a.t_window);
-      const bool has = lane < cnt;
-      const int p = has ? s_qp[m * kStep + lane] : 0;
-      double d = a.inf;
-      int pid = kNoId;
-      bool valid = false;
-      if (has) {
-        const float4 pv = ix.pt4[p];
-        const float pt = pv.w;
-        d = exact_dist(a.s, qp.x, qp.y, qp.z, qp.t, pv.x, pv.y, pv.z, pt);
-        pid = ix.pid[p];
-        valid = (double)pt < qp.thr;
-        const double approx = (double)s_qc[m * kStep + lane] +
-                              (double)kGamma * ((double)s_nu[m] + (double)nv[p]);
+    for (int f = 0; f < 4; ++f) sc[f] = s_a.s[f];
+    const double tw = s_a.t_window, inf = s_a.inf;
+    const bool want_err = s_a.stats != nullptr;
+    const bool has = lane < queued;
+    int mi = -1;
+    double d = inf;
+    int pid = kNoId;
+    bool valid = false;
+    if (has) {
+      mi = s_qm[wave][lane];
+      const int j = s_qp[wave][lane];
+      const float4 qv = s_q[wave][mi];
+      const QueryPoint qp = make_query(qv.x, qv.y, qv.z, qv.w, tw);
+      const float4 pv = st->pt[j];
+      d = exact_dist(sc, qp.x, qp.y, qp.z, qp.t, pv.x, pv.y, pv.z, pv.w);
+      pid = st->pid[j];
+      valid = (double)pv.w < qp.thr;
+      if (want_err) {
+        const double approx = (double)s_qc[wave][lane] +
+                              (double)kGamma * ((double)s_nu[wave][mi] + (double)s_a.nv[p0 + j]);
         max_err = fmax(max_err, fabs(approx - d));
       }
-      rescored += (uint32_t)cnt;
+    }
+    uint64_t pending = ballot(has);
+    while (pending) {
+      const int m = __builtin_amdgcn_readlane(mi, __ffsll((long long)pending) - 1);
+      const bool mine = has && mi == m;
+      pending &= ~ballot(mine);
       TopK tk;
-      tk.init(k, a.inf);
-      if (lane < k) {
-        tk.d = s_tkd[m * k + lane];
-        tk.id = s_tkid[m * k + lane];
+      tk.init(kk, inf);
+      if (lane < kk) {
+        tk.d = s_tkd[m * kk + lane];
+        tk.id = s_tkid[m * kk + lane];
       }
       tk.refresh();
-      const bool gate = valid && tk.admits(d, pid);
+      const bool gate = mine && valid && tk.admits(d, pid);
       const uint64_t gm = ballot(gate);
       if (gm) {
         tk.offer(gm, gate, d, pid);
-        if (lane < k) {
-          s_tkd[m * k + lane] = tk.d;
-          s_tkid[m * k + lane] = tk.id;
+        if (lane < kk) {
+          s_tkd[m * kk + lane] = tk.d;
+          s_tkid[m * kk + lane] = tk.id;
         }
-        if (lane == 0) s_tau[m] = round_up_f(tk.kd);
+        if (lane == 0) s_tau[wave][m] = round_up_f(tk.kd);
       }
-      if (lane == 0) s_qn[m] = 0;
+    }
+    rescored += (uint32_t)queued;
+  };
+
+  const int64_t n_items = n_tiles * n_chunks;
+  for (;;) {
+    if (tid == 0) s_item = (long long)atomicAdd(counter, 1ull);
+    __syncthreads();
+    const long long item = s_item;
+    if (item >= n_items) break;
+    const int chunk = (int)(item / n_tiles);
+    const int64_t qbase = (item % n_tiles) * kTileQ + wave * kMQ;
+
+    // ---- this wave's queries: A operands, bounds, time thresholds
+    float tau[4], thr[4];
+    bf16x8 aop;
+    {
+      const int64_t qa = qbase + row;
+      float u[4] = {0, 0, 0, 0};
+      float nu = 0.0f;
+      if (qa < nq) nu = scaled(mc, qxp[qa], qyp[qa], qzp[qa], qtp[qa], u);
+      aop = query_group(u, (1.0f - kGamma) * nu, g);
+      if (g == 0) s_nu[wave][row] = nu;
     }
 #pragma unroll
-    for (int e = 0; e < 4; ++e) tau[e] = s_tau[g * 4 + e];
-  }
-  for (int m = 0; m < kMQ; ++m) {
-    const int64_t q = qbase + m;
-    if (q < nq && lane < k) {
-      const int id = s_tkid[m * k + lane];
-      out_idx[q * k + lane] = id == kNoId ? -1 : id;
-      out_dist[q * k + lane] = s_tkd[m * k + lane];
+    for (int e = 0; e < 4; ++e) {
+      const int64_t q = qbase + g * 4 + e;
+      float t = -__builtin_huge_valf();  // an inactive row lets nothing pass
+      float h = -__builtin_huge_valf();
+      if (q < nq) {
+        t = __builtin_huge_valf();
+        for (int c = 0; c < n_chunks; ++c)
+          if (c != chunk) t = fminf(t, part_kd[q * n_chunks + c]);
+        h = round_up_f((double)qtp[q] - a.t_window);
+      }
+      tau[e] = t;
+      thr[e] = h;
     }
+    if (lane < kMQ) {
+      const int64_t q = qbase + lane;
+      s_q[wave][lane] = q < nq ? make_float4(qxp[q], qyp[q], qzp[q], qtp[q]) : make_float4(0, 0, 0, 0);
+      s_tau[wave][lane] = __builtin_huge_valf();
+    }
+    for (int i = lane; i < kMQ * k; i += 64) {
+      s_tkd[i] = a.inf;
+      s_tkid[i] = kNoId;
+    }
+
+    // ---- stream the chunk's stages
+    const int64_t s_lo = n_steps * chunk / n_chunks, s_hi = n_steps * (chunk + 1) / n_chunks;
+    // stage of step si: (si * tile_stride) mod n_steps
+    int64_t sb = (int64_t)(((unsigned long long)s_lo * (unsigned long long)tile_stride) %
+                           (unsigned long long)n_steps);
+    bf16x8 r_op[2];  // this lane's share of the next stage
+    float4 r_pt = make_float4(0, 0, 0, 0);
+    int r_pid = kNoId;
+    auto load_stage = [&](int64_t stage) {
+      const bf16x8 *src = ops + stage * (kStage * 4);
+      r_op[0] = src[tid];
+      r_op[1] = src[tid + kWaves * 64];
+      // lanes 0..127 fetch the coordinates, 128..255 the indices
+      const int64_t p = stage * kStage + (tid & (kStage - 1));
+      if (tid < kStage) {
+        r_pt = p < n_real ? ix.pt4[p] : make_float4(0, 0, 0, __builtin_huge_valf());
+      } else {
+        r_pid = p < n_real ? ix.pid[p] : kNoId;
+      }
+    };
+    auto store_stage = [&](int buf) {
+      Stage *dst = s_stage + buf;
+      dst->op[tid] = r_op[0];
+      dst->op[tid + kWaves * 64] = r_op[1];
+      if (tid < kStage)
+        dst->pt[tid] = r_pt;
+      else
+        dst->pid[tid - kStage] = r_pid;
+    };
+    auto next_stage = [&](int64_t x) {
+      x += tile_stride;
+      return x >= n_steps ? x - n_steps : x;
+    };
+    load_stage(sb);
+    store_stage(0);
+    int64_t sb_next = next_stage(sb);
+    if (s_lo + 1 < s_hi) load_stage(sb_next);
+    __syncthreads();
+    for (int64_t si = s_lo; si < s_hi; ++si) {
+      const int buf = (int)((si - s_lo) & 1);
+      const Stage *st = s_stage + buf;
+      const int64_t p0 = sb * kStage;
+      // all operand reads, then all MFMAs, then the tests: no dependency
+      // between tiles, so the latencies overlap
+      bf16x8 b[kStageTiles];
+#pragma unroll
+      for (int cb = 0; cb < kStageTiles; ++cb) b[cb] = st->op[cb * 64 + lane];
+      f32x4 acc[kStageTiles];
+#pragma unroll
+      for (int cb = 0; cb < kStageTiles; ++cb) {
+        const f32x4 z = {0.0f, 0.0f, 0.0f, 0.0f};
+        acc[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aop, b[cb], z, 0, 0, 0);
+      }
+      uint32_t near_tiles = 0;  // tiles with a value within its query's bound
+#pragma unroll
+      for (int cb = 0; cb < kStageTiles; ++cb) {
+        bool near = false;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) near |= acc[cb][e] <= tau[e];
+        near_tiles |= (ballot(near) != 0 ? 1u : 0u) << cb;
+      }
+      while (near_tiles) {
+        const int cb = __ffs(near_tiles) - 1;
+        near_tiles &= near_tiles - 1;
+        const f32x4 z = {0.0f, 0.0f, 0.0f, 0.0f};
+        const f32x4 acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aop, st->op[cb * 64 + lane], z, 0, 0, 0);
+        const int j = cb * 16 + row;  // this lane's point in the stage
+        const float pt = st->pt[j].w;
+        int queued = 0;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          // row (query) g*4+e, column (point) j; padding has time +inf
+          const float v = acc1[e];
+          const bool pass = (v <= tau[e]) & (pt < thr[e]);
+          const uint64_t pm = ballot(pass);
+          if (pm == 0) continue;
+          const int np = __popcll(pm);
+          if (queued + np > kQCap) {
+            flush(queued, st, p0);
+            queued = 0;
+          }
+          if (pass) {
+            const int slot = queued + (int)__builtin_amdgcn_mbcnt_hi(
+                                          (uint32_t)(pm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)pm, 0u));
+            s_qp[wave][slot] = j;
+            s_qc[wave][slot] = v;
+            s_qm[wave][slot] = (unsigned char)(g * 4 + e);
+          }
+          queued += np;
+        }
+        if (queued == 0) continue;
+        flush(queued, st, p0);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) tau[e] = fminf(tau[e], s_tau[wave][g * 4 + e]);
+      }
+      // the other buffer was last read before the previous barrier
+      if (si + 1 < s_hi) store_stage(buf ^ 1);
+      __syncthreads();
+      sb = sb_next;
+      sb_next = next_stage(sb);
+      if (si + 2 < s_hi) load_stage(sb_next);
+    }
+
+    // ---- this chunk's top-k of each query, and its k-th distance
+    for (int m = 0; m < kMQ; ++m) {
+      const int64_t q = qbase + m;
+      if (q >= nq) break;
+      const size_t o = ((size_t)q * n_chunks + chunk) * k;
+      if (lane < k) {
+        part_d[o + lane] = s_tkd[m * k + lane];
+        part_i[o + lane] = s_tkid[m * k + lane];
+      }
+      if (lane == 0) part_kd[q * n_chunks + chunk] = round_up_f(s_tkd[m * k + k - 1]);
+    }
+    if (chunk == 0) {
+      const int64_t left = nq - qbase;
+      queries_done += left < 0 ? 0 : (left > kMQ ? kMQ : left);
+    }
+    __syncthreads();
   }
   if (a.stats) {
     for (int o = 32; o > 0; o >>= 1) max_err = fmax(max_err, __shfl_xor(max_err, o, 64));
     if (lane == 0) {
-      int64_t nvalid = nq - qbase;
-      nvalid = nvalid < 0 ? 0 : (nvalid > kMQ ? kMQ : nvalid);
-      atomicAdd(a.stats + TNN_STAT_QUERIES, (unsigned long long)nvalid);
-      atomicAdd(a.stats + TNN_STAT_POINTS, (unsigned long long)(nvalid * n));
+      atomicAdd(a.stats + TNN_STAT_QUERIES, (unsigned long long)queries_done);
+      atomicAdd(a.stats + TNN_STAT_POINTS, (unsigned long long)(queries_done * ix.n_points));
       atomicAdd(a.stats + TNN_STAT_RESCORED, (unsigned long long)rescored);
       atomicMax(a.stats + TNN_STAT_MAX_ERR, (unsigned long long)__double_as_longlong(max_err));
     }
   }
 }
 
+// One wave per query: the exact top-k of the union of its chunks' partial
+// lists (each sorted by (distance, index), padded with (+inf, none)).
+__global__ __launch_bounds__(256) void mixed_merge_kernel(const double *part_d,
+                                                          const int32_t *part_i, int n_chunks,
+                                                          int64_t nq, int k, double inf,
+                                                          int32_t *out_idx, double *out_dist) {
+  const int64_t q = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (q >= nq) return;
+  const int lane = lane_id();
+  TopK tk;
+  tk.init(k, inf);
+  for (int c = 0; c < n_chunks; ++c) {
+    const size_t o = ((size_t)q * n_chunks + c) * k;
+    double d = inf;
+    int id = kNoId;
+    if (lane < k) {
+      d = part_d[o + lane];
+      id = part_i[o + lane];
+    }
+    if (c == 0) {
+      tk.d = d;
+      tk.id = id;
+      tk.refresh();
+      continue;
+    }
+    const bool gate = id != kNoId && tk.admits(d, id);
+    const uint64_t gm = ballot(gate);
+    if (gm) tk.offer(gm, gate, d, id);
+  }
+  if (lane < k) {
+    out_idx[q * k + lane] = tk.id == kNoId ? -1 : tk.id;
+    out_dist[q * k + lane] = tk.d;
+  }
+}
+
 }  // namespace
 
-size_t mixed_scratch_bytes(int64_t n_points) {
-  return align_up((size_t)n_points * 64) + 2 * align_up((size_t)n_points * 4);
+// Points padded to whole stages.
+static int64_t padded_points(int64_t n_points) {
+  return (n_points + kStage - 1) / kStage * kStage;
+}
+
+// Point chunks per query tile: enough work items to keep a full chip busy
+// to the end, at most one chunk per stage.
+static int mixed_chunks(int64_t n_points, int64_t nq) {
+  const int64_t tiles = (nq + kTileQ - 1) / kTileQ;
+  const int64_t stages = padded_points(n_points) / kStage;
+  int64_t c = tiles > 0 ? (8 * kNominalSlots + tiles - 1) / tiles : 1;
+  if (c > kMaxChunks) c = kMaxChunks;
+  if (c > stages) c = stages;
+  return c < 1 ? 1 : (int)c;
+}
+
+namespace {
+struct MixedLayout {
+  int64_t np, chunks;
+  size_t ops, nv, part_d, part_i, part_kd, counter, total;
+};
+
+MixedLayout mixed_layout(int64_t n_points, int64_t nq, int k) {
+  MixedLayout l;
+  l.np = padded_points(n_points);
+  l.chunks = mixed_chunks(n_points, nq);
+  const size_t entries = (size_t)nq * l.chunks * k;
+  size_t o = 0;
+  l.ops = o;
+  o += align_up((size_t)l.np * 64);
+  l.nv = o;
+  o += align_up((size_t)n_points * 4);
+  l.part_d = o;
+  o += align_up(entries * 8);
+  l.part_i = o;
+  o += align_up(entries * 4);
+  l.part_kd = o;
+  o += align_up((size_t)nq * l.chunks * 4);
+  l.counter = o;
+  o += 256;
+  l.total = o;
+  return l;
+}
+
+// Workgroups of mixed_brute_kernel resident on one CU, per (device, LDS).
+int mixed_per_cu(size_t lds) {
+  struct Entry {
+    int dev;
+    size_t lds;
+    int per_cu;
+  };
+  static Entry cache[16];
+  static int used = 0;
+  static std::mutex mu;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) dev = -1;
+  std::lock_guard<std::mutex> lock(mu);
+  for (int i = 0; i < used; ++i)
+    if (cache[i].dev == dev && cache[i].lds == lds) return cache[i].per_cu;
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, mixed_brute_kernel, kWaves * 64, lds) !=
+          hipSuccess ||
+      n <= 0)
+    n = 1;
+  if (used < 16) cache[used++] = Entry{dev, lds, n};
+  return n;
+}
+
+int cu_count_mixed() {
+  int dev = 0, c = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 256;
+  if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || c <= 0)
+    return 256;
+  return c;
+}
+}  // namespace
+
+size_t mixed_scratch_bytes(int64_t n_points, int64_t n_queries, int k) {
+  return mixed_layout(n_points, n_queries, k).total;
 }
 
 MixedCtx make_ctx(const IndexDesc &ix, const QueryArgs &a) {
@@ -347,18 +625,31 @@ hipError_t launch_mixed_brute(const IndexDesc &ix, const QueryArgs &a, const tnn
                               int32_t *out_idx, double *out_dist, void *scratch, hipStream_t st) {
   if (qs.n == 0) return hipSuccess;
   const MixedCtx mc = make_ctx(ix, a);
-  bf16x8 *ops = static_cast<bf16x8 *>(scratch);
-  float *nv = reinterpret_cast<float *>(static_cast<char *>(scratch) +
-                                        align_up((size_t)ix.n_points * 64));
-  float *tv = reinterpret_cast<float *>(reinterpret_cast<char *>(nv) +
-                                        align_up((size_t)ix.n_points * 4));
-  if (ix.n_points > 0) {
-    hipLaunchKernelGGL(mixed_prep_kernel, dim3((unsigned)((ix.n_points + 255) / 256)), dim3(256), 0,
-                       st, ix, mc, ops, nv, tv);
-    const hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+  const MixedLayout l = mixed_layout(ix.n_points, qs.n, a.k);
+  char *base = static_cast<char *>(scratch);
+  bf16x8 *ops = reinterpret_cast<bf16x8 *>(base + l.ops);
+  float *nv = reinterpret_cast<float *>(base + l.nv);
+  double *part_d = reinterpret_cast<double *>(base + l.part_d);
+  int32_t *part_i = reinterpret_cast<int32_t *>(base + l.part_i);
+  float *part_kd = reinterpret_cast<float *>(base + l.part_kd);
+  unsigned long long *counter = reinterpret_cast<unsigned long long *>(base + l.counter);
+  const int64_t n_steps = l.np / kStage;
+  const int64_t n_tiles = (qs.n + kTileQ - 1) / kTileQ;
+  const int64_t n_kd = qs.n * l.chunks;
+  if (n_steps == 0) {
+    // no points: merging no lists leaves every slot a pad
+    hipLaunchKernelGGL(mixed_merge_kernel, dim3((unsigned)((qs.n + 3) / 4)), dim3(256), 0, st,
+                       part_d, part_i, 0, qs.n, a.k, a.inf, out_idx, out_dist);
+    return hipGetLastError();
   }
-  const int64_t n_steps = (ix.n_points + kStep - 1) / kStep;
+  hipLaunchKernelGGL(mixed_prep_kernel, dim3((unsigned)((l.np + 255) / 256)), dim3(256), 0, st, ix,
+                     mc, ops, nv, l.np);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(mixed_reset_kernel, dim3((unsigned)((n_kd + 255) / 256)), dim3(256), 0, st,
+                     part_kd, n_kd, counter);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
   int64_t stride = 1;
   if (n_steps > 2) {
     auto gcd = [](int64_t x, int64_t y) {
@@ -372,10 +663,17 @@ hipError_t launch_mixed_brute(const IndexDesc &ix, const QueryArgs &a, const tnn
     stride = (int64_t)(0.6180339887 * (double)n_steps) | 1;
     while (gcd(stride, n_steps) != 1) stride += 2;
   }
-  const size_t lds = (size_t)kMQ * a.k * 12 + (size_t)kMQ * kStep * 8 + (size_t)kMQ * 16;
-  hipLaunchKernelGGL(mixed_brute_kernel, dim3((unsigned)((qs.n + kMQ - 1) / kMQ)), dim3(64), lds,
-                     st, ix, a, mc, ops, nv, tv, qs.x, qs.y, qs.z, qs.t, qs.n, out_idx, out_dist,
-                     stride);
+  const size_t lds = 2 * sizeof(Stage) + (size_t)kWaves * kMQ * a.k * 12;
+  const int64_t items = n_tiles * l.chunks;
+  const int64_t resident = (int64_t)cu_count_mixed() * mixed_per_cu(lds);
+  const int64_t grid = items < resident ? items : resident;
+  hipLaunchKernelGGL(mixed_brute_kernel, dim3((unsigned)grid), dim3(kWaves * 64), lds, st, ix, a,
+                     mc, ops, nv, qs.x, qs.y, qs.z, qs.t, qs.n, part_d, part_i, part_kd, counter,
+                     n_tiles, (int)l.chunks, n_steps, stride);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(mixed_merge_kernel, dim3((unsigned)((qs.n + 3) / 4)), dim3(256), 0, st, part_d,
+                     part_i, (int)l.chunks, qs.n, a.k, a.inf, out_idx, out_dist);
   return hipGetLastError();
 }
 

@@ -43,7 +43,7 @@ hipError_t launch_query(const IndexDesc &ix, const Prep &pr, const QueryArgs &a,
                         double *out_dist, hipStream_t st);
 hipError_t launch_brute(const IndexDesc &ix, const QueryArgs &a, const tnn_points &qs,
                         int waves_per_block, int32_t *out_idx, double *out_dist, hipStream_t st);
-size_t mixed_scratch_bytes(int64_t n_points);
+size_t mixed_scratch_bytes(int64_t n_points, int64_t n_queries, int k);
 hipError_t launch_mixed_brute(const IndexDesc &ix, const QueryArgs &a, const tnn_points &qs,
                               int32_t *out_idx, double *out_dist, void *scratch, hipStream_t st);
 hipError_t launch_debug_lb(const IndexDesc &ix, const Prep &pr, const QueryArgs &a,

@@ -1,4 +1,4 @@
-// Learned k-th radius: a 5-64-64-1 ReLU MLP (float32) with hand-written
+// Learned k-th radius: a 6-64-64-1 ReLU MLP (float32) with hand-written
 // inference, forward/backward and Adam kernels.  Not part of the paper; it
 // only seeds the search radius of TNN_LEARNED queries.
 #include <cmath>
