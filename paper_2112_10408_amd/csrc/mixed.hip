@@ -32,6 +32,7 @@ constexpr int kTileQ = kWaves * kMQ;      // queries per work item
 constexpr int kStage = 128;               // points per LDS stage
 constexpr int kStageTiles = kStage / 16;  // 16-column MFMA tiles per stage
 constexpr int kQCap = 64;                 // queued survivors per wave (one row of a tile)
+constexpr int kBatch = 4;                 // tiles whose reads and MFMAs are issued together
 constexpr int kMaxChunks = 8;             // point chunks per query tile
 // Workgroups resident on a full chip, nominally (256 CUs x 3): only sets
 // how finely the points are chunked, so the workspace size does not depend
@@ -219,11 +220,12 @@ struct Stage {
 // queries' bounds costs one LDS read, one MFMA and four compares per lane.
 // For the others the survivors (bound and time mask passed) go to the wave's
 // queue (slots from ballots), which is rescored in binary64 from the staged
-// coordinates (one lane per survivor) and merged into each query's top-k in
-// LDS.  A query's bound starts at the least k-th distance among the chunks
-// of its tile already finished (each is an upper bound on the final k-th
-// distance), and each chunk's top-k goes to a partial list that
-// mixed_merge_kernel combines.
+// coordinates (one lane per survivor) and merged into each query's top-k.
+// That top-k is kept in place in the chunk's list in global memory (L2
+// resident while the item runs): LDS holds only the stages, so four
+// workgroups fit on a CU.  A query's bound starts at the least k-th distance
+// among the chunks of its tile already finished (each is an upper bound on
+// the final k-th distance), and mixed_merge_kernel combines the chunk lists.
 __global__ __launch_bounds__(kWaves * 64) void mixed_brute_kernel(
     IndexDesc ix, QueryArgs a, MixedCtx mc, const bf16x8 *ops, const float *nv, const float *qxp,
     const float *qyp, const float *qzp, const float *qtp, int64_t nq, double *part_d,
@@ -245,12 +247,8 @@ __global__ __launch_bounds__(kWaves * 64) void mixed_brute_kernel(
   const int tid = (int)threadIdx.x;
   const int g = lane >> 4;    // K-group this lane supplies
   const int row = lane & 15;  // A row (query) / C column (point)
-  // dynamic LDS: the two stages, then per wave the top-k of its queries
+  // dynamic LDS: the two stages
   Stage *s_stage = reinterpret_cast<Stage *>(s_dyn4);
-  double *s_tkd = reinterpret_cast<double *>(s_stage + 2) + (size_t)wave * kMQ * k;   // [kMQ][k]
-  int *s_tkid = reinterpret_cast<int *>(reinterpret_cast<double *>(s_stage + 2) +
-                                        (size_t)kWaves * kMQ * k) +
-                (size_t)wave * kMQ * k;  // [kMQ][k]
   if (tid == 0) {
     for (int f = 0; f < 4; ++f) s_a.s[f] = a.s[f];
     s_a.t_window = a.t_window;
@@ -263,6 +261,11 @@ __global__ __launch_bounds__(kWaves * 64) void mixed_brute_kernel(
   uint32_t rescored = 0;
   double max_err = 0.0;
   int64_t queries_done = 0;
+  // The current item's top-k of query row m lives in place in its chunk list
+  // (in the L2 while the item runs): tkd_base[m * tk_stride + rank].
+  double *tkd_base = part_d;
+  int *tkid_base = part_i;
+  int64_t tk_stride = k;
 
   // Rescore the wave's queued survivors (stage `st`, first point p0) in
   // binary64, one lane each, and merge them query by query.
@@ -301,8 +304,8 @@ __global__ __launch_bounds__(kWaves * 64) void mixed_brute_kernel(
       TopK tk;
       tk.init(kk, inf);
       if (lane < kk) {
-        tk.d = s_tkd[m * kk + lane];
-        tk.id = s_tkid[m * kk + lane];
+        tk.d = tkd_base[m * tk_stride + lane];
+        tk.id = tkid_base[m * tk_stride + lane];
       }
       tk.refresh();
       const bool gate = mine && valid && tk.admits(d, pid);
@@ -310,8 +313,8 @@ __global__ __launch_bounds__(kWaves * 64) void mixed_brute_kernel(
       if (gm) {
         tk.offer(gm, gate, d, pid);
         if (lane < kk) {
-          s_tkd[m * kk + lane] = tk.d;
-          s_tkid[m * kk + lane] = tk.id;
+          tkd_base[m * tk_stride + lane] = tk.d;
+          tkid_base[m * tk_stride + lane] = tk.id;
         }
         if (lane == 0) s_tau[wave][m] = round_up_f(tk.kd);
       }
@@ -358,10 +361,14 @@ __global__ __launch_bounds__(kWaves * 64) void mixed_brute_kernel(
       s_q[wave][lane] = q < nq ? make_float4(qxp[q], qyp[q], qzp[q], qtp[q]) : make_float4(0, 0, 0, 0);
       s_tau[wave][lane] = __builtin_huge_valf();
     }
-    for (int i = lane; i < kMQ * k; i += 64) {
-      s_tkd[i] = a.inf;
-      s_tkid[i] = kNoId;
-    }
+    tk_stride = (int64_t)n_chunks * k;
+    tkd_base = part_d + ((size_t)qbase * n_chunks + chunk) * k;
+    tkid_base = part_i + ((size_t)qbase * n_chunks + chunk) * k;
+    for (int m = 0; m < kMQ && qbase + m < nq; ++m)
+      if (lane < k) {
+        tkd_base[m * tk_stride + lane] = a.inf;
+        tkid_base[m * tk_stride + lane] = kNoId;
+      }
 
     // ---- stream the chunk's stages
     const int64_t s_lo = n_steps * chunk / n_chunks, s_hi = n_steps * (chunk + 1) / n_chunks;
@@ -407,22 +414,25 @@ __global__ __launch_bounds__(kWaves * 64) void mixed_brute_kernel(
       const int64_t p0 = sb * kStage;
       // all operand reads, then all MFMAs, then the tests: no dependency
       // between tiles, so the latencies overlap
-      bf16x8 b[kStageTiles];
-#pragma unroll
-      for (int cb = 0; cb < kStageTiles; ++cb) b[cb] = st->op[cb * 64 + lane];
-      f32x4 acc[kStageTiles];
-#pragma unroll
-      for (int cb = 0; cb < kStageTiles; ++cb) {
-        const f32x4 z = {0.0f, 0.0f, 0.0f, 0.0f};
-        acc[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aop, b[cb], z, 0, 0, 0);
-      }
       uint32_t near_tiles = 0;  // tiles with a value within its query's bound
 #pragma unroll
-      for (int cb = 0; cb < kStageTiles; ++cb) {
-        bool near = false;
+      for (int c0 = 0; c0 < kStageTiles; c0 += kBatch) {
+        bf16x8 b[kBatch];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) near |= acc[cb][e] <= tau[e];
-        near_tiles |= (ballot(near) != 0 ? 1u : 0u) << cb;
+        for (int c = 0; c < kBatch; ++c) b[c] = st->op[(c0 + c) * 64 + lane];
+        f32x4 acc[kBatch];
+#pragma unroll
+        for (int c = 0; c < kBatch; ++c) {
+          const f32x4 z = {0.0f, 0.0f, 0.0f, 0.0f};
+          acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aop, b[c], z, 0, 0, 0);
+        }
+#pragma unroll
+        for (int c = 0; c < kBatch; ++c) {
+          bool near = false;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) near |= acc[c][e] <= tau[e];
+          near_tiles |= (ballot(near) != 0 ? 1u : 0u) << (c0 + c);
+        }
       }
       while (near_tiles) {
         const int cb = __ffs(near_tiles) - 1;
@@ -470,12 +480,8 @@ __global__ __launch_bounds__(kWaves * 64) void mixed_brute_kernel(
     for (int m = 0; m < kMQ; ++m) {
       const int64_t q = qbase + m;
       if (q >= nq) break;
-      const size_t o = ((size_t)q * n_chunks + chunk) * k;
-      if (lane < k) {
-        part_d[o + lane] = s_tkd[m * k + lane];
-        part_i[o + lane] = s_tkid[m * k + lane];
-      }
-      if (lane == 0) part_kd[q * n_chunks + chunk] = round_up_f(s_tkd[m * k + k - 1]);
+      // the rounded-up k-th distance (+inf with fewer than k)
+      if (lane == 0) part_kd[q * n_chunks + chunk] = s_tau[wave][m];
     }
     if (chunk == 0) {
       const int64_t left = nq - qbase;
@@ -663,7 +669,7 @@ hipError_t launch_mixed_brute(const IndexDesc &ix, const QueryArgs &a, const tnn
     stride = (int64_t)(0.6180339887 * (double)n_steps) | 1;
     while (gcd(stride, n_steps) != 1) stride += 2;
   }
-  const size_t lds = 2 * sizeof(Stage) + (size_t)kWaves * kMQ * a.k * 12;
+  const size_t lds = 2 * sizeof(Stage);
   const int64_t items = n_tiles * l.chunks;
   const int64_t resident = (int64_t)cu_count_mixed() * mixed_per_cu(lds);
   const int64_t grid = items < resident ? items : resident;
