@@ -8,6 +8,9 @@ Pieces and the passage each follows:
                         part, Sec. 3.5), ties by caller index.  The paper states
                         the trajectory search is exact (Sec. 4.2), so this is
                         the result it must reach.
+* ``knn`` with one scale row per query -- the same search when the scale
+                        vector is a function of position (Sec. 3.2), each
+                        query under its own metric.
 * ``segments``       -- partition into runs of K points, segment AB from first to
                         last point, per-axis approximation error from the
                         Euclidean clamped projection (Sec. 3.4).
@@ -49,6 +52,8 @@ def _load():
         i64, i32, f64 = ctypes.c_int64, ctypes.c_int32, ctypes.c_double
         lib.oracle_knn.argtypes = [i64, P, P, P, P, i64, P, P, P, P, P, f64, i32, P, P]
         lib.oracle_knn.restype = ctypes.c_int
+        lib.oracle_knn_qscale.argtypes = [i64, P, P, P, P, i64, P, P, P, P, P, f64, i32, P, P]
+        lib.oracle_knn_qscale.restype = ctypes.c_int
         lib.oracle_pair_dist.argtypes = [i64, P, P, P, P, P, P, P, P, P, P, P, P]
         lib.oracle_pair_dist.restype = ctypes.c_int
         lib.oracle_segment_count.argtypes = [P, i64, i32]
@@ -69,7 +74,9 @@ def _ptr(a):
 
 def knn(points, queries, scale, t_window: float, k: int):
     """points/queries: (x, y, z, t) float32 arrays.  Returns (idx int64 [nq,k],
-    dist float64 [nq,k]); empty slots are (-1, +inf)."""
+    dist float64 [nq,k]); empty slots are (-1, +inf).  `scale` is one vector of
+    4 scales, or one row of 4 per query (per-query metric; a row with a
+    negative or non-finite scale gives (-1, NaN) slots)."""
     lib = _load()
     px, py, pz, pt = (_f32(a) for a in points)
     qx, qy, qz, qt = (_f32(a) for a in queries)
@@ -77,8 +84,14 @@ def knn(points, queries, scale, t_window: float, k: int):
     s = np.ascontiguousarray(scale, dtype=np.float64)
     idx = np.empty((nq, k), dtype=np.int64)
     dist = np.empty((nq, k), dtype=np.float64)
-    rc = lib.oracle_knn(n, _ptr(px), _ptr(py), _ptr(pz), _ptr(pt), nq, _ptr(qx), _ptr(qy),
-                        _ptr(qz), _ptr(qt), _ptr(s), float(t_window), int(k), _ptr(idx), _ptr(dist))
+    if s.ndim == 2:
+        if s.shape != (nq, 4):
+            raise ValueError("per-query scales must be [n_queries, 4]")
+        fn = lib.oracle_knn_qscale
+    else:
+        fn = lib.oracle_knn
+    rc = fn(n, _ptr(px), _ptr(py), _ptr(pz), _ptr(pt), nq, _ptr(qx), _ptr(qy), _ptr(qz), _ptr(qt),
+            _ptr(s), float(t_window), int(k), _ptr(idx), _ptr(dist))
     if rc != 0:
         raise ValueError("oracle_knn: bad argument")
     return idx, dist

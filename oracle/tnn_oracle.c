@@ -80,6 +80,48 @@ int oracle_knn(int64_t n, const float *x, const float *y, const float *z,
   return 0;
 }
 
+/* The same k-NN when every query has its own scales (Sec. 3.2: the scale
+ * vector may be a function of position): query q uses scale[4 q .. 4 q + 3].
+ * A row with a negative or non-finite scale has no metric: every slot of
+ * that query is (-1, NaN). */
+int oracle_knn_qscale(int64_t n, const float *x, const float *y, const float *z,
+                      const float *t, int64_t nq, const float *qx, const float *qy,
+                      const float *qz, const float *qt, const double *scale,
+                      double t_window, int32_t k, int64_t *out_idx, double *out_dist) {
+  if (n < 0 || nq < 0 || k < 1 || (!scale && nq > 0)) return -1;
+#pragma omp parallel for schedule(dynamic, 8)
+  for (int64_t q = 0; q < nq; ++q) {
+    double *bd = out_dist + q * (int64_t)k;
+    int64_t *bi = out_idx + q * (int64_t)k;
+    double s[4];
+    int ok = 1;
+    for (int f = 0; f < 4; ++f) {
+      s[f] = scale[4 * q + f];
+      if (!(s[f] >= 0.0) || !isfinite(s[f])) ok = 0;
+    }
+    for (int32_t r = 0; r < k; ++r) {
+      bd[r] = ok ? INFINITY : NAN;
+      bi[r] = -1;
+    }
+    if (!ok) continue;
+    double thr = (double)qt[q] - t_window;
+    for (int64_t i = 0; i < n; ++i) {
+      if (!((double)t[i] < thr)) continue;
+      double d = scaled_sq_dist(s, qx[q], qy[q], qz[q], qt[q], x[i], y[i], z[i], t[i]);
+      if (!(d < bd[k - 1])) continue;
+      int32_t r = k - 1;
+      while (r > 0 && d < bd[r - 1]) {
+        bd[r] = bd[r - 1];
+        bi[r] = bi[r - 1];
+        --r;
+      }
+      bd[r] = d;
+      bi[r] = i;
+    }
+  }
+  return 0;
+}
+
 /* Distances of explicit (query, point) pairs with the same arithmetic:
  * used to check sampled outputs at full size. */
 int oracle_pair_dist(int64_t m, const int64_t *qi, const int64_t *pi,

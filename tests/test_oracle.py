@@ -392,3 +392,76 @@ def test_gka_average_closed_forms():
     # far neighbours barely count: exp(-50) relative weight
     out = oracle.gka_average(np.array([[1, 2]]), np.array([[0.0, 50.0]]), vals)
     assert np.allclose(out[0], vals[1], rtol=1e-20, atol=1e-19 * 10)
+
+
+def test_per_query_scales_hand_case():
+    """Two queries at the same place under different metrics (Sec. 3.2: the
+    scales may vary over space).  Query point (0, 0, 0, 10); A = (1, 0, 0, 0),
+    B = (0, 0, 0.5, 0), C = (0, 0, 0, 20) (after the query: masked).
+    s = (1, 1, 1, 0): d_A = 1, d_B = 0.25 -> B, A.
+    s = (1, 1, 10, 0): d_A = 1, d_B = 2.5 -> A, B.
+    s = (0, 0, 0, 1): d_A = d_B = 100 -> tie, lower index A first."""
+    pts = tuple(np.array(v, dtype=np.float32) for v in
+                ([1.0, 0.0, 0.0], [0.0, 0.0, 0.0], [0.0, 0.5, 0.0], [0.0, 0.0, 20.0]))
+    q = tuple(np.array([v] * 3, dtype=np.float32) for v in (0.0, 0.0, 0.0, 10.0))
+    s = np.array([[1, 1, 1, 0], [1, 1, 10, 0], [0, 0, 0, 1]], dtype=np.float64)
+    idx, dist = oracle.knn(pts, q, s, 0.0, 3)
+    assert idx.tolist() == [[1, 0, -1], [0, 1, -1], [0, 1, -1]]
+    assert dist[:, :2].tolist() == [[0.25, 1.0], [1.0, 2.5], [100.0, 100.0]]
+    assert np.isinf(dist[:, 2]).all()
+
+
+def test_per_query_scales_reduce_to_the_shared_metric():
+    """Equal rows give the shared-scale result; each row alone gives that
+    query's shared-scale result; a power-of-two factor on a row scales its
+    distances exactly and keeps its indices; a bad row is (-1, NaN) and leaves
+    the others alone."""
+    ps = synth.trajectories(30, 40, 300.0, 3600.0, seed=8)
+    rng = np.random.default_rng(4)
+    qs = ps.take(rng.choice(ps.n, 40, replace=False))
+    base = np.array(synth.SCALE)
+    k = 7
+    i0, d0 = oracle.knn(ps.soa(), qs.soa(), base, 0.0, k)
+    i1, d1 = oracle.knn(ps.soa(), qs.soa(), np.tile(base, (qs.n, 1)), 0.0, k)
+    assert np.array_equal(i0, i1) and np.array_equal(d0, d1)
+    rows = base * rng.uniform(0.25, 4.0, size=(qs.n, 4))
+    iq, dq = oracle.knn(ps.soa(), qs.soa(), rows, 0.0, k)
+    for j in range(0, qs.n, 5):
+        one = qs.take(np.array([j]))
+        ij, dj = oracle.knn(ps.soa(), one.soa(), rows[j], 0.0, k)
+        assert np.array_equal(iq[j], ij[0]) and np.array_equal(dq[j], dj[0])
+    scaled = rows.copy()
+    scaled[::2] *= 8.0
+    i2, d2 = oracle.knn(ps.soa(), qs.soa(), scaled, 0.0, k)
+    assert np.array_equal(i2, iq)
+    fin = np.isfinite(dq)
+    assert np.array_equal(d2[::2][fin[::2]], 8.0 * dq[::2][fin[::2]])
+    assert np.array_equal(d2[1::2], dq[1::2])
+    bad = rows.copy()
+    bad[3, 2] = -1.0
+    bad[5, 0] = np.nan
+    bad[6, 3] = np.inf
+    i3, d3 = oracle.knn(ps.soa(), qs.soa(), bad, 0.0, k)
+    for j in (3, 5, 6):
+        assert (i3[j] == -1).all() and np.isnan(d3[j]).all()
+    keep = np.setdiff1d(np.arange(qs.n), [3, 5, 6])
+    assert np.array_equal(i3[keep], iq[keep]) and np.array_equal(d3[keep], dq[keep])
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_per_query_scales_equal_exact_rational_on_dyadic(seed):
+    """Dyadic data and dyadic per-query scales: every binary64 operation is
+    exact, so each row equals the exact rational k-NN under its own metric."""
+    rng = np.random.default_rng(100 + seed)
+    n, nq, k = 40, 10, int(rng.integers(1, 9))
+    pts = tuple(_dyadic(rng, n) for _ in range(3)) + (_dyadic(rng, n, 0, 32, 4),)
+    qs = tuple(_dyadic(rng, nq) for _ in range(3)) + (_dyadic(rng, nq, 0, 32, 4),)
+    choices = np.array([0.0, 0.125, 0.25, 0.5, 1.0, 2.0, 4.0])
+    rows = rng.choice(choices, size=(nq, 4))
+    tw = [0.0, 0.5][seed % 2]
+    idx, dist = oracle.knn(pts, qs, rows, tw, k)
+    for j in range(nq):
+        one = tuple(a[j:j + 1] for a in qs)
+        ei, ed = exact_knn(pts, one, list(rows[j]), tw, k)
+        assert np.array_equal(idx[j], ei[0]), j
+        assert np.array_equal(dist[j], np.array([float(v) for v in ed[0]])), j
