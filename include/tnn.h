@@ -91,6 +91,14 @@ typedef struct {
                                value (0, inf, NaN) keeps results exact; it only changes
                                the work done. */
   unsigned long long *d_stats; /* device [TNN_STAT_COUNT] or NULL */
+  const double *d_query_scale; /* device [n_queries][4] per-query scales (s_x, s_y, s_z,
+                               s_t) replacing `scale` for each query, or NULL.  The scales
+                               may vary over space (Sec. 3.2: sigma as a function of
+                               position); the metric of query q is then s_q.  A row with a
+                               negative or non-finite entry yields (-1, NaN) in every slot
+                               of that query.  TNN (plain or learned) and TNN_BRUTE only:
+                               with TNN_MIXED_BF16 or in a tnn_query_batched item it is
+                               TNN_E_UNSUPPORTED. */
 } tnn_query_params;
 
 /* Human-readable name of a status code (static string). */

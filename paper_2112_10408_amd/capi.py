@@ -58,7 +58,7 @@ class TnnIndex(ctypes.Structure):
 class TnnQueryParams(ctypes.Structure):
     _fields_ = [("scale", f64 * 4), ("t_window", f64), ("k", i32), ("flags", u32),
                 ("seed_segments", i32), ("waves_per_block", i32), ("d_radius2", P),
-                ("d_stats", P)]
+                ("d_stats", P), ("d_query_scale", P)]
 
 
 class TnnBatchItem(ctypes.Structure):

@@ -112,6 +112,8 @@ tnn_status check_params(const tnn_query_params *p, int64_t n_queries = 1) {
   if (p->flags & ~(TNN_BRUTE | TNN_MIXED_BF16 | TNN_LEARNED)) return TNN_E_ARG;
   if ((p->flags & TNN_LEARNED) && !p->d_radius2 && n_queries > 0) return TNN_E_ARG;
   if ((p->flags & TNN_MIXED_BF16) && !(p->flags & TNN_BRUTE)) return TNN_E_UNSUPPORTED;
+  // the BF16 operands carry the scales: one metric per call
+  if ((p->flags & TNN_MIXED_BF16) && p->d_query_scale) return TNN_E_UNSUPPORTED;
   if (p->seed_segments < 0 || p->seed_segments > 64) return TNN_E_ARG;
   const int w = p->waves_per_block;
   if (!(w == 0 || w == 1 || w == 2 || w == 4 || w == 8)) return TNN_E_ARG;
@@ -376,12 +378,14 @@ tnn_status tnn_query(const tnn_index *index, tnn_points queries, const tnn_query
     return TNN_OK;
   }
   if (params->flags & TNN_BRUTE) {
-    TNN_HIP_CHECK(launch_brute(*d, a, queries, wpb, d_out_idx, d_out_dist, st));
+    TNN_HIP_CHECK(launch_brute(*d, a, queries, wpb, d_out_idx, d_out_dist, st,
+                               params->d_query_scale));
     return TNN_OK;
   }
   const Prep pr = prep_view(d_scratch, d->n_seg);
-  TNN_HIP_CHECK(launch_prep(*d, a, pr, st));
-  TNN_HIP_CHECK(launch_query(*d, pr, a, queries, wpb, d_out_idx, d_out_dist, st));
+  TNN_HIP_CHECK(launch_prep(*d, a, pr, st, params->d_query_scale != nullptr));
+  TNN_HIP_CHECK(launch_query(*d, pr, a, queries, wpb, d_out_idx, d_out_dist, st,
+                             params->d_query_scale));
   return TNN_OK;
 }
 
@@ -461,6 +465,7 @@ tnn_status check_items(const tnn_batch_item *items, int32_t n) {
     const tnn_status c = check_params(&it.params, it.queries.n);
     if (c != TNN_OK) return c;
     if (it.params.flags & (TNN_BRUTE | TNN_MIXED_BF16)) return TNN_E_UNSUPPORTED;
+    if (it.params.d_query_scale) return TNN_E_UNSUPPORTED;
     if (it.queries.n > 0 && (!it.d_out_idx || !it.d_out_dist)) return TNN_E_ARG;
   }
   return TNN_OK;

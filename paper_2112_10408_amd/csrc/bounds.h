@@ -112,4 +112,22 @@ __device__ __forceinline__ float seg_lb(const SegView &v, const QueryPoint &q, c
   return (g * g + sf[3] * (gt * gt)) * (1.0f - 0x1p-20f);
 }
 
+// The same bound when every query has its own scales s (per-query metric):
+// the record's third float4 then holds the segment's per-axis deviation
+// bounds (e_x, e_y, e_z) instead of the per-call constants, and this computes
+// those constants for s as the per-call preparation would.  1/|AB|^2_s and
+// R are formed the same way; the slack uses 2^-17 |f|_s (1 + 2^-20), which
+// is at least the per-call slack 2^-17 (|AB|_s + |f|_s) / 2 (1 + 2^-30):
+// f = fl(B - A) is within a relative 2^-24 of B - A in every component.
+__device__ __forceinline__ float seg_lb_q(SegView v, const QueryPoint &q, const double s[4],
+                                          const float sf[4]) {
+  const double fx = (double)v.r1.x, fy = (double)v.r1.y, fz = (double)v.r1.z;
+  const double n2 = s[0] * fx * fx + s[1] * fy * fy + s[2] * fz * fz;
+  const double ex = (double)v.r2.x, ey = (double)v.r2.y, ez = (double)v.r2.z;
+  v.r2.x = n2 > 0.0 ? (float)(1.0 / n2) : 0.0f;
+  v.r2.y = __double2float_ru(sqrt(s[0] * ex * ex + s[1] * ey * ey + s[2] * ez * ez) * (1.0 + 0x1p-40));
+  v.r2.z = __double2float_ru(0x1p-17 * sqrt(n2) * (1.0 + 0x1p-20));
+  return seg_lb(v, q, sf);
+}
+
 }  // namespace tnn

@@ -37,12 +37,17 @@ constexpr uint32_t kBatchMagic = 0x544e4e42u;  // "TNNB"
 
 hipError_t launch_batch(const BatchLaunch &bl, hipStream_t st);
 
-hipError_t launch_prep(const IndexDesc &ix, const QueryArgs &a, const Prep &pr, hipStream_t st);
+// per_query_scales: records carry the deviation bounds instead of the
+// per-call cylinder constants (each query forms its own).
+hipError_t launch_prep(const IndexDesc &ix, const QueryArgs &a, const Prep &pr, hipStream_t st,
+                       bool per_query_scales = false);
+// query_scale: per-query scales [n][4] (device) or null for the shared ones.
 hipError_t launch_query(const IndexDesc &ix, const Prep &pr, const QueryArgs &a,
                         const tnn_points &qs, int waves_per_block, int32_t *out_idx,
-                        double *out_dist, hipStream_t st);
+                        double *out_dist, hipStream_t st, const double *query_scale = nullptr);
 hipError_t launch_brute(const IndexDesc &ix, const QueryArgs &a, const tnn_points &qs,
-                        int waves_per_block, int32_t *out_idx, double *out_dist, hipStream_t st);
+                        int waves_per_block, int32_t *out_idx, double *out_dist, hipStream_t st,
+                        const double *query_scale = nullptr);
 size_t mixed_scratch_bytes(int64_t n_points, int64_t n_queries, int k);
 hipError_t launch_mixed_brute(const IndexDesc &ix, const QueryArgs &a, const tnn_points &qs,
                               int32_t *out_idx, double *out_dist, void *scratch, hipStream_t st);

@@ -34,7 +34,7 @@ static_assert(kQueues >= 1 && kQueues <= 16, "the query workspace holds 16 count
 // up, and the projection slack.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void prep_one(const IndexDesc &ix, const QueryArgs &a, float4 *rec,
-                                         int64_t s) {
+                                         int64_t s, bool raw = false) {
   const float ax = ix.ax[s], ay = ix.ay[s], az = ix.az[s];
   const float bx = ix.bx[s], by = ix.by[s], bz = ix.bz[s];
   // AB as the bound computes it (float32 differences), norms in binary64
@@ -54,16 +54,20 @@ __device__ __forceinline__ void prep_one(const IndexDesc &ix, const QueryArgs &a
   float4 *r = rec + kSegRec * s;
   r[0] = make_float4(ax, ay, az, ix.tmin[s]);
   r[1] = make_float4(fx, fy, fz, ix.tmax[s]);
-  r[2] = make_float4(inv_n2, rad, slack, 0.0f);
+  // with per-query scales the search forms these constants per query
+  // (seg_lb_q) from the deviation bounds
+  r[2] = raw ? make_float4(ix.ex[s], ix.ey[s], ix.ez[s], 0.0f)
+              : make_float4(inv_n2, rad, slack, 0.0f);
   r[3] = make_float4(__int_as_float(ix.pstart[s]), __int_as_float(ix.pcount[s]), 0.0f, 0.0f);
 }
 
-__global__ void prep_kernel(IndexDesc ix, QueryArgs a, float4 *rec, unsigned long long *ticket) {
+__global__ void prep_kernel(IndexDesc ix, QueryArgs a, float4 *rec, unsigned long long *ticket,
+                            bool raw) {
   const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   // the search kernel that follows starts its queues at 0
   if (s < kQueues && ticket) ticket[s * kTicketStride] = 0;
   if (s >= ix.n_seg) return;
-  prep_one(ix, a, rec, s);
+  prep_one(ix, a, rec, s, raw);
 }
 
 // ---------------------------------------------------------------------------
@@ -73,6 +77,7 @@ struct WaveStats {
   uint32_t blocks, segs, points, merges, rounds, fallback;
 };
 
+template <bool PerQ>
 struct Searcher {
   const IndexDesc &ix;
   const Prep &pr;
@@ -87,6 +92,14 @@ struct Searcher {
 
   __device__ Searcher(const IndexDesc &ix_, const Prep &pr_, const QueryArgs &a_)
       : ix(ix_), pr(pr_), a(a_) {}
+
+  // cylinder bound of a segment for this query's metric
+  __device__ __forceinline__ float seg_bound(const SegView &sv) const {
+    if constexpr (PerQ)
+      return seg_lb_q(sv, q, a.s, a.sf);
+    else
+      return seg_lb(sv, q, a.sf);
+  }
 
   // Scan the member points of the segments of block `bb` whose lanes are set
   // in `cm`, feeding the top-k, nearest key first.  Several segments share one
@@ -181,7 +194,7 @@ struct Searcher {
           if (s < S) sv = load_seg(pr, s);
           const int ps_l = sv.ps, pc_l = sv.pc;
           // both bounds hold for every member; the larger one decides the round
-          const float key_f = fmaxf(s < S ? seg_lb(sv, q, a.sf) : finf, bmin);
+          const float key_f = fmaxf(s < S ? seg_bound(sv) : finf, bmin);
           const double key = (double)key_f;
           st.segs += (uint32_t)min((int64_t)kBlockSegs, S - (int64_t)bb * kBlockSegs);
           const bool seeded = bb == seed_block && ((seed_mask >> lane) & 1ull);
@@ -215,12 +228,14 @@ __device__ __forceinline__ void flush_stats(unsigned long long *stats, const Wav
 //            continues from the k-th found (or a 16x larger radius).
 // Rounds only widen tau; a segment is scanned in the first round whose
 // radius reaches its bound, so no point enters the top-k twice.
-__device__ __forceinline__ void answer_query(const IndexDesc &ix, const Prep &pr,
-                                             const QueryArgs &a, const float *qx, const float *qy,
-                                             const float *qz, const float *qt, int64_t qi,
-                                             int32_t *out_idx, double *out_dist,
-                                             const float *box, const float *sbox) {
-  Searcher se(ix, pr, a);
+template <bool PerQ>
+__device__ __forceinline__ void answer_query_with(const IndexDesc &ix, const Prep &pr,
+                                                  const QueryArgs &a, const float *qx,
+                                                  const float *qy, const float *qz,
+                                                  const float *qt, int64_t qi, int32_t *out_idx,
+                                                  double *out_dist, const float *box,
+                                                  const float *sbox) {
+  Searcher<PerQ> se(ix, pr, a);
   se.lane = lane_id();
   se.box = box;
   se.sbox = sbox;
@@ -289,7 +304,7 @@ __device__ __forceinline__ void answer_query(const IndexDesc &ix, const Prep &pr
       SegView sv{};
       if (s < S) sv = load_seg(pr, s);
       const int ps_l = sv.ps, pc_l = sv.pc;
-      const float v0 = s < S ? seg_lb(sv, se.q, a.sf) : __builtin_huge_valf();
+      const float v0 = s < S ? se.seg_bound(sv) : __builtin_huge_valf();
       float v = v0;
       se.st.segs += (uint32_t)min((int64_t)kBlockSegs, S - (int64_t)bestb * kBlockSegs);
       const int F = a.seed_segments;
@@ -335,14 +350,60 @@ write_out:
   flush_stats(a.stats, se.st);
 }
 
+// The query's own scales (wave-uniform), rounded toward zero to float32 for
+// the float bounds.  False when one is negative or not finite.
+__device__ __forceinline__ bool load_query_scales(const double *qscale, int64_t qi, QueryArgs &aq) {
+  bool ok = true;
+  for (int f = 0; f < 4; ++f) {
+    const double v = qscale[4 * qi + f];
+    ok = ok && v >= 0.0 && v < kInf;
+    aq.s[f] = v;
+    aq.sf[f] = __double2float_rz(v);
+  }
+  return ok;
+}
+
+// A query whose scales are invalid: (-1, NaN) in every slot.
+__device__ __forceinline__ void write_bad_scale_row(const QueryArgs &a, int64_t qi,
+                                                    int32_t *out_idx, double *out_dist) {
+  const int lane = lane_id();
+  if (lane < a.k) {
+    out_idx[qi * a.k + lane] = -1;
+    out_dist[qi * a.k + lane] = a.inf - a.inf;  // NaN (no 64-bit literal)
+  }
+  if (a.stats && lane == 0) atomicAdd(a.stats + TNN_STAT_QUERIES, 1ull);
+}
+
+template <bool PerQ>
+__device__ __forceinline__ void answer_query(const IndexDesc &ix, const Prep &pr,
+                                             const QueryArgs &a, const float *qx, const float *qy,
+                                             const float *qz, const float *qt, int64_t qi,
+                                             int32_t *out_idx, double *out_dist,
+                                             const float *box, const float *sbox,
+                                             const double *qscale) {
+  if constexpr (PerQ) {
+    QueryArgs aq = a;
+    if (!load_query_scales(qscale, qi, aq)) {
+      write_bad_scale_row(a, qi, out_idx, out_dist);
+      return;
+    }
+    answer_query_with<true>(ix, pr, aq, qx, qy, qz, qt, qi, out_idx, out_dist, box, sbox);
+  } else {
+    answer_query_with<false>(ix, pr, a, qx, qy, qz, qt, qi, out_idx, out_dist, box, sbox);
+  }
+}
+
+// qscale (last, so the other arguments keep their places): per-query scales
+// when PerQ, else unused.
+template <bool PerQ>
 __global__ __launch_bounds__(512) void tnn_query_kernel(IndexDesc ix, Prep pr, QueryArgs a,
                                                         const float *qx, const float *qy,
                                                         const float *qz, const float *qt,
                                                         int64_t nq, int32_t *out_idx,
-                                                        double *out_dist) {
+                                                        double *out_dist, const double *qscale) {
   const int64_t qi = (int64_t)blockIdx.x * (blockDim.x >> 6) + uniform_i((int)(threadIdx.x >> 6));
   if (qi >= nq) return;
-  answer_query(ix, pr, a, qx, qy, qz, qt, qi, out_idx, out_dist, ix.box, ix.sbox);
+  answer_query<PerQ>(ix, pr, a, qx, qy, qz, qt, qi, out_idx, out_dist, ix.box, ix.sbox, qscale);
 }
 
 // Same search with the block boxes staged once per workgroup in LDS (small
@@ -351,11 +412,11 @@ __global__ __launch_bounds__(512) void tnn_query_kernel(IndexDesc ix, Prep pr, Q
 // orders of magnitude, so a fixed share per wave leaves a long tail).
 // BoxesInLds: the block boxes fit in LDS too (the superblock boxes always
 // do); a template argument so that every box read is a plain LDS or global
-// access rather than a generic one.
-template <bool BoxesInLds>
+// access rather than a generic one.  PerQ: every query has its own scales.
+template <bool BoxesInLds, bool PerQ>
 __global__ __launch_bounds__(512, TNN_QUERY_MIN_WAVES) void tnn_query_lds_kernel(
     IndexDesc ix, Prep pr, QueryArgs a, const float *qx, const float *qy, const float *qz,
-    const float *qt, int64_t nq, int32_t *out_idx, double *out_dist) {
+    const float *qt, int64_t nq, int32_t *out_idx, double *out_dist, const double *qscale) {
   extern __shared__ float4 s_box4[];
   // superblock boxes first, then (when they fit) the block boxes
   const int nsbox = 2 * ix.n_super;
@@ -381,7 +442,7 @@ __global__ __launch_bounds__(512, TNN_QUERY_MIN_WAVES) void tnn_query_lds_kernel
       if (base >= hi) break;
       const int64_t end = base + TNN_QUERY_CHUNK < hi ? base + TNN_QUERY_CHUNK : hi;
       for (int64_t qi = base; qi < end; ++qi)
-        answer_query(ix, pr, a, qx, qy, qz, qt, qi, out_idx, out_dist, box, s_box);
+        answer_query<PerQ>(ix, pr, a, qx, qy, qz, qt, qi, out_idx, out_dist, box, s_box, qscale);
     }
   }
 #else
@@ -389,7 +450,7 @@ __global__ __launch_bounds__(512, TNN_QUERY_MIN_WAVES) void tnn_query_lds_kernel
   const int64_t stride = (int64_t)gridDim.x * wpb;
   for (int64_t qi = (int64_t)blockIdx.x * wpb + uniform_i((int)(threadIdx.x >> 6)); qi < nq;
        qi += stride)
-    answer_query(ix, pr, a, qx, qy, qz, qt, qi, out_idx, out_dist, box, s_box);
+    answer_query<PerQ>(ix, pr, a, qx, qy, qz, qt, qi, out_idx, out_dist, box, s_box, qscale);
 #endif
 }
 
@@ -400,10 +461,20 @@ __global__ __launch_bounds__(512, TNN_QUERY_MIN_WAVES) void tnn_query_lds_kernel
 __global__ __launch_bounds__(512) void brute_kernel(IndexDesc ix, QueryArgs a, const float *qxp,
                                                     const float *qyp, const float *qzp,
                                                     const float *qtp, int64_t nq,
-                                                    int32_t *out_idx, double *out_dist) {
+                                                    int32_t *out_idx, double *out_dist,
+                                                    const double *qscale) {
   const int64_t qi = (int64_t)blockIdx.x * (blockDim.x >> 6) + uniform_i((int)(threadIdx.x >> 6));
   if (qi >= nq) return;
   const int lane = lane_id();
+  double s[4] = {a.s[0], a.s[1], a.s[2], a.s[3]};
+  if (qscale) {
+    QueryArgs aq = a;
+    if (!load_query_scales(qscale, qi, aq)) {
+      write_bad_scale_row(a, qi, out_idx, out_dist);
+      return;
+    }
+    for (int f = 0; f < 4; ++f) s[f] = aq.s[f];
+  }
   const QueryPoint q = make_query(qxp[qi], qyp[qi], qzp[qi], qtp[qi], a.t_window);
   TopK tk;
   tk.init(a.k, a.inf);
@@ -418,7 +489,7 @@ __global__ __launch_bounds__(512) void brute_kernel(IndexDesc ix, QueryArgs a, c
       pv = ix.pt4[p];
       pid = ix.pid[p];
     }
-    const double d = exact_dist(a.s, q.x, q.y, q.z, q.t, pv.x, pv.y, pv.z, pv.w);
+    const double d = exact_dist(s, q.x, q.y, q.z, q.t, pv.x, pv.y, pv.z, pv.w);
     const bool gate = ok && (double)pv.w < q.thr && tk.admits(d, pid);
     const uint64_t gm = ballot(gate);
     if (gm) {
@@ -522,8 +593,8 @@ __global__ __launch_bounds__(512) void batch_kernel(const BatchItemDev *items,
         const BatchItemDev &it = items[item];
         const int64_t run = item_end - gq;
         for (; gq < item_end; ++gq)
-          answer_query(it.ix, it.pr, it.a, it.qx, it.qy, it.qz, it.qt, gq - qprefix[pos],
-                       it.out_idx, it.out_dist, it.ix.box, it.ix.sbox);
+          answer_query<false>(it.ix, it.pr, it.a, it.qx, it.qy, it.qz, it.qt, gq - qprefix[pos],
+                       it.out_idx, it.out_dist, it.ix.box, it.ix.sbox, nullptr);
         if (lane == 0) {
           const unsigned d = atomicAdd(&done[item], (unsigned)run) + (unsigned)run;
           if ((int64_t)d == it.nq) ticks[item + 1] = wall_clock64();
@@ -556,11 +627,12 @@ hipError_t launch_batch(const BatchLaunch &bl, hipStream_t st) {
 // ---------------------------------------------------------------------------
 // Host launchers.
 // ---------------------------------------------------------------------------
-hipError_t launch_prep(const IndexDesc &ix, const QueryArgs &a, const Prep &pr, hipStream_t st) {
+hipError_t launch_prep(const IndexDesc &ix, const QueryArgs &a, const Prep &pr, hipStream_t st,
+                       bool per_query_scales) {
   const int tpb = 256;
   const int64_t grid = ix.n_seg > 0 ? (ix.n_seg + tpb - 1) / tpb : 1;
   hipLaunchKernelGGL(prep_kernel, dim3((unsigned)grid), dim3(tpb), 0, st, ix, a, pr.rec,
-                     pr.ticket);
+                     pr.ticket, per_query_scales);
   return hipGetLastError();
 }
 
@@ -605,7 +677,7 @@ static int resident_per_cu(int variant, int wpb, size_t lds, Query query) {
 
 hipError_t launch_query(const IndexDesc &ix, const Prep &pr, const QueryArgs &a,
                         const tnn_points &qs, int waves_per_block, int32_t *out_idx,
-                        double *out_dist, hipStream_t st) {
+                        double *out_dist, hipStream_t st, const double *query_scale) {
   if (qs.n == 0) return hipSuccess;
   const int64_t grid = (qs.n + waves_per_block - 1) / waves_per_block;
   const size_t sl = (size_t)ix.n_super * 8 * sizeof(float);
@@ -613,27 +685,32 @@ hipError_t launch_query(const IndexDesc &ix, const Prep &pr, const QueryArgs &a,
   if (sl <= kLdsBoxBytes) {
     const int in_lds = sl + bl <= kLdsBoxBytes ? 1 : 0;
     const size_t lds = in_lds ? sl + bl : sl;
-    const auto kern = in_lds ? tnn_query_lds_kernel<true> : tnn_query_lds_kernel<false>;
-    const int per_cu = resident_per_cu(in_lds, waves_per_block, lds, [&](int *n) {
+    const bool perq = query_scale != nullptr;
+    const auto kern = perq ? (in_lds ? tnn_query_lds_kernel<true, true> : tnn_query_lds_kernel<false, true>)
+                           : (in_lds ? tnn_query_lds_kernel<true, false> : tnn_query_lds_kernel<false, false>);
+    const int variant = in_lds + (perq ? 2 : 0);
+    const int per_cu = resident_per_cu(variant, waves_per_block, lds, [&](int *n) {
       return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, kern, waves_per_block * kWave, lds);
     });
     const int64_t resident = (int64_t)cu_count() * per_cu;
     const int64_t g = grid < resident ? grid : resident;
     hipLaunchKernelGGL(kern, dim3((unsigned)g), dim3(waves_per_block * kWave), lds, st, ix, pr, a,
-                       qs.x, qs.y, qs.z, qs.t, qs.n, out_idx, out_dist);
+                       qs.x, qs.y, qs.z, qs.t, qs.n, out_idx, out_dist, query_scale);
     return hipGetLastError();
   }
-  hipLaunchKernelGGL(tnn_query_kernel, dim3((unsigned)grid), dim3(waves_per_block * kWave), 0, st,
-                     ix, pr, a, qs.x, qs.y, qs.z, qs.t, qs.n, out_idx, out_dist);
+  const auto kern = query_scale ? tnn_query_kernel<true> : tnn_query_kernel<false>;
+  hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(waves_per_block * kWave), 0, st, ix, pr, a,
+                     qs.x, qs.y, qs.z, qs.t, qs.n, out_idx, out_dist, query_scale);
   return hipGetLastError();
 }
 
 hipError_t launch_brute(const IndexDesc &ix, const QueryArgs &a, const tnn_points &qs,
-                        int waves_per_block, int32_t *out_idx, double *out_dist, hipStream_t st) {
+                        int waves_per_block, int32_t *out_idx, double *out_dist, hipStream_t st,
+                        const double *query_scale) {
   if (qs.n == 0) return hipSuccess;
   const int64_t grid = (qs.n + waves_per_block - 1) / waves_per_block;
   hipLaunchKernelGGL(brute_kernel, dim3((unsigned)grid), dim3(waves_per_block * kWave), 0, st, ix,
-                     a, qs.x, qs.y, qs.z, qs.t, qs.n, out_idx, out_dist);
+                     a, qs.x, qs.y, qs.z, qs.t, qs.n, out_idx, out_dist, query_scale);
   return hipGetLastError();
 }
 

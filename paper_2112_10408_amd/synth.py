@@ -199,6 +199,29 @@ CONFIGS = {
 }
 
 
+def scale_field(x, y, z, box_km: float, seed: int, base=SCALE, spread: float = 0.7):
+    """Per-query scales that vary smoothly over space, the shape of the
+    paper's proposal of the scale vector as a function of position (Sec. 3.2):
+    s_xy, s_z and s_t each the base value times exp(spread * a smooth field
+    in [-1, 1]) with random phases, so they range over about exp(+-spread).
+    s_x = s_y (one horizontal scale).  Returns float64 [n, 4]."""
+    rng = np.random.default_rng(seed)
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    z = np.asarray(z, dtype=np.float64)
+    ph = rng.uniform(0.0, 2.0 * np.pi, size=6)
+    w = 2.0 * np.pi / box_km
+    fxy = np.sin(w * 1.3 * x + ph[0]) * np.cos(w * 0.9 * y + ph[1])
+    fz = np.sin(0.5 * z + ph[2]) * np.cos(w * 0.7 * x + ph[3])
+    ft = np.cos(w * 1.1 * y + ph[4]) * np.sin(w * 0.6 * x + ph[5])
+    out = np.empty((x.shape[0], 4), dtype=np.float64)
+    out[:, 0] = base[0] * np.exp(spread * fxy)
+    out[:, 1] = out[:, 0]
+    out[:, 2] = base[2] * np.exp(spread * fz)
+    out[:, 3] = base[3] * np.exp(spread * ft)
+    return out
+
+
 def make_config(name: str):
     """Return (points, queries, query point indices, cfg dict)."""
     cfg = dict(CONFIGS[name])

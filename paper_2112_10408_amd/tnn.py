@@ -78,7 +78,7 @@ def tnn_build_segments(x, y, z, t, traj_offsets, seg_len, order_scale=(1.0, 1.0,
 
 
 def make_params(scale, t_window, k, flags=0, seed_segments=0, waves_per_block=0, radius2=None,
-                stats=None):
+                stats=None, query_scale=None):
     p = TnnQueryParams()
     for i in range(4):
         p.scale[i] = float(scale[i])
@@ -89,6 +89,12 @@ def make_params(scale, t_window, k, flags=0, seed_segments=0, waves_per_block=0,
     p.waves_per_block = int(waves_per_block)
     p.d_radius2 = _ptr(radius2) if radius2 is not None else None
     p.d_stats = _ptr(stats) if stats is not None else None
+    if query_scale is not None:
+        if query_scale.dtype != torch.float64 or query_scale.dim() != 2 or query_scale.shape[1] != 4:
+            raise ValueError("query_scale must be a float64 [n_queries, 4] device tensor")
+        if not query_scale.is_contiguous():
+            raise ValueError("query_scale must be contiguous")
+    p.d_query_scale = _ptr(query_scale) if query_scale is not None else None
     return p
 
 
@@ -112,11 +118,17 @@ def stats_dict(stats):
 
 
 def tnn_query(index, qx, qy, qz, qt, scale, t_window, k, flags=0, seed_segments=0,
-              waves_per_block=0, radius2=None, stats=None, out=None, scratch=None):
-    """Returns (idx int32 [nq, k], dist float64 [nq, k]) device tensors."""
+              waves_per_block=0, radius2=None, stats=None, out=None, scratch=None,
+              query_scale=None):
+    """Returns (idx int32 [nq, k], dist float64 [nq, k]) device tensors.
+    query_scale: optional float64 [nq, 4] device tensor of per-query scales
+    (replaces `scale`, which must still be valid)."""
     L = capi.lib()
     nq = qx.shape[0]
-    params = make_params(scale, t_window, k, flags, seed_segments, waves_per_block, radius2, stats)
+    if query_scale is not None and query_scale.shape[0] != nq:
+        raise ValueError("query_scale needs one row per query")
+    params = make_params(scale, t_window, k, flags, seed_segments, waves_per_block, radius2, stats,
+                         query_scale)
     need = tnn_query_workspace(index, nq, params)
     if scratch is None or scratch.numel() < need:
         scratch = torch.empty(max(need, 256), dtype=torch.uint8, device=qx.device)

@@ -117,3 +117,13 @@ def test_gka_rejects_bad_arguments_without_gpu():
     assert L.tnn_gka_average(None, None, -1, 8, None, 2, 100, None, None) == E    # negative count
     assert L.tnn_gka_average(None, None, 10, 8, None, 2, 100, None, None) == E    # null buffers
     assert L.tnn_gka_average(None, None, 0, 8, None, 2, 100, None, None) == capi.TNN_OK  # nothing to do
+
+
+def test_query_params_struct_matches_header():
+    """The binding's tnn_query_params has the header's fields, in order (the
+    struct crosses the C ABI by value)."""
+    src = open(os.path.join(ROOT, "include", "tnn.h")).read()
+    body = re.search(r"typedef struct \{([^}]*)\} tnn_query_params;", src).group(1)
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    names = re.findall(r"\**\s*([a-z_0-9]+)\s*(?:\[[^\]]*\])?\s*;", body)
+    assert names == [f[0] for f in capi.TnnQueryParams._fields_]

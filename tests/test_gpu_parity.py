@@ -315,3 +315,68 @@ def test_gka_average_matches_oracle(k, n_comp):
     assert np.isnan(want).any() and not np.isnan(want).all()
     ok = ~np.isnan(want)
     assert np.allclose(got[ok], want[ok], rtol=1e-12, atol=1e-12)
+
+
+PERQ_PATHS = [capi.TNN_PLAIN, capi.TNN_LEARNED, capi.TNN_BRUTE]
+
+
+def _perq_query(ix, qs, rows, tw, k, flags, model=None):
+    q = dev_points(qs)
+    qscale = torch.from_numpy(np.ascontiguousarray(rows)).cuda()
+    r2 = None
+    if flags & capi.TNN_LEARNED:
+        r2 = T.tnn_radius_infer(model, *q, alpha=1.0)
+    i, d = T.tnn_query(ix, *q, SCALE, tw, k, flags=flags, radius2=r2, query_scale=qscale)
+    torch.cuda.synchronize()
+    return i.cpu().numpy(), d.cpu().numpy()
+
+
+@pytest.mark.parametrize("flags", PERQ_PATHS)
+@pytest.mark.parametrize("tw", [0.0, 1800.0])
+def test_per_query_scales_match_oracle(flags, tw):
+    """Scales varying over space (Sec. 3.2), one row per query: every path
+    against the oracle under each query's own metric; rows with zero scales,
+    wide factors, and invalid rows (negative, NaN, inf) -> (-1, NaN)."""
+    ps = synth.trajectories(300, 80, 800.0, 4 * 3600.0, seed=41)
+    ix = build(ps, 16)
+    rng = np.random.default_rng(7)
+    qs = ps.take(rng.choice(ps.n, 700, replace=False))
+    rows = synth.scale_field(qs.x, qs.y, qs.z, 800.0, seed=3)
+    rows[0] = 0.0                                   # every point at distance 0
+    rows[1, 3] = 0.0                                # time ignored
+    rows[2, :3] = 0.0                               # time only
+    rows[3] *= np.array([1e-3, 1e-3, 1e3, 1e2])     # far from the shared metric
+    rows[4] *= 1e6
+    rows[10, 1] = -0.5                              # invalid rows
+    rows[11, 2] = np.nan
+    rows[12, 0] = np.inf
+    model = T.tnn_radius_model_init(ix, seed=5) if flags & capi.TNN_LEARNED else None
+    for k in (1, 8, 64):
+        say("per-query scales", flags, tw, k)
+        gi, gd = _perq_query(ix, qs, rows, tw, k, flags, model)
+        oi, od = oracle.knn(ps.soa(), qs.soa(), rows, tw, k)
+        bad = np.array([10, 11, 12])
+        assert (gi[bad] == -1).all() and np.isnan(gd[bad]).all()
+        keep = np.setdiff1d(np.arange(qs.n), bad)
+        assert_same(gi[keep], gd[keep], oi[keep], od[keep], f"per-query scales k={k}")
+
+
+def test_per_query_scales_equal_rows_match_shared_metric():
+    """Equal rows reproduce the shared-scale search bit for bit."""
+    ps, qs, _, cfg = config_data("c1")
+    ix = build(ps, cfg["seg_len"])
+    k = cfg["k"]
+    rows = np.tile(np.array(SCALE, dtype=np.float64), (qs.n, 1))
+    gi, gd = _perq_query(ix, qs, rows, 0.0, k, capi.TNN_PLAIN)
+    si, sd = gpu_query(ix, qs, SCALE, 0.0, k)
+    assert np.array_equal(gi, si) and np.array_equal(gd, sd)
+
+
+def test_per_query_scales_refused_where_unsupported():
+    ps = synth.trajectories(20, 30, 300.0, 3600.0, seed=2)
+    ix = build(ps, 16)
+    q = dev_points(ps)
+    qscale = torch.ones((ps.n, 4), dtype=torch.float64, device="cuda")
+    with pytest.raises(capi.TnnError) as e:
+        T.tnn_query(ix, *q, SCALE, 0.0, 4, flags=MIXED, query_scale=qscale)
+    assert e.value.code == capi.TNN_E_UNSUPPORTED
