@@ -283,6 +283,70 @@ def run_config(name, args, T, capi, radius, synth, torch, stream):
     return res
 
 
+def run_query_scales(args, T, capi, radius, synth, torch, stream):
+    """The 1M-point, 100k-query workload with scales that vary over space
+    (one row per query, within exp(+-0.7) of the shared scales): plain TNN,
+    learned-radius TNN (radius trained under the shared scales, so only a
+    rough guess here: exact either way) and binary64 brute force under the
+    same per-query metric."""
+    scale = synth.SCALE
+    ps, qs, qidx, cfg = synth.make_config("c2")
+    k, K, tw = cfg["k"], cfg["seg_len"], cfg["t_window"]
+    x, y, z, t = T.to_device(ps.x, ps.y, ps.z, ps.t)
+    q = T.to_device(qs.x, qs.y, qs.z, qs.t)
+    rows = synth.scale_field(qs.x, qs.y, qs.z, 3000.0, seed=cfg["seed"] + 77)
+    qscale = torch.from_numpy(rows).cuda()
+    ix = T.tnn_build_segments(x, y, z, t, ps.offsets, K, scale)
+    n = qs.n
+    out = (torch.empty((n, k), dtype=torch.int32, device="cuda"),
+           torch.empty((n, k), dtype=torch.float64, device="cuda"))
+    scratch = torch.empty(max(T.tnn_query_workspace(ix, n, T.make_params(scale, tw, k)), 256),
+                          dtype=torch.uint8, device="cuda")
+    steps = max(1, min(args.steps, 5))
+    res = {"points": ps.n, "queries": n, "k": k, "seg_len": K,
+           "scales": "per query, exp(+-0.7) smooth field around (1, 1, 10, 0.05)"}
+
+    def plain():
+        T.tnn_query(ix, *q, scale, tw, k, out=out, scratch=scratch, query_scale=qscale)
+
+    ms = timed(plain, steps, 1, stream)
+    ref = (out[0].clone(), out[1].clone())
+    res["plain_qps"] = n / ms * 1e3
+    n_tr = min(100_000, ps.n // 2)
+    tq, _ = synth.sample_queries(ps, n_tr, cfg["seed"] + 2000, exclude=qidx)
+    tx = T.to_device(tq.x, tq.y, tq.z, tq.t)
+    model, loss, pdist, ptr = radius.train(ix, *tx, scale, tw, k, epochs=args.train_epochs,
+                                           batch=4096, lr=3e-3)
+    alpha = radius.calibrate(model, *ptr, pdist, k, quantile=0.8)
+    r2 = torch.empty(n, dtype=torch.float32, device="cuda")
+
+    def learned():
+        T.tnn_radius_infer(model, *q, alpha, out=r2)
+        T.tnn_query(ix, *q, scale, tw, k, flags=capi.TNN_LEARNED, radius2=r2, out=out,
+                    scratch=scratch, query_scale=qscale)
+
+    ms_l = timed(learned, steps, 1, stream)
+    st = T.new_stats()
+    T.tnn_query(ix, *q, scale, tw, k, flags=capi.TNN_LEARNED, radius2=r2, out=out,
+                scratch=scratch, stats=st, query_scale=qscale)
+    torch.cuda.synchronize()
+    st = T.stats_dict(st)
+    res.update(learned_qps=n / ms_l * 1e3,
+               learned_matches_plain=bool(torch.equal(out[0], ref[0])) and bool(torch.equal(out[1], ref[1])),
+               fallback_rate=st["fallbacks"] / max(n, 1))
+    if not args.no_brute:
+        def brute():
+            T.tnn_query(ix, *q, scale, tw, k, flags=capi.TNN_BRUTE, out=out, scratch=scratch,
+                        query_scale=qscale)
+
+        ms_b = timed(brute, 1, 1, stream)
+        res.update(brute_qps=n / ms_b * 1e3,
+                   brute_matches_tnn=bool(torch.equal(out[0], ref[0])) and bool(torch.equal(out[1], ref[1])),
+                   learned_speedup_vs_brute=ms_b / ms_l)
+    log("scales:", res)
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -295,7 +359,7 @@ def main():
     ap.add_argument("--airspaces", type=int, default=64)
     ap.add_argument("--no-configs", action="store_true",
                     help="skip the other workloads (10k points, 1M queries, 8M points, "
-                         "30-min window, airways, random points)")
+                         "30-min window, airways, random points, per-query scales)")
     ap.add_argument("--train-epochs", type=int, default=8)
     ap.add_argument("--radius-quantile", type=float, default=0.8,
                     help="calibration quantile of the radius safety factor; 0 sweeps "
@@ -499,6 +563,9 @@ def main():
                             ("rand", "1M_random_points_100k_queries_k32")):
             res["configs"][label] = run_config(name, args, T, capi, radius, synth, torch, stream)
             torch.cuda.empty_cache()
+        res["configs"]["1M_points_100k_queries_k32_per_query_scales"] = run_query_scales(
+            args, T, capi, radius, synth, torch, stream)
+        torch.cuda.empty_cache()
     if not args.no_batched:
         res["batched"] = run_batched(args, T, capi, radius, synth, torch, stream)
     if not args.no_cpu_baseline:

@@ -96,3 +96,32 @@ def test_window_airways_random_full_size(name):
     sample = np.sort(rng.choice(qs.n, 128, replace=False))
     oi, od = oracle.knn(ps.soa(), qs.take(sample).soa(), SCALE, tw, k)
     assert_same(pi.cpu().numpy()[sample], pd.cpu().numpy()[sample], oi, od, name)
+
+
+def test_per_query_scales_full_size():
+    """1M points, 100k queries, scales varying over space (one row per
+    query): plain and learned TNN agree with the binary64 linear search under
+    the same per-query metric on every query, and a seeded sample (plus the
+    earliest queries) agrees with the oracle."""
+    ps, qs, _, cfg = config_data("c2")
+    k = cfg["k"]
+    ix = build(ps, cfg["seg_len"])
+    q = dev_points(qs)
+    rows = synth.scale_field(qs.x, qs.y, qs.z, 3000.0, seed=11)
+    qscale = torch.from_numpy(rows).cuda()
+    say("per-query scales plain")
+    pi, pd = T.tnn_query(ix, *q, SCALE, 0.0, k, query_scale=qscale)
+    say("per-query scales learned")
+    model = T.tnn_radius_model_init(ix, seed=3)
+    r2 = T.tnn_radius_infer(model, *q, alpha=1.0)
+    li, ld = T.tnn_query(ix, *q, SCALE, 0.0, k, flags=capi.TNN_LEARNED, radius2=r2, query_scale=qscale)
+    say("per-query scales binary64 linear search")
+    bi, bd = T.tnn_query(ix, *q, SCALE, 0.0, k, flags=capi.TNN_BRUTE, query_scale=qscale)
+    torch.cuda.synchronize()
+    assert torch.equal(pi, bi) and torch.equal(pd, bd)
+    assert torch.equal(li, bi) and torch.equal(ld, bd)
+    gi, gd = pi.cpu().numpy(), pd.cpu().numpy()
+    rng = np.random.default_rng(5)
+    sample = np.concatenate([np.sort(rng.choice(qs.n, 160, replace=False)), np.argsort(qs.t)[:8]])
+    oi, od = oracle.knn(ps.soa(), qs.take(sample).soa(), rows[sample], 0.0, k)
+    assert_same(gi[sample], gd[sample], oi, od, "per-query scales sample")
