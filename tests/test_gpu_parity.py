@@ -175,14 +175,15 @@ def test_scales_windows_and_off_data_queries(scale, t_window):
         assert_same(gi, gd, oi, od, f"scale={scale} tw={t_window} flags={flags}")
 
 
-def test_empty_and_tiny_inputs():
+@pytest.mark.parametrize("flags", ALL_PATHS)
+def test_empty_and_tiny_inputs(flags):
     ps = synth.trajectories(3, 4, 10.0, 100.0, seed=1)
     ix = build(ps, 16)
     empty = synth.PointSet(*(np.zeros(0, np.float32) for _ in range(4)), np.array([0, 0]))
-    gi, gd = gpu_query(ix, empty, SCALE, 0.0, 5)
+    gi, gd = gpu_query(ix, empty, SCALE, 0.0, 5, flags=flags)
     assert gi.shape == (0, 5)
     qs = ps.take(np.arange(ps.n))
-    gi, gd = gpu_query(ix, qs, SCALE, 0.0, 64)  # k far above the data
+    gi, gd = gpu_query(ix, qs, SCALE, 0.0, 64, flags=flags)  # k far above the data
     oi, od = oracle.knn(ps.soa(), qs.soa(), SCALE, 0.0, 64)
     assert_same(gi, gd, oi, od, "k>N")
 
