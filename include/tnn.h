@@ -92,7 +92,8 @@ typedef struct {
                                the work done. */
   unsigned long long *d_stats; /* device [TNN_STAT_COUNT] or NULL */
   const double *d_query_scale; /* device [n_queries][4] per-query scales (s_x, s_y, s_z,
-                               s_t) replacing `scale` for each query, or NULL.  The scales
+                               s_t) replacing `scale` for each query, or NULL (`scale` is
+                               still checked: pass any valid values).  The scales
                                may vary over space (Sec. 3.2: sigma as a function of
                                position); the metric of query q is then s_q.  A row with a
                                negative or non-finite entry yields (-1, NaN) in every slot
