@@ -381,3 +381,55 @@ def test_per_query_scales_refused_where_unsupported():
     with pytest.raises(capi.TnnError) as e:
         T.tnn_query(ix, *q, SCALE, 0.0, 4, flags=MIXED, query_scale=qscale)
     assert e.value.code == capi.TNN_E_UNSUPPORTED
+
+
+@pytest.mark.parametrize("path", ["plain", "learned", "mixed", "brute", "per_query"])
+def test_single_query_call_graph_replay_equals_eager(path):
+    """tnn_query allocates nothing and launches only kernels (no memsets), so
+    a call captured in a HIP graph replays to the eager result, with eager
+    work between replays."""
+    ps = synth.trajectories(120, 60, 500.0, 7200.0, seed=13)
+    ix = build(ps, 16)
+    qs, _ = synth.sample_queries(ps, 900, seed=14)
+    q = dev_points(qs)
+    k = 16
+    flags = {"plain": capi.TNN_PLAIN, "learned": capi.TNN_LEARNED, "mixed": MIXED,
+             "brute": capi.TNN_BRUTE, "per_query": capi.TNN_PLAIN}[path]
+    r2 = None
+    if path == "learned":
+        model = T.tnn_radius_model_init(ix, seed=2)
+        r2 = T.tnn_radius_infer(model, *q, alpha=1.0)
+    qscale = None
+    if path == "per_query":
+        qscale = torch.from_numpy(synth.scale_field(qs.x, qs.y, qs.z, 500.0, seed=4)).cuda()
+    params = T.make_params(SCALE, 0.0, k, flags, radius2=r2, query_scale=qscale)
+    scratch = torch.empty(max(T.tnn_query_workspace(ix, qs.n, params), 256), dtype=torch.uint8,
+                          device="cuda")
+    out = (torch.empty((qs.n, k), dtype=torch.int32, device="cuda"),
+           torch.empty((qs.n, k), dtype=torch.float64, device="cuda"))
+
+    def call():
+        T.tnn_query(ix, *q, SCALE, 0.0, k, flags=flags, radius2=r2, out=out, scratch=scratch,
+                    query_scale=qscale)
+
+    call()
+    torch.cuda.synchronize()
+    ref = (out[0].clone(), out[1].clone())
+    rows = qscale.cpu().numpy() if qscale is not None else SCALE
+    oi, od = oracle.knn(ps.soa(), qs.soa(), rows, 0.0, k)
+    assert_same(ref[0].cpu().numpy(), ref[1].cpu().numpy(), oi, od, f"eager {path}")
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        call()
+    torch.cuda.current_stream().wait_stream(s)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        call()
+    for rep in range(3):
+        out[0].fill_(-7)
+        out[1].fill_(-1.0)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out[0], ref[0]) and torch.equal(out[1], ref[1]), (path, rep)
