@@ -138,11 +138,15 @@ tnn_status tnn_build_segments(tnn_points pts, const int64_t *h_traj_offsets, int
 tnn_status tnn_index_info(const tnn_index *index, int64_t *n_points, int64_t *n_segments,
                           int64_t *n_blocks, int32_t *seg_len);
 
-/* Scratch bytes tnn_query needs for n_queries queries with these params:
- * the per-call segment constants that depend on the scales, and the
- * counters of the search's work queues (both written by tnn_query itself, so
- * the buffer needs no initialisation, but two calls in flight at once must
- * not share it). */
+/* Scratch bytes tnn_query needs for n_queries queries with these params.
+ * TNN: the per-call segment records (constants that depend on the scales)
+ * and the counters of the search's work queues.  TNN_BRUTE: none (256).
+ * TNN_BRUTE | TNN_MIXED_BF16: the BF16 point operands (64 B per point,
+ * padded to 128 points), |v|^2 per point, each query's per-chunk top-k lists
+ * (12 B per slot, 1 to 8 chunks chosen from n_queries and the point count)
+ * with their k-th distances, and a work counter.  tnn_query writes all of it
+ * itself, so the buffer needs no initialisation, but two calls in flight at
+ * once must not share it. */
 tnn_status tnn_query_workspace(const tnn_index *index, int64_t n_queries,
                                const tnn_query_params *params, size_t *bytes);
 
