@@ -62,7 +62,9 @@ typedef struct {
 #define TNN_PLAIN 0u       /* TNN, plain: seed from the nearest block, then expand */
 #define TNN_BRUTE 1u       /* linear search over every point (Sec. 3.6 baseline) */
 #define TNN_MIXED_BF16 2u  /* with TNN_BRUTE: BF16 MFMA distance tiles as a proven
-                              lower-bound filter, survivors rescored in binary64 */
+                              lower-bound filter, survivors rescored in binary64.
+                              A query whose own scaled squared norm (about the index
+                              box centre) reaches 1e30 gets (-1, NaN) slots. */
 #define TNN_LEARNED 4u     /* TNN seeded with a predicted k-th distance d_radius2[q] */
 
 /* Statistics counters (TNN_STAT_*), unsigned 64-bit, accumulated with atomics
@@ -78,6 +80,10 @@ typedef struct {
 #define TNN_STAT_MAX_ERR 8     /* bit pattern of the largest |approx - exact| distance (double) */
 #define TNN_STAT_COUNT 16
 
+/* Float32 range: TNN's bounds and the BF16 tiles need the scaled squared
+ * half-diagonal of the index box, sum_f s_f ((hi_f - lo_f) / 2)^2, below 1e30
+ * (TNN_E_UNSUPPORTED otherwise; the binary64 linear search has no limit), and
+ * queries within about 1e8 box widths of the data. */
 typedef struct {
   double scale[4];          /* s_x, s_y, s_z, s_t >= 0, finite */
   double t_window;          /* t_w >= 0: only points with t < t_q - t_w are candidates */
@@ -96,8 +102,8 @@ typedef struct {
                                still checked: pass any valid values).  The scales
                                may vary over space (Sec. 3.2: sigma as a function of
                                position); the metric of query q is then s_q.  A row with a
-                               negative or non-finite entry yields (-1, NaN) in every slot
-                               of that query.  TNN (plain or learned) and TNN_BRUTE only:
+                               negative or non-finite entry, or (TNN) out of the float32
+                               range above, yields (-1, NaN) in every slot of that query.  TNN (plain or learned) and TNN_BRUTE only:
                                with TNN_MIXED_BF16 or in a tnn_query_batched item it is
                                TNN_E_UNSUPPORTED. */
 } tnn_query_params;

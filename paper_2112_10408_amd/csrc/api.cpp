@@ -373,6 +373,11 @@ tnn_status tnn_query(const tnn_index *index, tnn_points queries, const tnn_query
   hipStream_t st = static_cast<hipStream_t>(stream);
   const QueryArgs a = make_args(params);
   const int wpb = params->waves_per_block ? params->waves_per_block : 4;
+  // float32 bounds and tiles: the scaled index box must stay in range (the
+  // binary64 linear search has no such limit)
+  const bool float_path = !(params->flags & TNN_BRUTE) || (params->flags & TNN_MIXED_BF16);
+  if (float_path && !params->d_query_scale && !scaled_box_ok(d->lo, d->hi, params->scale))
+    return TNN_E_UNSUPPORTED;
   if ((params->flags & TNN_BRUTE) && (params->flags & TNN_MIXED_BF16)) {
     TNN_HIP_CHECK(launch_mixed_brute(*d, a, queries, d_out_idx, d_out_dist, d_scratch, st));
     return TNN_OK;
@@ -466,6 +471,8 @@ tnn_status check_items(const tnn_batch_item *items, int32_t n) {
     if (c != TNN_OK) return c;
     if (it.params.flags & (TNN_BRUTE | TNN_MIXED_BF16)) return TNN_E_UNSUPPORTED;
     if (it.params.d_query_scale) return TNN_E_UNSUPPORTED;
+    const IndexDesc *d = desc_of(it.index);
+    if (!scaled_box_ok(d->lo, d->hi, it.params.scale)) return TNN_E_UNSUPPORTED;
     if (it.queries.n > 0 && (!it.d_out_idx || !it.d_out_dist)) return TNN_E_ARG;
   }
   return TNN_OK;

@@ -67,7 +67,9 @@ __device__ __forceinline__ float block_lb(const float *box, int b, const QueryPo
   const float gz = fmaxf(fmaxf(lo.z - q.z, q.z - hi.z), 0.0f);
   const float gt = fmaxf(fmaxf(q.t - hi.w, q.gwf), 0.0f);
   const float v = sf[0] * (gx * gx) + sf[1] * (gy * gy) + sf[2] * (gz * gz) + sf[3] * (gt * gt);
-  return v * (1.0f - 0x1p-18f);
+  // saturate: a float32 overflow (huge scales or coordinates) must not read
+  // as +inf, which means "masked"; the largest float is still a lower bound
+  return fminf(v * (1.0f - 0x1p-18f), 0x1.fffffep+127f);
 }
 
 // A segment's record as the search reads it.
@@ -109,7 +111,9 @@ __device__ __forceinline__ float seg_lb(const SegView &v, const QueryPoint &q, c
   const float dlo = sqrtf(d2) * (1.0f - 0x1p-18f) - v.r2.z;
   const float g = fmaxf(dlo - v.r2.y, 0.0f);
   const float gt = fmaxf(fmaxf(q.t - v.r1.w, q.gwf), 0.0f);
-  return (g * g + sf[3] * (gt * gt)) * (1.0f - 0x1p-20f);
+  // saturated like block_lb (an overflow gives a NaN or +inf on the way,
+  // which fmaxf / fminf turn into 0 or the largest float: both lower bounds)
+  return fminf((g * g + sf[3] * (gt * gt)) * (1.0f - 0x1p-20f), 0x1.fffffep+127f);
 }
 
 // The same bound when every query has its own scales s (per-query metric):

@@ -26,6 +26,9 @@ typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
 
 constexpr float kGamma = 0x1p-16f;
+// Largest scaled squared norm |u|^2 of a point or query the float32 tiles
+// take: tile values then stay below 4e30, far from float32 overflow.
+constexpr float kMaxNorm = (float)kMaxScaledNorm;
 constexpr int kWaves = 4;                 // waves per workgroup
 constexpr int kMQ = 16;                   // queries per wave (the MFMA rows)
 constexpr int kTileQ = kWaves * kMQ;      // queries per work item
@@ -347,7 +350,9 @@ __global__ __launch_bounds__(kWaves * 64) void mixed_brute_kernel(
       const int64_t q = qbase + g * 4 + e;
       float t = -__builtin_huge_valf();  // an inactive row lets nothing pass
       float h = -__builtin_huge_valf();
-      if (q < nq) {
+      // a query too far out for the float32 tiles takes no part (its rows
+      // are reported as (-1, NaN) by the merge)
+      if (q < nq && s_nu[wave][g * 4 + e] < kMaxNorm) {
         t = __builtin_huge_valf();
         for (int c = 0; c < n_chunks; ++c)
           if (c != chunk) t = fminf(t, part_kd[q * n_chunks + c]);
@@ -359,7 +364,8 @@ __global__ __launch_bounds__(kWaves * 64) void mixed_brute_kernel(
     if (lane < kMQ) {
       const int64_t q = qbase + lane;
       s_q[wave][lane] = q < nq ? make_float4(qxp[q], qyp[q], qzp[q], qtp[q]) : make_float4(0, 0, 0, 0);
-      s_tau[wave][lane] = __builtin_huge_valf();
+      // NaN marks a query outside the tiles' range in its chunk bound
+      s_tau[wave][lane] = s_nu[wave][lane] < kMaxNorm ? __builtin_huge_valf() : __builtin_nanf("");
     }
     tk_stride = (int64_t)n_chunks * k;
     tkd_base = part_d + ((size_t)qbase * n_chunks + chunk) * k;
@@ -503,12 +509,22 @@ __global__ __launch_bounds__(kWaves * 64) void mixed_brute_kernel(
 // One wave per query: the exact top-k of the union of its chunks' partial
 // lists (each sorted by (distance, index), padded with (+inf, none)).
 __global__ __launch_bounds__(256) void mixed_merge_kernel(const double *part_d,
-                                                          const int32_t *part_i, int n_chunks,
+                                                          const int32_t *part_i,
+                                                          const float *part_kd, int n_chunks,
                                                           int64_t nq, int k, double inf,
                                                           int32_t *out_idx, double *out_dist) {
   const int64_t q = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (q >= nq) return;
   const int lane = lane_id();
+  bool out_of_range = false;
+  for (int c = 0; c < n_chunks; ++c) out_of_range = out_of_range || __builtin_isnan(part_kd[q * n_chunks + c]);
+  if (out_of_range) {  // the query's scaled norm exceeds the tiles' range
+    if (lane < k) {
+      out_idx[q * k + lane] = -1;
+      out_dist[q * k + lane] = inf - inf;  // NaN (no 64-bit literal)
+    }
+    return;
+  }
   TopK tk;
   tk.init(k, inf);
   for (int c = 0; c < n_chunks; ++c) {
@@ -645,7 +661,7 @@ hipError_t launch_mixed_brute(const IndexDesc &ix, const QueryArgs &a, const tnn
   if (n_steps == 0) {
     // no points: merging no lists leaves every slot a pad
     hipLaunchKernelGGL(mixed_merge_kernel, dim3((unsigned)((qs.n + 3) / 4)), dim3(256), 0, st,
-                       part_d, part_i, 0, qs.n, a.k, a.inf, out_idx, out_dist);
+                       part_d, part_i, part_kd, 0, qs.n, a.k, a.inf, out_idx, out_dist);
     return hipGetLastError();
   }
   hipLaunchKernelGGL(mixed_prep_kernel, dim3((unsigned)((l.np + 255) / 256)), dim3(256), 0, st, ix,
@@ -679,7 +695,7 @@ hipError_t launch_mixed_brute(const IndexDesc &ix, const QueryArgs &a, const tnn
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(mixed_merge_kernel, dim3((unsigned)((qs.n + 3) / 4)), dim3(256), 0, st, part_d,
-                     part_i, (int)l.chunks, qs.n, a.k, a.inf, out_idx, out_dist);
+                     part_i, part_kd, (int)l.chunks, qs.n, a.k, a.inf, out_idx, out_dist);
   return hipGetLastError();
 }
 

@@ -351,8 +351,10 @@ write_out:
 }
 
 // The query's own scales (wave-uniform), rounded toward zero to float32 for
-// the float bounds.  False when one is negative or not finite.
-__device__ __forceinline__ bool load_query_scales(const double *qscale, int64_t qi, QueryArgs &aq) {
+// the float bounds.  False when one is negative or not finite, or (with
+// `box`, for the float32 bounds) when the scaled index box leaves their range.
+__device__ __forceinline__ bool load_query_scales(const double *qscale, int64_t qi, QueryArgs &aq,
+                                                  const IndexDesc *box) {
   bool ok = true;
   for (int f = 0; f < 4; ++f) {
     const double v = qscale[4 * qi + f];
@@ -360,7 +362,7 @@ __device__ __forceinline__ bool load_query_scales(const double *qscale, int64_t 
     aq.s[f] = v;
     aq.sf[f] = __double2float_rz(v);
   }
-  return ok;
+  return ok && (!box || scaled_box_ok(box->lo, box->hi, aq.s));
 }
 
 // A query whose scales are invalid: (-1, NaN) in every slot.
@@ -383,7 +385,7 @@ __device__ __forceinline__ void answer_query(const IndexDesc &ix, const Prep &pr
                                              const double *qscale) {
   if constexpr (PerQ) {
     QueryArgs aq = a;
-    if (!load_query_scales(qscale, qi, aq)) {
+    if (!load_query_scales(qscale, qi, aq, &ix)) {
       write_bad_scale_row(a, qi, out_idx, out_dist);
       return;
     }
@@ -469,7 +471,7 @@ __global__ __launch_bounds__(512) void brute_kernel(IndexDesc ix, QueryArgs a, c
   double s[4] = {a.s[0], a.s[1], a.s[2], a.s[3]};
   if (qscale) {
     QueryArgs aq = a;
-    if (!load_query_scales(qscale, qi, aq)) {
+    if (!load_query_scales(qscale, qi, aq, nullptr)) {
       write_bad_scale_row(a, qi, out_idx, out_dist);
       return;
     }

@@ -66,6 +66,22 @@ struct QueryArgs {
 
 inline size_t align_up(size_t v, size_t a = 256) { return (v + a - 1) / a * a; }
 
+// Float32 bounds and BF16 tiles take scaled squared norms up to this: the
+// scaled squared half-diagonal of the index box, sum_f s_f ((hi_f - lo_f) / 2)^2,
+// must stay below it (queries may lie far outside the box, up to about 1e8
+// box widths, before float32 products could overflow).
+constexpr double kMaxScaledNorm = 1e30;
+
+__host__ __device__ inline bool scaled_box_ok(const float lo[4], const float hi[4],
+                                              const double s[4]) {
+  double n2 = 0.0;
+  for (int f = 0; f < 4; ++f) {
+    const double h = 0.5 * ((double)hi[f] - (double)lo[f]);
+    n2 += s[f] * h * h;
+  }
+  return n2 < kMaxScaledNorm;
+}
+
 }  // namespace tnn
 
 #define TNN_HIP_CHECK(expr)                   \

@@ -433,3 +433,43 @@ def test_single_query_call_graph_replay_equals_eager(path):
         g.replay()
         torch.cuda.synchronize()
         assert torch.equal(out[0], ref[0]) and torch.equal(out[1], ref[1]), (path, rep)
+
+
+def test_huge_scales_and_far_queries():
+    """Scales whose scaled index box leaves float32 range are refused by the
+    float paths (TNN, BF16) and answered by the binary64 linear search; large
+    scales inside the range and far-out queries stay exact on TNN (its bounds
+    saturate instead of overflowing to the "masked" +inf); the BF16 tiles
+    report queries beyond their range as (-1, NaN)."""
+    ps = synth.trajectories(60, 40, 300.0, 3600.0, seed=17)
+    ix = build(ps, 16)
+    rng = np.random.default_rng(18)
+    qs = ps.take(rng.choice(ps.n, 200, replace=False))
+    huge = (1e34, 1e34, 1e35, 1e30)
+    oi, od = oracle.knn(ps.soa(), qs.soa(), huge, 0.0, 8)
+    gi, gd = gpu_query(ix, qs, huge, 0.0, 8, flags=capi.TNN_BRUTE)
+    assert_same(gi, gd, oi, od, "huge scales, binary64 linear search")
+    for flags in (capi.TNN_PLAIN, capi.TNN_LEARNED, MIXED):
+        with pytest.raises(capi.TnnError) as e:
+            q = dev_points(qs)
+            r2 = torch.ones(qs.n, dtype=torch.float32, device="cuda")
+            T.tnn_query(ix, *q, huge, 0.0, 8, flags=flags, radius2=r2)
+        assert e.value.code == capi.TNN_E_UNSUPPORTED, flags
+    # just inside the range: float32 bounds still exact
+    edge = tuple(v * 1e24 for v in SCALE)
+    oi, od = oracle.knn(ps.soa(), qs.soa(), edge, 0.0, 8)
+    for flags in (capi.TNN_PLAIN, capi.TNN_BRUTE, MIXED):
+        gi, gd = gpu_query(ix, qs, edge, 0.0, 8, flags=flags)
+        assert_same(gi, gd, oi, od, f"large scales flags={flags}")
+    far = qs.take(np.arange(qs.n))
+    far.x = far.x.copy()
+    far.x[::7] = np.float32(3e16)  # scaled squared norm ~1e33
+    oi, od = oracle.knn(ps.soa(), far.soa(), SCALE, 0.0, 8)
+    gi, gd = gpu_query(ix, far, SCALE, 0.0, 8, flags=MIXED)
+    bad = np.arange(0, far.n, 7)
+    assert (gi[bad] == -1).all() and np.isnan(gd[bad]).all()
+    keep = np.setdiff1d(np.arange(far.n), bad)
+    assert_same(gi[keep], gd[keep], oi[keep], od[keep], "far queries, BF16")
+    for flags in (capi.TNN_PLAIN, capi.TNN_BRUTE):
+        gi, gd = gpu_query(ix, far, SCALE, 0.0, 8, flags=flags)
+        assert_same(gi, gd, oi, od, f"far queries flags={flags}")
