@@ -38,7 +38,7 @@ FLOPS_POINT = 15           # binary64 exact distance
 # only; after any change to them the figure is reported as null.
 KERNEL_SOURCES = ("query.hip", "bounds.h", "wave.h", "tnn_internal.h")
 MEASURED_TRAFFIC = {
-    "sha256": "8454d16361b734cd149eafd9c0b7eb54e8d0a5b05ace27c07877c2e19df1ecdd",
+    "sha256": "4eb1633acc89c28e46cfe588988fe564bcf353797211bc221ad0ce068f1d3b88",
     "bytes_per_launch": 251.5e6,
 }
 
