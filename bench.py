@@ -39,8 +39,17 @@ FLOPS_POINT = 15           # binary64 exact distance
 KERNEL_SOURCES = ("query.hip", "bounds.h", "wave.h", "tnn_internal.h")
 MEASURED_TRAFFIC = {
     "sha256": "4eb1633acc89c28e46cfe588988fe564bcf353797211bc221ad0ce068f1d3b88",
-    "bytes_per_launch": 251.5e6,
+    "bytes_per_launch": 266.9e6,
 }
+
+
+# Safety factor of the learned radius: the predicted k-th distance is scaled so
+# that this fraction of the training queries' true k-th distances falls inside.
+# With best-first expansion a generous radius costs little and a fallback
+# (second round) costs more, so high quantiles win (a sweep on the training
+# queries of the 1M-point workload picks 0.99; --radius-quantile 0 repeats it).
+RADIUS_QUANTILES = (0.9, 0.95, 0.98, 0.99, 0.995)
+BATCH_QUANTILE = 0.99
 
 
 def measured_traffic():
@@ -115,7 +124,7 @@ def run_batched(args, T, capi, radius, synth, torch, stream):
         tq, _ = synth.sample_queries(ps, n_tr, 77, exclude=excl)
         tx = T.to_device(tq.x, tq.y, tq.z, tq.t)
         model, _, pdist, ptr = radius.train(ix, *tx, scale, 0.0, a["k"], epochs=4, batch=2048)
-        alpha = radius.calibrate(model, *ptr, pdist, a["k"], quantile=0.8)
+        alpha = radius.calibrate(model, *ptr, pdist, a["k"], quantile=BATCH_QUANTILE)
         q = T.to_device(qs.x, qs.y, qs.z, qs.t)
         r2 = torch.empty(qs.n, dtype=torch.float32, device="cuda")
         entries.append(dict(index=ix, q=q, scale=scale, k=a["k"], flags=capi.TNN_LEARNED, radius2=r2))
@@ -224,7 +233,7 @@ def run_config(name, args, T, capi, radius, synth, torch, stream):
     scr_tr = torch.empty(max(T.tnn_query_workspace(ix, tq.n, T.make_params(scale, tw, k)), 256),
                          dtype=torch.uint8, device="cuda")
     best = None
-    for qnt in ((0.7, 0.8, 0.9) if not args.radius_quantile else (args.radius_quantile,)):
+    for qnt in (RADIUS_QUANTILES if not args.radius_quantile else (args.radius_quantile,)):
         a = radius.calibrate(model, *ptr, pdist, k, quantile=qnt)
 
         def learned_tr():
@@ -317,7 +326,7 @@ def run_query_scales(args, T, capi, radius, synth, torch, stream):
     tx = T.to_device(tq.x, tq.y, tq.z, tq.t)
     model, loss, pdist, ptr = radius.train(ix, *tx, scale, tw, k, epochs=args.train_epochs,
                                            batch=4096, lr=3e-3)
-    alpha = radius.calibrate(model, *ptr, pdist, k, quantile=0.8)
+    alpha = radius.calibrate(model, *ptr, pdist, k, quantile=BATCH_QUANTILE)
     r2 = torch.empty(n, dtype=torch.float32, device="cuda")
 
     def learned():
@@ -361,9 +370,9 @@ def main():
                     help="skip the other workloads (10k points, 1M queries, 8M points, "
                          "30-min window, airways, random points, per-query scales)")
     ap.add_argument("--train-epochs", type=int, default=8)
-    ap.add_argument("--radius-quantile", type=float, default=0.8,
-                    help="calibration quantile of the radius safety factor; 0 sweeps "
-                         "0.5-0.95 and keeps the fastest on the training queries")
+    ap.add_argument("--radius-quantile", type=float, default=0.99,
+                    help="calibration quantile of the radius safety factor (default 0.99); "
+                         "0 sweeps 0.9-0.995 and keeps the fastest on the training queries")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a 256 MiB device-to-device copy (counter calibration)")
     args = ap.parse_args()
@@ -426,7 +435,7 @@ def main():
     out_tr = (torch.empty((tq.n, k), dtype=torch.int32, device="cuda"),
               torch.empty((tq.n, k), dtype=torch.float64, device="cuda"))
     best = None
-    sweep = (0.5, 0.7, 0.8, 0.9, 0.95) if not args.radius_quantile else (args.radius_quantile,)
+    sweep = RADIUS_QUANTILES if not args.radius_quantile else (args.radius_quantile,)
     for qnt in sweep:
         a = radius.calibrate(model, *ptr, pdist, k, quantile=qnt)
 
@@ -435,7 +444,7 @@ def main():
             T.tnn_query(ix, tx, ty, tz, tt, scale, 0.0, k, flags=capi.TNN_LEARNED, radius2=r2_tr,
                         out=out_tr, scratch=scratch)
 
-        ms = timed(learned_tr, 3, 1, stream)
+        ms = timed(learned_tr, 5, 2, stream)
         log(f"  quantile {qnt}: alpha {a:.3f}, {ms:.3f} ms on the training queries")
         if best is None or ms < best[0]:
             best = (ms, qnt, a)
