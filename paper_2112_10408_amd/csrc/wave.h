@@ -135,60 +135,137 @@ __device__ __forceinline__ double mk_double(int lo, int hi) {
   return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
 }
 
-// Compare-exchange of the keys of lanes l and l ^ J: lanes with `keep_min`
-// keep the smaller key, the others the larger.  One comparison decides both
-// sides (equal keys are identical, so taking either is the same).
-template <int J>
-__device__ __forceinline__ void cmpx(double &d, int &id, bool keep_min) {
-  if constexpr (J >= 16) {
-    int al, bl, ah, bh, ai, bi;
-    lane_pair<J>(lo32(d), al, bl);
-    lane_pair<J>(hi32(d), ah, bh);
-    lane_pair<J>(id, ai, bi);
-    const double ad = mk_double(al, ah), bd = mk_double(bl, bh);
-    const bool b_lt = key_lt(bd, bi, ad, ai);  // the upper lane's key is the smaller
-    const bool take_b = keep_min == b_lt;
-    d = take_b ? bd : ad;
-    id = take_b ? bi : ai;
-  } else {
-    const double od = mk_double(xor_lane<J>(lo32(d)), xor_lane<J>(hi32(d)));
-    const int oid = xor_lane<J>(id);
-    const bool o_lt = key_lt(od, oid, d, id);
-    if (keep_min == o_lt) {
-      d = od;
-      id = oid;
-    }
+// A (distance, index) key as three words: the distance's high and low halves
+// and the index.  Distances handed to the sorting network are +0 .. +inf and
+// indices are non-negative, so the unsigned lexicographic order of (hi, lo,
+// index) is the order of key_lt, and a 96-bit subtraction's borrow decides a
+// comparison in three carry-chained instructions.
+struct Key3 {
+  unsigned h, l, i;
+};
+
+__device__ __forceinline__ Key3 key3(double d, int id) {
+  return Key3{(unsigned)hi32(d), (unsigned)lo32(d), (unsigned)id};
+}
+
+// Lanes that keep the smaller key of their pair in the stage (Size, J) of a
+// bitonic sort over 64 lanes (ascending blocks of Size alternate with
+// descending ones; Desc flips them all).
+constexpr uint64_t keep_min_mask(int size, int j, bool desc) {
+  uint64_t m = 0;
+  for (int l = 0; l < 64; ++l) {
+    const bool asc = ((l & size) == 0) != desc;
+    if (((l & j) == 0) == asc) m |= 1ull << l;
   }
+  return m;
+}
+
+// One compare-exchange stage with the partner lane read through a DPP
+// control.  vcc first gets (partner < mine), then is flipped in the lanes
+// that keep the smaller key, so that it is set exactly where a lane keeps its
+// own key; the selects read the partner through the same control.  Each
+// stage starts with two wait states: a DPP read of a register written by the
+// previous vector instruction needs them.
+#define TNN_CX_DPP(CTRL)                                                                   \
+  "s_nop 1\n\t"                                                                            \
+  "v_sub_co_u32_dpp %[t], vcc, %[i], %[i] " CTRL " row_mask:0xf bank_mask:0xf\n\t"         \
+  "v_subb_co_u32_dpp %[t], vcc, %[l], %[l], vcc " CTRL " row_mask:0xf bank_mask:0xf\n\t"   \
+  "v_subb_co_u32_dpp %[t], vcc, %[h], %[h], vcc " CTRL " row_mask:0xf bank_mask:0xf\n\t"   \
+  "s_xor_b32 vcc_lo, vcc_lo, %[mlo]\n\t"                                                   \
+  "s_xor_b32 vcc_hi, vcc_hi, %[mhi]\n\t"                                                   \
+  "v_cndmask_b32_dpp %[i], %[i], %[i], vcc " CTRL " row_mask:0xf bank_mask:0xf\n\t"        \
+  "v_cndmask_b32_dpp %[l], %[l], %[l], vcc " CTRL " row_mask:0xf bank_mask:0xf\n\t"        \
+  "v_cndmask_b32_dpp %[h], %[h], %[h], vcc " CTRL " row_mask:0xf bank_mask:0xf"
+
+// Keeps `k` where the mask bit of the lane says so given (o < k), else takes
+// `o` (the partner's key, already in registers).
+template <uint64_t M>
+__device__ __forceinline__ void cx_with(Key3 &k, const Key3 &o) {
+  unsigned t;
+  asm volatile(
+      "v_sub_co_u32 %[t], vcc, %[oi], %[i]\n\t"
+      "v_subb_co_u32 %[t], vcc, %[ol], %[l], vcc\n\t"
+      "v_subb_co_u32 %[t], vcc, %[oh], %[h], vcc\n\t"
+      "s_xor_b32 vcc_lo, vcc_lo, %[mlo]\n\t"
+      "s_xor_b32 vcc_hi, vcc_hi, %[mhi]\n\t"
+      "v_cndmask_b32 %[i], %[oi], %[i], vcc\n\t"
+      "v_cndmask_b32 %[l], %[ol], %[l], vcc\n\t"
+      "v_cndmask_b32 %[h], %[oh], %[h], vcc"
+      : [h] "+v"(k.h), [l] "+v"(k.l), [i] "+v"(k.i), [t] "=&v"(t)
+      : [oh] "v"(o.h), [ol] "v"(o.l), [oi] "v"(o.i), [mlo] "i"((unsigned)M),
+        [mhi] "i"((unsigned)(M >> 32))
+      : "vcc");
+}
+
+// Compare-exchange of the keys of lanes l and l ^ J: lanes whose bit is set
+// in M keep the smaller key, the others the larger.  Equal keys are
+// identical, so either choice is the same.
+template <int J, uint64_t M>
+__device__ __forceinline__ void cmpx(Key3 &k) {
+  constexpr unsigned mlo = (unsigned)M, mhi = (unsigned)(M >> 32);
+  unsigned t;
+  if constexpr (J == 1) {
+    asm volatile(TNN_CX_DPP("quad_perm:[1,0,3,2]")
+                 : [h] "+v"(k.h), [l] "+v"(k.l), [i] "+v"(k.i), [t] "=&v"(t)
+                 : [mlo] "i"(mlo), [mhi] "i"(mhi)
+                 : "vcc");
+  } else if constexpr (J == 2) {
+    asm volatile(TNN_CX_DPP("quad_perm:[2,3,0,1]")
+                 : [h] "+v"(k.h), [l] "+v"(k.l), [i] "+v"(k.i), [t] "=&v"(t)
+                 : [mlo] "i"(mlo), [mhi] "i"(mhi)
+                 : "vcc");
+  } else if constexpr (J == 8) {
+    asm volatile(TNN_CX_DPP("row_ror:8")
+                 : [h] "+v"(k.h), [l] "+v"(k.l), [i] "+v"(k.i), [t] "=&v"(t)
+                 : [mlo] "i"(mlo), [mhi] "i"(mhi)
+                 : "vcc");
+  } else if constexpr (J == 4) {
+    // no single DPP control swaps lanes 4 apart: an LDS swizzle
+    const Key3 o{(unsigned)xor_lane<4>((int)k.h), (unsigned)xor_lane<4>((int)k.l),
+                 (unsigned)xor_lane<4>((int)k.i)};
+    cx_with<M>(k, o);
+  } else {
+    // 16 or 32 lanes apart: permlane swaps give the lower lane's key (a) and
+    // the upper lane's key (b) in both lanes; keep a where (b < a) differs
+    // from the mask, else take b
+    int ah, bh, al, bl, ai, bi;
+    lane_pair<J>((int)k.h, ah, bh);
+    lane_pair<J>((int)k.l, al, bl);
+    lane_pair<J>((int)k.i, ai, bi);
+    k = Key3{(unsigned)ah, (unsigned)al, (unsigned)ai};
+    cx_with<M>(k, Key3{(unsigned)bh, (unsigned)bl, (unsigned)bi});
+  }
+  (void)t;
 }
 
 template <bool Desc, int Size, int J>
-__device__ __forceinline__ void sort_stage(double &d, int &id, int l) {
-  const bool asc = ((l & Size) == 0) != Desc;
-  const bool lower = (l & J) == 0;
-  cmpx<J>(d, id, lower == asc);
-  if constexpr (J > 1) sort_stage<Desc, Size, J / 2>(d, id, l);
+__device__ __forceinline__ void sort_stage(Key3 &k) {
+  cmpx<J, keep_min_mask(Size, J, Desc)>(k);
+  if constexpr (J > 1) sort_stage<Desc, Size, J / 2>(k);
 }
 
 template <bool Desc, int Size>
-__device__ __forceinline__ void sort_upto(double &d, int &id, int l) {
-  if constexpr (Size > 2) sort_upto<Desc, Size / 2>(d, id, l);
-  sort_stage<Desc, Size, Size / 2>(d, id, l);
+__device__ __forceinline__ void sort_upto(Key3 &k) {
+  if constexpr (Size > 2) sort_upto<Desc, Size / 2>(k);
+  sort_stage<Desc, Size, Size / 2>(k);
 }
 
 // Bitonic sort of 64 keys by lane, ascending (Desc = false) or descending.
-template <bool Desc = false>
-__device__ __forceinline__ void sort64(double &d, int &id) {
-  sort_upto<Desc, 64>(d, id, lane_id());
-}
+// A DPP read needs five wait states after a write of EXEC, which the code
+// before a network may end with.
+__device__ __forceinline__ void dpp_entry() { asm volatile("s_nop 4"); }
 
-template <int J>
-__device__ __forceinline__ void merge_stage(double &d, int &id, int l) {
-  cmpx<J>(d, id, (l & J) == 0);
-  if constexpr (J > 1) merge_stage<J / 2>(d, id, l);
+template <bool Desc = false>
+__device__ __forceinline__ void sort64(Key3 &k) {
+  dpp_entry();
+  sort_upto<Desc, 64>(k);
 }
 
 // Sort a bitonic sequence of 64 keys ascending.
-__device__ __forceinline__ void merge64(double &d, int &id) { merge_stage<32>(d, id, lane_id()); }
+__device__ __forceinline__ void merge64(Key3 &k) {
+  dpp_entry();
+  sort_stage<false, 64, 32>(k);
+}
 
 // Top-k over (distance, index): lane r holds the r-th smallest key seen so
 // far (r < 64; ranks >= k are kept but never reported).  kd/kid mirror rank
@@ -244,6 +321,7 @@ struct TopK {
   // Offer one key per lane; lanes with gate=false offer nothing.  `gm` is the
   // ballot of gate.  Returns nothing; updates the threshold.
   __device__ __forceinline__ void offer(uint64_t gm, bool gate, double nd, int nid) {
+    nd += 0.0;  // -0.0 becomes +0.0, which the word order of the merge needs
     const int n = __popcll(gm);
     if (n <= kInsertMax) {
       while (gm) {
@@ -252,22 +330,20 @@ struct TopK {
         insert_one(readlane_d(nd, l), readlane_i(nid, l));
       }
     } else {
-      double cd = gate ? nd : inf_;
-      int cid = gate ? nid : kNoId;
+      Key3 c = key3(gate ? nd : inf_, gate ? nid : kNoId);
       if (!(readlane_d(d, 0) < inf_)) {  // empty top-k: the sorted batch is the result
-        sort64<false>(cd, cid);
-        d = cd;
-        id = cid;
+        sort64<false>(c);
       } else {
         // descending batch against the ascending top-k: the lane-wise
         // smaller keys form a bitonic sequence holding the 64 smallest
-        sort64<true>(cd, cid);
-        if (key_lt(cd, cid, d, id)) {
-          d = cd;
-          id = cid;
-        }
-        merge64(d, id);
+        sort64<true>(c);
+        Key3 m = key3(d, id);
+        cx_with<~0ull>(m, c);
+        c = m;
+        merge64(c);
       }
+      d = mk_double((int)c.l, (int)c.h);
+      id = (int)c.i;
     }
     refresh();
   }
