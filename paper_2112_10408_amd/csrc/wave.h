@@ -85,22 +85,32 @@ __device__ __forceinline__ void lane_pair(int v, int &lo, int &hi) {
   }
 }
 
-// Wave-wide minimum / maximum of non-negative floats (or +inf), the result in
-// every lane: quad and row steps by DPP, row pairs and wave halves by
-// permlane swaps.  Non-negative floats order like their bit patterns as
-// int32, so integer min / max does the comparisons.
+// Wave-wide minimum / maximum of non-negative floats (or +inf) as a
+// wave-uniform value.  Non-negative floats order like their bit patterns as
+// int32, so integer min / max does the comparisons.  DPP steps reduce each
+// row of 16 lanes (lanes a step does not write read the identity of the
+// operation, which lets the compiler fold each step into one min / max), row
+// broadcasts carry the row results into lane 63, and reading that lane makes
+// the result uniform.
+constexpr int kDppRowBcast15 = 0x142;  // lane 15 of each row to the next row
+constexpr int kDppRowBcast31 = 0x143;  // lane 31 to rows 2 and 3
+
+template <bool Max, int Ctrl, int RowMask = 0xF>
+__device__ __forceinline__ int ext_step(int v) {
+  constexpr int ident = Max ? (int)0x80000000 : 0x7fffffff;
+  const int o = __builtin_amdgcn_update_dpp(ident, v, Ctrl, RowMask, 0xF, false);
+  return Max ? max(v, o) : min(v, o);
+}
+
 template <bool Max>
 __device__ __forceinline__ int wave_ext_bits(int v) {
-  auto f = [](int a, int b) { return Max ? max(a, b) : min(a, b); };
-  v = f(v, dpp_i<kDppQuadXor1>(v));
-  v = f(v, dpp_i<kDppQuadXor2>(v));
-  v = f(v, dpp_i<kDppRowRor4>(v));
-  v = f(v, dpp_i<kDppRowRor8>(v));
-  int a, b;
-  lane_pair<16>(v, a, b);
-  v = f(a, b);
-  lane_pair<32>(v, a, b);
-  return f(a, b);
+  v = ext_step<Max, kDppQuadXor1>(v);
+  v = ext_step<Max, kDppQuadXor2>(v);
+  v = ext_step<Max, kDppRowRor4>(v);
+  v = ext_step<Max, kDppRowRor8>(v);
+  v = ext_step<Max, kDppRowBcast15, 0xA>(v);
+  v = ext_step<Max, kDppRowBcast31, 0xC>(v);
+  return __builtin_amdgcn_readlane(v, 63);
 }
 
 __device__ __forceinline__ float wave_min_nonneg(float v) {
