@@ -522,12 +522,14 @@ tnn_status tnn_batch_prepare(const tnn_batch_item *items, int32_t n_items,
   std::vector<BatchItemDev> dev(n);
   std::vector<int64_t> seg_prefix(n + 1, 0), qprefix(n + 1, 0);
   std::vector<double> cost(n);
+  bool stats = false;
   for (int32_t i = 0; i < n; ++i) {
     const tnn_batch_item &it = items[i];
     const IndexDesc *d = desc_of(it.index);
     BatchItemDev &b = dev[i];
     b.ix = *d;
     b.a = make_args(&it.params);
+    stats = stats || b.a.stats != nullptr;
     b.pr = prep_view(m + L.prep[i], d->n_seg);
     b.qx = it.queries.x;
     b.qy = it.queries.y;
@@ -556,6 +558,7 @@ tnn_status tnn_batch_prepare(const tnn_batch_item *items, int32_t n_items,
   bl.n = n;
   bl.chunk = cfg.chunk;
   bl.waves_per_block = w;
+  bl.stats = stats ? 1 : 0;
   bl.grid = (int64_t)cus * cfg.blocks_per_cu;
   bl.total_q = qprefix[n];
   bl.total_seg = seg_prefix[n];

@@ -314,7 +314,7 @@ __global__ __launch_bounds__(kWaves * 64) void mixed_brute_kernel(
       const bool gate = mine && valid && tk.admits(d, pid);
       const uint64_t gm = ballot(gate);
       if (gm) {
-        tk.offer(gm, gate, d, pid);
+        tk.offer(gm, d, pid);
         if (lane < kk) {
           tkd_base[m * tk_stride + lane] = tk.d;
           tkid_base[m * tk_stride + lane] = tk.id;
@@ -543,7 +543,7 @@ __global__ __launch_bounds__(256) void mixed_merge_kernel(const double *part_d,
     }
     const bool gate = id != kNoId && tk.admits(d, id);
     const uint64_t gm = ballot(gate);
-    if (gm) tk.offer(gm, gate, d, id);
+    if (gm) tk.offer(gm, d, id);
   }
   if (lane < k) {
     out_idx[q * k + lane] = tk.id == kNoId ? -1 : tk.id;

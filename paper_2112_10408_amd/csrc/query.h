@@ -21,6 +21,7 @@ struct BatchLaunch {
   int32_t n;
   int32_t chunk;
   int32_t waves_per_block;
+  int32_t stats;  // some item collects statistics
   int64_t grid;
   int64_t total_q;
   int64_t total_seg;

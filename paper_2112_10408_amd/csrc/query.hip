@@ -73,18 +73,36 @@ __global__ void prep_kernel(IndexDesc ix, QueryArgs a, float4 *rec, unsigned lon
 // ---------------------------------------------------------------------------
 // One wavefront answers one query.
 // ---------------------------------------------------------------------------
-struct WaveStats {
-  uint32_t blocks, segs, points, merges, rounds, fallback;
+// Per-wave work counters for the statistics output.  With On = false every
+// update compiles to nothing, so searches run without statistics carry no
+// counter registers or instructions.
+template <bool On>
+struct Counter {
+  uint32_t v = 0;
+  __device__ __forceinline__ void operator+=(uint32_t x) { v += x; }
+  __device__ __forceinline__ void operator++() { ++v; }
+  __device__ __forceinline__ void set(uint32_t x) { v = x; }
+};
+template <>
+struct Counter<false> {
+  __device__ __forceinline__ void operator+=(uint32_t) {}
+  __device__ __forceinline__ void operator++() {}
+  __device__ __forceinline__ void set(uint32_t) {}
 };
 
-template <bool PerQ>
+template <bool On>
+struct WaveStats {
+  Counter<On> blocks, segs, points, merges, rounds, fallback;
+};
+
+template <bool PerQ, bool Stats>
 struct Searcher {
   const IndexDesc &ix;
   const Prep &pr;
   const QueryArgs &a;
   QueryPoint q;
   TopK tk;
-  WaveStats st;
+  WaveStats<Stats> st;
   int lane;
   int spi_shift;  // log2(kpad): lanes per segment when scanning points
   const float *box;   // block boxes (global memory or an LDS copy)
@@ -115,7 +133,7 @@ struct Searcher {
       int my_l = -1;
       for (int i = 0; i < spi && cm; ++i) {
         float kmin;
-        const int l = wave_argmin_lane(((cm >> lane) & 1ull) ? key_l : __builtin_huge_valf(), kmin);
+        const int l = wave_argmin_lane(lane_in(cm) ? key_l : __builtin_huge_valf(), kmin);
         cm &= ~(1ull << l);
         if (slot == i) my_l = l;
       }
@@ -140,7 +158,7 @@ struct Searcher {
       const bool gate = valid && tk.admits(d, pid);
       const uint64_t gm = ballot(gate);
       if (gm) {
-        tk.offer(gm, gate, d, pid);
+        tk.offer(gm, d, pid);
         ++st.merges;
         cm &= ballot((double)key_l <= tk.kd);
       }
@@ -171,7 +189,7 @@ struct Searcher {
       // early; once the next bound exceeds min(tau, k-th) so do all later ones
       while (ms) {
         float smin;
-        const int sl = wave_argmin_lane(((ms >> lane) & 1ull) ? lbs : finf, smin);
+        const int sl = wave_argmin_lane(lane_in(ms) ? lbs : finf, smin);
         ms &= ~(1ull << sl);
         if ((double)smin > fmin(tau, tk.kd)) break;
         // block level: the superblock's 64 blocks, one per lane
@@ -183,7 +201,7 @@ struct Searcher {
         uint64_t m = ballot(lbb < finf && (double)lbb <= fmin(tau, tk.kd));
         while (m) {
           float bmin;
-          const int bl = wave_argmin_lane(((m >> lane) & 1ull) ? lbb : finf, bmin);
+          const int bl = wave_argmin_lane(lane_in(m) ? lbb : finf, bmin);
           m &= ~(1ull << bl);
           const double tau_cur = fmin(tau, tk.kd);
           const double lbb_b = (double)bmin;
@@ -197,7 +215,7 @@ struct Searcher {
           const float key_f = fmaxf(s < S ? seg_bound(sv) : finf, bmin);
           const double key = (double)key_f;
           st.segs += (uint32_t)min((int64_t)kBlockSegs, S - (int64_t)bb * kBlockSegs);
-          const bool seeded = bb == seed_block && ((seed_mask >> lane) & 1ull);
+          const bool seeded = bb == seed_block && lane_in(seed_mask);
           // a masked segment (infinite key) holds no candidate
           const bool cand = s < S && key < kInf && key <= tau_cur && key > prev && !seeded;
           const uint64_t cm = ballot(cand);
@@ -209,15 +227,18 @@ struct Searcher {
   }
 };
 
-__device__ __forceinline__ void flush_stats(unsigned long long *stats, const WaveStats &st) {
-  if (!stats || lane_id() != 0) return;
-  atomicAdd(stats + TNN_STAT_QUERIES, 1ull);
-  atomicAdd(stats + TNN_STAT_BLOCKS, (unsigned long long)st.blocks);
-  atomicAdd(stats + TNN_STAT_SEGMENTS, (unsigned long long)st.segs);
-  atomicAdd(stats + TNN_STAT_POINTS, (unsigned long long)st.points);
-  atomicAdd(stats + TNN_STAT_MERGES, (unsigned long long)st.merges);
-  atomicAdd(stats + TNN_STAT_ROUNDS, (unsigned long long)st.rounds);
-  atomicAdd(stats + TNN_STAT_FALLBACKS, (unsigned long long)st.fallback);
+template <bool On>
+__device__ __forceinline__ void flush_stats(unsigned long long *stats, const WaveStats<On> &st) {
+  if constexpr (On) {
+    if (!stats || lane_id() != 0) return;
+    atomicAdd(stats + TNN_STAT_QUERIES, 1ull);
+    atomicAdd(stats + TNN_STAT_BLOCKS, (unsigned long long)st.blocks.v);
+    atomicAdd(stats + TNN_STAT_SEGMENTS, (unsigned long long)st.segs.v);
+    atomicAdd(stats + TNN_STAT_POINTS, (unsigned long long)st.points.v);
+    atomicAdd(stats + TNN_STAT_MERGES, (unsigned long long)st.merges.v);
+    atomicAdd(stats + TNN_STAT_ROUNDS, (unsigned long long)st.rounds.v);
+    atomicAdd(stats + TNN_STAT_FALLBACKS, (unsigned long long)st.fallback.v);
+  }
 }
 
 // Answer query `qi` with one wavefront (Algorithm 2 in radius form).
@@ -228,21 +249,21 @@ __device__ __forceinline__ void flush_stats(unsigned long long *stats, const Wav
 //            continues from the k-th found (or a 16x larger radius).
 // Rounds only widen tau; a segment is scanned in the first round whose
 // radius reaches its bound, so no point enters the top-k twice.
-template <bool PerQ>
+template <bool PerQ, bool Stats>
 __device__ __forceinline__ void answer_query_with(const IndexDesc &ix, const Prep &pr,
                                                   const QueryArgs &a, const float *qx,
                                                   const float *qy, const float *qz,
                                                   const float *qt, int64_t qi, int32_t *out_idx,
                                                   double *out_dist, const float *box,
                                                   const float *sbox) {
-  Searcher<PerQ> se(ix, pr, a);
+  Searcher<PerQ, Stats> se(ix, pr, a);
   se.lane = lane_id();
   se.box = box;
   se.sbox = sbox;
   se.spi_shift = 31 - __clz(ix.kpad);
   se.q = make_query(qx[qi], qy[qi], qz[qi], qt[qi], a.t_window);
   se.tk.init(a.k, a.inf);
-  se.st = WaveStats{0, 0, 0, 0, 0, 0};
+  se.st = WaveStats<Stats>{};
   const int nb = ix.n_blocks;
   const int64_t S = ix.n_seg;
   // scale of the data, used to grow the radius when nothing is known yet
@@ -295,7 +316,7 @@ __device__ __forceinline__ void answer_query_with(const IndexDesc &ix, const Pre
     }
     if (!(best < __builtin_huge_valf())) {  // nothing early enough anywhere
       tau = kInf;
-      se.st.rounds = 0;
+      se.st.rounds.set(0);
       goto write_out;
     }
     seed_block = bestb;
@@ -332,7 +353,7 @@ __device__ __forceinline__ void answer_query_with(const IndexDesc &ix, const Pre
       ++se.st.rounds;
       const float maxfin = se.round(prev, tau, seed_block, seed_mask);
       if (se.tk.kd <= tau || !(tau < kInf)) break;
-      if (learned) se.st.fallback = 1;
+      if (learned) se.st.fallback.set(1);
       prev = tau;
       if (se.tk.kd < kInf) {
         tau = se.tk.kd;
@@ -376,7 +397,7 @@ __device__ __forceinline__ void write_bad_scale_row(const QueryArgs &a, int64_t 
   if (a.stats && lane == 0) atomicAdd(a.stats + TNN_STAT_QUERIES, 1ull);
 }
 
-template <bool PerQ>
+template <bool PerQ, bool Stats>
 __device__ __forceinline__ void answer_query(const IndexDesc &ix, const Prep &pr,
                                              const QueryArgs &a, const float *qx, const float *qy,
                                              const float *qz, const float *qt, int64_t qi,
@@ -389,15 +410,15 @@ __device__ __forceinline__ void answer_query(const IndexDesc &ix, const Prep &pr
       write_bad_scale_row(a, qi, out_idx, out_dist);
       return;
     }
-    answer_query_with<true>(ix, pr, aq, qx, qy, qz, qt, qi, out_idx, out_dist, box, sbox);
+    answer_query_with<true, Stats>(ix, pr, aq, qx, qy, qz, qt, qi, out_idx, out_dist, box, sbox);
   } else {
-    answer_query_with<false>(ix, pr, a, qx, qy, qz, qt, qi, out_idx, out_dist, box, sbox);
+    answer_query_with<false, Stats>(ix, pr, a, qx, qy, qz, qt, qi, out_idx, out_dist, box, sbox);
   }
 }
 
 // qscale (last, so the other arguments keep their places): per-query scales
-// when PerQ, else unused.
-template <bool PerQ>
+// when PerQ, else unused.  Stats: the call collects statistics (a.stats set).
+template <bool PerQ, bool Stats>
 __global__ __launch_bounds__(512) void tnn_query_kernel(IndexDesc ix, Prep pr, QueryArgs a,
                                                         const float *qx, const float *qy,
                                                         const float *qz, const float *qt,
@@ -405,7 +426,8 @@ __global__ __launch_bounds__(512) void tnn_query_kernel(IndexDesc ix, Prep pr, Q
                                                         double *out_dist, const double *qscale) {
   const int64_t qi = (int64_t)blockIdx.x * (blockDim.x >> 6) + uniform_i((int)(threadIdx.x >> 6));
   if (qi >= nq) return;
-  answer_query<PerQ>(ix, pr, a, qx, qy, qz, qt, qi, out_idx, out_dist, ix.box, ix.sbox, qscale);
+  answer_query<PerQ, Stats>(ix, pr, a, qx, qy, qz, qt, qi, out_idx, out_dist, ix.box, ix.sbox,
+                            qscale);
 }
 
 // Same search with the block boxes staged once per workgroup in LDS (small
@@ -415,7 +437,8 @@ __global__ __launch_bounds__(512) void tnn_query_kernel(IndexDesc ix, Prep pr, Q
 // BoxesInLds: the block boxes fit in LDS too (the superblock boxes always
 // do); a template argument so that every box read is a plain LDS or global
 // access rather than a generic one.  PerQ: every query has its own scales.
-template <bool BoxesInLds, bool PerQ>
+// Stats: the call collects statistics (a.stats set).
+template <bool BoxesInLds, bool PerQ, bool Stats>
 __global__ __launch_bounds__(512, TNN_QUERY_MIN_WAVES) void tnn_query_lds_kernel(
     IndexDesc ix, Prep pr, QueryArgs a, const float *qx, const float *qy, const float *qz,
     const float *qt, int64_t nq, int32_t *out_idx, double *out_dist, const double *qscale) {
@@ -444,7 +467,8 @@ __global__ __launch_bounds__(512, TNN_QUERY_MIN_WAVES) void tnn_query_lds_kernel
       if (base >= hi) break;
       const int64_t end = base + TNN_QUERY_CHUNK < hi ? base + TNN_QUERY_CHUNK : hi;
       for (int64_t qi = base; qi < end; ++qi)
-        answer_query<PerQ>(ix, pr, a, qx, qy, qz, qt, qi, out_idx, out_dist, box, s_box, qscale);
+        answer_query<PerQ, Stats>(ix, pr, a, qx, qy, qz, qt, qi, out_idx, out_dist, box, s_box,
+                                  qscale);
     }
   }
 #else
@@ -452,7 +476,7 @@ __global__ __launch_bounds__(512, TNN_QUERY_MIN_WAVES) void tnn_query_lds_kernel
   const int64_t stride = (int64_t)gridDim.x * wpb;
   for (int64_t qi = (int64_t)blockIdx.x * wpb + uniform_i((int)(threadIdx.x >> 6)); qi < nq;
        qi += stride)
-    answer_query<PerQ>(ix, pr, a, qx, qy, qz, qt, qi, out_idx, out_dist, box, s_box, qscale);
+    answer_query<PerQ, Stats>(ix, pr, a, qx, qy, qz, qt, qi, out_idx, out_dist, box, s_box, qscale);
 #endif
 }
 
@@ -495,7 +519,7 @@ __global__ __launch_bounds__(512) void brute_kernel(IndexDesc ix, QueryArgs a, c
     const bool gate = ok && (double)pv.w < q.thr && tk.admits(d, pid);
     const uint64_t gm = ballot(gate);
     if (gm) {
-      tk.offer(gm, gate, d, pid);
+      tk.offer(gm, d, pid);
       ++merges;
     }
   }
@@ -569,6 +593,8 @@ __global__ void batch_prep_kernel(const BatchItemDev *items, const int64_t *seg_
 // single-index search; each query is answered exactly as by tnn_query.
 // Completion is counted once per item run of a chunk; the wave that completes
 // an item stamps its tick.  Every wave leaves once every slice is used up.
+// Stats: some item collects statistics.
+template <bool Stats>
 __global__ __launch_bounds__(512) void batch_kernel(const BatchItemDev *items,
                                                     const int64_t *qprefix, const int32_t *order,
                                                     int n, int chunk,
@@ -595,8 +621,9 @@ __global__ __launch_bounds__(512) void batch_kernel(const BatchItemDev *items,
         const BatchItemDev &it = items[item];
         const int64_t run = item_end - gq;
         for (; gq < item_end; ++gq)
-          answer_query<false>(it.ix, it.pr, it.a, it.qx, it.qy, it.qz, it.qt, gq - qprefix[pos],
-                       it.out_idx, it.out_dist, it.ix.box, it.ix.sbox, nullptr);
+          answer_query<false, Stats>(it.ix, it.pr, it.a, it.qx, it.qy, it.qz, it.qt,
+                                     gq - qprefix[pos], it.out_idx, it.out_dist, it.ix.box,
+                                     it.ix.sbox, nullptr);
         if (lane == 0) {
           const unsigned d = atomicAdd(&done[item], (unsigned)run) + (unsigned)run;
           if ((int64_t)d == it.nq) ticks[item + 1] = wall_clock64();
@@ -618,7 +645,7 @@ hipError_t launch_batch(const BatchLaunch &bl, hipStream_t st) {
     if (e != hipSuccess) return e;
   }
   if (bl.total_q > 0) {
-    hipLaunchKernelGGL(batch_kernel, dim3((unsigned)bl.grid), dim3(bl.waves_per_block * kWave), 0,
+    hipLaunchKernelGGL(bl.stats ? batch_kernel<true> : batch_kernel<false>, dim3((unsigned)bl.grid), dim3(bl.waves_per_block * kWave), 0,
                        st, bl.items, bl.qprefix, bl.order, bl.n, bl.chunk, bl.counter, bl.done,
                        bl.ticks);
     e = hipGetLastError();
@@ -688,9 +715,14 @@ hipError_t launch_query(const IndexDesc &ix, const Prep &pr, const QueryArgs &a,
     const int in_lds = sl + bl <= kLdsBoxBytes ? 1 : 0;
     const size_t lds = in_lds ? sl + bl : sl;
     const bool perq = query_scale != nullptr;
-    const auto kern = perq ? (in_lds ? tnn_query_lds_kernel<true, true> : tnn_query_lds_kernel<false, true>)
-                           : (in_lds ? tnn_query_lds_kernel<true, false> : tnn_query_lds_kernel<false, false>);
-    const int variant = in_lds + (perq ? 2 : 0);
+    using Kern = decltype(&tnn_query_lds_kernel<true, true, true>);
+    static const Kern kerns[8] = {
+        tnn_query_lds_kernel<false, false, false>, tnn_query_lds_kernel<true, false, false>,
+        tnn_query_lds_kernel<false, true, false>,  tnn_query_lds_kernel<true, true, false>,
+        tnn_query_lds_kernel<false, false, true>,  tnn_query_lds_kernel<true, false, true>,
+        tnn_query_lds_kernel<false, true, true>,   tnn_query_lds_kernel<true, true, true>};
+    const int variant = in_lds + (perq ? 2 : 0) + (a.stats ? 4 : 0);
+    const Kern kern = kerns[variant];
     const int per_cu = resident_per_cu(variant, waves_per_block, lds, [&](int *n) {
       return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, kern, waves_per_block * kWave, lds);
     });
@@ -700,7 +732,8 @@ hipError_t launch_query(const IndexDesc &ix, const Prep &pr, const QueryArgs &a,
                        qs.x, qs.y, qs.z, qs.t, qs.n, out_idx, out_dist, query_scale);
     return hipGetLastError();
   }
-  const auto kern = query_scale ? tnn_query_kernel<true> : tnn_query_kernel<false>;
+  const auto kern = query_scale ? (a.stats ? tnn_query_kernel<true, true> : tnn_query_kernel<true, false>)
+                                : (a.stats ? tnn_query_kernel<false, true> : tnn_query_kernel<false, false>);
   hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(waves_per_block * kWave), 0, st, ix, pr, a,
                      qs.x, qs.y, qs.z, qs.t, qs.n, out_idx, out_dist, query_scale);
   return hipGetLastError();

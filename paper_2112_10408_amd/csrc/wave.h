@@ -16,6 +16,12 @@ __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63u); }
 
 __device__ __forceinline__ uint64_t ballot(bool p) { return (uint64_t)__ballot(p); }
 
+// This lane's bit of a wave-uniform lane mask (the mask itself serves as the
+// per-lane condition: no shift or compare).
+__device__ __forceinline__ bool lane_in(uint64_t mask) {
+  return __builtin_amdgcn_inverse_ballot_w64(mask);
+}
+
 __device__ __forceinline__ int uniform_i(int v) { return __builtin_amdgcn_readfirstlane(v); }
 __device__ __forceinline__ unsigned long long uniform_u64(unsigned long long v) {
   const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(v >> 32));
@@ -328,9 +334,9 @@ struct TopK {
     }
   }
 
-  // Offer one key per lane; lanes with gate=false offer nothing.  `gm` is the
-  // ballot of gate.  Returns nothing; updates the threshold.
-  __device__ __forceinline__ void offer(uint64_t gm, bool gate, double nd, int nid) {
+  // Offer one key per lane; lanes outside the lane mask `gm` offer nothing.
+  // Returns nothing; updates the threshold.
+  __device__ __forceinline__ void offer(uint64_t gm, double nd, int nid) {
     nd += 0.0;  // -0.0 becomes +0.0, which the word order of the merge needs
     const int n = __popcll(gm);
     if (n <= kInsertMax) {
@@ -340,7 +346,8 @@ struct TopK {
         insert_one(readlane_d(nd, l), readlane_i(nid, l));
       }
     } else {
-      Key3 c = key3(gate ? nd : inf_, gate ? nid : kNoId);
+      const bool in = lane_in(gm);
+      Key3 c = key3(in ? nd : inf_, in ? nid : kNoId);
       if (!(readlane_d(d, 0) < inf_)) {  // empty top-k: the sorted batch is the result
         sort64<false>(c);
       } else {
