@@ -132,8 +132,14 @@ struct Searcher {
     while (cm) {
       int my_l = -1;
       for (int i = 0; i < spi && cm; ++i) {
-        float kmin;
-        const int l = wave_argmin_lane(lane_in(cm) ? key_l : __builtin_huge_valf(), kmin);
+        int l;
+        if (__popcll(cm) <= spi - i) {
+          // every remaining segment gets a slot in this pass: order is moot
+          l = __ffsll((long long)cm) - 1;
+        } else {
+          float kmin;
+          l = wave_argmin_lane(lane_in(cm) ? key_l : __builtin_huge_valf(), kmin);
+        }
         cm &= ~(1ull << l);
         if (slot == i) my_l = l;
       }
@@ -189,7 +195,7 @@ struct Searcher {
       // early; once the next bound exceeds min(tau, k-th) so do all later ones
       while (ms) {
         float smin;
-        const int sl = wave_argmin_lane(lane_in(ms) ? lbs : finf, smin);
+        const int sl = pick_min(ms, lbs, smin);
         ms &= ~(1ull << sl);
         if ((double)smin > fmin(tau, tk.kd)) break;
         // block level: the superblock's 64 blocks, one per lane
@@ -201,7 +207,7 @@ struct Searcher {
         uint64_t m = ballot(lbb < finf && (double)lbb <= fmin(tau, tk.kd));
         while (m) {
           float bmin;
-          const int bl = wave_argmin_lane(lane_in(m) ? lbb : finf, bmin);
+          const int bl = pick_min(m, lbb, bmin);
           m &= ~(1ull << bl);
           const double tau_cur = fmin(tau, tk.kd);
           const double lbb_b = (double)bmin;

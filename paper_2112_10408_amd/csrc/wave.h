@@ -134,6 +134,18 @@ __device__ __forceinline__ int wave_argmin_lane(float v, float &vmin) {
   return __ffsll((long long)ballot(v == vmin)) - 1;
 }
 
+// The lane holding the smallest of the non-negative floats `v` of the lanes
+// set in `mask` (wave-uniform, non-zero; the lowest such lane on ties) and
+// that value.  A single candidate needs no reduction.
+__device__ __forceinline__ int pick_min(uint64_t mask, float v, float &vmin) {
+  if ((mask & (mask - 1)) == 0) {
+    const int l = __ffsll((long long)mask) - 1;
+    vmin = readlane_f(v, l);
+    return l;
+  }
+  return wave_argmin_lane(lane_in(mask) ? v : __builtin_huge_valf(), vmin);
+}
+
 // Value of lane ^ J for J = 1, 2, 4, 8 (DPP quad permutes and row rotation;
 // an LDS swizzle for 4).
 template <int J>
