@@ -38,8 +38,8 @@ FLOPS_POINT = 15           # binary64 exact distance
 # only; after any change to them the figure is reported as null.
 KERNEL_SOURCES = ("query.hip", "bounds.h", "wave.h", "tnn_internal.h")
 MEASURED_TRAFFIC = {
-    "sha256": "4eb1633acc89c28e46cfe588988fe564bcf353797211bc221ad0ce068f1d3b88",
-    "bytes_per_launch": 266.9e6,
+    "sha256": "d0e06f76bbd06af53597e0e21f5228eb495336ce5cd3ec9fc0eeb5206e75bf86",
+    "bytes_per_launch": 266.8e6,
 }
 
 
