@@ -38,7 +38,7 @@ FLOPS_POINT = 15           # binary64 exact distance
 # only; after any change to them the figure is reported as null.
 KERNEL_SOURCES = ("query.hip", "bounds.h", "wave.h", "tnn_internal.h")
 MEASURED_TRAFFIC = {
-    "sha256": "d0e06f76bbd06af53597e0e21f5228eb495336ce5cd3ec9fc0eeb5206e75bf86",
+    "sha256": "13b48dca2ef7f8a3d78218b45b4485c1c612e2620f7c9bafb72bcb002c9ae936",
     "bytes_per_launch": 266.8e6,
 }
 

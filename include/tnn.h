@@ -160,8 +160,9 @@ tnn_status tnn_query_workspace(const tnn_index *index, int64_t n_queries,
  * k-NN of every query (Algorithms 1 and 2).  For query q, writes
  * d_out_idx[q*k + r] (int32, caller's point index) and d_out_dist[q*k + r]
  * (binary64 scaled squared distance), r = 0..k-1 ascending by (distance,
- * index); empty slots are (-1, +inf).  Queries are device SoA float32 and need
- * not be data points.  Asynchronous on `stream`.
+ * index); empty slots are (-1, +inf).  A zero distance is reported as +0.0
+ * (scales of -0.0 would otherwise give -0.0, which equals it).  Queries are
+ * device SoA float32 and need not be data points.  Asynchronous on `stream`.
  */
 tnn_status tnn_query(const tnn_index *index, tnn_points queries, const tnn_query_params *params,
                      int32_t *d_out_idx, double *d_out_dist, void *d_scratch,

@@ -9,10 +9,6 @@ namespace tnn {
 
 constexpr size_t kLdsBoxBytes = 48 * 1024;  // stage block boxes in LDS up to this size
 
-// Minimum resident waves per SIMD the search kernels are compiled for.
-#ifndef TNN_QUERY_MIN_WAVES
-#define TNN_QUERY_MIN_WAVES 1
-#endif
 #ifndef TNN_QUERY_QUEUES
 #define TNN_QUERY_QUEUES 8
 #endif
@@ -443,9 +439,12 @@ __global__ __launch_bounds__(512) void tnn_query_kernel(IndexDesc ix, Prep pr, Q
 // BoxesInLds: the block boxes fit in LDS too (the superblock boxes always
 // do); a template argument so that every box read is a plain LDS or global
 // access rather than a generic one.  PerQ: every query has its own scales.
-// Stats: the call collects statistics (a.stats set).
+// Stats: the call collects statistics (a.stats set).  The per-query-scale
+// instances are compiled for 5 waves per SIMD (96 VGPRs; 113 and 4 waves
+// otherwise); the shared-scale ones fit 6 as they are (75 VGPRs).
 template <bool BoxesInLds, bool PerQ, bool Stats>
-__global__ __launch_bounds__(512, TNN_QUERY_MIN_WAVES) void tnn_query_lds_kernel(
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(PerQ ? 5 : 1))) void
+tnn_query_lds_kernel(
     IndexDesc ix, Prep pr, QueryArgs a, const float *qx, const float *qy, const float *qz,
     const float *qt, int64_t nq, int32_t *out_idx, double *out_dist, const double *qscale) {
   extern __shared__ float4 s_box4[];

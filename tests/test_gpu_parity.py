@@ -47,6 +47,44 @@ def test_golden_cases(case, flags):
     assert np.array_equal(gd, want)
 
 
+def _tie_points():
+    """3 trajectories of 100 points around (100, 100, 10) at offsets whose
+    scaled squared distance is exact in binary64: 0, 1 or 25 under unit
+    spatial scales, so most keys tie on the distance and the index decides."""
+    offs = [(0, 0), (1, 0), (0, 1), (3, 4), (4, 3), (-3, 4), (-4, -3), (5, 0), (0, -5), (-1, 0)]
+    n_traj, per = 3, 100
+    x, y = [], []
+    for j in range(n_traj * per):
+        dx, dy = offs[(7 * j + j // per) % len(offs)]
+        x.append(100.0 + dx)
+        y.append(100.0 + dy)
+    t = np.tile(np.arange(per, dtype=np.float32) * 4.0, n_traj)
+    return synth.PointSet(np.array(x, np.float32), np.array(y, np.float32),
+                          np.full(n_traj * per, 10.0, np.float32), t,
+                          offsets=np.arange(0, n_traj * per + 1, per, dtype=np.int64))
+
+
+@pytest.mark.parametrize("flags", ALL_PATHS)
+@pytest.mark.parametrize("scale", [(1.0, 1.0, 1.0, 0.0), (0.0, 0.0, 0.0, 0.0), (-0.0, -0.0, -0.0, -0.0)],
+                         ids=["unit", "zero", "negzero"])
+def test_exact_ties_and_signed_zero_distances(flags, scale):
+    """Keys that tie on the distance are ordered by index, through the one-by-one
+    insertion (few newcomers) and the sorting network (many), k up to 64; with
+    all scales -0.0 every distance is a signed zero, which the result reports
+    as +0.0 (equal to the oracle's -0.0)."""
+    say("ties", flags, scale)
+    ps = _tie_points()
+    ix = build(ps, seg_len=8)
+    qt = np.array([1000.0, 200.0, 41.0, 4.5, 0.0], np.float32)
+    qs = synth.PointSet(np.full(5, 100.0, np.float32), np.full(5, 100.0, np.float32),
+                        np.full(5, 10.0, np.float32), qt, offsets=np.array([0, 5], dtype=np.int64))
+    for k in (5, 32, 64):
+        gi, gd = gpu_query(ix, qs, scale, 0.0, k, flags=flags)
+        oi, od = oracle.knn(ps.soa(), qs.soa(), scale, 0.0, k)
+        assert_same(gi, gd, oi, od, f"ties k={k}")
+        assert not np.signbit(gd[np.isfinite(gd)]).any()
+
+
 @pytest.mark.parametrize("flags", ALL_PATHS)
 def test_c1_all_queries(flags):
     """10k points (200 x 50), K=16, every point a query, k=8."""
