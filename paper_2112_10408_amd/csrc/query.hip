@@ -8,6 +8,10 @@
 namespace tnn {
 
 constexpr size_t kLdsBoxBytes = 48 * 1024;  // stage block boxes in LDS up to this size
+#ifndef TNN_BRUTE_Q
+#define TNN_BRUTE_Q 4
+#endif
+constexpr int kBruteQ = TNN_BRUTE_Q;  // queries per wave of the linear search
 
 #ifndef TNN_QUERY_QUEUES
 #define TNN_QUERY_QUEUES 8
@@ -487,28 +491,40 @@ tnn_query_lds_kernel(
 
 // ---------------------------------------------------------------------------
 // Linear search (the paper's baseline, Sec. 3.6): every point, binary64
-// distances, same top-k.  One wavefront per query.
+// distances, same top-k.  One wavefront answers Q consecutive queries, so
+// each 64-point pass loads and converts its points once for all of them
+// (Q = 1 with per-query scales).
 // ---------------------------------------------------------------------------
+template <int Q>
 __global__ __launch_bounds__(512) void brute_kernel(IndexDesc ix, QueryArgs a, const float *qxp,
                                                     const float *qyp, const float *qzp,
                                                     const float *qtp, int64_t nq,
                                                     int32_t *out_idx, double *out_dist,
                                                     const double *qscale) {
-  const int64_t qi = (int64_t)blockIdx.x * (blockDim.x >> 6) + uniform_i((int)(threadIdx.x >> 6));
-  if (qi >= nq) return;
+  const int64_t q0 =
+      ((int64_t)blockIdx.x * (blockDim.x >> 6) + uniform_i((int)(threadIdx.x >> 6))) * Q;
+  if (q0 >= nq) return;
   const int lane = lane_id();
   double s[4] = {a.s[0], a.s[1], a.s[2], a.s[3]};
-  if (qscale) {
-    QueryArgs aq = a;
-    if (!load_query_scales(qscale, qi, aq, nullptr)) {
-      write_bad_scale_row(a, qi, out_idx, out_dist);
-      return;
+  if constexpr (Q == 1) {
+    if (qscale) {
+      QueryArgs aq = a;
+      if (!load_query_scales(qscale, q0, aq, nullptr)) {
+        write_bad_scale_row(a, q0, out_idx, out_dist);
+        return;
+      }
+      for (int f = 0; f < 4; ++f) s[f] = aq.s[f];
     }
-    for (int f = 0; f < 4; ++f) s[f] = aq.s[f];
   }
-  const QueryPoint q = make_query(qxp[qi], qyp[qi], qzp[qi], qtp[qi], a.t_window);
-  TopK tk;
-  tk.init(a.k, a.inf);
+  // queries past the end repeat the last one and are not written
+  QueryPoint q[Q];
+  TopK tk[Q];
+#pragma unroll
+  for (int j = 0; j < Q; ++j) {
+    const int64_t qi = q0 + j < nq ? q0 + j : nq - 1;
+    q[j] = make_query(qxp[qi], qyp[qi], qzp[qi], qtp[qi], a.t_window);
+    tk[j].init(a.k, a.inf);
+  }
   uint32_t merges = 0;
   const int64_t n = ix.n_points;
   for (int64_t p0 = 0; p0 < n; p0 += kWave) {
@@ -520,21 +536,30 @@ __global__ __launch_bounds__(512) void brute_kernel(IndexDesc ix, QueryArgs a, c
       pv = ix.pt4[p];
       pid = ix.pid[p];
     }
-    const double d = exact_dist(s, q.x, q.y, q.z, q.t, pv.x, pv.y, pv.z, pv.w);
-    const bool gate = ok && (double)pv.w < q.thr && tk.admits(d, pid);
-    const uint64_t gm = ballot(gate);
-    if (gm) {
-      tk.offer(gm, d, pid);
-      ++merges;
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+      const double d = exact_dist(s, q[j].x, q[j].y, q[j].z, q[j].t, pv.x, pv.y, pv.z, pv.w);
+      // bitwise, not short-circuit: no divergent branch in the inner loop
+      const bool gate = ok & ((double)pv.w < q[j].thr) & tk[j].admits(d, pid);
+      const uint64_t gm = ballot(gate);
+      if (gm) {
+        tk[j].offer(gm, d, pid);
+        ++merges;
+      }
     }
   }
-  if (lane < a.k) {
-    out_idx[qi * a.k + lane] = tk.id == kNoId ? -1 : tk.id;
-    out_dist[qi * a.k + lane] = tk.d;
+#pragma unroll
+  for (int j = 0; j < Q; ++j) {
+    const int64_t qi = q0 + j;
+    if (qi < nq && lane < a.k) {
+      out_idx[qi * a.k + lane] = tk[j].id == kNoId ? -1 : tk[j].id;
+      out_dist[qi * a.k + lane] = tk[j].d;
+    }
   }
   if (a.stats && lane == 0) {
-    atomicAdd(a.stats + TNN_STAT_QUERIES, 1ull);
-    atomicAdd(a.stats + TNN_STAT_POINTS, (unsigned long long)n);
+    const int nmine = (int)(nq - q0 < Q ? nq - q0 : Q);
+    atomicAdd(a.stats + TNN_STAT_QUERIES, (unsigned long long)nmine);
+    atomicAdd(a.stats + TNN_STAT_POINTS, (unsigned long long)n * nmine);
     atomicAdd(a.stats + TNN_STAT_MERGES, (unsigned long long)merges);
   }
 }
@@ -749,9 +774,14 @@ hipError_t launch_brute(const IndexDesc &ix, const QueryArgs &a, const tnn_point
                         int waves_per_block, int32_t *out_idx, double *out_dist, hipStream_t st,
                         const double *query_scale) {
   if (qs.n == 0) return hipSuccess;
-  const int64_t grid = (qs.n + waves_per_block - 1) / waves_per_block;
-  hipLaunchKernelGGL(brute_kernel, dim3((unsigned)grid), dim3(waves_per_block * kWave), 0, st, ix,
-                     a, qs.x, qs.y, qs.z, qs.t, qs.n, out_idx, out_dist, query_scale);
+  // queries per wave: one with per-query scales (each query's scales would
+  // take scalar registers), else kBruteQ sharing every point pass
+  const int qpw = query_scale ? 1 : kBruteQ;
+  const int64_t waves = (qs.n + qpw - 1) / qpw;
+  const int64_t grid = (waves + waves_per_block - 1) / waves_per_block;
+  hipLaunchKernelGGL(query_scale ? brute_kernel<1> : brute_kernel<kBruteQ>, dim3((unsigned)grid),
+                     dim3(waves_per_block * kWave), 0, st, ix, a, qs.x, qs.y, qs.z, qs.t, qs.n,
+                     out_idx, out_dist, query_scale);
   return hipGetLastError();
 }
 
