@@ -38,7 +38,7 @@ FLOPS_POINT = 15           # binary64 exact distance
 # only; after any change to them the figure is reported as null.
 KERNEL_SOURCES = ("query.hip", "bounds.h", "wave.h", "tnn_internal.h")
 MEASURED_TRAFFIC = {
-    "sha256": "13b48dca2ef7f8a3d78218b45b4485c1c612e2620f7c9bafb72bcb002c9ae936",
+    "sha256": "74a301e2f885917b2c6cd1e24d99dcee02d6d3547e36493e23d6c47085629d7c",
     "bytes_per_launch": 266.8e6,
 }
 
