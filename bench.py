@@ -38,7 +38,7 @@ FLOPS_POINT = 15           # binary64 exact distance
 # only; after any change to them the figure is reported as null.
 KERNEL_SOURCES = ("query.hip", "bounds.h", "wave.h", "tnn_internal.h")
 MEASURED_TRAFFIC = {
-    "sha256": "74a301e2f885917b2c6cd1e24d99dcee02d6d3547e36493e23d6c47085629d7c",
+    "sha256": "6a905ed70ba7786ad47f3b5ede364a426cb1f5213b62cdd9e73d58794c8a359d",
     "bytes_per_launch": 266.8e6,
 }
 

@@ -774,12 +774,14 @@ hipError_t launch_brute(const IndexDesc &ix, const QueryArgs &a, const tnn_point
                         int waves_per_block, int32_t *out_idx, double *out_dist, hipStream_t st,
                         const double *query_scale) {
   if (qs.n == 0) return hipSuccess;
-  // queries per wave: one with per-query scales (each query's scales would
-  // take scalar registers), else kBruteQ sharing every point pass
-  const int qpw = query_scale ? 1 : kBruteQ;
+  // queries per wave: kBruteQ sharing every point pass when that still gives
+  // about 8 waves per SIMD, else one; one with per-query scales (each query's
+  // scales would take scalar registers)
+  const bool tiled = !query_scale && qs.n >= (int64_t)32 * cu_count() * kBruteQ;
+  const int qpw = tiled ? kBruteQ : 1;
   const int64_t waves = (qs.n + qpw - 1) / qpw;
   const int64_t grid = (waves + waves_per_block - 1) / waves_per_block;
-  hipLaunchKernelGGL(query_scale ? brute_kernel<1> : brute_kernel<kBruteQ>, dim3((unsigned)grid),
+  hipLaunchKernelGGL(tiled ? brute_kernel<kBruteQ> : brute_kernel<1>, dim3((unsigned)grid),
                      dim3(waves_per_block * kWave), 0, st, ix, a, qs.x, qs.y, qs.z, qs.t, qs.n,
                      out_idx, out_dist, query_scale);
   return hipGetLastError();

@@ -85,6 +85,24 @@ def test_exact_ties_and_signed_zero_distances(flags, scale):
         assert not np.signbit(gd[np.isfinite(gd)]).any()
 
 
+def test_linear_search_query_tiles_and_tail():
+    """Enough queries that the binary64 linear search answers several per
+    wave (from 32 x CUs x queries-per-wave on), and a count that leaves a
+    partial last tile: every row against the oracle."""
+    ps, qs0, _, cfg = config_data("c1")
+    say("linear search tiles")
+    n = 40003
+    reps = -(-n // qs0.x.shape[0])
+    cols = []
+    for a, step in ((qs0.x, 0.37), (qs0.y, -0.21), (qs0.z, 0.0), (qs0.t, 11.0)):
+        cols.append(np.concatenate([a + np.float32(step * r) for r in range(reps)])[:n].astype(np.float32))
+    qs = synth.PointSet(*cols, offsets=np.array([0, n], dtype=np.int64))
+    ix = build(ps, cfg["seg_len"])
+    gi, gd = gpu_query(ix, qs, SCALE, 0.0, cfg["k"], flags=capi.TNN_BRUTE)
+    oi, od = oracle.knn(ps.soa(), qs.soa(), SCALE, 0.0, cfg["k"])
+    assert_same(gi, gd, oi, od, "linear search tiles")
+
+
 @pytest.mark.parametrize("flags", ALL_PATHS)
 def test_c1_all_queries(flags):
     """10k points (200 x 50), K=16, every point a query, k=8."""
