@@ -164,7 +164,20 @@ __global__ __launch_bounds__(64 * kInferWaves) void infer_kernel(
   static_assert(NI == 6, "the first layer's LDS layout holds six weights and a bias per unit");
   __shared__ float part[kInferWaves][kInferTile][kInferTile + 1];
   const float *__restrict__ W = m->params;
-  for (int i = threadIdx.x; i < H * H; i += blockDim.x) w2s[i / H][i % H] = W[OW2 + i];
+  {
+    // all of a thread's loads in flight before its first LDS write (a rolled
+    // loop waits out one global-load latency per element)
+    constexpr int kThreads = 64 * kInferWaves, kPer = H * H / kThreads;
+    static_assert(H * H % kThreads == 0, "hidden weights split evenly over the threads");
+    float wv[kPer];
+#pragma unroll
+    for (int r = 0; r < kPer; ++r) wv[r] = W[OW2 + threadIdx.x + r * kThreads];
+#pragma unroll
+    for (int r = 0; r < kPer; ++r) {
+      const int i = threadIdx.x + r * kThreads;
+      w2s[i / H][i % H] = wv[r];
+    }
+  }
   for (int k = threadIdx.x; k < H; k += blockDim.x) {
     w1s[k][0] = make_float4(W[OW1 + k * NI], W[OW1 + k * NI + 1], W[OW1 + k * NI + 2],
                             W[OW1 + k * NI + 3]);
