@@ -70,6 +70,27 @@ __global__ void prep_kernel(IndexDesc ix, QueryArgs a, float4 *rec, unsigned lon
   prep_one(ix, a, rec, s, raw);
 }
 
+// Copy n float4 from global memory to LDS with this workgroup's threads, four
+// loads of a thread in flight before its first store (a rolled loop would wait
+// out one global-load latency per element).  The loads are unconditional (an
+// index past the end reads the last element; n >= 1 inside the loop) so that
+// no branch makes the compiler wait for each one.
+__device__ __forceinline__ void stage_to_lds(float4 *dst, const float4 *src, int n) {
+  const int bs = (int)blockDim.x;
+  for (int i0 = threadIdx.x; i0 < n; i0 += 4 * bs) {
+    const int i1 = i0 + bs, i2 = i0 + 2 * bs, i3 = i0 + 3 * bs;
+    const float4 a0 = src[i0];
+    const float4 a1 = src[i1 < n ? i1 : n - 1];
+    const float4 a2 = src[i2 < n ? i2 : n - 1];
+    const float4 a3 = src[i3 < n ? i3 : n - 1];
+    __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the stores
+    dst[i0] = a0;
+    if (i1 < n) dst[i1] = a1;
+    if (i2 < n) dst[i2] = a2;
+    if (i3 < n) dst[i3] = a3;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // One wavefront answers one query.
 // ---------------------------------------------------------------------------
@@ -456,9 +477,9 @@ tnn_query_lds_kernel(
   const int nsbox = 2 * ix.n_super;
   const float4 *g_sbox = reinterpret_cast<const float4 *>(ix.sbox);
   const float4 *g_box = reinterpret_cast<const float4 *>(ix.box);
-  for (int i = threadIdx.x; i < nsbox; i += blockDim.x) s_box4[i] = g_sbox[i];
+  stage_to_lds(s_box4, g_sbox, nsbox);
   const int nbox = BoxesInLds ? 2 * ix.n_blocks : 0;
-  for (int i = threadIdx.x; i < nbox; i += blockDim.x) s_box4[nsbox + i] = g_box[i];
+  stage_to_lds(s_box4 + nsbox, g_box, nbox);
   __syncthreads();
   const float *s_box = reinterpret_cast<const float *>(s_box4);
   const float *box = BoxesInLds ? reinterpret_cast<const float *>(s_box4 + nsbox) : ix.box;
