@@ -38,8 +38,8 @@ FLOPS_POINT = 15           # binary64 exact distance
 # only; after any change to them the figure is reported as null.
 KERNEL_SOURCES = ("query.hip", "bounds.h", "wave.h", "tnn_internal.h")
 MEASURED_TRAFFIC = {
-    "sha256": "6a905ed70ba7786ad47f3b5ede364a426cb1f5213b62cdd9e73d58794c8a359d",
-    "bytes_per_launch": 266.8e6,
+    "sha256": "db4becd434624ef7508866e41461ebc990b04c7d958498f60539c194f30af864",
+    "bytes_per_launch": 266.7e6,
 }
 
 
