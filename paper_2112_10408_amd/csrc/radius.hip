@@ -164,6 +164,24 @@ __global__ __launch_bounds__(64 * kInferWaves) void infer_kernel(
   static_assert(NI == 6, "the first layer's LDS layout holds six weights and a bias per unit");
   __shared__ float part[kInferWaves][kInferTile][kInferTile + 1];
   const float *__restrict__ W = m->params;
+  const int wv = threadIdx.x >> 6;
+  const int l = threadIdx.x & 63;
+  const int col = l & 31;   // unit within an output block / query within the tile
+  const int half = l >> 5;  // which of the two inputs of a K-step
+  const int64_t n_tiles = (q.n + kInferTile - 1) / kInferTile;
+  const int64_t tile0 = (int64_t)blockIdx.x * kInferWaves + wv;
+  // the first tile's query point is requested before the weights are staged,
+  // so the two latencies overlap
+  float px = 0.0f, py = 0.0f, pz = 0.0f, pt = 0.0f;
+  {
+    const int64_t qi = tile0 * kInferTile + col;
+    if (tile0 < n_tiles && qi < q.n) {
+      px = q.x[qi];
+      py = q.y[qi];
+      pz = q.z[qi];
+      pt = q.t[qi];
+    }
+  }
   {
     // all of a thread's loads in flight before its first LDS write (a rolled
     // loop waits out one global-load latency per element)
@@ -184,10 +202,6 @@ __global__ __launch_bounds__(64 * kInferWaves) void infer_kernel(
     w1s[k][1] = make_float4(W[OW1 + k * NI + 4], W[OW1 + k * NI + 5], W[OB1 + k], 0.0f);
   }
   __syncthreads();
-  const int wv = threadIdx.x >> 6;
-  const int l = threadIdx.x & 63;
-  const int col = l & 31;   // unit within an output block / query within the tile
-  const int half = l >> 5;  // which of the two inputs of a K-step
   // B operands for all 32 K-steps of both blocks: W2[unit][input]
   float wb0[H / 2], wb1[H / 2];
 #pragma unroll
@@ -199,13 +213,17 @@ __global__ __launch_bounds__(64 * kInferWaves) void infer_kernel(
   const float w3_0 = W[OW3 + col], w3_1 = W[OW3 + 32 + col];
   const float b3 = W[OB3];
   float(*pw)[kInferTile + 1] = part[wv];
-  const int64_t n_tiles = (q.n + kInferTile - 1) / kInferTile;
-  for (int64_t tile = (int64_t)blockIdx.x * kInferWaves + wv; tile < n_tiles;
-       tile += (int64_t)gridDim.x * kInferWaves) {
+  for (int64_t tile = tile0; tile < n_tiles; tile += (int64_t)gridDim.x * kInferWaves) {
     const int64_t qi = tile * kInferTile + col;
     const bool ok = qi < q.n;
+    if (tile != tile0 && ok) {
+      px = q.x[qi];
+      py = q.y[qi];
+      pz = q.z[qi];
+      pt = q.t[qi];
+    }
     float f[NI] = {};
-    if (ok) features(m, q.x[qi], q.y[qi], q.z[qi], q.t[qi], f);
+    if (ok) features(m, px, py, pz, pt, f);
     // first layer, the inputs this lane feeds to the matrix cores
     float h1[H / 2];
 #pragma unroll
