@@ -38,8 +38,8 @@ FLOPS_POINT = 15           # binary64 exact distance
 # only; after any change to them the figure is reported as null.
 KERNEL_SOURCES = ("query.hip", "bounds.h", "wave.h", "tnn_internal.h")
 MEASURED_TRAFFIC = {
-    "sha256": "db4becd434624ef7508866e41461ebc990b04c7d958498f60539c194f30af864",
-    "bytes_per_launch": 266.7e6,
+    "sha256": "187ea28ab059e4975ec3c3bcbbdfd29b536e5f42f99db67aa15079e019cf35ae",
+    "bytes_per_launch": 273.2e6,
 }
 
 
