@@ -18,7 +18,8 @@ constexpr int kBruteQ = TNN_BRUTE_Q;  // queries per wave of the linear search
 #endif
 // Queries a wave takes from a work queue at a time (0: fixed grid stride).
 // The atomics on a counter serialise: with 8 counters, tickets of 2 queries
-// cost 8 % of the 1M-point learned search against tickets of 8.
+// cost 8 % of the 1M-point learned search against tickets of 8.  (The largest
+// ticket; small query counts take smaller ones.)
 #ifndef TNN_QUERY_CHUNK
 #define TNN_QUERY_CHUNK 8
 #endif
@@ -488,6 +489,12 @@ tnn_query_lds_kernel(
   const float *box = BoxesInLds ? reinterpret_cast<const float *>(s_box4 + nsbox) : ix.box;
 #if TNN_QUERY_CHUNK > 0
   const int lane = lane_id();
+  // Ticket size: TNN_QUERY_CHUNK queries, fewer when that would leave less
+  // than two tickets per resident wave (a small query count would otherwise
+  // gather on a few waves).
+  const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
+  const int64_t fit = nq / (2 * waves);
+  const int step = (int)(fit < 1 ? 1 : fit > TNN_QUERY_CHUNK ? TNN_QUERY_CHUNK : fit);
   const int first = (int)(blockIdx.x % kQueues);
   for (int j = 0; j < kQueues; ++j) {
     const int qn = (first + j) % kQueues;
@@ -495,10 +502,10 @@ tnn_query_lds_kernel(
     unsigned long long *ctr = pr.ticket + qn * kTicketStride;
     for (;;) {
       unsigned long long b = 0;
-      if (lane == 0) b = atomicAdd(ctr, (unsigned long long)TNN_QUERY_CHUNK);
+      if (lane == 0) b = atomicAdd(ctr, (unsigned long long)step);
       const int64_t base = lo + (int64_t)uniform_u64(b);
       if (base >= hi) break;
-      const int64_t end = base + TNN_QUERY_CHUNK < hi ? base + TNN_QUERY_CHUNK : hi;
+      const int64_t end = base + step < hi ? base + step : hi;
       for (int64_t qi = base; qi < end; ++qi)
         answer_query<PerQ, Stats>(ix, pr, a, qx, qy, qz, qt, qi, out_idx, out_dist, box, s_box,
                                   qscale);
