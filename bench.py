@@ -38,8 +38,8 @@ FLOPS_POINT = 15           # binary64 exact distance
 # only; after any change to them the figure is reported as null.
 KERNEL_SOURCES = ("query.hip", "bounds.h", "wave.h", "tnn_internal.h")
 MEASURED_TRAFFIC = {
-    "sha256": "187ea28ab059e4975ec3c3bcbbdfd29b536e5f42f99db67aa15079e019cf35ae",
-    "bytes_per_launch": 273.2e6,
+    "sha256": "6fb4088af957749d6a8d088245360ec0d94a5415e5dbeb9d1b0df77fb3a02c8d",
+    "bytes_per_launch": 272.8e6,
 }
 
 
