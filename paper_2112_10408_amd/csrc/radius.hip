@@ -150,7 +150,7 @@ __global__ void features_kernel(const tnn_radius_model *m, tnn_points q, float *
 //   B (2 x 32): lane l holds B[l / 32][l % 32]   (input 2s + l / 32, unit l % 32)
 //   D (32 x 32): element e of lane l is D[(e / 4) 8 + (l / 32) 4 + e % 4][l % 32]
 // Two output blocks cover units 0..31 and 32..63; 32 K-steps of 2 cover the
-// 64 inputs.  The first layer (5 -> 64) and the output layer run on the
+// 64 inputs.  The first layer (6 -> 64) and the output layer run on the
 // vector units; the output layer's sum over units goes through LDS.
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 constexpr int kInferTile = 32;
@@ -202,13 +202,6 @@ __global__ __launch_bounds__(64 * kInferWaves) void infer_kernel(
     w1s[k][1] = make_float4(W[OW1 + k * NI + 4], W[OW1 + k * NI + 5], W[OB1 + k], 0.0f);
   }
   __syncthreads();
-  // B operands for all 32 K-steps of both blocks: W2[unit][input]
-  float wb0[H / 2], wb1[H / 2];
-#pragma unroll
-  for (int st = 0; st < H / 2; ++st) {
-    wb0[st] = w2s[col][2 * st + half];
-    wb1[st] = w2s[32 + col][2 * st + half];
-  }
   const float b2_0 = W[OB2 + col], b2_1 = W[OB2 + 32 + col];
   const float w3_0 = W[OW3 + col], w3_1 = W[OW3 + 32 + col];
   const float b3 = W[OB3];
@@ -224,25 +217,24 @@ __global__ __launch_bounds__(64 * kInferWaves) void infer_kernel(
     }
     float f[NI] = {};
     if (ok) features(m, px, py, pz, pt, f);
-    // first layer, the inputs this lane feeds to the matrix cores
-    float h1[H / 2];
-#pragma unroll
-    for (int st = 0; st < H / 2; ++st) {
-      const float4 wa = w1s[2 * st + half][0], wb = w1s[2 * st + half][1];
-      const float a =
-          wb.z + wa.x * f[0] + wa.y * f[1] + wa.z * f[2] + wa.w * f[3] + wb.x * f[4] + wb.y * f[5];
-      h1[st] = fmaxf(a, 0.0f);
-    }
     f32x16 c0, c1;
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
       c0[e] = b2_0;
       c1[e] = b2_1;
     }
+    // per K-step: the first-layer unit this lane feeds to the matrix cores
+    // and the B operands W2[unit][input], formed just before their MFMAs (a
+    // wave usually answers one tile: holding all 32 steps' operands in
+    // registers only limited how many waves fit on a SIMD)
 #pragma unroll
     for (int st = 0; st < H / 2; ++st) {
-      c0 = __builtin_amdgcn_mfma_f32_32x32x2f32(h1[st], wb0[st], c0, 0, 0, 0);
-      c1 = __builtin_amdgcn_mfma_f32_32x32x2f32(h1[st], wb1[st], c1, 0, 0, 0);
+      const float4 wa = w1s[2 * st + half][0], wb = w1s[2 * st + half][1];
+      const float a =
+          wb.z + wa.x * f[0] + wa.y * f[1] + wa.z * f[2] + wa.w * f[3] + wb.x * f[4] + wb.y * f[5];
+      const float h1 = fmaxf(a, 0.0f);
+      c0 = __builtin_amdgcn_mfma_f32_32x32x2f32(h1, w2s[col][2 * st + half], c0, 0, 0, 0);
+      c1 = __builtin_amdgcn_mfma_f32_32x32x2f32(h1, w2s[32 + col][2 * st + half], c1, 0, 0, 0);
     }
     // output layer: per (query row, unit) terms, summed over units through
     // this wave's LDS rows
