@@ -162,6 +162,8 @@ __global__ __launch_bounds__(64 * kInferWaves) void infer_kernel(
   __shared__ float w2s[H][H + 1];  // hidden-to-hidden weights, padded rows
   __shared__ float4 w1s[H][2];     // first layer, per unit: weights 0..3 | weights 4, 5, bias
   static_assert(NI == 6, "the first layer's LDS layout holds six weights and a bias per unit");
+  static_assert(H == 64, "the MFMA tiling covers 64 hidden units: two 32-unit output blocks "
+                         "(c0, c1) and H / 2 K-steps of two inputs");
   __shared__ float part[kInferWaves][kInferTile][kInferTile + 1];
   const float *__restrict__ W = m->params;
   const int wv = threadIdx.x >> 6;

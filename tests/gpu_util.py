@@ -33,20 +33,34 @@ def gpu_query(index, qs, scale, t_window, k, **kw):
     return i.cpu().numpy(), d.cpu().numpy()
 
 
-def assert_same(gi, gd, oi, od, what=""):
-    """Indices bit-exact; distances bit-identical (the binary64 formula and
-    its order are the same on both sides)."""
+def assert_same(gi, gd, oi, od, what="", rtol=1e-12):
+    """Indices bit-exact on every slot; every distance equal to the oracle's
+    (both +inf, or both NaN for a row without a metric) or, where not
+    bit-identical, within `rtol` relative of it -- checked on every slot of
+    every query, not only the first that differs."""
     gi = np.asarray(gi, dtype=np.int64)
+    oi = np.asarray(oi, dtype=np.int64)
+    gd = np.asarray(gd, dtype=np.float64)
+    od = np.asarray(od, dtype=np.float64)
+    assert gi.shape == oi.shape and gd.shape == od.shape, f"{what}: shape {gi.shape} vs {oi.shape}"
     bad = np.argwhere(gi != oi)
     if bad.size:
         q = bad[0][0]
-        raise AssertionError(f"{what}: index mismatch at query {q}: gpu {gi[q].tolist()} "
-                             f"oracle {oi[q].tolist()} gpu_d {gd[q].tolist()} oracle_d {od[q].tolist()}")
-    same = (gd == od) | (np.isinf(gd) & np.isinf(od))
+        raise AssertionError(f"{what}: index mismatch in {len(np.unique(bad[:, 0]))} queries, first "
+                             f"{q}: gpu {gi[q].tolist()} oracle {oi[q].tolist()} "
+                             f"gpu_d {gd[q].tolist()} oracle_d {od[q].tolist()}")
+    same = (gd == od) | (np.isinf(gd) & np.isinf(od) & (np.sign(gd) == np.sign(od))) | \
+        (np.isnan(gd) & np.isnan(od))
     if not same.all():
-        q = np.argwhere(~same)[0][0]
-        rel = np.max(np.abs(gd[q] - od[q]) / np.maximum(np.abs(od[q]), 1e-300))
-        assert rel <= 1e-12, f"{what}: distance mismatch at query {q}: rel {rel}"
+        diff = ~same
+        with np.errstate(invalid="ignore", divide="ignore"):
+            rel = np.abs(gd[diff] - od[diff]) / np.maximum(np.abs(od[diff]), 1e-300)
+        worst = np.nanargmax(np.where(np.isnan(rel), np.inf, rel))
+        q = np.argwhere(diff)[worst][0]
+        ok = np.isfinite(rel) & (rel <= rtol)
+        assert ok.all(), (f"{what}: {int((~ok).sum())} distances beyond rtol {rtol} in "
+                          f"{len(np.unique(np.argwhere(diff)[~ok][:, 0]))} queries; worst "
+                          f"query {q}: rel {rel[worst]}")
 
 
 @functools.lru_cache(maxsize=None)

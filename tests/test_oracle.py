@@ -213,7 +213,11 @@ def _climbing(seed, n_traj=12, n_pts=45):
 
 @pytest.mark.parametrize("seed", range(3))
 @pytest.mark.parametrize("scale", [(1, 1, 10, 0.05), (1, 3, 100, 0.5), (0.2, 1, 1, 0.0)])
-def test_lower_bound_never_exceeds_member_distance(seed, scale):
+@pytest.mark.parametrize("t_window", [0.0, 25.0, 200.0, 1800.0])
+def test_lower_bound_never_exceeds_member_distance(seed, scale, t_window):
+    """lb <= every candidate member's distance, and the mask is exact, also
+    with a window (candidates t_i < t_q - t_w; gap at least t_w).  The
+    trajectories span about 800 s, so t_w = 1800 masks every segment."""
     ps = _climbing(seed)
     seg = oracle.segments(ps.soa(), ps.offsets, 11)
     rng = np.random.default_rng(seed + 50)
@@ -223,14 +227,14 @@ def test_lower_bound_never_exceeds_member_distance(seed, scale):
     qy = np.concatenate([ps.y[qi], rng.uniform(-5, 90, 40).astype(np.float32)])
     qz = np.concatenate([ps.z[qi], rng.uniform(0, 20, 40).astype(np.float32)])
     qt = np.concatenate([ps.t[qi] + 0.5, rng.uniform(0, 700, 40)]).astype(np.float32)
-    lb = oracle.lower_bound(seg, (qx, qy, qz, qt), scale, 0.0)
+    lb = oracle.lower_bound(seg, (qx, qy, qz, qt), scale, t_window)
     P = np.stack([a.astype(np.float64) for a in ps.soa()], 1)
     s = np.array(scale, dtype=np.float64)
     for j in range(seg["start"].shape[0]):
         mem = slice(seg["start"][j], seg["start"][j] + seg["count"][j])
         diff = np.stack([qx, qy, qz, qt], 1).astype(np.float64)[:, None, :] - P[None, mem]
         d = (s * diff ** 2).sum(-1)
-        valid = P[None, mem, 3] < qt.astype(np.float64)[:, None]
+        valid = P[None, mem, 3] < qt.astype(np.float64)[:, None] - t_window
         dmin = np.where(valid, d, np.inf).min(1)
         assert np.all(lb[:, j] <= dmin * (1 + 1e-12))
         # mask is exact: finite bound iff some member is valid
@@ -274,6 +278,113 @@ def test_mlp_closed_form_constant_network():
     assert loss == pytest.approx(((1.5 - y) ** 2).mean())
     assert g[-1] == pytest.approx(2 * (1.5 - y).mean())
     assert np.all(g[:-1] == 0)
+
+
+def _mlp_golden():
+    with open(os.path.join(GOLDEN, "mlp_cases.json")) as f:
+        g = json.load(f)
+    w = g["weights"]
+    p = {name: np.zeros(sh) for name, sh in oracle.PARAM_SHAPES}
+    for r, c, v in w["W1"]:
+        p["W1"][r, c] = v
+    for r, c, v in w["W2"]:
+        p["W2"][r, c] = v
+    for key in ("b1", "b2", "W3"):
+        for u, v in w[key]:
+            p[key][u] = v
+    p["b3"][0] = w["b3"]
+    X = np.array([c["x"] for c in g["cases"]], dtype=np.float64)
+    want = np.array([c["out"] for c in g["cases"]], dtype=np.float64)
+    return p, X, want
+
+
+def test_mlp_forward_hand_worked_cases():
+    """Hand-worked forward passes (tests/golden/mlp_cases.json): dyadic
+    weights and inputs, so the binary64 output is exact."""
+    p, X, want = _mlp_golden()
+    out, _ = oracle.mlp_forward(p, X)
+    assert np.array_equal(out, want)
+    # the flat parameter order of the device layout gives the same network
+    out_flat, _ = oracle.mlp_forward(oracle.pack_params(p), X)
+    assert np.array_equal(out_flat, want)
+
+
+def test_mlp_forward_pins_catch_planted_mistakes(monkeypatch):
+    """Plausible slips in the forward pass each miss a hand-worked value:
+    W2 read transposed, a feature column swapped, and the ReLUs dropped
+    (planted in the oracle module by replacing np.maximum)."""
+    p, X, want = _mlp_golden()
+    pt = dict(p)
+    pt["W2"] = p["W2"].T.copy()
+    assert not np.array_equal(oracle.mlp_forward(pt, X)[0], want)
+    ps = dict(p)
+    ps["W1"] = p["W1"][:, [0, 1, 2, 4, 3, 5]].copy()
+    assert not np.array_equal(oracle.mlp_forward(ps, X)[0], want)
+
+    class NoRelu:
+        def __getattr__(self, name):
+            return getattr(np, name)
+
+        @staticmethod
+        def maximum(a, b):
+            return a
+
+    import oracle.oracle as om
+    monkeypatch.setattr(om, "np", NoRelu())
+    assert not np.array_equal(om.mlp_forward(p, X)[0], want)
+
+
+def test_adam_steps_two_and_three_closed_form():
+    """Adam (Kingma & Ba 2015, Alg. 1) beyond the first step.
+    Constant gradient g: m_t = (1 - b1^t) g and v_t = (1 - b2^t) g^2, so the
+    bias-corrected m_hat = g and v_hat = g^2 at every step and each update is
+    lr g / (|g| + eps).
+    Gradient g, -g, g: m_1 = g/10, m_2 = 0.09 g - 0.1 g = -g/100,
+    m_3 = -0.009 g + 0.1 g = 0.091 g; m_hat_2 = (-1/100)/(19/100) g = -g/19,
+    m_hat_3 = 0.091/0.271 g = 91/271 g; |g| constant gives v_hat_t = g^2."""
+    lr, eps = 0.01, 1e-8
+    g = np.array([0.5, -2.0, 1e-3, 3.0])
+    th, m, v = np.zeros(4), np.zeros(4), np.zeros(4)
+    for step in (1, 2, 3):
+        th, m, v = oracle.adam_step(th, g, m, v, step, lr=lr)
+        assert np.allclose(th, -step * lr * g / (np.abs(g) + eps), rtol=1e-12)
+    # sign-flipping gradient
+    th, m, v = np.zeros(4), np.zeros(4), np.zeros(4)
+    ups = []
+    for step, sgn in ((1, 1.0), (2, -1.0), (3, 1.0)):
+        before = th.copy()
+        th, m, v = oracle.adam_step(th, sgn * g, m, v, step, lr=lr)
+        ups.append(before - th)
+    assert np.allclose(m, 0.091 * g, rtol=1e-12)
+    assert np.allclose(v, (0.999 ** 2 * 0.001 + 0.999 * 0.001 + 0.001) * g * g, rtol=1e-12)
+    assert np.allclose(ups[0], lr * g / (np.abs(g) + eps), rtol=1e-12)
+    assert np.allclose(ups[1], lr * (-g / 19.0) / (np.abs(g) + eps), rtol=1e-10)
+    assert np.allclose(ups[2], lr * (91.0 / 271.0) * g / (np.abs(g) + eps), rtol=1e-10)
+
+
+def test_adam_pin_catches_bias_correction_slip():
+    """Bias correction by beta instead of beta^step (a plausible slip: the
+    step count ignored) misses the step-2 closed form: planted by giving the
+    oracle step 1 where it should see step 2."""
+    lr, eps = 0.01, 1e-8
+    g = np.array([0.5, -2.0, 3.0])
+    th, m, v = oracle.adam_step(np.zeros(3), g, np.zeros(3), np.zeros(3), 1, lr=lr)
+    th_bad, _, _ = oracle.adam_step(th, g, m, v, 1, lr=lr)
+    assert not np.allclose(th_bad, -2 * lr * g / (np.abs(g) + eps), rtol=1e-6)
+
+
+def test_lower_bound_window_pins_catch_a_dropped_window():
+    """The golden bounds with t_w > 0 reject a bound that ignores the
+    window in the time gap or in the mask (planted by calling the oracle
+    with t_w = 0)."""
+    cases = [c for c in _cases("segment_cases.json", "lower_bounds") if c["t_window"] > 0]
+    assert len(cases) >= 4
+    for case in cases:
+        pts = _soa(case["points"])
+        seg = oracle.segments(pts, np.array(case["offsets"]), case["seg_len"])
+        q = tuple(np.array([v], dtype=np.float32) for v in case["query"])
+        lb0 = oracle.lower_bound(seg, q, case["scale"], 0.0)[0, 0]
+        assert lb0 != _val(case["lb"]), case["name"]
 
 
 def test_adam_first_step_closed_form():
