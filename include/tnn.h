@@ -182,10 +182,16 @@ tnn_status tnn_debug_export_index(const tnn_index *index, float *d_seg_f32, int3
 /*
  * Test export of the bounds the query kernels use: d_seg_lb[q*S + s]
  * (binary64, segment s in index order) and d_block_lb[q*nb + b] (float32);
- * +inf where masked.  Either output may be NULL.  Asynchronous.
+ * +inf where masked.  Either output may be NULL.  h_scale: the shared scales.
+ * d_query_scale: device [n_queries][4] per-query scales or NULL; with it each
+ * query's cylinder bounds are the ones the per-query-scale search forms for
+ * its own metric, and a row the search would refuse (a negative or
+ * non-finite scale, or out of the float32 range) gets NaN bounds.
+ * Asynchronous.
  */
 tnn_status tnn_debug_lower_bounds(const tnn_index *index, tnn_points queries,
-                                  const double *h_scale, double t_window, double *d_seg_lb,
+                                  const double *h_scale, double t_window,
+                                  const double *d_query_scale, double *d_seg_lb,
                                   float *d_block_lb, void *d_scratch, size_t scratch_bytes,
                                   void *stream);
 

@@ -56,6 +56,8 @@ def _load():
         lib.oracle_knn_qscale.restype = ctypes.c_int
         lib.oracle_pair_dist.argtypes = [i64, P, P, P, P, P, P, P, P, P, P, P, P]
         lib.oracle_pair_dist.restype = ctypes.c_int
+        lib.oracle_pair_dist_qscale.argtypes = [i64, P, P, P, P, P, P, P, P, P, P, P, P]
+        lib.oracle_pair_dist_qscale.restype = ctypes.c_int
         lib.oracle_segment_count.argtypes = [P, i64, i32]
         lib.oracle_segment_count.restype = i64
         lib.oracle_segments.argtypes = [P, P, P, P, P, i64, i32, i64, P, P, P, P, P, P, P]
@@ -98,6 +100,9 @@ def knn(points, queries, scale, t_window: float, k: int):
 
 
 def pair_dist(points, queries, qi, pi, scale):
+    """Binary64 scaled squared distance of each pair (queries[qi[j]],
+    points[pi[j]]) with the k-NN's arithmetic.  `scale`: one vector of 4, or
+    one row of 4 per query (each pair under its query's metric)."""
     lib = _load()
     px, py, pz, pt = (_f32(a) for a in points)
     qx, qy, qz, qt = (_f32(a) for a in queries)
@@ -105,7 +110,13 @@ def pair_dist(points, queries, qi, pi, scale):
     pi = np.ascontiguousarray(pi, dtype=np.int64)
     s = np.ascontiguousarray(scale, dtype=np.float64)
     out = np.empty(qi.shape[0], dtype=np.float64)
-    rc = lib.oracle_pair_dist(qi.shape[0], _ptr(qi), _ptr(pi), _ptr(qx), _ptr(qy), _ptr(qz),
+    if s.ndim == 2:
+        if s.shape != (qx.shape[0], 4):
+            raise ValueError("per-query scales must be [n_queries, 4]")
+        fn = lib.oracle_pair_dist_qscale
+    else:
+        fn = lib.oracle_pair_dist
+    rc = fn(qi.shape[0], _ptr(qi), _ptr(pi), _ptr(qx), _ptr(qy), _ptr(qz),
                               _ptr(qt), _ptr(px), _ptr(py), _ptr(pz), _ptr(pt), _ptr(s), _ptr(out))
     if rc != 0:
         raise ValueError("oracle_pair_dist: bad argument")

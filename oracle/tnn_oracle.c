@@ -139,6 +139,23 @@ int oracle_pair_dist(int64_t m, const int64_t *qi, const int64_t *pi,
   return 0;
 }
 
+/* The same with one scale row per query (Sec. 3.2, scales as a function of
+ * position): pair j uses the metric of its query, scale[4*qi[j] .. +3]. */
+int oracle_pair_dist_qscale(int64_t m, const int64_t *qi, const int64_t *pi,
+                            const float *qx, const float *qy, const float *qz,
+                            const float *qt, const float *x, const float *y,
+                            const float *z, const float *t, const double *scale,
+                            double *out) {
+  if (m < 0 || !scale) return -1;
+#pragma omp parallel for schedule(static)
+  for (int64_t j = 0; j < m; ++j) {
+    int64_t a = qi[j], b = pi[j];
+    const double *s = scale + 4 * a;
+    out[j] = scaled_sq_dist(s, qx[a], qy[a], qz[a], qt[a], x[b], y[b], z[b], t[b]);
+  }
+  return 0;
+}
+
 /* Number of segments that cutting every trajectory into runs of seg_len
  * consecutive points produces (the last run of a trajectory may be shorter:
  * no padding copies). */

@@ -85,7 +85,8 @@ _SIGS = {
     "tnn_query": (i32, [ctypes.POINTER(TnnIndex), TnnPoints, ctypes.POINTER(TnnQueryParams), P, P,
                         P, sz, P]),
     "tnn_debug_export_index": (i32, [ctypes.POINTER(TnnIndex), P, P, P, P, P]),
-    "tnn_debug_lower_bounds": (i32, [ctypes.POINTER(TnnIndex), TnnPoints, P, f64, P, P, P, sz, P]),
+    "tnn_debug_lower_bounds": (i32, [ctypes.POINTER(TnnIndex), TnnPoints, P, f64, P, P, P, P, sz,
+                                     P]),
     "tnn_radius_model_bytes": (i32, [ctypes.POINTER(sz)]),
     "tnn_radius_model_init": (i32, [ctypes.POINTER(TnnIndex), P, u64, P]),
     "tnn_radius_train_workspace": (i32, [i64, ctypes.POINTER(sz)]),

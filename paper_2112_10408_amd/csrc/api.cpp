@@ -404,7 +404,8 @@ tnn_status tnn_debug_export_index(const tnn_index *index, float *d_seg_f32, int3
 }
 
 tnn_status tnn_debug_lower_bounds(const tnn_index *index, tnn_points queries,
-                                  const double *h_scale, double t_window, double *d_seg_lb,
+                                  const double *h_scale, double t_window,
+                                  const double *d_query_scale, double *d_seg_lb,
                                   float *d_block_lb, void *d_scratch, size_t scratch_bytes,
                                   void *stream) {
   const IndexDesc *d = desc_of(index);
@@ -420,8 +421,8 @@ tnn_status tnn_debug_lower_bounds(const tnn_index *index, tnn_points queries,
   hipStream_t st = static_cast<hipStream_t>(stream);
   const QueryArgs a = make_args(&p);
   const Prep pr = prep_view(d_scratch, d->n_seg);
-  TNN_HIP_CHECK(launch_prep(*d, a, pr, st));
-  TNN_HIP_CHECK(launch_debug_lb(*d, pr, a, queries, d_seg_lb, d_block_lb, st));
+  TNN_HIP_CHECK(launch_prep(*d, a, pr, st, d_query_scale != nullptr));
+  TNN_HIP_CHECK(launch_debug_lb(*d, pr, a, queries, d_seg_lb, d_block_lb, st, d_query_scale));
   return TNN_OK;
 }
 

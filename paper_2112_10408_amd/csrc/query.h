@@ -54,7 +54,7 @@ hipError_t launch_mixed_brute(const IndexDesc &ix, const QueryArgs &a, const tnn
                               int32_t *out_idx, double *out_dist, void *scratch, hipStream_t st);
 hipError_t launch_debug_lb(const IndexDesc &ix, const Prep &pr, const QueryArgs &a,
                            const tnn_points &qs, double *seg_lb_out, float *block_lb_out,
-                           hipStream_t st);
+                           hipStream_t st, const double *query_scale = nullptr);
 
 // Index construction (build.hip).
 hipError_t launch_seg_stats(const tnn_points &pts, const int32_t *start, const int32_t *cnt_flags,

@@ -600,20 +600,31 @@ __global__ __launch_bounds__(512) void brute_kernel(IndexDesc ix, QueryArgs a, c
 
 // ---------------------------------------------------------------------------
 // Test export of the bounds, one thread per (query, segment) / (query, block).
+// With per-query scales (qscale) the records hold the deviation bounds and
+// each cylinder bound is formed for the query's own metric, as the
+// per-query-scale search forms it; a row the search refuses gets NaN.
 // ---------------------------------------------------------------------------
 __global__ void debug_lb_kernel(IndexDesc ix, Prep pr, QueryArgs a, const float *qx,
                                 const float *qy, const float *qz, const float *qt, int64_t nq,
-                                double *seg_lb_out, float *block_lb_out) {
+                                double *seg_lb_out, float *block_lb_out, const double *qscale) {
   const int64_t S = ix.n_seg, nb = ix.n_blocks;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t per_q = S + nb;
   if (i >= nq * per_q) return;
   const int64_t qi = i / per_q, j = i % per_q;
   const QueryPoint q = make_query(qx[qi], qy[qi], qz[qi], qt[qi], a.t_window);
+  QueryArgs aq = a;
+  bool ok = true;
+  if (qscale) ok = load_query_scales(qscale, qi, aq, &ix);
   if (j < S) {
-    if (seg_lb_out) seg_lb_out[qi * S + j] = (double)seg_lb(load_seg(pr, j), q, a.sf);
+    if (!seg_lb_out) return;
+    const SegView v = load_seg(pr, j);
+    double lb = a.inf - a.inf;  // NaN (no 64-bit literal)
+    if (ok) lb = qscale ? (double)seg_lb_q(v, q, aq.s, aq.sf) : (double)seg_lb(v, q, aq.sf);
+    seg_lb_out[qi * S + j] = lb;
   } else if (block_lb_out) {
-    block_lb_out[qi * nb + (j - S)] = block_lb(ix.box, (int)(j - S), q, a.sf);
+    block_lb_out[qi * nb + (j - S)] =
+        ok ? block_lb(ix.box, (int)(j - S), q, aq.sf) : __int_as_float(0x7fc00000);
   }
 }
 
@@ -823,12 +834,13 @@ hipError_t launch_brute(const IndexDesc &ix, const QueryArgs &a, const tnn_point
 
 hipError_t launch_debug_lb(const IndexDesc &ix, const Prep &pr, const QueryArgs &a,
                            const tnn_points &qs, double *seg_lb_out, float *block_lb_out,
-                           hipStream_t st) {
+                           hipStream_t st, const double *query_scale) {
   const int64_t total = qs.n * (ix.n_seg + ix.n_blocks);
   if (total == 0) return hipSuccess;
   const int tpb = 256;
   hipLaunchKernelGGL(debug_lb_kernel, dim3((unsigned)((total + tpb - 1) / tpb)), dim3(tpb), 0, st,
-                     ix, pr, a, qs.x, qs.y, qs.z, qs.t, qs.n, seg_lb_out, block_lb_out);
+                     ix, pr, a, qs.x, qs.y, qs.z, qs.t, qs.n, seg_lb_out, block_lb_out,
+                     query_scale);
   return hipGetLastError();
 }
 

@@ -152,19 +152,26 @@ def tnn_debug_export_index(index):
     return dict(seg_f32=seg_f, seg_i32=seg_i, point_id=pid, block_box=box)
 
 
-def tnn_debug_lower_bounds(index, qx, qy, qz, qt, scale, t_window):
+def tnn_debug_lower_bounds(index, qx, qy, qz, qt, scale, t_window, query_scale=None,
+                           block_bounds=True):
+    """(seg_lb float64 [nq, S], blk_lb float32 [nq, nb] or None).  query_scale:
+    optional float64 [nq, 4] device tensor of per-query scales."""
     L = capi.lib()
     nq = qx.shape[0]
     dev = qx.device
     seg_lb = torch.empty((nq, index.n_segments), dtype=torch.float64, device=dev)
-    blk_lb = torch.empty((nq, index.n_blocks), dtype=torch.float32, device=dev)
+    blk_lb = torch.empty((nq, index.n_blocks), dtype=torch.float32, device=dev) if block_bounds else None
     params = make_params(scale, t_window, 1)
     need = tnn_query_workspace(index, nq, params)
     scratch = torch.empty(max(need, 256), dtype=torch.uint8, device=dev)
     sc = (ctypes.c_double * 4)(*[float(v) for v in scale])
-    check(L.tnn_debug_lower_bounds(index.ref, points(qx, qy, qz, qt), sc, float(t_window), _ptr(seg_lb),
-                                   _ptr(blk_lb), _ptr(scratch), scratch.numel(), _stream()),
-          "tnn_debug_lower_bounds")
+    if query_scale is not None:
+        if query_scale.dtype != torch.float64 or tuple(query_scale.shape) != (nq, 4) or \
+                not query_scale.is_contiguous():
+            raise ValueError("query_scale must be a contiguous float64 [n_queries, 4] device tensor")
+    check(L.tnn_debug_lower_bounds(index.ref, points(qx, qy, qz, qt), sc, float(t_window),
+                                   _ptr(query_scale), _ptr(seg_lb), _ptr(blk_lb), _ptr(scratch),
+                                   scratch.numel(), _stream()), "tnn_debug_lower_bounds")
     return seg_lb, blk_lb
 
 

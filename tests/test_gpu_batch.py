@@ -110,3 +110,41 @@ def test_autotuner_picks_and_caches(tmp_path):
     outs = T.tnn_query_batched(b)
     torch.cuda.synchronize()
     _check(airs, outs)
+
+
+def test_full_size_64_airspaces_sampled_against_the_oracle():
+    """The 64-airspace serving workload at full size (about 7.4M points and
+    873k queries, k in {8, 32, 64}), learned radius from each airspace's own
+    (untrained) model: one persistent launch; a seeded sample of 64 queries
+    per airspace (plus its earliest query) checked against the oracle, every
+    query against the airspace's own plain search, and a second launch
+    byte-identical to the first (the work queue's atomics only reorder work)."""
+    airs = synth.airspaces(64)
+    entries, samples = [], []
+    for i, a in enumerate(airs):
+        ps, qs = a["points"], a["queries"]
+        ix = build(ps, a["seg_len"])
+        q = dev_points(qs)
+        model = T.tnn_radius_model_init(ix, seed=i + 1)
+        r2 = T.tnn_radius_infer(model, *q, alpha=2.0)
+        entries.append(dict(index=ix, q=q, scale=SCALE, k=a["k"], flags=capi.TNN_LEARNED,
+                            radius2=r2))
+        rng = np.random.default_rng(500 + i)
+        smp = np.sort(rng.choice(qs.n, min(64, qs.n), replace=False))
+        samples.append(np.unique(np.concatenate([smp, [int(np.argmin(qs.t))]])))
+    say("full-size batch:", sum(a["points"].n for a in airs), "points,",
+        sum(a["queries"].n for a in airs), "queries")
+    b = T.tnn_batch_prepare(entries)
+    outs = T.tnn_query_batched(b)
+    torch.cuda.synchronize()
+    first = [(i.cpu().numpy().copy(), d.cpu().numpy().copy()) for i, d in outs]
+    T.tnn_query_batched(b)
+    torch.cuda.synchronize()
+    for (i, d), (fi, fd) in zip(outs, first):
+        assert i.cpu().numpy().tobytes() == fi.tobytes() and d.cpu().numpy().tobytes() == fd.tobytes()
+    for n_a, (a, e, smp, (gi, gd)) in enumerate(zip(airs, entries, samples, first)):
+        oi, od = oracle.knn(a["points"].soa(), a["queries"].take(smp).soa(), SCALE, 0.0, a["k"])
+        assert_same(gi[smp], gd[smp], oi, od, f"airspace {n_a} sample")
+        pi, pd = T.tnn_query(e["index"], *e["q"], SCALE, 0.0, a["k"])
+        torch.cuda.synchronize()
+        assert np.array_equal(pi.cpu().numpy(), gi) and np.array_equal(pd.cpu().numpy(), gd), n_a

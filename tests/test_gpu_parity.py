@@ -291,11 +291,18 @@ def test_c2_full_size_sampled_parity():
     assert np.all(ps.t[np.where(ok, gi, 0)][ok] < qs.t[:, None].repeat(k, 1)[ok])
 
 
-def test_repeat_runs_are_bitwise_identical():
+@pytest.mark.parametrize("flags", [0, capi.TNN_LEARNED, MIXED], ids=["plain", "learned", "bf16"])
+def test_repeat_runs_are_bitwise_identical(flags):
+    """Work-queue atomics (the search's tickets, the BF16 search's items)
+    change only which wave does what: two runs give the same bytes."""
     ps, qs, _, cfg = config_data("c1")
     ix = build(ps, cfg["seg_len"])
-    a = gpu_query(ix, qs, SCALE, 0.0, cfg["k"])
-    b = gpu_query(ix, qs, SCALE, 0.0, cfg["k"])
+    kw = {}
+    if flags & capi.TNN_LEARNED:
+        model = T.tnn_radius_model_init(ix, seed=4)
+        kw["radius2"] = T.tnn_radius_infer(model, *dev_points(qs), alpha=1.0)
+    a = gpu_query(ix, qs, SCALE, 0.0, cfg["k"], flags=flags, **kw)
+    b = gpu_query(ix, qs, SCALE, 0.0, cfg["k"], flags=flags, **kw)
     assert a[0].tobytes() == b[0].tobytes() and a[1].tobytes() == b[1].tobytes()
 
 

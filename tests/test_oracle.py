@@ -576,3 +576,29 @@ def test_per_query_scales_equal_exact_rational_on_dyadic(seed):
         ei, ed = exact_knn(pts, one, list(rows[j]), tw, k)
         assert np.array_equal(idx[j], ei[0]), j
         assert np.array_equal(dist[j], np.array([float(v) for v in ed[0]])), j
+
+
+def test_pair_dist_with_query_rows_reduces_to_the_shared_metric():
+    """One scale row per query: equal rows give the shared-metric distances,
+    and a row scaled by a power of two scales exactly its pairs; every pair
+    equals the k-NN's own distance for that pair (k = n on one query)."""
+    ps = synth.trajectories(5, 20, 100.0, 600.0, seed=2)
+    qs = ps.take(np.array([99, 50, 7]))
+    QQ, PP = np.meshgrid(np.arange(3), np.arange(ps.n), indexing="ij")
+    QQ, PP = QQ.ravel(), PP.ravel()
+    base = np.array(synth.SCALE)
+    d0 = oracle.pair_dist(ps.soa(), qs.soa(), QQ, PP, base)
+    rows = np.tile(base, (3, 1))
+    assert np.array_equal(oracle.pair_dist(ps.soa(), qs.soa(), QQ, PP, rows), d0)
+    rows[1] *= 4.0
+    d1 = oracle.pair_dist(ps.soa(), qs.soa(), QQ, PP, rows)
+    m = QQ == 1
+    assert np.array_equal(d1[m], 4.0 * d0[m]) and np.array_equal(d1[~m], d0[~m])
+    # against the k-NN: every point of the earliest-to-latest order, no mask
+    qt = tuple(a.copy() for a in qs.soa())
+    qt[3][:] = np.float32(1e9)
+    idx, dist = oracle.knn(ps.soa(), qt, rows, 0.0, ps.n)
+    late = synth.PointSet(*qt, np.array([0, 3]))
+    d2 = oracle.pair_dist(ps.soa(), late.soa(), QQ, PP, rows).reshape(3, ps.n)
+    for q in range(3):
+        assert np.array_equal(dist[q], d2[q][idx[q]])
