@@ -169,6 +169,26 @@ tnn_status tnn_query(const tnn_index *index, tnn_points queries, const tnn_query
                      size_t scratch_bytes, void *stream);
 
 /*
+ * tnn_query without a scratch argument, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid allocation).  Same arguments, results and flags as tnn_query;
+ * the scratch it needs is a library-owned device array of
+ * TNN_NOALLOC_SCRATCH_BYTES per GPU (one copy on each device the library runs
+ * on, kept until the process ends), so calls whose tnn_query_workspace size
+ * exceeds it return TNN_E_WORKSPACE before anything is queued (TNN: about
+ * 64 B per segment, so indexes of up to about 262k segments, 8M points at
+ * K = 32).  The array is resolved once per device on that device's first
+ * call.  Nothing is allocated: no hipMalloc, no hipFree.  Every call on a
+ * device shares that device's array: two calls that overlap in time on one
+ * device (two streams, two threads) race and must not be issued.  Asynchronous
+ * on `stream`.
+ */
+#define TNN_NOALLOC_SCRATCH_BYTES ((size_t)16 << 20)
+tnn_status tnn_query_noalloc(const tnn_index *index, tnn_points queries,
+                             const tnn_query_params *params, int32_t *d_out_idx,
+                             double *d_out_dist, void *stream);
+
+/*
  * Test export of the index: per segment in index order
  * d_seg_f32[12*s + 0..11] = A.xyz, B.xyz, t_min, t_max, e.xyz, 0;
  * d_seg_i32[4*s + 0..3] = trajectory-order segment number, first point slot in

@@ -27,6 +27,7 @@ TNN_LEARNED = 4
 STAT_NAMES = ["queries", "blocks", "segments", "points", "merges", "rounds", "fallbacks",
               "rescored", "max_err_bits"]
 TNN_STAT_COUNT = 16
+NOALLOC_SCRATCH_BYTES = 16 << 20  # TNN_NOALLOC_SCRATCH_BYTES
 
 # Radius model (layout of the device blob, see tnn.h)
 RADIUS_HIDDEN = 64
@@ -84,6 +85,8 @@ _SIGS = {
                                   ctypes.POINTER(sz)]),
     "tnn_query": (i32, [ctypes.POINTER(TnnIndex), TnnPoints, ctypes.POINTER(TnnQueryParams), P, P,
                         P, sz, P]),
+    "tnn_query_noalloc": (i32, [ctypes.POINTER(TnnIndex), TnnPoints, ctypes.POINTER(TnnQueryParams),
+                                P, P, P]),
     "tnn_debug_export_index": (i32, [ctypes.POINTER(TnnIndex), P, P, P, P, P]),
     "tnn_debug_lower_bounds": (i32, [ctypes.POINTER(TnnIndex), TnnPoints, P, f64, P, P, P, P, sz,
                                      P]),

@@ -140,6 +140,25 @@ def tnn_query(index, qx, qy, qz, qt, scale, t_window, k, flags=0, seed_segments=
     return out
 
 
+def tnn_query_noalloc(index, qx, qy, qz, qt, scale, t_window, k, flags=0, seed_segments=0,
+                      waves_per_block=0, radius2=None, stats=None, out=None, query_scale=None):
+    """tnn_query with the library's own per-device scratch (no scratch
+    argument; the library allocates nothing).  Returns (idx, dist); `out`
+    supplies them preallocated."""
+    L = capi.lib()
+    nq = qx.shape[0]
+    if query_scale is not None and query_scale.shape[0] != nq:
+        raise ValueError("query_scale needs one row per query")
+    params = make_params(scale, t_window, k, flags, seed_segments, waves_per_block, radius2, stats,
+                         query_scale)
+    if out is None:
+        out = (torch.empty((nq, k), dtype=torch.int32, device=qx.device),
+               torch.empty((nq, k), dtype=torch.float64, device=qx.device))
+    check(L.tnn_query_noalloc(index.ref, points(qx, qy, qz, qt), ctypes.byref(params),
+                              _ptr(out[0]), _ptr(out[1]), _stream()), "tnn_query_noalloc")
+    return out
+
+
 def tnn_debug_export_index(index):
     L = capi.lib()
     dev = index.mem.device

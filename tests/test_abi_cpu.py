@@ -127,3 +127,17 @@ def test_query_params_struct_matches_header():
     body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
     names = re.findall(r"\**\s*([a-z_0-9]+)\s*(?:\[[^\]]*\])?\s*;", body)
     assert names == [f[0] for f in capi.TnnQueryParams._fields_]
+
+
+def test_noalloc_rejects_bad_arguments_before_the_gpu():
+    """Argument checks of the scratch-free entry point run on the host,
+    before any device is touched."""
+    L = capi.lib()
+    pts = capi.TnnPoints(None, None, None, None, 0)
+    assert L.tnn_query_noalloc(None, pts, None, None, None, None) == capi.TNN_E_ARG
+    idx = capi.TnnIndex()
+    p = capi.TnnQueryParams()
+    p.scale[:] = [1.0, 1.0, 10.0, 0.05]
+    p.k = 8
+    # an index that was never built
+    assert L.tnn_query_noalloc(ctypes.byref(idx), pts, ctypes.byref(p), None, None, None) == capi.TNN_E_ARG
