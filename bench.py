@@ -483,13 +483,19 @@ def main():
                 out=out, scratch=scratch)
     ms_gka = timed(lambda: T.tnn_gka_average(out[0], out[1], wind, out=gka_out), args.steps, 1,
                    stream)
+    gka_sep = gka_out.clone()
 
+    # the averaging as the search's epilogue, from the top-k in registers
     def learned_gka():
-        learned()
-        T.tnn_gka_average(out[0], out[1], wind, out=gka_out)
+        T.tnn_radius_infer(model, qx, qy, qz, qt, alpha, out=r2)
+        T.tnn_query(ix, qx, qy, qz, qt, scale, 0.0, k, flags=capi.TNN_LEARNED, radius2=r2,
+                    out=out, scratch=scratch, gka_values=wind, gka_out=gka_out)
 
     ms_learned_gka = timed(learned_gka, args.steps, 1, stream)
-    log(f"GKA average: {ms_gka:.3f} ms; learned TNN + GKA {ms_learned_gka:.3f} ms/step")
+    # byte comparison: queries without a past have NaN rows on both sides
+    gka_fused_same = gka_out.cpu().numpy().tobytes() == gka_sep.cpu().numpy().tobytes()
+    log(f"GKA average kernel: {ms_gka:.3f} ms; learned TNN with the averaging fused "
+        f"{ms_learned_gka:.3f} ms/step (same as the kernel: {gka_fused_same})")
 
     if args.calib_copy:
         src = torch.empty(64 << 20, dtype=torch.float32, device="cuda").fill_(1.0)
@@ -558,6 +564,7 @@ def main():
         "learned_speedup_vs_plain": ms_plain / ms_learned,
         "learned_matches_plain": exact, "fallback_rate": st["fallbacks"] / qs.n,
         "gka_average_ms": ms_gka, "learned_plus_gka_qps": qs.n / ms_learned_gka * 1e3,
+        "learned_plus_gka_ms_per_step": ms_learned_gka, "gka_fused_matches_kernel": gka_fused_same,
         "radius_alpha": alpha, "radius_quantile": best[1], "radius_train_s": train_s,
         "radius_train_queries": args.train_queries,
         "index_build_s": build_s, "stats_learned": st, "stats_plain": st_plain,

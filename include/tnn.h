@@ -44,6 +44,8 @@ typedef int32_t tnn_status;
 #define TNN_E_WORKSPACE (-4)   /* buffer smaller than the size the matching *_workspace call gave */
 #define TNN_E_HIP (-5)         /* a HIP runtime call failed */
 #define TNN_E_UNSUPPORTED (-6) /* valid request outside this build's limits */
+#define TNN_E_FORMAT (-7)      /* a checkpoint that is not a complete, intact checkpoint of
+                                  this build's radius model */
 
 /* Structure-of-arrays float32 points in device memory: x, y, z (km), t (s). */
 typedef struct {
@@ -106,6 +108,19 @@ typedef struct {
                                range above, yields (-1, NaN) in every slot of that query.  TNN (plain or learned) and TNN_BRUTE only:
                                with TNN_MIXED_BF16 or in a tnn_query_batched item it is
                                TNN_E_UNSUPPORTED. */
+  /* Optional Gaussian kernel averaging of the neighbours' measurements (Sec.
+   * 3.2, Eq. gka; the definition of tnn_gka_average, below): with
+   * d_gka_values set, each query's d_gka_out row receives the average of
+   * d_gka_values over its k neighbours.  TNN (and tnn_query_batched items)
+   * compute it from the search's registers as soon as a query's neighbours
+   * are final; the linear searches run tnn_gka_average's kernel after the
+   * search.  Results equal tnn_gka_average on the returned idx and dist. */
+  const float *d_gka_values;   /* device float32 [n_points][gka_comp], row p = the
+                                  measurement at caller point p; NULL = no averaging */
+  double *d_gka_out;           /* device binary64 [n_queries][gka_comp]; NaN rows for
+                                  queries without context (or without a metric) */
+  int32_t gka_comp;            /* components per point, 1..8 (with d_gka_values) */
+  int32_t reserved;
 } tnn_query_params;
 
 /* Human-readable name of a status code (static string). */
@@ -235,7 +250,7 @@ tnn_status tnn_debug_lower_bounds(const tnn_index *index, tnn_points queries,
                             TNN_RADIUS_HIDDEN * TNN_RADIUS_HIDDEN + TNN_RADIUS_HIDDEN +     \
                             TNN_RADIUS_HIDDEN + 1)
 
-/* Device layout of a radius model; its bytes are the checkpoint format. */
+/* Device layout of a radius model (the payload of a checkpoint, below). */
 typedef struct {
   float params[TNN_RADIUS_NPARAMS]; /* W1[64][6] b1[64] W2[64][64] b2[64] W3[64] b3 */
   float pad[3];
@@ -259,16 +274,27 @@ tnn_status tnn_radius_model_init(const tnn_index *index, void *d_model, uint64_t
 tnn_status tnn_radius_train_workspace(int64_t batch, size_t *bytes);
 
 /*
+ * Training order for one epoch: d_order[i] (device int32 [n]) receives a
+ * permutation of 0 .. n-1 drawn from `seed` (a keyed 4-round Feistel
+ * permutation of [0, 4^h), 4^h >= n, walked along its cycles until it lands
+ * below n; SplitMix64 round function).  The same seed gives the same order.
+ * Async.  TNN_E_ARG for n < 0, n > INT32_MAX or a null d_order with n > 0.
+ */
+tnn_status tnn_radius_shuffle(int64_t n, uint64_t seed, int32_t *d_order, void *stream);
+
+/*
  * Gradient of the mean squared error between the MLP output and the label
- * log(sqrt(d)) over the samples [first, first + batch) of `samples`, where d =
- * d_dist[i*k + k-1] (the k-th distance tnn_query wrote for sample i); samples
- * whose d is not finite and positive are left out.  Writes d_grad[NPARAMS]
- * (float32, device) and *d_loss (float32, device; may be NULL).  Sums run in
- * a fixed order: the result is deterministic.  Async.
+ * log(sqrt(d)) over the batch b = 0 .. batch-1 of samples i = d_order[first + b]
+ * (or first + b when d_order is NULL), where d = d_dist[i*k + k-1] (the k-th
+ * distance tnn_query wrote for sample i); samples whose d is not finite and
+ * positive are left out.  Writes d_grad[NPARAMS] (float32, device) and
+ * *d_loss (float32, device; may be NULL).  Sums run in a fixed order: the
+ * result is deterministic.  Async.
  */
 tnn_status tnn_radius_grad(const void *d_model, tnn_points samples, const double *d_dist,
-                           int32_t k, int64_t first, int64_t batch, float *d_grad,
-                           float *d_loss, void *d_scratch, size_t scratch_bytes, void *stream);
+                           const int32_t *d_order, int32_t k, int64_t first, int64_t batch,
+                           float *d_grad, float *d_loss, void *d_scratch, size_t scratch_bytes,
+                           void *stream);
 
 /*
  * One Adam step (Kingma & Ba 2015, beta1 0.9, beta2 0.999, eps 1e-8) on that
@@ -276,9 +302,40 @@ tnn_status tnn_radius_grad(const void *d_model, tnn_points samples, const double
  * zero before step 1; `step` counts from 1.  Async.
  */
 tnn_status tnn_radius_train_step(void *d_model, float *d_adam, tnn_points samples,
-                                 const double *d_dist, int32_t k, int64_t first, int64_t batch,
-                                 int32_t step, float lr, float *d_loss, void *d_scratch,
-                                 size_t scratch_bytes, void *stream);
+                                 const double *d_dist, const int32_t *d_order, int32_t k,
+                                 int64_t first, int64_t batch, int32_t step, float lr,
+                                 float *d_loss, void *d_scratch, size_t scratch_bytes,
+                                 void *stream);
+
+/* Scratch bytes of tnn_radius_calibrate for n_samples samples. */
+tnn_status tnn_radius_calibrate_workspace(int64_t n_samples, size_t *bytes);
+
+/*
+ * Safety factor of the predicted radius: *d_alpha (device float32) =
+ * exp(x_q) with x_q the q-quantile (linear interpolation between the order
+ * statistics at position (m - 1) q, q in [0, 1]) of the binary64
+ * log-residuals 0.5 log d_i - out_i over the m samples whose k-th distance
+ * d_i = d_dist[i*k + k-1] is finite and positive and whose residual is
+ * finite; out_i is the model's output for sample i.  About (1 - q) of such
+ * samples then lie outside the radius alpha exp(out).  m = 0 gives 1.  Async.
+ */
+tnn_status tnn_radius_calibrate(const void *d_model, tnn_points samples, const double *d_dist,
+                                int32_t k, double quantile, float *d_alpha, void *d_scratch,
+                                size_t scratch_bytes, void *stream);
+
+/*
+ * Checkpoint of a radius model: a 64-byte header (magic "TNNRADM", format
+ * version 1, payload size, the model's dimensions: hidden units, inputs,
+ * grid sizes, parameter count; FNV-1a 64 checksum of the payload) followed
+ * by the model's bytes.  tnn_radius_checkpoint_bytes gives the size;
+ * tnn_radius_model_save writes it to host memory h_buf (at least that many
+ * bytes) and tnn_radius_model_load reads one back into a device model,
+ * returning TNN_E_FORMAT for a buffer that is not exactly a complete, intact
+ * checkpoint of this version and these dimensions.  Both are synchronous.
+ */
+tnn_status tnn_radius_checkpoint_bytes(size_t *bytes);
+tnn_status tnn_radius_model_save(const void *d_model, void *h_buf, size_t bytes, void *stream);
+tnn_status tnn_radius_model_load(const void *h_buf, size_t bytes, void *d_model, void *stream);
 
 /* Test export: the 5 features of each query, d_feat[5*i + j].  Async. */
 tnn_status tnn_radius_features(const void *d_model, tnn_points queries, float *d_feat,

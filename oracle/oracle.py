@@ -26,7 +26,8 @@ Pieces and the passage each follows:
 * ``radius_*``/``mlp_*``/``adam_step`` -- the learned k-th radius predictor
                         (not in the paper): feature map, a 6-64-64-1 ReLU MLP,
                         squared-error loss on log r_k, its gradient by
-                        backpropagation, and Adam (Kingma & Ba 2015, Alg. 1).
+                        backpropagation, Adam (Kingma & Ba 2015, Alg. 1), and
+                        the safety factor's quantile of log-residuals.
 """
 from __future__ import annotations
 
@@ -341,6 +342,29 @@ def adam_step(theta, grad, m, v, step: int, lr: float, beta1=0.9, beta2=0.999, e
     vhat = v / (1.0 - beta2 ** step)
     theta = theta - lr * mhat / (np.sqrt(vhat) + eps)
     return theta, m, v
+
+
+def radius_calibrate(logr, kth_dist, quantile):
+    """Safety factor of the predicted radius: alpha = exp(x_q), x_q the
+    q-quantile of the log-residuals 0.5 log d_k - logr over the samples whose
+    k-th distance d_k is finite and positive and whose residual is finite.
+    The quantile interpolates linearly between the order statistics at
+    position (m - 1) q of the m sorted residuals: x_lo + (h - lo)(x_hi - x_lo)
+    with h = (m - 1) q, lo = floor(h).  No such sample: alpha = 1."""
+    d = np.asarray(kth_dist, dtype=np.float64)
+    lr = np.asarray(logr, dtype=np.float32).astype(np.float64)
+    ok = np.isfinite(d) & (d > 0)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        r = 0.5 * np.log(np.where(ok, d, 1.0)) - lr
+    r = np.sort(r[ok & np.isfinite(r)])
+    m = r.shape[0]
+    if m == 0:
+        return 1.0
+    h = float(m - 1) * float(quantile)
+    lo = int(math.floor(h))
+    x_lo = r[lo]
+    x_hi = r[lo + 1] if lo + 1 < m else x_lo
+    return math.exp(x_lo + (h - lo) * (x_hi - x_lo))
 
 
 def radius_label(kth_dist):

@@ -18,6 +18,7 @@ TNN_E_NONFINITE = -3
 TNN_E_WORKSPACE = -4
 TNN_E_HIP = -5
 TNN_E_UNSUPPORTED = -6
+TNN_E_FORMAT = -7
 
 TNN_PLAIN = 0
 TNN_BRUTE = 1
@@ -59,7 +60,8 @@ class TnnIndex(ctypes.Structure):
 class TnnQueryParams(ctypes.Structure):
     _fields_ = [("scale", f64 * 4), ("t_window", f64), ("k", i32), ("flags", u32),
                 ("seed_segments", i32), ("waves_per_block", i32), ("d_radius2", P),
-                ("d_stats", P), ("d_query_scale", P)]
+                ("d_stats", P), ("d_query_scale", P), ("d_gka_values", P), ("d_gka_out", P),
+                ("gka_comp", i32), ("reserved", i32)]
 
 
 class TnnBatchItem(ctypes.Structure):
@@ -93,8 +95,14 @@ _SIGS = {
     "tnn_radius_model_bytes": (i32, [ctypes.POINTER(sz)]),
     "tnn_radius_model_init": (i32, [ctypes.POINTER(TnnIndex), P, u64, P]),
     "tnn_radius_train_workspace": (i32, [i64, ctypes.POINTER(sz)]),
-    "tnn_radius_grad": (i32, [P, TnnPoints, P, i32, i64, i64, P, P, P, sz, P]),
-    "tnn_radius_train_step": (i32, [P, P, TnnPoints, P, i32, i64, i64, i32, f32, P, P, sz, P]),
+    "tnn_radius_shuffle": (i32, [i64, u64, P, P]),
+    "tnn_radius_grad": (i32, [P, TnnPoints, P, P, i32, i64, i64, P, P, P, sz, P]),
+    "tnn_radius_train_step": (i32, [P, P, TnnPoints, P, P, i32, i64, i64, i32, f32, P, P, sz, P]),
+    "tnn_radius_calibrate_workspace": (i32, [i64, ctypes.POINTER(sz)]),
+    "tnn_radius_calibrate": (i32, [P, TnnPoints, P, i32, f64, P, P, sz, P]),
+    "tnn_radius_checkpoint_bytes": (i32, [ctypes.POINTER(sz)]),
+    "tnn_radius_model_save": (i32, [P, P, sz, P]),
+    "tnn_radius_model_load": (i32, [P, sz, P, P]),
     "tnn_radius_features": (i32, [P, TnnPoints, P, P]),
     "tnn_radius_infer": (i32, [P, TnnPoints, f32, P, P, P]),
     "tnn_gka_average": (i32, [P, P, i64, i32, P, i32, i64, P, P]),

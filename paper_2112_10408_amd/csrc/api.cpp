@@ -7,89 +7,20 @@
 #include <numeric>
 #include <vector>
 
+#include "gka.h"
+#include "host.h"
 #include "query.h"
 
 using namespace tnn;
+using host::BuildLayout;
+using host::count_segments;
+using host::offsets_ok;
+
+static BuildLayout build_layout(int64_t n, int64_t S) {
+  return host::build_layout(n, S, kBlockSegs, kSuperBlocks);
+}
 
 namespace {
-
-struct BuildLayout {
-  size_t pt4, pid;                             // index-order points
-  size_t f[11], pstart, pcount, sorig, sfirst;  // index-order segments
-  size_t box, sbox;                             // block and superblock boxes
-  size_t tf[11], tstart, tcf, keys, perm, dpstart, status;  // build temporaries
-  size_t total;
-};
-
-BuildLayout build_layout(int64_t n, int64_t S) {
-  BuildLayout L;
-  size_t o = 0;
-  auto take = [&](size_t bytes) {
-    size_t r = o;
-    o = align_up(o + bytes);
-    return r;
-  };
-  const int64_t nb = (S + kBlockSegs - 1) / kBlockSegs;
-  L.pt4 = take(16 * n);
-  L.pid = take(4 * n);
-  for (int i = 0; i < 11; ++i) L.f[i] = take(4 * S);
-  L.pstart = take(4 * S);
-  L.pcount = take(4 * S);
-  L.sorig = take(4 * S);
-  L.sfirst = take(4 * S);
-  L.box = take(4 * 8 * nb);
-  L.sbox = take(4 * 8 * ((nb + kSuperBlocks - 1) / kSuperBlocks));
-  for (int i = 0; i < 11; ++i) L.tf[i] = take(4 * S);
-  L.tstart = take(4 * S);
-  L.tcf = take(4 * S);
-  L.keys = take(16 * S);
-  L.perm = take(4 * S);
-  L.dpstart = take(4 * S);
-  L.status = take(32);
-  L.total = o;
-  return L;
-}
-
-bool offsets_ok(const int64_t *off, int64_t n_traj) {
-  if (!off || n_traj < 0 || off[0] != 0) return false;
-  for (int64_t j = 0; j < n_traj; ++j)
-    if (off[j + 1] < off[j]) return false;
-  return true;
-}
-
-int64_t count_segments(const int64_t *off, int64_t n_traj, int32_t K) {
-  int64_t s = 0;
-  for (int64_t j = 0; j < n_traj; ++j) s += (off[j + 1] - off[j] + K - 1) / K;
-  return s;
-}
-
-// Recursive median split along the widest axis; split points fall on
-// multiples of the block size so that every block but the last is full.
-void kd_order(int32_t *idx, int64_t n, const std::vector<float> &keys) {
-  if (n <= kBlockSegs) return;
-  float lo[4], hi[4];
-  for (int f = 0; f < 4; ++f) {
-    lo[f] = INFINITY;
-    hi[f] = -INFINITY;
-  }
-  for (int64_t i = 0; i < n; ++i)
-    for (int f = 0; f < 4; ++f) {
-      const float v = keys[4 * (size_t)idx[i] + f];
-      lo[f] = std::min(lo[f], v);
-      hi[f] = std::max(hi[f], v);
-    }
-  int axis = 0;
-  for (int f = 1; f < 4; ++f)
-    if (hi[f] - lo[f] > hi[axis] - lo[axis]) axis = f;
-  int64_t m = ((n / 2 + kBlockSegs - 1) / kBlockSegs) * kBlockSegs;
-  if (m >= n) m = (n - 1) / kBlockSegs * kBlockSegs;
-  std::nth_element(idx, idx + m, idx + n, [&](int32_t a, int32_t b) {
-    const float ka = keys[4 * (size_t)a + axis], kb = keys[4 * (size_t)b + axis];
-    return ka < kb || (ka == kb && a < b);
-  });
-  kd_order(idx, m, keys);
-  kd_order(idx + m, n - m, keys);
-}
 
 const IndexDesc *desc_of(const tnn_index *index) {
   if (!index) return nullptr;
@@ -115,6 +46,9 @@ tnn_status check_params(const tnn_query_params *p, int64_t n_queries = 1) {
   // the BF16 operands carry the scales: one metric per call
   if ((p->flags & TNN_MIXED_BF16) && p->d_query_scale) return TNN_E_UNSUPPORTED;
   if (p->seed_segments < 0 || p->seed_segments > 64) return TNN_E_ARG;
+  if (p->d_gka_values &&
+      (p->gka_comp < 1 || p->gka_comp > kGkaMaxComp || (n_queries > 0 && !p->d_gka_out)))
+    return TNN_E_ARG;
   const int w = p->waves_per_block;
   if (!(w == 0 || w == 1 || w == 2 || w == 4 || w == 8)) return TNN_E_ARG;
   return TNN_OK;
@@ -133,8 +67,12 @@ QueryArgs make_args(const tnn_query_params *p) {
   a.k = p->k;
   a.flags = p->flags;
   a.seed_segments = p->seed_segments ? p->seed_segments : 4;
+  a.floor_tau = 1e-300;  // set from the index by the callers that search
   a.radius2 = p->d_radius2;
   a.stats = p->d_stats;
+  a.gka_values = p->d_gka_values;
+  a.gka_comp = p->d_gka_values ? p->gka_comp : 0;
+  a.gka_out = p->d_gka_values ? p->d_gka_out : nullptr;
   return a;
 }
 
@@ -162,6 +100,7 @@ const char *tnn_status_string(tnn_status s) {
     case TNN_E_WORKSPACE: return "workspace too small";
     case TNN_E_HIP: return "HIP runtime error";
     case TNN_E_UNSUPPORTED: return "unsupported request";
+    case TNN_E_FORMAT: return "not a valid checkpoint for this build";
     default: return "unknown status";
   }
 }
@@ -243,7 +182,7 @@ tnn_status tnn_build_segments(tnn_points pts, const int64_t *h_traj_offsets, int
 
   std::vector<int32_t> perm(S);
   std::iota(perm.begin(), perm.end(), 0);
-  if (order_scale && S > 0) kd_order(perm.data(), S, keys);
+  if (order_scale && S > 0) host::kd_order(perm.data(), S, keys.data(), kBlockSegs);
   std::vector<int32_t> dpstart(S);
   {
     int64_t acc = 0;
@@ -378,18 +317,26 @@ tnn_status tnn_query(const tnn_index *index, tnn_points queries, const tnn_query
   const bool float_path = !(params->flags & TNN_BRUTE) || (params->flags & TNN_MIXED_BF16);
   if (float_path && !params->d_query_scale && !scaled_box_ok(d->lo, d->hi, params->scale))
     return TNN_E_UNSUPPORTED;
-  if ((params->flags & TNN_BRUTE) && (params->flags & TNN_MIXED_BF16)) {
-    TNN_HIP_CHECK(launch_mixed_brute(*d, a, queries, d_out_idx, d_out_dist, d_scratch, st));
-    return TNN_OK;
-  }
   if (params->flags & TNN_BRUTE) {
-    TNN_HIP_CHECK(launch_brute(*d, a, queries, wpb, d_out_idx, d_out_dist, st,
-                               params->d_query_scale));
+    // the linear searches write their outputs from several kernels: the
+    // averaging runs as a kernel of its own on them
+    QueryArgs ab = a;
+    ab.gka_values = nullptr;
+    if (params->flags & TNN_MIXED_BF16)
+      TNN_HIP_CHECK(launch_mixed_brute(*d, ab, queries, d_out_idx, d_out_dist, d_scratch, st));
+    else
+      TNN_HIP_CHECK(launch_brute(*d, ab, queries, wpb, d_out_idx, d_out_dist, st,
+                                 params->d_query_scale));
+    if (a.gka_values)
+      TNN_HIP_CHECK(launch_gka(d_out_idx, d_out_dist, queries.n, a.k, a.gka_values, a.gka_comp,
+                               d->n_points, a.gka_out, st));
     return TNN_OK;
   }
   const Prep pr = prep_view(d_scratch, d->n_seg);
-  TNN_HIP_CHECK(launch_prep(*d, a, pr, st, params->d_query_scale != nullptr));
-  TNN_HIP_CHECK(launch_query(*d, pr, a, queries, wpb, d_out_idx, d_out_dist, st,
+  QueryArgs at = a;
+  at.floor_tau = radius_floor(d->lo, d->hi, a.s);
+  TNN_HIP_CHECK(launch_prep(*d, at, pr, st, params->d_query_scale != nullptr));
+  TNN_HIP_CHECK(launch_query(*d, pr, at, queries, wpb, d_out_idx, d_out_dist, st,
                              params->d_query_scale));
   return TNN_OK;
 }
@@ -530,6 +477,7 @@ tnn_status tnn_batch_prepare(const tnn_batch_item *items, int32_t n_items,
     BatchItemDev &b = dev[i];
     b.ix = *d;
     b.a = make_args(&it.params);
+    b.a.floor_tau = radius_floor(d->lo, d->hi, b.a.s);
     stats = stats || b.a.stats != nullptr;
     b.pr = prep_view(m + L.prep[i], d->n_seg);
     b.qx = it.queries.x;
@@ -560,6 +508,9 @@ tnn_status tnn_batch_prepare(const tnn_batch_item *items, int32_t n_items,
   bl.chunk = cfg.chunk;
   bl.waves_per_block = w;
   bl.stats = stats ? 1 : 0;
+  bool gka = false;
+  for (int32_t i = 0; i < n; ++i) gka = gka || dev[i].a.gka_values != nullptr;
+  bl.gka = gka ? 1 : 0;
   bl.grid = (int64_t)cus * cfg.blocks_per_cu;
   bl.total_q = qprefix[n];
   bl.total_seg = seg_prefix[n];
@@ -616,21 +567,17 @@ tnn_status tnn_autotune_batched(const tnn_batch_item *items, int32_t n_items, vo
   hipDeviceProp_t prop;
   TNN_HIP_CHECK(hipGetDeviceProperties(&prop, dev));
   char key[256];
-  std::snprintf(key, sizeof(key), "batch %s %d %lld %lld", prop.gcnArchName, n_items,
-                (long long)total_q, (long long)total_p);
-  for (char *p = key; *p; ++p)
-    if (*p == ':') *p = '_';
+  if (!host::cache_key(key, sizeof(key), prop.gcnArchName, n_items, (long long)total_q,
+                       (long long)total_p))
+    cache_path = nullptr;  // no key: tune without the cache
   if (cache_path) {
     if (FILE *f = std::fopen(cache_path, "r")) {
       char line[512];
       while (std::fgets(line, sizeof(line), f)) {
-        const size_t kl = std::strlen(key);
-        tnn_batch_config cfg = {0, 0, 0, 0};
-        if (std::strncmp(line, key, kl) == 0 && line[kl] == ' ' &&
-            std::sscanf(line + kl, "%d %d %d", &cfg.chunk, &cfg.waves_per_block,
-                        &cfg.blocks_per_cu) == 3) {
+        int cfg[3];
+        if (host::cache_parse_line(line, key, cfg)) {
           std::fclose(f);
-          *best = cfg;
+          *best = tnn_batch_config{cfg[0], cfg[1], cfg[2], 0};
           return TNN_OK;
         }
       }

@@ -34,6 +34,9 @@ __device__ __forceinline__ double exact_dist(const double s[4], float qx, float 
 struct QueryPoint {
   float x, y, z, t;
   double thr;   // (double)t - t_w: a point is a candidate iff (double)t_p < thr
+  float thrf;   // thr rounded up to float32: for a float32 t_p, t_p < thr iff
+                // t_p < thrf, and t_min >= thr iff t_min >= thrf (no float lies
+                // strictly between thr and thrf), so the masks compare floats
   double gw;    // lower bound on t - t_p for any candidate (0 when t_w = 0)
   float gwf;    // the same, rounded down to float32
 };
@@ -45,6 +48,7 @@ __device__ __forceinline__ QueryPoint make_query(float x, float y, float z, floa
   q.z = z;
   q.t = t;
   q.thr = (double)t - t_window;
+  q.thrf = __double2float_ru(q.thr);
   double gw = 0.0;
   if (t_window > 0.0) gw = fmax(t_window - 0x1p-50 * (fabs((double)t) + t_window), 0.0);
   q.gw = gw;
@@ -61,7 +65,7 @@ __device__ __forceinline__ float block_lb(const float *box, int b, const QueryPo
                                           const float sf[4]) {
   const float4 lo = reinterpret_cast<const float4 *>(box)[2 * b];
   const float4 hi = reinterpret_cast<const float4 *>(box)[2 * b + 1];
-  if ((double)lo.w >= q.thr) return __builtin_huge_valf();
+  if (lo.w >= q.thrf) return __builtin_huge_valf();
   const float gx = fmaxf(fmaxf(lo.x - q.x, q.x - hi.x), 0.0f);
   const float gy = fmaxf(fmaxf(lo.y - q.y, q.y - hi.y), 0.0f);
   const float gz = fmaxf(fmaxf(lo.z - q.z, q.z - hi.z), 0.0f);
@@ -101,7 +105,7 @@ __device__ __forceinline__ SegView load_seg(const Prep &pr, int64_t s) {
 // rounded toward zero, R is rounded up, and the final (1 - 2^-20) factor
 // covers the remaining float32 roundings.
 __device__ __forceinline__ float seg_lb(const SegView &v, const QueryPoint &q, const float sf[4]) {
-  if ((double)v.r0.w >= q.thr) return __builtin_huge_valf();
+  if (v.r0.w >= q.thrf) return __builtin_huge_valf();
   const float abx = v.r1.x, aby = v.r1.y, abz = v.r1.z;
   const float apx = q.x - v.r0.x, apy = q.y - v.r0.y, apz = q.z - v.r0.z;
   const float dot = sf[0] * (apx * abx) + sf[1] * (apy * aby) + sf[2] * (apz * abz);

@@ -22,6 +22,7 @@ struct BatchLaunch {
   int32_t chunk;
   int32_t waves_per_block;
   int32_t stats;  // some item collects statistics
+  int32_t gka;    // some item averages values over its neighbours
   int64_t grid;
   int64_t total_q;
   int64_t total_seg;
@@ -49,6 +50,9 @@ hipError_t launch_query(const IndexDesc &ix, const Prep &pr, const QueryArgs &a,
 hipError_t launch_brute(const IndexDesc &ix, const QueryArgs &a, const tnn_points &qs,
                         int waves_per_block, int32_t *out_idx, double *out_dist, hipStream_t st,
                         const double *query_scale = nullptr);
+hipError_t launch_gka(const int32_t *idx, const double *dist, int64_t nq, int k,
+                      const float *values, int n_comp, int64_t n_points, double *out,
+                      hipStream_t st);
 size_t mixed_scratch_bytes(int64_t n_points, int64_t n_queries, int k);
 hipError_t launch_mixed_brute(const IndexDesc &ix, const QueryArgs &a, const tnn_points &qs,
                               int32_t *out_idx, double *out_dist, void *scratch, hipStream_t st);

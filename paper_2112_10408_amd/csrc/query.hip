@@ -3,6 +3,7 @@
 #include <mutex>
 
 #include "bounds.h"
+#include "gka.h"
 #include "query.h"
 
 namespace tnn {
@@ -187,7 +188,7 @@ struct Searcher {
         pid = ix.pid[p];
       }
       const double d = exact_dist(a.s, q.x, q.y, q.z, q.t, pv.x, pv.y, pv.z, pv.w);
-      const bool valid = ok && (double)pv.w < q.thr;
+      const bool valid = ok && pv.w < q.thrf;
       st.points += (uint32_t)__popcll(ballot(ok));
       const bool gate = valid && tk.admits(d, pid);
       const uint64_t gm = ballot(gate);
@@ -283,36 +284,49 @@ __device__ __forceinline__ void flush_stats(unsigned long long *stats, const Wav
 //            continues from the k-th found (or a 16x larger radius).
 // Rounds only widen tau; a segment is scanned in the first round whose
 // radius reaches its bound, so no point enters the top-k twice.
-template <bool PerQ, bool Stats>
+// A query's inputs: its point and (learned radius) predicted k-th distance,
+// read ahead of its search so that the loads of the next query of a ticket
+// are in flight while the current one runs.
+struct QueryIn {
+  float x, y, z, t, r2;
+};
+
+__device__ __forceinline__ QueryIn load_query_in(const float *qx, const float *qy,
+                                                 const float *qz, const float *qt,
+                                                 const QueryArgs &a, int64_t qi) {
+  QueryIn in;
+  in.x = qx[qi];
+  in.y = qy[qi];
+  in.z = qz[qi];
+  in.t = qt[qi];
+  in.r2 = (a.flags & TNN_LEARNED) ? a.radius2[qi] : 0.0f;
+  return in;
+}
+
+template <bool PerQ, bool Stats, bool Gka>
 __device__ __forceinline__ void answer_query_with(const IndexDesc &ix, const Prep &pr,
-                                                  const QueryArgs &a, const float *qx,
-                                                  const float *qy, const float *qz,
-                                                  const float *qt, int64_t qi, int32_t *out_idx,
-                                                  double *out_dist, const float *box,
-                                                  const float *sbox) {
+                                                  const QueryArgs &a, const QueryIn &in,
+                                                  int64_t qi, int32_t *out_idx, double *out_dist,
+                                                  const float *box, const float *sbox) {
   Searcher<PerQ, Stats> se(ix, pr, a);
   se.lane = lane_id();
   se.box = box;
   se.sbox = sbox;
   se.spi_shift = 31 - __clz(ix.kpad);
-  se.q = make_query(qx[qi], qy[qi], qz[qi], qt[qi], a.t_window);
+  se.q = make_query(in.x, in.y, in.z, in.t, a.t_window);
   se.tk.init(a.k, a.inf);
   se.st = WaveStats<Stats>{};
   const int nb = ix.n_blocks;
   const int64_t S = ix.n_seg;
   // scale of the data, used to grow the radius when nothing is known yet
-  double diag2 = 0.0;
-  for (int f = 0; f < 4; ++f) {
-    const double e = (double)ix.hi[f] - (double)ix.lo[f];
-    diag2 += a.s[f] * e * e;
-  }
-  const double floor_tau = fmax(diag2 * 0x1p-24, 1e-300);
+  // (set by the host for the shared scales)
+  const double floor_tau = PerQ ? radius_floor(ix.lo, ix.hi, a.s) : a.floor_tau;
 
   int seed_block = -1;
   uint64_t seed_mask = 0;
   double tau;
   bool learned = (a.flags & TNN_LEARNED) != 0;
-  double r2 = learned ? (double)a.radius2[qi] : 0.0;
+  double r2 = learned ? (double)in.r2 : 0.0;
   if (learned && !(r2 > 0.0 && r2 < kInf)) learned = false;  // no usable prediction
   if (learned) {
     tau = r2;
@@ -402,6 +416,12 @@ write_out:
     out_idx[qi * a.k + se.lane] = se.tk.id == kNoId ? -1 : se.tk.id;
     out_dist[qi * a.k + se.lane] = se.tk.d;
   }
+  // Gaussian kernel averaging straight from the registers of the top-k (a
+  // kernel instance of its own: its registers would cost the plain search
+  // occupancy)
+  if constexpr (Gka)
+    gka_context_average(se.lane < a.k && se.tk.id != kNoId && se.tk.d < kInf, se.tk.id, se.tk.d,
+                        a.gka_values, a.gka_comp, a.gka_out + qi * a.gka_comp);
   flush_stats(a.stats, se.st);
 }
 
@@ -428,13 +448,15 @@ __device__ __forceinline__ void write_bad_scale_row(const QueryArgs &a, int64_t 
     out_idx[qi * a.k + lane] = -1;
     out_dist[qi * a.k + lane] = a.inf - a.inf;  // NaN (no 64-bit literal)
   }
+  if (a.gka_values)  // no context: the averaging's NaN row
+    gka_context_average(false, 0, 0.0, a.gka_values, a.gka_comp, a.gka_out + qi * a.gka_comp);
+  // (cold path: the scale check fails before any search state exists)
   if (a.stats && lane == 0) atomicAdd(a.stats + TNN_STAT_QUERIES, 1ull);
 }
 
-template <bool PerQ, bool Stats>
+template <bool PerQ, bool Stats, bool Gka>
 __device__ __forceinline__ void answer_query(const IndexDesc &ix, const Prep &pr,
-                                             const QueryArgs &a, const float *qx, const float *qy,
-                                             const float *qz, const float *qt, int64_t qi,
+                                             const QueryArgs &a, const QueryIn &in, int64_t qi,
                                              int32_t *out_idx, double *out_dist,
                                              const float *box, const float *sbox,
                                              const double *qscale) {
@@ -444,15 +466,16 @@ __device__ __forceinline__ void answer_query(const IndexDesc &ix, const Prep &pr
       write_bad_scale_row(a, qi, out_idx, out_dist);
       return;
     }
-    answer_query_with<true, Stats>(ix, pr, aq, qx, qy, qz, qt, qi, out_idx, out_dist, box, sbox);
+    answer_query_with<true, Stats, Gka>(ix, pr, aq, in, qi, out_idx, out_dist, box, sbox);
   } else {
-    answer_query_with<false, Stats>(ix, pr, a, qx, qy, qz, qt, qi, out_idx, out_dist, box, sbox);
+    answer_query_with<false, Stats, Gka>(ix, pr, a, in, qi, out_idx, out_dist, box, sbox);
   }
 }
 
 // qscale (last, so the other arguments keep their places): per-query scales
 // when PerQ, else unused.  Stats: the call collects statistics (a.stats set).
-template <bool PerQ, bool Stats>
+// Gka: the call averages values over each query's neighbours (a.gka_values).
+template <bool PerQ, bool Stats, bool Gka>
 __global__ __launch_bounds__(512) void tnn_query_kernel(IndexDesc ix, Prep pr, QueryArgs a,
                                                         const float *qx, const float *qy,
                                                         const float *qz, const float *qt,
@@ -460,8 +483,8 @@ __global__ __launch_bounds__(512) void tnn_query_kernel(IndexDesc ix, Prep pr, Q
                                                         double *out_dist, const double *qscale) {
   const int64_t qi = (int64_t)blockIdx.x * (blockDim.x >> 6) + uniform_i((int)(threadIdx.x >> 6));
   if (qi >= nq) return;
-  answer_query<PerQ, Stats>(ix, pr, a, qx, qy, qz, qt, qi, out_idx, out_dist, ix.box, ix.sbox,
-                            qscale);
+  answer_query<PerQ, Stats, Gka>(ix, pr, a, load_query_in(qx, qy, qz, qt, a, qi), qi, out_idx,
+                                 out_dist, ix.box, ix.sbox, qscale);
 }
 
 // Same search with the block boxes staged once per workgroup in LDS (small
@@ -471,10 +494,11 @@ __global__ __launch_bounds__(512) void tnn_query_kernel(IndexDesc ix, Prep pr, Q
 // BoxesInLds: the block boxes fit in LDS too (the superblock boxes always
 // do); a template argument so that every box read is a plain LDS or global
 // access rather than a generic one.  PerQ: every query has its own scales.
-// Stats: the call collects statistics (a.stats set).  The per-query-scale
-// instances are compiled for 5 waves per SIMD (96 VGPRs; 113 and 4 waves
-// otherwise); the shared-scale ones fit 6 as they are (75 VGPRs).
-template <bool BoxesInLds, bool PerQ, bool Stats>
+// Stats: the call collects statistics (a.stats set).  Gka: the call averages
+// values over each query's neighbours.  The per-query-scale instances are
+// compiled for 5 waves per SIMD (96 VGPRs; 113 and 4 waves otherwise); the
+// shared-scale ones fit 7 as they are (68 VGPRs).
+template <bool BoxesInLds, bool PerQ, bool Stats, bool Gka>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(PerQ ? 5 : 1))) void
 tnn_query_lds_kernel(
     IndexDesc ix, Prep pr, QueryArgs a, const float *qx, const float *qy, const float *qz,
@@ -510,8 +534,8 @@ tnn_query_lds_kernel(
       if (base >= hi) break;
       const int64_t end = base + step < hi ? base + step : hi;
       for (int64_t qi = base; qi < end; ++qi)
-        answer_query<PerQ, Stats>(ix, pr, a, qx, qy, qz, qt, qi, out_idx, out_dist, box, s_box,
-                                  qscale);
+        answer_query<PerQ, Stats, Gka>(ix, pr, a, load_query_in(qx, qy, qz, qt, a, qi), qi,
+                                       out_idx, out_dist, box, s_box, qscale);
     }
   }
 #else
@@ -519,7 +543,8 @@ tnn_query_lds_kernel(
   const int64_t stride = (int64_t)gridDim.x * wpb;
   for (int64_t qi = (int64_t)blockIdx.x * wpb + uniform_i((int)(threadIdx.x >> 6)); qi < nq;
        qi += stride)
-    answer_query<PerQ, Stats>(ix, pr, a, qx, qy, qz, qt, qi, out_idx, out_dist, box, s_box, qscale);
+    answer_query<PerQ, Stats, Gka>(ix, pr, a, load_query_in(qx, qy, qz, qt, a, qi), qi, out_idx,
+                                   out_dist, box, s_box, qscale);
 #endif
 }
 
@@ -574,7 +599,7 @@ __global__ __launch_bounds__(512) void brute_kernel(IndexDesc ix, QueryArgs a, c
     for (int j = 0; j < Q; ++j) {
       const double d = exact_dist(s, q[j].x, q[j].y, q[j].z, q[j].t, pv.x, pv.y, pv.z, pv.w);
       // bitwise, not short-circuit: no divergent branch in the inner loop
-      const bool gate = ok & ((double)pv.w < q[j].thr) & tk[j].admits(d, pid);
+      const bool gate = ok & (pv.w < q[j].thrf) & tk[j].admits(d, pid);
       const uint64_t gm = ballot(gate);
       if (gm) {
         tk[j].offer(gm, d, pid);
@@ -670,7 +695,7 @@ __global__ void batch_prep_kernel(const BatchItemDev *items, const int64_t *seg_
 // an item stamps its tick.  Every wave leaves once every slice is used up.
 // Stats: some item collects statistics.  Compiled for 5 waves per SIMD (96
 // VGPRs, no spills; left to itself the compiler takes 102 and 4 waves).
-template <bool Stats>
+template <bool Stats, bool Gka>
 __global__ __launch_bounds__(512, 5) void batch_kernel(const BatchItemDev *items,
                                                     const int64_t *qprefix, const int32_t *order,
                                                     int n, int chunk,
@@ -697,9 +722,10 @@ __global__ __launch_bounds__(512, 5) void batch_kernel(const BatchItemDev *items
         const BatchItemDev &it = items[item];
         const int64_t run = item_end - gq;
         for (; gq < item_end; ++gq)
-          answer_query<false, Stats>(it.ix, it.pr, it.a, it.qx, it.qy, it.qz, it.qt,
-                                     gq - qprefix[pos], it.out_idx, it.out_dist, it.ix.box,
-                                     it.ix.sbox, nullptr);
+          answer_query<false, Stats, Gka>(
+              it.ix, it.pr, it.a,
+              load_query_in(it.qx, it.qy, it.qz, it.qt, it.a, gq - qprefix[pos]),
+              gq - qprefix[pos], it.out_idx, it.out_dist, it.ix.box, it.ix.sbox, nullptr);
         if (lane == 0) {
           const unsigned d = atomicAdd(&done[item], (unsigned)run) + (unsigned)run;
           if ((int64_t)d == it.nq) ticks[item + 1] = wall_clock64();
@@ -721,9 +747,12 @@ hipError_t launch_batch(const BatchLaunch &bl, hipStream_t st) {
     if (e != hipSuccess) return e;
   }
   if (bl.total_q > 0) {
-    hipLaunchKernelGGL(bl.stats ? batch_kernel<true> : batch_kernel<false>, dim3((unsigned)bl.grid), dim3(bl.waves_per_block * kWave), 0,
-                       st, bl.items, bl.qprefix, bl.order, bl.n, bl.chunk, bl.counter, bl.done,
-                       bl.ticks);
+    using BK = decltype(&batch_kernel<true, true>);
+    static const BK bkerns[4] = {batch_kernel<false, false>, batch_kernel<true, false>,
+                                 batch_kernel<false, true>, batch_kernel<true, true>};
+    hipLaunchKernelGGL(bkerns[(bl.stats ? 1 : 0) + (bl.gka ? 2 : 0)], dim3((unsigned)bl.grid),
+                       dim3(bl.waves_per_block * kWave), 0, st, bl.items, bl.qprefix, bl.order,
+                       bl.n, bl.chunk, bl.counter, bl.done, bl.ticks);
     e = hipGetLastError();
   }
   return e;
@@ -791,13 +820,15 @@ hipError_t launch_query(const IndexDesc &ix, const Prep &pr, const QueryArgs &a,
     const int in_lds = sl + bl <= kLdsBoxBytes ? 1 : 0;
     const size_t lds = in_lds ? sl + bl : sl;
     const bool perq = query_scale != nullptr;
-    using Kern = decltype(&tnn_query_lds_kernel<true, true, true>);
-    static const Kern kerns[8] = {
-        tnn_query_lds_kernel<false, false, false>, tnn_query_lds_kernel<true, false, false>,
-        tnn_query_lds_kernel<false, true, false>,  tnn_query_lds_kernel<true, true, false>,
-        tnn_query_lds_kernel<false, false, true>,  tnn_query_lds_kernel<true, false, true>,
-        tnn_query_lds_kernel<false, true, true>,   tnn_query_lds_kernel<true, true, true>};
-    const int variant = in_lds + (perq ? 2 : 0) + (a.stats ? 4 : 0);
+    using Kern = decltype(&tnn_query_lds_kernel<true, true, true, true>);
+#define TNN_LDS_KERNELS(G)                                                                    \
+  tnn_query_lds_kernel<false, false, false, G>, tnn_query_lds_kernel<true, false, false, G>, \
+      tnn_query_lds_kernel<false, true, false, G>, tnn_query_lds_kernel<true, true, false, G>, \
+      tnn_query_lds_kernel<false, false, true, G>, tnn_query_lds_kernel<true, false, true, G>, \
+      tnn_query_lds_kernel<false, true, true, G>, tnn_query_lds_kernel<true, true, true, G>
+    static const Kern kerns[16] = {TNN_LDS_KERNELS(false), TNN_LDS_KERNELS(true)};
+#undef TNN_LDS_KERNELS
+    const int variant = in_lds + (perq ? 2 : 0) + (a.stats ? 4 : 0) + (a.gka_values ? 8 : 0);
     const Kern kern = kerns[variant];
     const int per_cu = resident_per_cu(variant, waves_per_block, lds, [&](int *n) {
       return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, kern, waves_per_block * kWave, lds);
@@ -808,8 +839,14 @@ hipError_t launch_query(const IndexDesc &ix, const Prep &pr, const QueryArgs &a,
                        qs.x, qs.y, qs.z, qs.t, qs.n, out_idx, out_dist, query_scale);
     return hipGetLastError();
   }
-  const auto kern = query_scale ? (a.stats ? tnn_query_kernel<true, true> : tnn_query_kernel<true, false>)
-                                : (a.stats ? tnn_query_kernel<false, true> : tnn_query_kernel<false, false>);
+  using GKern = decltype(&tnn_query_kernel<true, true, true>);
+  static const GKern gkerns[8] = {
+      tnn_query_kernel<false, false, false>, tnn_query_kernel<true, false, false>,
+      tnn_query_kernel<false, true, false>,  tnn_query_kernel<true, true, false>,
+      tnn_query_kernel<false, false, true>,  tnn_query_kernel<true, false, true>,
+      tnn_query_kernel<false, true, true>,   tnn_query_kernel<true, true, true>};
+  const GKern kern =
+      gkerns[(query_scale ? 1 : 0) + (a.stats ? 2 : 0) + (a.gka_values ? 4 : 0)];
   hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(waves_per_block * kWave), 0, st, ix, pr, a,
                      qs.x, qs.y, qs.z, qs.t, qs.n, out_idx, out_dist, query_scale);
   return hipGetLastError();

@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstring>
 
+#include "host.h"
 #include "tnn_internal.h"
 #include "wave.h"
 
@@ -261,10 +262,17 @@ __global__ __launch_bounds__(64 * kInferWaves) void infer_kernel(
 // Forward and backward over kTrainBlock samples per workgroup; writes this
 // workgroup's un-normalised gradient sum (2 r dout/dtheta) and its loss
 // partials (sum r^2, count) to partial[blockIdx].
+// Sample b of the batch is samples[order[first + b]] (order: a permutation of
+// the samples, device int32), or samples[first + b] without one.
+__device__ __forceinline__ int64_t sample_of(const int32_t *order, int64_t first, int64_t b) {
+  return order ? (int64_t)order[first + b] : first + b;
+}
+
 __global__ __launch_bounds__(kTrainBlock) void fwd_bwd_kernel(const tnn_radius_model *m,
                                                               tnn_points smp, const double *dist,
-                                                              int32_t k, int64_t first,
-                                                              int64_t batch, float *partial) {
+                                                              const int32_t *order, int32_t k,
+                                                              int64_t first, int64_t batch,
+                                                              float *partial) {
   __shared__ float W[NP];
   __shared__ float F[kTrainBlock][NI];
   __shared__ float H1[kTrainBlock][H + 1];   // h1
@@ -280,7 +288,7 @@ __global__ __launch_bounds__(kTrainBlock) void fwd_bwd_kernel(const tnn_radius_m
   float go = 0.0f, r2 = 0.0f;
   float f[NI] = {};
   if (b < batch) {
-    const int64_t si = first + b;
+    const int64_t si = sample_of(order, first, b);
     features(m, smp.x[si], smp.y[si], smp.z[si], smp.t[si], f);
     const double dk = dist[si * k + (k - 1)];
     const bool lab = dk > 0.0 && dk < __builtin_huge_val();
@@ -351,7 +359,7 @@ __global__ __launch_bounds__(kTrainBlock) void fwd_bwd_kernel(const tnn_radius_m
       l += R2[s];
       const int64_t bs = (int64_t)blockIdx.x * kTrainBlock + s;
       if (bs < batch) {
-        const double dk = dist[(first + bs) * k + (k - 1)];
+        const double dk = dist[sample_of(order, first, bs) * k + (k - 1)];
         c += (dk > 0.0 && dk < __builtin_huge_val()) ? 1.0f : 0.0f;
       }
     }
@@ -393,6 +401,132 @@ __global__ void adam_kernel(float *params, float *mom, const float *grad, int st
   params[p] -= lr * mh / (sqrtf(vh) + eps);
 }
 
+// ---------------------------------------------------------------------------
+// Training order: a permutation of [0, n) drawn from a seed, element i being
+// a keyed 4-round Feistel permutation of [0, 4^h) (4^h >= n, the smallest
+// such) walked along its cycle until it lands below n (cycle walking keeps
+// it a bijection on [0, n)).  The round function is SplitMix64 of the seed,
+// the round and the half.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t feistel(uint64_t v, int h, uint64_t seed) {
+  const uint64_t mask = (1ull << h) - 1;
+  uint64_t l = v >> h, r = v & mask;
+#pragma unroll
+  for (int round = 0; round < 4; ++round) {
+    const uint64_t f = splitmix64(seed ^ ((uint64_t)(round + 1) << 56) ^ r) & mask;
+    const uint64_t nl = r;
+    r = l ^ f;
+    l = nl;
+  }
+  return (l << h) | r;
+}
+
+__global__ void shuffle_kernel(int64_t n, int h, uint64_t seed, int32_t *order) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  // each step moves along the cycle of i; the first value below n ends the
+  // walk (the cycle holds i itself, so the walk is finite)
+  uint64_t v = (uint64_t)i;
+  do {
+    v = feistel(v, h, seed);
+  } while (v >= (uint64_t)n);
+  order[i] = (int32_t)v;
+}
+
+// ---------------------------------------------------------------------------
+// Safety factor of the predicted radius: alpha = exp(x_q), x_q the quantile q
+// (linear interpolation between order statistics, position (m - 1) q) of the
+// log-residuals 0.5 log d_k - out over the m samples whose k-th distance is
+// finite and positive and whose residual is finite.  Residuals are binary64,
+// kept as order-preserving 64-bit keys; one workgroup selects the two order
+// statistics by an 8-bit radix select.
+// ---------------------------------------------------------------------------
+constexpr unsigned long long kNoKey = ~0ull;  // above every finite value's key
+constexpr int kSelectThreads = 1024;
+
+__device__ __forceinline__ unsigned long long order_key(double v) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  return (b >> 63) ? ~b : (b | (1ull << 63));
+}
+
+__device__ __forceinline__ double key_value(unsigned long long k) {
+  const unsigned long long b = (k >> 63) ? (k & ~(1ull << 63)) : ~k;
+  return __longlong_as_double((long long)b);
+}
+
+__global__ void calib_keys_kernel(const double *dist, int32_t k, const float *logr, int64_t n,
+                                  unsigned long long *keys) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double dk = dist[i * k + (k - 1)];
+  unsigned long long key = kNoKey;
+  if (dk > 0.0 && dk < __builtin_huge_val()) {
+    const double r = 0.5 * log(dk) - (double)logr[i];
+    if (r - r == 0.0) key = order_key(r);  // finite
+  }
+  keys[i] = key;
+}
+
+// The r-th smallest (0-based) of the keys other than kNoKey; every thread of
+// the (single) workgroup calls it.
+__device__ unsigned long long select_key(const unsigned long long *keys, int64_t n, long long r,
+                                         unsigned *hist, unsigned long long *shared) {
+  unsigned long long prefix = 0, mask = 0;
+  for (int shift = 56; shift >= 0; shift -= 8) {
+    for (int i = threadIdx.x; i < 256; i += blockDim.x) hist[i] = 0;
+    __syncthreads();
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+      const unsigned long long key = keys[i];
+      if (key != kNoKey && (key & mask) == prefix) atomicAdd(&hist[(key >> shift) & 255], 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      long long below = 0;
+      int d = 0;
+      for (; d < 255; ++d) {
+        if (below + (long long)hist[d] > r) break;
+        below += hist[d];
+      }
+      shared[0] = prefix | ((unsigned long long)d << shift);
+      shared[1] = (unsigned long long)(r - below);
+    }
+    __syncthreads();
+    prefix = shared[0];
+    r = (long long)shared[1];
+    mask |= 255ull << shift;
+    __syncthreads();
+  }
+  return prefix;
+}
+
+__global__ __launch_bounds__(kSelectThreads) void calib_select_kernel(
+    const unsigned long long *keys, int64_t n, double quantile, float *alpha) {
+  __shared__ unsigned hist[256];
+  __shared__ unsigned long long shared[2];
+  __shared__ unsigned long long count;
+  if (threadIdx.x == 0) count = 0;
+  __syncthreads();
+  unsigned long long mine = 0;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) mine += keys[i] != kNoKey ? 1 : 0;
+  atomicAdd(&count, mine);
+  __syncthreads();
+  const long long m = (long long)count;
+  if (m == 0) {
+    if (threadIdx.x == 0) *alpha = 1.0f;
+    return;
+  }
+  const double h = (double)(m - 1) * quantile;
+  const long long lo = (long long)floor(h);
+  const double frac = h - (double)lo;
+  const double x_lo = key_value(select_key(keys, n, lo, hist, shared));
+  const double x_hi = lo + 1 < m ? key_value(select_key(keys, n, lo + 1, hist, shared)) : x_lo;
+  if (threadIdx.x == 0) *alpha = (float)exp(x_lo + frac * (x_hi - x_lo));
+}
+
+size_t calib_scratch(int64_t n) {
+  return align_up((size_t)n * 8) + 2 * align_up((size_t)n * 4) + 256;
+}
+
 size_t train_scratch(int64_t batch) {
   const int64_t nblk = (batch + kTrainBlock - 1) / kTrainBlock;
   return align_up((size_t)nblk * (NP + 3) * sizeof(float)) + align_up(NP * sizeof(float)) + 256;
@@ -408,9 +542,9 @@ bool pts_ok(const tnn_points &p) {
   return p.n >= 0 && (p.n == 0 || (p.x && p.y && p.z && p.t));
 }
 
-tnn_status launch_grad(const void *d_model, tnn_points smp, const double *d_dist, int32_t k,
-                       int64_t first, int64_t batch, float *grad, float *loss, void *scratch,
-                       size_t bytes, hipStream_t st) {
+tnn_status launch_grad(const void *d_model, tnn_points smp, const double *d_dist,
+                       const int32_t *d_order, int32_t k, int64_t first, int64_t batch,
+                       float *grad, float *loss, void *scratch, size_t bytes, hipStream_t st) {
   if (!d_model || !pts_ok(smp) || !d_dist || k < 1 || k > kMaxK || first < 0 || batch < 1 ||
       first + batch > smp.n || !grad)
     return TNN_E_ARG;
@@ -418,8 +552,8 @@ tnn_status launch_grad(const void *d_model, tnn_points smp, const double *d_dist
   const int nblk = (int)((batch + kTrainBlock - 1) / kTrainBlock);
   float *partial = static_cast<float *>(scratch);
   hipLaunchKernelGGL(fwd_bwd_kernel, dim3(nblk), dim3(kTrainBlock), 0, st,
-                     static_cast<const tnn_radius_model *>(d_model), smp, d_dist, k, first, batch,
-                     partial);
+                     static_cast<const tnn_radius_model *>(d_model), smp, d_dist, d_order, k,
+                     first, batch, partial);
   TNN_HIP_CHECK(hipGetLastError());
   hipLaunchKernelGGL(reduce_kernel, dim3((NP + 255) / 256), dim3(256), 0, st, partial, nblk, grad,
                      loss);
@@ -466,24 +600,26 @@ tnn_status tnn_radius_train_workspace(int64_t batch, size_t *bytes) {
 }
 
 tnn_status tnn_radius_grad(const void *d_model, tnn_points samples, const double *d_dist,
-                           int32_t k, int64_t first, int64_t batch, float *d_grad, float *d_loss,
-                           void *d_scratch, size_t scratch_bytes, void *stream) {
-  return launch_grad(d_model, samples, d_dist, k, first, batch, d_grad, d_loss, d_scratch,
-                     scratch_bytes, static_cast<hipStream_t>(stream));
+                           const int32_t *d_order, int32_t k, int64_t first, int64_t batch,
+                           float *d_grad, float *d_loss, void *d_scratch, size_t scratch_bytes,
+                           void *stream) {
+  return launch_grad(d_model, samples, d_dist, d_order, k, first, batch, d_grad, d_loss,
+                     d_scratch, scratch_bytes, static_cast<hipStream_t>(stream));
 }
 
 tnn_status tnn_radius_train_step(void *d_model, float *d_adam, tnn_points samples,
-                                 const double *d_dist, int32_t k, int64_t first, int64_t batch,
-                                 int32_t step, float lr, float *d_loss, void *d_scratch,
-                                 size_t scratch_bytes, void *stream) {
+                                 const double *d_dist, const int32_t *d_order, int32_t k,
+                                 int64_t first, int64_t batch, int32_t step, float lr,
+                                 float *d_loss, void *d_scratch, size_t scratch_bytes,
+                                 void *stream) {
   if (!d_adam || step < 1 || !(lr > 0.0f) || !std::isfinite(lr)) return TNN_E_ARG;
   if (!d_scratch || scratch_bytes < train_scratch(batch > 0 ? batch : 1)) return TNN_E_WORKSPACE;
   hipStream_t st = static_cast<hipStream_t>(stream);
   const int64_t nblk = (batch + kTrainBlock - 1) / kTrainBlock;
   float *grad = reinterpret_cast<float *>(static_cast<char *>(d_scratch) +
                                           align_up((size_t)nblk * (NP + 3) * sizeof(float)));
-  const tnn_status s = launch_grad(d_model, samples, d_dist, k, first, batch, grad, d_loss,
-                                   d_scratch, scratch_bytes, st);
+  const tnn_status s = launch_grad(d_model, samples, d_dist, d_order, k, first, batch, grad,
+                                   d_loss, d_scratch, scratch_bytes, st);
   if (s != TNN_OK) return s;
   hipLaunchKernelGGL(adam_kernel, dim3((NP + 255) / 256), dim3(256), 0, st,
                      static_cast<tnn_radius_model *>(d_model)->params, d_adam, grad, step, lr);
@@ -514,6 +650,83 @@ tnn_status tnn_radius_infer(const void *d_model, tnn_points queries, float alpha
                      static_cast<hipStream_t>(stream),
                      static_cast<const tnn_radius_model *>(d_model), queries, alpha, d_radius2,
                      d_logr);
+  TNN_HIP_CHECK(hipGetLastError());
+  return TNN_OK;
+}
+
+static host::CkptDims ckpt_dims() {
+  return host::CkptDims{(uint32_t)H, (uint32_t)NI, (uint32_t)G, (uint32_t)SXY, (uint32_t)ST,
+                        (uint32_t)NP};
+}
+
+tnn_status tnn_radius_checkpoint_bytes(size_t *bytes) {
+  if (!bytes) return TNN_E_ARG;
+  *bytes = host::kCkptHeaderBytes + sizeof(tnn_radius_model);
+  return TNN_OK;
+}
+
+tnn_status tnn_radius_model_save(const void *d_model, void *h_buf, size_t bytes, void *stream) {
+  if (!d_model || !h_buf) return TNN_E_ARG;
+  const size_t mb = sizeof(tnn_radius_model);
+  if (bytes < host::kCkptHeaderBytes + mb) return TNN_E_WORKSPACE;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  char *b = static_cast<char *>(h_buf);
+  TNN_HIP_CHECK(hipMemcpyAsync(b + host::kCkptHeaderBytes, d_model, mb, hipMemcpyDeviceToHost, st));
+  TNN_HIP_CHECK(hipStreamSynchronize(st));
+  host::ckpt_write_header(b, mb, ckpt_dims(), host::fnv1a64(b + host::kCkptHeaderBytes, mb));
+  return TNN_OK;
+}
+
+tnn_status tnn_radius_model_load(const void *h_buf, size_t bytes, void *d_model, void *stream) {
+  if (!d_model || !h_buf) return TNN_E_ARG;
+  const size_t mb = sizeof(tnn_radius_model);
+  if (host::ckpt_check(h_buf, bytes, mb, ckpt_dims()) != 0) return TNN_E_FORMAT;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  TNN_HIP_CHECK(hipMemcpyAsync(d_model, static_cast<const char *>(h_buf) + host::kCkptHeaderBytes,
+                               mb, hipMemcpyHostToDevice, st));
+  TNN_HIP_CHECK(hipStreamSynchronize(st));
+  return TNN_OK;
+}
+
+tnn_status tnn_radius_shuffle(int64_t n, uint64_t seed, int32_t *d_order, void *stream) {
+  if (n < 0 || n > INT32_MAX || (n > 0 && !d_order)) return TNN_E_ARG;
+  if (n == 0) return TNN_OK;
+  int h = 1;
+  while ((1ull << (2 * h)) < (uint64_t)n) ++h;
+  hipLaunchKernelGGL(shuffle_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
+                     static_cast<hipStream_t>(stream), n, h, seed, d_order);
+  TNN_HIP_CHECK(hipGetLastError());
+  return TNN_OK;
+}
+
+tnn_status tnn_radius_calibrate_workspace(int64_t n_samples, size_t *bytes) {
+  if (!bytes || n_samples < 0) return TNN_E_ARG;
+  *bytes = calib_scratch(n_samples);
+  return TNN_OK;
+}
+
+tnn_status tnn_radius_calibrate(const void *d_model, tnn_points samples, const double *d_dist,
+                                int32_t k, double quantile, float *d_alpha, void *d_scratch,
+                                size_t scratch_bytes, void *stream) {
+  if (!d_model || !pts_ok(samples) || (samples.n > 0 && !d_dist) || k < 1 || k > kMaxK ||
+      !d_alpha || !(quantile >= 0.0 && quantile <= 1.0))
+    return TNN_E_ARG;
+  const int64_t n = samples.n;
+  if (!d_scratch || scratch_bytes < calib_scratch(n)) return TNN_E_WORKSPACE;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  char *b = static_cast<char *>(d_scratch);
+  unsigned long long *keys = reinterpret_cast<unsigned long long *>(b);
+  float *logr = reinterpret_cast<float *>(b + align_up((size_t)n * 8));
+  float *r2 = reinterpret_cast<float *>(b + align_up((size_t)n * 8) + align_up((size_t)n * 4));
+  if (n > 0) {
+    const tnn_status s = tnn_radius_infer(d_model, samples, 1.0f, r2, logr, stream);
+    if (s != TNN_OK) return s;
+    hipLaunchKernelGGL(calib_keys_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
+                       d_dist, k, logr, n, keys);
+    TNN_HIP_CHECK(hipGetLastError());
+  }
+  hipLaunchKernelGGL(calib_select_kernel, dim3(1), dim3(kSelectThreads), 0, st, keys, n, quantile,
+                     d_alpha);
   TNN_HIP_CHECK(hipGetLastError());
   return TNN_OK;
 }

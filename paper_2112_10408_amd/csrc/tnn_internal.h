@@ -62,6 +62,11 @@ struct QueryArgs {
   int32_t seed_segments;
   const float *radius2;
   unsigned long long *stats;
+  double floor_tau;    // smallest search radius a growing round starts from (radius_floor)
+  // Gaussian kernel averaging epilogue (gka_values null: none)
+  const float *gka_values;
+  int32_t gka_comp;
+  double *gka_out;
 };
 
 inline size_t align_up(size_t v, size_t a = 256) { return (v + a - 1) / a * a; }
@@ -80,6 +85,20 @@ __host__ __device__ inline bool scaled_box_ok(const float lo[4], const float hi[
     n2 += s[f] * h * h;
   }
   return n2 < kMaxScaledNorm;
+}
+
+// Scale of the data for a metric: 2^-24 of the scaled squared diagonal of the
+// index box (at least 1e-300), the radius a round grows from when a query has
+// found nothing yet.
+__host__ __device__ inline double radius_floor(const float lo[4], const float hi[4],
+                                               const double s[4]) {
+  double diag2 = 0.0;
+  for (int f = 0; f < 4; ++f) {
+    const double e = (double)hi[f] - (double)lo[f];
+    diag2 += s[f] * e * e;
+  }
+  const double v = diag2 * 0x1p-24;
+  return v > 1e-300 ? v : 1e-300;
 }
 
 }  // namespace tnn

@@ -78,7 +78,7 @@ def tnn_build_segments(x, y, z, t, traj_offsets, seg_len, order_scale=(1.0, 1.0,
 
 
 def make_params(scale, t_window, k, flags=0, seed_segments=0, waves_per_block=0, radius2=None,
-                stats=None, query_scale=None):
+                stats=None, query_scale=None, gka_values=None, gka_out=None):
     p = TnnQueryParams()
     for i in range(4):
         p.scale[i] = float(scale[i])
@@ -95,6 +95,15 @@ def make_params(scale, t_window, k, flags=0, seed_segments=0, waves_per_block=0,
         if not query_scale.is_contiguous():
             raise ValueError("query_scale must be contiguous")
     p.d_query_scale = _ptr(query_scale) if query_scale is not None else None
+    if gka_values is not None:
+        if gka_values.dtype != torch.float32 or gka_values.dim() != 2 or not gka_values.is_contiguous():
+            raise ValueError("gka_values must be a contiguous float32 [n_points, n_comp] device tensor")
+        if gka_out is None or gka_out.dtype != torch.float64 or not gka_out.is_contiguous() or \
+                gka_out.dim() != 2 or gka_out.shape[1] != gka_values.shape[1]:
+            raise ValueError("gka_out must be a contiguous float64 [n_queries, n_comp] device tensor")
+        p.d_gka_values = _ptr(gka_values)
+        p.d_gka_out = _ptr(gka_out)
+        p.gka_comp = int(gka_values.shape[1])
     return p
 
 
@@ -119,16 +128,22 @@ def stats_dict(stats):
 
 def tnn_query(index, qx, qy, qz, qt, scale, t_window, k, flags=0, seed_segments=0,
               waves_per_block=0, radius2=None, stats=None, out=None, scratch=None,
-              query_scale=None):
+              query_scale=None, gka_values=None, gka_out=None):
     """Returns (idx int32 [nq, k], dist float64 [nq, k]) device tensors.
     query_scale: optional float64 [nq, 4] device tensor of per-query scales
-    (replaces `scale`, which must still be valid)."""
+    (replaces `scale`, which must still be valid).  gka_values (float32
+    [n_points, n_comp]) with gka_out (float64 [nq, n_comp]): also the Gaussian
+    kernel average of the values over each query's neighbours."""
     L = capi.lib()
     nq = qx.shape[0]
     if query_scale is not None and query_scale.shape[0] != nq:
         raise ValueError("query_scale needs one row per query")
+    if gka_values is not None and gka_values.dim() == 1:
+        gka_values = gka_values.view(-1, 1)
+    if gka_values is not None and gka_out is None:
+        gka_out = torch.empty((nq, gka_values.shape[1]), dtype=torch.float64, device=qx.device)
     params = make_params(scale, t_window, k, flags, seed_segments, waves_per_block, radius2, stats,
-                         query_scale)
+                         query_scale, gka_values, gka_out)
     need = tnn_query_workspace(index, nq, params)
     if scratch is None or scratch.numel() < need:
         scratch = torch.empty(max(need, 256), dtype=torch.uint8, device=qx.device)
@@ -141,7 +156,8 @@ def tnn_query(index, qx, qy, qz, qt, scale, t_window, k, flags=0, seed_segments=
 
 
 def tnn_query_noalloc(index, qx, qy, qz, qt, scale, t_window, k, flags=0, seed_segments=0,
-                      waves_per_block=0, radius2=None, stats=None, out=None, query_scale=None):
+                      waves_per_block=0, radius2=None, stats=None, out=None, query_scale=None,
+                      gka_values=None, gka_out=None):
     """tnn_query with the library's own per-device scratch (no scratch
     argument; the library allocates nothing).  Returns (idx, dist); `out`
     supplies them preallocated."""
@@ -150,7 +166,7 @@ def tnn_query_noalloc(index, qx, qy, qz, qt, scale, t_window, k, flags=0, seed_s
     if query_scale is not None and query_scale.shape[0] != nq:
         raise ValueError("query_scale needs one row per query")
     params = make_params(scale, t_window, k, flags, seed_segments, waves_per_block, radius2, stats,
-                         query_scale)
+                         query_scale, gka_values, gka_out)
     if out is None:
         out = (torch.empty((nq, k), dtype=torch.int32, device=qx.device),
                torch.empty((nq, k), dtype=torch.float64, device=qx.device))
@@ -243,30 +259,82 @@ def tnn_radius_train_workspace(batch):
     return n.value
 
 
-def tnn_radius_grad(model, sx, sy, sz, st, dist, k, first, batch, scratch=None):
+def tnn_radius_shuffle(n, seed, out=None, device="cuda"):
+    """Device permutation of 0 .. n-1 (int32) drawn from `seed`."""
+    if out is None:
+        out = torch.empty(max(int(n), 1), dtype=torch.int32, device=device)
+    check(capi.lib().tnn_radius_shuffle(int(n), int(seed) & (2 ** 64 - 1), _ptr(out), _stream()),
+          "tnn_radius_shuffle")
+    return out[:n]
+
+
+def tnn_radius_grad(model, sx, sy, sz, st, dist, k, first, batch, scratch=None, order=None):
     dev = sx.device
     grad = torch.empty(capi.RADIUS_NPARAMS, dtype=torch.float32, device=dev)
     loss = torch.empty(1, dtype=torch.float32, device=dev)
     need = tnn_radius_train_workspace(batch)
     if scratch is None or scratch.numel() < need:
         scratch = torch.empty(need, dtype=torch.uint8, device=dev)
-    check(capi.lib().tnn_radius_grad(_ptr(model), points(sx, sy, sz, st), _ptr(dist), int(k),
-                                     int(first), int(batch), _ptr(grad), _ptr(loss), _ptr(scratch),
-                                     scratch.numel(), _stream()), "tnn_radius_grad")
+    check(capi.lib().tnn_radius_grad(_ptr(model), points(sx, sy, sz, st), _ptr(dist), _ptr(order),
+                                     int(k), int(first), int(batch), _ptr(grad), _ptr(loss),
+                                     _ptr(scratch), scratch.numel(), _stream()), "tnn_radius_grad")
     return grad, loss
 
 
 def tnn_radius_train_step(model, adam, sx, sy, sz, st, dist, k, first, batch, step, lr,
-                          loss=None, scratch=None):
+                          loss=None, scratch=None, order=None):
     dev = sx.device
     need = tnn_radius_train_workspace(batch)
     if scratch is None or scratch.numel() < need:
         scratch = torch.empty(need, dtype=torch.uint8, device=dev)
     check(capi.lib().tnn_radius_train_step(_ptr(model), _ptr(adam), points(sx, sy, sz, st), _ptr(dist),
-                                           int(k), int(first), int(batch), int(step), float(lr),
-                                           _ptr(loss), _ptr(scratch), scratch.numel(), _stream()),
+                                           _ptr(order), int(k), int(first), int(batch), int(step),
+                                           float(lr), _ptr(loss), _ptr(scratch), scratch.numel(),
+                                           _stream()),
           "tnn_radius_train_step")
     return scratch
+
+
+def tnn_radius_calibrate(model, sx, sy, sz, st, dist, k, quantile, out=None, scratch=None):
+    """Safety factor alpha (device float32 [1]) for quantile q of the
+    log-residuals of the labelled samples."""
+    dev = sx.device
+    n = ctypes.c_size_t(0)
+    check(capi.lib().tnn_radius_calibrate_workspace(int(sx.shape[0]), ctypes.byref(n)),
+          "tnn_radius_calibrate_workspace")
+    if scratch is None or scratch.numel() < n.value:
+        scratch = torch.empty(max(n.value, 256), dtype=torch.uint8, device=dev)
+    if out is None:
+        out = torch.empty(1, dtype=torch.float32, device=dev)
+    check(capi.lib().tnn_radius_calibrate(_ptr(model), points(sx, sy, sz, st), _ptr(dist), int(k),
+                                          float(quantile), _ptr(out), _ptr(scratch), scratch.numel(),
+                                          _stream()), "tnn_radius_calibrate")
+    return out
+
+
+def tnn_radius_checkpoint_bytes():
+    n = ctypes.c_size_t(0)
+    check(capi.lib().tnn_radius_checkpoint_bytes(ctypes.byref(n)), "tnn_radius_checkpoint_bytes")
+    return n.value
+
+
+def tnn_radius_model_save(model):
+    """Checkpoint bytes (numpy uint8) of a device model."""
+    buf = np.empty(tnn_radius_checkpoint_bytes(), dtype=np.uint8)
+    check(capi.lib().tnn_radius_model_save(_ptr(model), buf.ctypes.data_as(ctypes.c_void_p),
+                                           buf.nbytes, _stream()), "tnn_radius_model_save")
+    return buf
+
+
+def tnn_radius_model_load(buf, model=None, device="cuda"):
+    """Device model from checkpoint bytes (TnnError TNN_E_FORMAT if invalid)."""
+    buf = np.ascontiguousarray(np.frombuffer(buf, dtype=np.uint8) if isinstance(buf, (bytes, bytearray))
+                               else buf, dtype=np.uint8)
+    if model is None:
+        model = torch.empty(tnn_radius_model_bytes(), dtype=torch.uint8, device=device)
+    check(capi.lib().tnn_radius_model_load(buf.ctypes.data_as(ctypes.c_void_p), buf.nbytes,
+                                           _ptr(model), _stream()), "tnn_radius_model_load")
+    return model
 
 
 def tnn_radius_features(model, qx, qy, qz, qt):
@@ -328,8 +396,15 @@ def _batch_items(entries):
                    torch.empty((qx.shape[0], k), dtype=torch.float64, device=qx.device))
         arr[i].index = ctypes.pointer(e["index"].c)
         arr[i].queries = points(qx, qy, qz, qt)
+        gv = e.get("gka_values")
+        if gv is not None and gv.dim() == 1:
+            gv = gv.view(-1, 1)
+        if gv is not None and e.get("gka_out") is None:
+            e["gka_out"] = torch.empty((qx.shape[0], gv.shape[1]), dtype=torch.float64,
+                                       device=qx.device)
         arr[i].params = make_params(e["scale"], e.get("t_window", 0.0), k, e.get("flags", 0),
-                                    e.get("seed_segments", 0), 0, e.get("radius2"), e.get("stats"))
+                                    e.get("seed_segments", 0), 0, e.get("radius2"), e.get("stats"),
+                                    None, gv, e.get("gka_out"))
         arr[i].d_out_idx = _ptr(out[0])
         arr[i].d_out_dist = _ptr(out[1])
         keep.append((e, out))

@@ -35,7 +35,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_status_strings():
     L = capi.lib()
-    for code in range(0, -7, -1):
+    for code in range(0, -8, -1):
         s = L.tnn_status_string(code).decode()
         assert s and s != "unknown status"
     assert L.tnn_status_string(-99).decode() == "unknown status"

@@ -381,6 +381,74 @@ def test_gka_average_matches_oracle(k, n_comp):
     assert np.allclose(got[ok], want[ok], rtol=1e-12, atol=1e-12)
 
 
+@pytest.mark.parametrize("flags", [capi.TNN_PLAIN, capi.TNN_LEARNED, capi.TNN_BRUTE, MIXED],
+                         ids=["plain", "learned", "brute", "bf16"])
+@pytest.mark.parametrize("k,n_comp", [(1, 1), (8, 2), (32, 3), (64, 8)])
+def test_gka_epilogue_of_the_search(flags, k, n_comp):
+    """The averaging requested with the search (computed from the top-k in
+    registers on the TNN paths, by the averaging kernel after the linear
+    searches) equals tnn_gka_average on the returned context bit for bit, and
+    the oracle's average within 1e-12; the neighbours are unchanged."""
+    ps = synth.trajectories(60, 90, 40.0, 900.0, seed=23)
+    _, qi = synth.sample_queries(ps, 600, seed=24)
+    qs = ps.take(np.concatenate([qi, np.argsort(ps.t)[:3]]))
+    ix = build(ps, 16)
+    scale = (0.5, 0.5, 4.0, 0.02)
+    q = dev_points(qs)
+    kw = {}
+    if flags & capi.TNN_LEARNED:
+        model = T.tnn_radius_model_init(ix, seed=2)
+        kw["radius2"] = T.tnn_radius_infer(model, *q, alpha=1.0)
+    vals = torch.from_numpy(np.random.default_rng(k).normal(0.0, 10.0, (ps.n, n_comp))
+                            .astype(np.float32)).cuda()
+    gi, gd = T.tnn_query(ix, *q, scale, 0.0, k, flags=flags, **kw)
+    fi, fd = T.tnn_query(ix, *q, scale, 0.0, k, flags=flags, gka_values=vals,
+                         gka_out=(g := torch.empty((qs.n, n_comp), dtype=torch.float64,
+                                                   device="cuda")), **kw)
+    sep = T.tnn_gka_average(gi, gd, vals)
+    torch.cuda.synchronize()
+    assert torch.equal(gi, fi) and torch.equal(gd, fd)
+    got, ref = g.cpu().numpy(), sep.cpu().numpy()
+    assert got.tobytes() == ref.tobytes()
+    want = oracle.gka_average(gi.cpu().numpy(), gd.cpu().numpy(), vals.cpu().numpy())
+    assert np.array_equal(np.isnan(got), np.isnan(want)) and np.isnan(want).any()
+    ok = ~np.isnan(want)
+    assert np.allclose(got[ok], want[ok], rtol=1e-12, atol=1e-12)
+
+
+def test_gka_epilogue_per_query_scales_and_batched():
+    """The epilogue under per-query scales (a row without a metric gets a NaN
+    average) and in a batched launch (each item its own values)."""
+    ps = synth.trajectories(40, 80, 40.0, 900.0, seed=25)
+    qs, _ = synth.sample_queries(ps, 300, seed=26)
+    ix = build(ps, 16)
+    q = dev_points(qs)
+    vals = torch.from_numpy(np.random.default_rng(5).normal(0, 3, (ps.n, 2)).astype(np.float32)).cuda()
+    rows = synth.scale_field(qs.x, qs.y, qs.z, 40.0, seed=27)
+    rows[7, 1] = -1.0
+    qsc = torch.from_numpy(np.ascontiguousarray(rows)).cuda()
+    gi, gd = T.tnn_query(ix, *q, SCALE, 0.0, 8, query_scale=qsc)
+    g = torch.empty((qs.n, 2), dtype=torch.float64, device="cuda")
+    T.tnn_query(ix, *q, SCALE, 0.0, 8, query_scale=qsc, gka_values=vals, gka_out=g)
+    sep = T.tnn_gka_average(gi, gd, vals)
+    torch.cuda.synchronize()
+    assert g.cpu().numpy().tobytes() == sep.cpu().numpy().tobytes()
+    assert np.isnan(g[7].cpu().numpy()).all()
+    ps2 = synth.trajectories(30, 70, 30.0, 900.0, seed=28)
+    qs2, _ = synth.sample_queries(ps2, 200, seed=29)
+    ix2 = build(ps2, 8)
+    vals2 = torch.from_numpy(np.random.default_rng(6).normal(0, 3, ps2.n).astype(np.float32)).cuda()
+    entries = [dict(index=ix, q=q, scale=SCALE, k=8, gka_values=vals),
+               dict(index=ix2, q=dev_points(qs2), scale=SCALE, k=32, gka_values=vals2)]
+    b = T.tnn_batch_prepare(entries)
+    outs = T.tnn_query_batched(b)
+    torch.cuda.synchronize()
+    for e, (bi, bd) in zip(entries, outs):
+        sep = T.tnn_gka_average(bi, bd, e["gka_values"].view(-1, e["gka_out"].shape[1]))
+        torch.cuda.synchronize()
+        assert e["gka_out"].cpu().numpy().tobytes() == sep.cpu().numpy().tobytes()
+
+
 PERQ_PATHS = [capi.TNN_PLAIN, capi.TNN_LEARNED, capi.TNN_BRUTE]
 
 

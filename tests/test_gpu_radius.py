@@ -156,3 +156,100 @@ def test_training_learns_more_than_a_constant():
     say("learned", sl, "plain", sp)
     assert sl["blocks"] < sp["blocks"]
     assert sl["fallbacks"] < 0.35 * te.n
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 17, 4096, 100_000])
+def test_shuffle_is_a_seeded_permutation(n):
+    """The training order is a permutation of 0 .. n-1, the same for the same
+    seed, different for another seed (n > 3)."""
+    a = T.tnn_radius_shuffle(n, 7).cpu().numpy()
+    b = T.tnn_radius_shuffle(n, 7).cpu().numpy()
+    c = T.tnn_radius_shuffle(n, 8).cpu().numpy()
+    assert np.array_equal(np.sort(a), np.arange(n))
+    assert np.array_equal(a, b)
+    if n > 3:
+        assert not np.array_equal(a, c)
+        assert not np.array_equal(a, np.arange(n))
+
+
+def test_gradient_in_a_given_order_matches_oracle(setup):
+    """A batch taken through an order array: the samples order[first + b]
+    (the order here comes from numpy, and is the same input on both sides)."""
+    ps, ix, model, lo, hi, grids = setup
+    k = 8
+    rng = np.random.default_rng(9)
+    qs = ps.take(rng.choice(ps.n, 700, replace=False))
+    _, dist = oracle.knn(ps.soa(), qs.soa(), SCALE, 0.0, k)
+    order = rng.permutation(qs.n).astype(np.int32)
+    first, batch = 100, 300
+    g, loss = T.tnn_radius_grad(model, *dev_points(qs), torch.from_numpy(dist).cuda(), k, first,
+                                batch, order=torch.from_numpy(order).cuda())
+    g = g.cpu().numpy().astype(np.float64)
+    theta = T.radius_params(model).cpu().numpy().astype(np.float64)
+    sel = order[first:first + batch]
+    X = oracle.radius_features(*qs.take(sel).soa(), lo, hi, *grids)
+    y = oracle.radius_label(dist[sel, k - 1])
+    lo_, go = oracle.mlp_loss_grad(theta, X, y)
+    assert float(loss.item()) == pytest.approx(lo_, rel=1e-4, abs=1e-6)
+    assert np.linalg.norm(g - go) <= 1e-4 * np.linalg.norm(go) + 1e-7
+
+
+@pytest.mark.parametrize("quantile", [0.0, 0.5, 0.9, 0.99, 1.0])
+def test_calibration_matches_oracle_quantile(setup, quantile):
+    """The safety factor computed on the device (inference, log-residuals,
+    radix selection of the two order statistics) against the oracle's
+    quantile of the same model outputs and k-th distances, including samples
+    without a label."""
+    ps, ix, model, lo, hi, grids = setup
+    k = 8
+    rng = np.random.default_rng(11)
+    # the earliest points have fewer than k points in their past: no label
+    sel = np.unique(np.concatenate([rng.choice(ps.n, 5000, replace=False), np.argsort(ps.t)[:20]]))
+    qs = ps.take(sel)
+    _, dist = oracle.knn(ps.soa(), qs.soa(), SCALE, 0.0, k)
+    assert np.isinf(dist[:, k - 1]).any()
+    q = dev_points(qs)
+    dd = torch.from_numpy(dist).cuda()
+    alpha = float(T.tnn_radius_calibrate(model, *q, dd, k, quantile).item())
+    logr = torch.empty(qs.n, dtype=torch.float32, device="cuda")
+    T.tnn_radius_infer(model, *q, 1.0, logr=logr)
+    want = oracle.radius_calibrate(logr.cpu().numpy(), dist[:, k - 1], quantile)
+    assert alpha == pytest.approx(want, rel=2e-7)
+
+
+def test_calibration_without_labels_is_one(setup):
+    ps, ix, model, lo, hi, grids = setup
+    qs = ps.take(np.arange(10))
+    dd = torch.full((10, 8), float("inf"), dtype=torch.float64, device="cuda")
+    assert float(T.tnn_radius_calibrate(model, *dev_points(qs), dd, 8, 0.9).item()) == 1.0
+
+
+def test_checkpoint_round_trip_gives_identical_radii(setup, tmp_path):
+    """A trained model saved to a versioned checkpoint and loaded back into a
+    fresh buffer predicts bit-identical radii; a damaged, truncated or
+    foreign file is refused with TNN_E_FORMAT."""
+    ps, ix, _, lo, hi, grids = setup
+    rng = np.random.default_rng(12)
+    tr = ps.take(rng.choice(ps.n, 4000, replace=False))
+    model, _, _, _ = radius.train(ix, *dev_points(tr), SCALE, 0.0, 8, epochs=3, batch=512)
+    path = str(tmp_path / "radius.ckpt")
+    radius.save(model, path)
+    loaded = radius.load(path)
+    assert loaded.data_ptr() != model.data_ptr()
+    assert torch.equal(loaded, model)
+    te = ps.take(rng.choice(ps.n, 3000, replace=False))
+    q = dev_points(te)
+    a = T.tnn_radius_infer(model, *q, 1.7)
+    b = T.tnn_radius_infer(loaded, *q, 1.7)
+    torch.cuda.synchronize()
+    assert a.cpu().numpy().tobytes() == b.cpu().numpy().tobytes()
+    raw = bytearray(open(path, "rb").read())
+    for bad in (raw[:-1], raw[:100], bytes(b"x") + raw[1:]):
+        with pytest.raises(capi.TnnError) as e:
+            T.tnn_radius_model_load(bytes(bad))
+        assert e.value.code == capi.TNN_E_FORMAT
+    flipped = bytearray(raw)
+    flipped[64 + 1234] ^= 1  # one payload bit
+    with pytest.raises(capi.TnnError) as e:
+        T.tnn_radius_model_load(bytes(flipped))
+    assert e.value.code == capi.TNN_E_FORMAT

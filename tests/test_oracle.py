@@ -602,3 +602,33 @@ def test_pair_dist_with_query_rows_reduces_to_the_shared_metric():
     d2 = oracle.pair_dist(ps.soa(), late.soa(), QQ, PP, rows).reshape(3, ps.n)
     for q in range(3):
         assert np.array_equal(dist[q], d2[q][idx[q]])
+
+
+def test_radius_calibrate_closed_forms_and_numpy_quantile():
+    """The safety factor's quantile: hand cases, then np.quantile's default
+    (linear) method on random residuals; unlabelled and non-finite samples
+    are left out, and no labelled sample gives alpha = 1."""
+    # residuals 0, 1, ..., 9 (logr = 0, d_k = e^(2 i)): median position 4.5
+    d = np.exp(2.0 * np.arange(10))
+    lr = np.zeros(10, np.float32)
+    assert oracle.radius_calibrate(lr, d, 0.5) == pytest.approx(math.exp(4.5), rel=1e-14)
+    assert oracle.radius_calibrate(lr, d, 0.0) == pytest.approx(1.0, rel=1e-14)
+    assert oracle.radius_calibrate(lr, d, 1.0) == pytest.approx(math.exp(9.0), rel=1e-14)
+    # q = 0.9 over 10 values: position 8.1 -> 8.1
+    assert oracle.radius_calibrate(lr, d, 0.9) == pytest.approx(math.exp(8.1), rel=1e-13)
+    # unlabelled samples (inf, 0, NaN distance) are skipped
+    d2 = np.concatenate([d, [np.inf, 0.0, np.nan]])
+    lr2 = np.zeros(13, np.float32)
+    assert oracle.radius_calibrate(lr2, d2, 0.5) == pytest.approx(math.exp(4.5), rel=1e-14)
+    # a non-finite prediction is skipped too
+    lr3 = lr2.copy()
+    lr3[0] = np.inf
+    assert oracle.radius_calibrate(lr3, d2, 0.0) == pytest.approx(math.exp(1.0), rel=1e-14)
+    assert oracle.radius_calibrate(lr2[:3], np.array([np.inf, 0.0, np.nan]), 0.5) == 1.0
+    rng = np.random.default_rng(3)
+    lr = rng.normal(0, 1, 5001).astype(np.float32)
+    d = np.exp(rng.normal(2, 3, 5001))
+    r = 0.5 * np.log(d) - lr.astype(np.float64)
+    for q in (0.0, 0.37, 0.9, 0.99, 1.0):
+        want = math.exp(float(np.quantile(r, q)))
+        assert oracle.radius_calibrate(lr, d, q) == pytest.approx(want, rel=1e-13)
