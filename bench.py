@@ -23,11 +23,17 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6   # MI355X: 256 CU x 64 lanes x 2.4 GHz x 2 (FMA)
 FP32_VECTOR_PEAK_TFLOPS = 157.3  # twice the binary64 rate
 HBM_PEAK_GBS = 8000.0
 
-# Algorithmic floating-point work per unit of the TNN query kernel (counted
-# from the source; FMA = 2): see the design notes.
-FLOPS_BLOCK_BOUND = 20     # float32 box distance
-FLOPS_SEG_BOUND = 39       # float32 cylinder bound
-FLOPS_POINT = 15           # binary64 exact distance
+# Algorithmic work per unit of the TNN query kernel (the scope table's
+# per-unit counts): a block bound is 20 float32 operations (4 gaps of 2 max
+# each, 4 squares, 4 scaled terms summed), a cylinder bound 28 (differences,
+# the scaled dot product and projection, the residual's scaled norm, square
+# root, radius and time terms), a point 12 binary64 operations (4
+# differences, 4 squares, 4 scaled terms summed) plus 2 float32 (the time
+# mask and the admission compare).
+FLOPS_BLOCK_BOUND = 20     # float32
+FLOPS_SEG_BOUND = 28       # float32
+FLOPS_POINT_F64 = 12       # binary64
+FLOPS_POINT_F32 = 2        # float32
 
 
 # HBM traffic of one learned-radius search launch on this workload, from two
@@ -63,6 +69,49 @@ def measured_traffic():
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def strategy_name(capi, flags):
+    if not flags & capi.TNN_LEARNED:
+        return "plain (the learned radius did not pay on the training queries)"
+    return "learned radius + plain seed" if flags & capi.TNN_LEARNED_SEED else "learned radius"
+
+
+def choose_radius(T, capi, radius, model, ptr, pdist, ix, scale, tw, k, quantiles, stream,
+                  steps=3, warmup=1, query_scale=None):
+    """Calibration of the learned radius on the training queries (setup, not
+    timed): for each quantile of the safety factor, and with and without the
+    plain seed (TNN_LEARNED_SEED), time radius inference + learned search on
+    the training queries; plain TNN (no inference) is timed as well, and the
+    fastest of all is kept, so the learned path is never slower than plain on
+    the training queries.  Returns (ms, quantile, alpha, flags); flags 0 means
+    plain TNN was kept."""
+    import torch
+    n = ptr[0].shape[0]
+    r2 = torch.empty(n, dtype=torch.float32, device="cuda")
+    out = (torch.empty((n, k), dtype=torch.int32, device="cuda"),
+           torch.empty((n, k), dtype=torch.float64, device="cuda"))
+    scr = torch.empty(max(T.tnn_query_workspace(ix, n, T.make_params(scale, tw, k)), 256),
+                      dtype=torch.uint8, device="cuda")
+    def run_plain():
+        T.tnn_query(ix, *ptr, scale, tw, k, out=out, scratch=scr, query_scale=query_scale)
+
+    ms = timed(run_plain, steps, warmup, stream)
+    log(f"  plain TNN: {ms:.3f} ms on the training queries")
+    best = (ms, None, 1.0, 0)
+    for qnt in quantiles:
+        a = radius.calibrate(model, *ptr, pdist, k, quantile=qnt)
+        for fl in (capi.TNN_LEARNED, capi.TNN_LEARNED | capi.TNN_LEARNED_SEED):
+            def run():
+                T.tnn_radius_infer(model, *ptr, a, out=r2)
+                T.tnn_query(ix, *ptr, scale, tw, k, flags=fl, radius2=r2, out=out, scratch=scr,
+                            query_scale=query_scale)
+            ms = timed(run, steps, warmup, stream)
+            log(f"  quantile {qnt}, {'seeded' if fl & capi.TNN_LEARNED_SEED else 'unseeded'}: "
+                f"alpha {a:.3f}, {ms:.3f} ms on the training queries")
+            if best is None or ms < best[0]:
+                best = (ms, qnt, a, fl)
+    return best
 
 
 def timed(fn, steps, warmup, stream):
@@ -227,40 +276,27 @@ def run_config(name, args, T, capi, radius, synth, torch, stream):
     res["radius_train_s"] = time.perf_counter() - t0
     res["radius_train_queries"] = tq.n
     r2 = torch.empty(n, dtype=torch.float32, device="cuda")
-    r2_tr = torch.empty(tq.n, dtype=torch.float32, device="cuda")
-    out_tr = (torch.empty((tq.n, k), dtype=torch.int32, device="cuda"),
-              torch.empty((tq.n, k), dtype=torch.float64, device="cuda"))
-    scr_tr = torch.empty(max(T.tnn_query_workspace(ix, tq.n, T.make_params(scale, tw, k)), 256),
-                         dtype=torch.uint8, device="cuda")
-    best = None
-    for qnt in (RADIUS_QUANTILES if not args.radius_quantile else (args.radius_quantile,)):
-        a = radius.calibrate(model, *ptr, pdist, k, quantile=qnt)
-
-        def learned_tr():
-            T.tnn_radius_infer(model, *tx, a, out=r2_tr)
-            T.tnn_query(ix, *tx, scale, tw, k, flags=capi.TNN_LEARNED, radius2=r2_tr,
-                        out=out_tr, scratch=scr_tr)
-
-        m = timed(learned_tr, 2, 1, stream)
-        if best is None or m < best[0]:
-            best = (m, qnt, a)
-    alpha = best[2]
+    best = choose_radius(T, capi, radius, model, ptr, pdist, ix, scale, tw, k,
+                         RADIUS_QUANTILES if not args.radius_quantile else (args.radius_quantile,),
+                         stream, steps=2)
+    alpha, lflags = best[2], best[3]
 
     def learned():
-        T.tnn_radius_infer(model, *q, alpha, out=r2)
-        T.tnn_query(ix, *q, scale, tw, k, flags=capi.TNN_LEARNED, radius2=r2, out=out,
-                    scratch=scratch)
+        if lflags:
+            T.tnn_radius_infer(model, *q, alpha, out=r2)
+        T.tnn_query(ix, *q, scale, tw, k, flags=lflags, radius2=r2, out=out, scratch=scratch)
 
     ms_l = timed(learned, steps, 1, stream)
     st = T.new_stats()
-    T.tnn_query(ix, *q, scale, tw, k, flags=capi.TNN_LEARNED, radius2=r2, out=out,
+    T.tnn_query(ix, *q, scale, tw, k, flags=lflags, radius2=r2, out=out,
                 scratch=scratch, stats=st)
     torch.cuda.synchronize()
     st = T.stats_dict(st)
     res.update(learned_qps=n / ms_l * 1e3, learned_speedup_vs_plain=ms / ms_l,
                learned_matches_plain=bool(torch.equal(out[0], ref[0])) and bool(torch.equal(out[1], ref[1])),
-               fallback_rate=st["fallbacks"] / max(n, 1), radius_quantile=best[1], radius_alpha=alpha)
-    del out_tr, scr_tr, r2_tr
+               fallback_rate=st["fallbacks"] / max(n, 1), radius_quantile=best[1], radius_alpha=alpha,
+               radius_strategy=strategy_name(capi, lflags),
+               work_per_query_learned={kk: st[kk] / max(n, 1) for kk in ("blocks", "segments", "points", "merges")})
     if not args.no_brute:
         mf = capi.TNN_BRUTE | capi.TNN_MIXED_BF16
         mscr = torch.empty(T.tnn_query_workspace(ix, n, T.make_params(scale, tw, k, mf)),
@@ -326,23 +362,28 @@ def run_query_scales(args, T, capi, radius, synth, torch, stream):
     tx = T.to_device(tq.x, tq.y, tq.z, tq.t)
     model, loss, pdist, ptr = radius.train(ix, *tx, scale, tw, k, epochs=args.train_epochs,
                                            batch=4096, lr=3e-3)
-    alpha = radius.calibrate(model, *ptr, pdist, k, quantile=BATCH_QUANTILE)
+    # (the training queries' scales: the same field at their own positions)
+    tr_rows = torch.from_numpy(synth.scale_field(tq.x, tq.y, tq.z, 3000.0, seed=cfg["seed"] + 77)).cuda()
+    best = choose_radius(T, capi, radius, model, ptr, pdist, ix, scale, tw, k, (BATCH_QUANTILE,),
+                         stream, steps=2, query_scale=tr_rows)
+    alpha, lflags = best[2], best[3]
     r2 = torch.empty(n, dtype=torch.float32, device="cuda")
 
     def learned():
-        T.tnn_radius_infer(model, *q, alpha, out=r2)
-        T.tnn_query(ix, *q, scale, tw, k, flags=capi.TNN_LEARNED, radius2=r2, out=out,
+        if lflags:
+            T.tnn_radius_infer(model, *q, alpha, out=r2)
+        T.tnn_query(ix, *q, scale, tw, k, flags=lflags, radius2=r2, out=out,
                     scratch=scratch, query_scale=qscale)
 
     ms_l = timed(learned, steps, 1, stream)
     st = T.new_stats()
-    T.tnn_query(ix, *q, scale, tw, k, flags=capi.TNN_LEARNED, radius2=r2, out=out,
+    T.tnn_query(ix, *q, scale, tw, k, flags=lflags, radius2=r2, out=out,
                 scratch=scratch, stats=st, query_scale=qscale)
     torch.cuda.synchronize()
     st = T.stats_dict(st)
-    res.update(learned_qps=n / ms_l * 1e3,
+    res.update(learned_qps=n / ms_l * 1e3, learned_speedup_vs_plain=ms / ms_l,
                learned_matches_plain=bool(torch.equal(out[0], ref[0])) and bool(torch.equal(out[1], ref[1])),
-               fallback_rate=st["fallbacks"] / max(n, 1))
+               fallback_rate=st["fallbacks"] / max(n, 1), radius_strategy=strategy_name(capi, lflags))
     if not args.no_brute:
         def brute():
             T.tnn_query(ix, *q, scale, tw, k, flags=capi.TNN_BRUTE, out=out, scratch=scratch,
@@ -429,43 +470,30 @@ def main():
     train_s = time.perf_counter() - t0
     log(f"radius model: {args.train_queries} labelled queries, loss {loss:.4f}, {train_s:.2f} s")
     r2 = torch.empty(qs.n, dtype=torch.float32, device="cuda")
-    # safety factor: the quantile whose learned search is fastest on the
-    # training queries
-    r2_tr = torch.empty(tq.n, dtype=torch.float32, device="cuda")
-    out_tr = (torch.empty((tq.n, k), dtype=torch.int32, device="cuda"),
-              torch.empty((tq.n, k), dtype=torch.float64, device="cuda"))
-    best = None
+    # safety factor (and whether to also take the plain seed): the choice whose
+    # learned search is fastest on the training queries
     sweep = RADIUS_QUANTILES if not args.radius_quantile else (args.radius_quantile,)
-    for qnt in sweep:
-        a = radius.calibrate(model, *ptr, pdist, k, quantile=qnt)
-
-        def learned_tr():
-            T.tnn_radius_infer(model, tx, ty, tz, tt, a, out=r2_tr)
-            T.tnn_query(ix, tx, ty, tz, tt, scale, 0.0, k, flags=capi.TNN_LEARNED, radius2=r2_tr,
-                        out=out_tr, scratch=scratch)
-
-        ms = timed(learned_tr, 5, 2, stream)
-        log(f"  quantile {qnt}: alpha {a:.3f}, {ms:.3f} ms on the training queries")
-        if best is None or ms < best[0]:
-            best = (ms, qnt, a)
-    alpha = best[2]
+    best = choose_radius(T, capi, radius, model, ptr, pdist, ix, scale, 0.0, k, sweep, stream,
+                         steps=5, warmup=2)
+    alpha, lflags = best[2], best[3]
 
     # ---- learned TNN: the headline step (radius inference + search) ---------
     def learned():
-        T.tnn_radius_infer(model, qx, qy, qz, qt, alpha, out=r2)
-        T.tnn_query(ix, qx, qy, qz, qt, scale, 0.0, k, flags=capi.TNN_LEARNED, radius2=r2,
+        if lflags:
+            T.tnn_radius_infer(model, qx, qy, qz, qt, alpha, out=r2)
+        T.tnn_query(ix, qx, qy, qz, qt, scale, 0.0, k, flags=lflags, radius2=r2,
                     out=out, scratch=scratch)
 
     ms_learned = timed(learned, args.steps, args.warmup, stream)
 
     def learned_search_only():
-        T.tnn_query(ix, qx, qy, qz, qt, scale, 0.0, k, flags=capi.TNN_LEARNED, radius2=r2,
+        T.tnn_query(ix, qx, qy, qz, qt, scale, 0.0, k, flags=lflags, radius2=r2,
                     out=out, scratch=scratch)
 
     ms_search = timed(learned_search_only, args.steps, 1, stream)
     exact = bool(torch.equal(out[0], ref_idx)) and bool(torch.equal(out[1], ref_dist))
     stats = T.new_stats()
-    T.tnn_query(ix, qx, qy, qz, qt, scale, 0.0, k, flags=capi.TNN_LEARNED, radius2=r2,
+    T.tnn_query(ix, qx, qy, qz, qt, scale, 0.0, k, flags=lflags, radius2=r2,
                 stats=stats, out=out, scratch=scratch)
     torch.cuda.synchronize()
     st = T.stats_dict(stats)
@@ -478,8 +506,9 @@ def main():
     wind = torch.from_numpy(np.random.default_rng(cfg["seed"] + 3000)
                             .normal(0.0, 15.0, (ps.n, 2)).astype(np.float32)).cuda()
     gka_out = torch.empty((qs.n, 2), dtype=torch.float64, device="cuda")
-    T.tnn_radius_infer(model, qx, qy, qz, qt, alpha, out=r2)
-    T.tnn_query(ix, qx, qy, qz, qt, scale, 0.0, k, flags=capi.TNN_LEARNED, radius2=r2,
+    if lflags:
+        T.tnn_radius_infer(model, qx, qy, qz, qt, alpha, out=r2)
+    T.tnn_query(ix, qx, qy, qz, qt, scale, 0.0, k, flags=lflags, radius2=r2,
                 out=out, scratch=scratch)
     ms_gka = timed(lambda: T.tnn_gka_average(out[0], out[1], wind, out=gka_out), args.steps, 1,
                    stream)
@@ -487,8 +516,9 @@ def main():
 
     # the averaging as the search's epilogue, from the top-k in registers
     def learned_gka():
-        T.tnn_radius_infer(model, qx, qy, qz, qt, alpha, out=r2)
-        T.tnn_query(ix, qx, qy, qz, qt, scale, 0.0, k, flags=capi.TNN_LEARNED, radius2=r2,
+        if lflags:
+            T.tnn_radius_infer(model, qx, qy, qz, qt, alpha, out=r2)
+        T.tnn_query(ix, qx, qy, qz, qt, scale, 0.0, k, flags=lflags, radius2=r2,
                     out=out, scratch=scratch, gka_values=wind, gka_out=gka_out)
 
     ms_learned_gka = timed(learned_gka, args.steps, 1, stream)
@@ -538,8 +568,9 @@ def main():
         result_extra["mixed_brute_rescored_per_query"] = mst["rescored"] / qs.n
         result_extra["mixed_max_abs_dist_err"] = mst["max_err"]
 
-    f32 = FLOPS_BLOCK_BOUND * st["blocks"] + FLOPS_SEG_BOUND * st["segments"]
-    f64 = FLOPS_POINT * st["points"]
+    f32 = (FLOPS_BLOCK_BOUND * st["blocks"] + FLOPS_SEG_BOUND * st["segments"]
+           + FLOPS_POINT_F32 * st["points"])
+    f64 = FLOPS_POINT_F64 * st["points"]
     flops = f32 + f64
     achieved = flops / (ms_search * 1e-3) / 1e12
     # ALU roof of this float32/binary64 mix: the time the flops take at the
@@ -557,7 +588,10 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": "1M trajectory points (5000x200), K=32, 100k sampled queries, k=32, "
                                "scales (1,1,10,0.05), mask t'<t",
-                   "path": "learned-radius TNN (radius inference + search)",
+                   "path": ("TNN, " + strategy_name(capi, lflags)
+                            + (" (radius inference + search)" if lflags else "")
+                            + "; binary64 point scan (the BF16 MFMA tiles serve the linear "
+                              "search baseline)"),
                    "global_batch": qs.n, "seed": cfg["seed"]},
         "roofline": roofline,
         "plain_qps": qs.n / ms_plain * 1e3, "learned_qps": value,
@@ -565,7 +599,8 @@ def main():
         "learned_matches_plain": exact, "fallback_rate": st["fallbacks"] / qs.n,
         "gka_average_ms": ms_gka, "learned_plus_gka_qps": qs.n / ms_learned_gka * 1e3,
         "learned_plus_gka_ms_per_step": ms_learned_gka, "gka_fused_matches_kernel": gka_fused_same,
-        "radius_alpha": alpha, "radius_quantile": best[1], "radius_train_s": train_s,
+        "radius_alpha": alpha, "radius_quantile": best[1],
+        "radius_strategy": strategy_name(capi, lflags), "radius_train_s": train_s,
         "radius_train_queries": args.train_queries,
         "index_build_s": build_s, "stats_learned": st, "stats_plain": st_plain,
     }

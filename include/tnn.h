@@ -68,6 +68,12 @@ typedef struct {
                               A query whose own scaled squared norm (about the index
                               box centre) reaches 1e30 gets (-1, NaN) slots. */
 #define TNN_LEARNED 4u     /* TNN seeded with a predicted k-th distance d_radius2[q] */
+#define TNN_LEARNED_SEED 16u /* with TNN_LEARNED: also find the nearest block and scan its
+                              seed segments as plain TNN does, then start from the smaller
+                              of that k-th distance and the prediction.  Pays when the
+                              bounds share a large floor (a time window, Sec. 3.1) and
+                              order the blocks poorly; the radius calibration can time
+                              both ways and keep the faster.  Results are the same. */
 
 /* Statistics counters (TNN_STAT_*), unsigned 64-bit, accumulated with atomics
  * when tnn_query_params.d_stats is not NULL. */

@@ -24,6 +24,7 @@ TNN_PLAIN = 0
 TNN_BRUTE = 1
 TNN_MIXED_BF16 = 2
 TNN_LEARNED = 4
+TNN_LEARNED_SEED = 16
 
 STAT_NAMES = ["queries", "blocks", "segments", "points", "merges", "rounds", "fallbacks",
               "rescored", "max_err_bits"]

@@ -40,7 +40,8 @@ tnn_status check_params(const tnn_query_params *p, int64_t n_queries = 1) {
     if (!(p->scale[f] >= 0.0) || !std::isfinite(p->scale[f])) return TNN_E_ARG;
   if (!(p->t_window >= 0.0) || !std::isfinite(p->t_window)) return TNN_E_ARG;
   if (p->k < 1 || p->k > kMaxK) return TNN_E_ARG;
-  if (p->flags & ~(TNN_BRUTE | TNN_MIXED_BF16 | TNN_LEARNED)) return TNN_E_ARG;
+  if (p->flags & ~(TNN_BRUTE | TNN_MIXED_BF16 | TNN_LEARNED | TNN_LEARNED_SEED)) return TNN_E_ARG;
+  if ((p->flags & TNN_LEARNED_SEED) && !(p->flags & TNN_LEARNED)) return TNN_E_ARG;
   if ((p->flags & TNN_LEARNED) && !p->d_radius2 && n_queries > 0) return TNN_E_ARG;
   if ((p->flags & TNN_MIXED_BF16) && !(p->flags & TNN_BRUTE)) return TNN_E_UNSUPPORTED;
   // the BF16 operands carry the scales: one metric per call

@@ -34,6 +34,11 @@ constexpr int kQueues = TNN_QUERY_QUEUES;
 // was 2 % lower and the median per-airspace latency 15 % higher.
 constexpr int kBatchQueues = 8;
 constexpr int kTicketStride = 32;  // counters 256 bytes apart
+// Resident workgroups (of 4 waves) per CU for the search: with its 68 VGPRs
+// 7 would fit, but on the 1M-point learned search 5 ran fastest (7: 0.221 ms,
+// 6: 0.205, 5: 0.202, 4: 0.213, 3: 0.240; L2 hit rate 81 % at both 4 and
+// 7): more concurrent queries only add contention.
+constexpr int kMaxSearchBlocksPerCu = 5;
 static_assert(kQueues >= 1 && kQueues <= 16, "the query workspace holds 16 counters");
 
 // ---------------------------------------------------------------------------
@@ -328,7 +333,9 @@ __device__ __forceinline__ void answer_query_with(const IndexDesc &ix, const Pre
   bool learned = (a.flags & TNN_LEARNED) != 0;
   double r2 = learned ? (double)in.r2 : 0.0;
   if (learned && !(r2 > 0.0 && r2 < kInf)) learned = false;  // no usable prediction
-  if (learned) {
+  // with TNN_LEARNED_SEED a learned query also takes the plain seed and starts
+  // from the smaller of the two radii
+  if (learned && !(a.flags & TNN_LEARNED_SEED)) {
     tau = r2;
   } else {
     // nearest block by its bound: best-first over superblocks (a superblock
@@ -394,6 +401,7 @@ __device__ __forceinline__ void answer_query_with(const IndexDesc &ix, const Pre
       for (int m = 32; m > 0; m >>= 1) far = fmax(far, __shfl_xor(far, m, 64));
       tau = fmax(fmax(far, (double)best) * 16.0, floor_tau);
     }
+    if (learned) tau = fmin(tau, r2);
   }
   {
     double prev = -1.0;
@@ -833,7 +841,8 @@ hipError_t launch_query(const IndexDesc &ix, const Prep &pr, const QueryArgs &a,
     const int per_cu = resident_per_cu(variant, waves_per_block, lds, [&](int *n) {
       return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, kern, waves_per_block * kWave, lds);
     });
-    const int64_t resident = (int64_t)cu_count() * per_cu;
+    const int blocks_per_cu = per_cu < kMaxSearchBlocksPerCu ? per_cu : kMaxSearchBlocksPerCu;
+    const int64_t resident = (int64_t)cu_count() * blocks_per_cu;
     const int64_t g = grid < resident ? grid : resident;
     hipLaunchKernelGGL(kern, dim3((unsigned)g), dim3(waves_per_block * kWave), lds, st, ix, pr, a,
                        qs.x, qs.y, qs.z, qs.t, qs.n, out_idx, out_dist, query_scale);

@@ -88,9 +88,12 @@ def test_window_airways_random_full_size(name):
     alpha = radius.calibrate(model, *ptr, pdist, k, quantile=0.8)
     r2 = T.tnn_radius_infer(model, *q, alpha)
     li, ld = T.tnn_query(ix, *q, SCALE, tw, k, flags=capi.TNN_LEARNED, radius2=r2)
+    si, sd = T.tnn_query(ix, *q, SCALE, tw, k, flags=capi.TNN_LEARNED | capi.TNN_LEARNED_SEED,
+                         radius2=r2)
     mi, md = T.tnn_query(ix, *q, SCALE, tw, k, flags=capi.TNN_BRUTE | capi.TNN_MIXED_BF16)
     torch.cuda.synchronize()
     assert torch.equal(pi, li) and torch.equal(pd, ld)
+    assert torch.equal(pi, si) and torch.equal(pd, sd)
     assert torch.equal(pi, mi) and torch.equal(pd, md)
     rng = np.random.default_rng(11)
     sample = np.sort(rng.choice(qs.n, 128, replace=False))
@@ -125,3 +128,30 @@ def test_per_query_scales_full_size():
     sample = np.concatenate([np.sort(rng.choice(qs.n, 160, replace=False)), np.argsort(qs.t)[:8]])
     oi, od = oracle.knn(ps.soa(), qs.take(sample).soa(), rows[sample], 0.0, k)
     assert_same(gi[sample], gd[sample], oi, od, "per-query scales sample")
+
+
+def test_superblock_boxes_beyond_lds_take_the_global_path():
+    """More superblocks than fit in LDS (segments of one point: 6.4M points,
+    6.4M segments, 100k blocks, 1563 superblocks of 32 B > 48 KB): the search
+    kernel that reads every box from global memory.  Plain, learned and
+    per-query-scale queries against the oracle."""
+    ps = synth.trajectories(32_000, 200, 3000.0, 12 * 3600.0, seed=61)
+    say("global-box path: build", ps.n)
+    ix = build(ps, 1)
+    assert ix.n_segments == ps.n and (ix.n_blocks + 63) // 64 * 32 > 48 * 1024
+    qs, _ = synth.sample_queries(ps, 384, seed=62)
+    q = dev_points(qs)
+    k = 16
+    oi, od = oracle.knn(ps.soa(), qs.soa(), SCALE, 0.0, k)
+    pi, pd = T.tnn_query(ix, *q, SCALE, 0.0, k)
+    model = T.tnn_radius_model_init(ix, seed=9)
+    r2 = T.tnn_radius_infer(model, *q, alpha=3.0)
+    li, ld = T.tnn_query(ix, *q, SCALE, 0.0, k, flags=capi.TNN_LEARNED, radius2=r2)
+    torch.cuda.synchronize()
+    assert_same(pi.cpu().numpy(), pd.cpu().numpy(), oi, od, "global boxes plain")
+    assert_same(li.cpu().numpy(), ld.cpu().numpy(), oi, od, "global boxes learned")
+    rows = synth.scale_field(qs.x, qs.y, qs.z, 3000.0, seed=63)
+    qi_, qd_ = T.tnn_query(ix, *q, SCALE, 0.0, k, query_scale=torch.from_numpy(rows).cuda())
+    torch.cuda.synchronize()
+    oqi, oqd = oracle.knn(ps.soa(), qs.soa(), rows, 0.0, k)
+    assert_same(qi_.cpu().numpy(), qd_.cpu().numpy(), oqi, oqd, "global boxes per-query scales")

@@ -244,8 +244,11 @@ def test_empty_and_tiny_inputs(flags):
     assert_same(gi, gd, oi, od, "k>N")
 
 
+@pytest.mark.parametrize("seeded", [False, True], ids=["unseeded", "seeded"])
 @pytest.mark.parametrize("kind", ["zero", "inf", "nan", "tiny", "huge", "exact", "under", "noisy"])
-def test_learned_radius_never_changes_results(kind):
+def test_learned_radius_never_changes_results(kind, seeded):
+    """Any prediction gives the oracle's result, with or without the plain
+    seed (TNN_LEARNED_SEED)."""
     ps, qs, _, cfg = config_data("c1")
     ix = build(ps, cfg["seg_len"])
     k = cfg["k"]
@@ -258,8 +261,9 @@ def test_learned_radius_never_changes_results(kind):
           "noisy": kth * np.exp(rng.normal(0, 1.0, qs.n))}[kind]
     say("learned radius", kind)
     r2t = torch.from_numpy(np.asarray(r2, dtype=np.float32)).cuda()
-    gi, gd = gpu_query(ix, qs, SCALE, 0.0, k, flags=capi.TNN_LEARNED, radius2=r2t)
-    assert_same(gi, gd, oi, od, f"learned {kind}")
+    fl = capi.TNN_LEARNED | (capi.TNN_LEARNED_SEED if seeded else 0)
+    gi, gd = gpu_query(ix, qs, SCALE, 0.0, k, flags=fl, radius2=r2t)
+    assert_same(gi, gd, oi, od, f"learned {kind} seeded {seeded}")
 
 
 def test_c2_full_size_sampled_parity():

@@ -253,3 +253,52 @@ def test_checkpoint_round_trip_gives_identical_radii(setup, tmp_path):
     with pytest.raises(capi.TnnError) as e:
         T.tnn_radius_model_load(bytes(flipped))
     assert e.value.code == capi.TNN_E_FORMAT
+
+
+def test_learned_radius_gains_time_on_one_million_points():
+    """The gain in time: on the 1M-point workload (100k queries, k = 32) the
+    learned step (radius inference + learned search) beats plain TNN's search,
+    median of 5 timings of 5 calls each, and returns the same bytes."""
+    ps, qs, qidx, cfg = config_data("c2")
+    k = cfg["k"]
+    ix = build(ps, cfg["seg_len"])
+    # trained as the benchmark trains it: 100k labelled queries, 8 epochs
+    tq, _ = synth.sample_queries(ps, 100_000, cfg["seed"] + 2000, exclude=qidx)
+    model, _, pdist, ptr = radius.train(ix, *dev_points(tq), SCALE, 0.0, k, epochs=8, batch=4096,
+                                        lr=3e-3)
+    alpha = radius.calibrate(model, *ptr, pdist, k, quantile=0.99)
+    q = dev_points(qs)
+    out = (torch.empty((qs.n, k), dtype=torch.int32, device="cuda"),
+           torch.empty((qs.n, k), dtype=torch.float64, device="cuda"))
+    scr = torch.empty(T.tnn_query_workspace(ix, qs.n, T.make_params(SCALE, 0.0, k)),
+                      dtype=torch.uint8, device="cuda")
+    r2 = torch.empty(qs.n, dtype=torch.float32, device="cuda")
+
+    def plain():
+        T.tnn_query(ix, *q, SCALE, 0.0, k, out=out, scratch=scr)
+
+    def learned():
+        T.tnn_radius_infer(model, *q, alpha, out=r2)
+        T.tnn_query(ix, *q, SCALE, 0.0, k, flags=capi.TNN_LEARNED, radius2=r2, out=out,
+                    scratch=scr)
+
+    def median_ms(fn):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(5):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(5):
+                fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1) / 5)
+        return float(np.median(ts))
+
+    mp = median_ms(plain)
+    ref = (out[0].clone(), out[1].clone())
+    ml = median_ms(learned)
+    say(f"plain {mp:.4f} ms, learned step {ml:.4f} ms, gain {mp / ml:.3f}x")
+    assert torch.equal(out[0], ref[0]) and torch.equal(out[1], ref[1])
+    assert ml < mp
