@@ -99,11 +99,13 @@ __device__ __forceinline__ SegView load_seg(const Prep &pr, int64_t s) {
 // max(0, D - R)^2 + s_t max(0, t_q - t_max, t_w)^2 with D the distance from
 // the query to segment AB in the scaled metric (projection in that metric).
 // Float32 with a proven margin: the computed distance to the segment exceeds
-// the true one by at most 7u D + 14u |AB|_s (u = 2^-24; rounding of the
-// differences, the projection parameter's second-order effect, sqrt), which
-// the (1 - 2^-18) factor and the 2^-17 |AB|_s slack remove; the scales are
-// rounded toward zero, R is rounded up, and the final (1 - 2^-20) factor
-// covers the remaining float32 roundings.
+// the true one by at most 8u D + 14u |AB|_s (u = 2^-24; rounding of the
+// differences, the projection parameter's second-order effect, and the
+// hardware square root v_sqrt_f32, within 1 ulp = 2u relative), which the
+// (1 - 2^-18) = (1 - 64u) factor and the 2^-17 |AB|_s slack remove; the
+// scales are rounded toward zero, R is rounded up, and the final (1 - 2^-20)
+// factor covers the remaining float32 roundings.  (The square root flushes a
+// denormal argument to 0: a smaller distance, still a lower bound.)
 __device__ __forceinline__ float seg_lb(const SegView &v, const QueryPoint &q, const float sf[4]) {
   if (v.r0.w >= q.thrf) return __builtin_huge_valf();
   const float abx = v.r1.x, aby = v.r1.y, abz = v.r1.z;
@@ -112,7 +114,7 @@ __device__ __forceinline__ float seg_lb(const SegView &v, const QueryPoint &q, c
   const float del = fminf(fmaxf(dot * v.r2.x, 0.0f), 1.0f);
   const float rx = apx - del * abx, ry = apy - del * aby, rz = apz - del * abz;
   const float d2 = sf[0] * (rx * rx) + sf[1] * (ry * ry) + sf[2] * (rz * rz);
-  const float dlo = sqrtf(d2) * (1.0f - 0x1p-18f) - v.r2.z;
+  const float dlo = __builtin_amdgcn_sqrtf(d2) * (1.0f - 0x1p-18f) - v.r2.z;
   const float g = fmaxf(dlo - v.r2.y, 0.0f);
   const float gt = fmaxf(fmaxf(q.t - v.r1.w, q.gwf), 0.0f);
   // saturated like block_lb (an overflow gives a NaN or +inf on the way,

@@ -209,8 +209,9 @@ struct Searcher {
   // bound and its block's bound; every segment with prev < key <= min(tau,
   // k-th) is scanned (seeded segments excluded).  Rounds use increasing tau,
   // so a segment is scanned in the first round whose tau reaches its key, or
-  // never when its key already exceeded the k-th distance then.  Returns the largest finite
-  // block bound seen (uniform).
+  // never when its key already exceeded the k-th distance then.  Returns, per
+  // lane, the largest finite block or superblock bound that lane saw (the
+  // caller reduces it only in the rare round that found fewer than k points).
   __device__ float round(double prev, double tau, int seed_block, uint64_t seed_mask) {
     const int nb = ix.n_blocks;
     const int ns = ix.n_super;
@@ -263,7 +264,7 @@ struct Searcher {
         }
       }
     }
-    return wave_max_nonneg(maxfin);
+    return maxfin;
   }
 };
 
@@ -415,7 +416,7 @@ __device__ __forceinline__ void answer_query_with(const IndexDesc &ix, const Pre
         tau = se.tk.kd;
       } else {
         tau = fmax(tau * 16.0, floor_tau);
-        if (tau >= (double)maxfin) tau = kInf;
+        if (tau >= (double)wave_max_nonneg(maxfin)) tau = kInf;
       }
     }
   }
