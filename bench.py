@@ -39,13 +39,14 @@ FLOPS_POINT_F32 = 2        # float32
 # HBM traffic of one learned-radius search launch on this workload, from two
 # rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE, KiB per dispatch), each
 # scaled by what the counter reads for a 256 MiB device-to-device copy
-# (FETCH_SIZE x 2.00, WRITE_SIZE x 1.00): 102,500 KiB fetched and 40,598 KiB
-# written.  It describes the kernel built from the sources with this SHA-256
+# (FETCH_SIZE x 2.00, WRITE_SIZE x 1.00): 111,865 KiB fetched (x 2 = 229.1 MB)
+# and 40,451 KiB written (41.4 MB).  It describes the kernel built from the
+# sources with this SHA-256 (the search kernel's sources and the C header)
 # only; after any change to them the figure is reported as null.
-KERNEL_SOURCES = ("query.hip", "bounds.h", "wave.h", "tnn_internal.h")
+KERNEL_SOURCES = ("query.hip", "query.h", "bounds.h", "wave.h", "gka.h", "tnn_internal.h")
 MEASURED_TRAFFIC = {
-    "sha256": "4bcb55d9e84193525e2dd61a3064627bc844eddd34795f452db9b16c8ba326cb",
-    "bytes_per_launch": 272.8e6,
+    "sha256": "e9ab675f28578f129adafa1a0961034734da5a3cfc361732d7a15d647451733d",
+    "bytes_per_launch": 270.5e6,
 }
 
 
@@ -64,6 +65,8 @@ def measured_traffic():
     for f in KERNEL_SOURCES:
         with open(os.path.join(ROOT, "paper_2112_10408_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
+    with open(os.path.join(ROOT, "include", "tnn.h"), "rb") as fh:
+        h.update(fh.read())
     return MEASURED_TRAFFIC["bytes_per_launch"] if h.hexdigest() == MEASURED_TRAFFIC["sha256"] else None
 
 
@@ -75,6 +78,9 @@ def strategy_name(capi, flags):
     if not flags & capi.TNN_LEARNED:
         return "plain (the learned radius did not pay on the training queries)"
     return "learned radius + plain seed" if flags & capi.TNN_LEARNED_SEED else "learned radius"
+
+
+STRATEGY = "auto"  # --radius-strategy
 
 
 def choose_radius(T, capi, radius, model, ptr, pdist, ix, scale, tw, k, quantiles, stream,
@@ -96,12 +102,17 @@ def choose_radius(T, capi, radius, model, ptr, pdist, ix, scale, tw, k, quantile
     def run_plain():
         T.tnn_query(ix, *ptr, scale, tw, k, out=out, scratch=scr, query_scale=query_scale)
 
-    ms = timed(run_plain, steps, warmup, stream)
-    log(f"  plain TNN: {ms:.3f} ms on the training queries")
-    best = (ms, None, 1.0, 0)
-    for qnt in quantiles:
+    best = None
+    if STRATEGY in ("auto", "plain"):
+        ms = timed(run_plain, steps, warmup, stream)
+        log(f"  plain TNN: {ms:.3f} ms on the training queries")
+        best = (ms, None, 1.0, 0)
+    flag_sets = {"auto": (capi.TNN_LEARNED, capi.TNN_LEARNED | capi.TNN_LEARNED_SEED),
+                 "plain": (), "learned": (capi.TNN_LEARNED,),
+                 "seeded": (capi.TNN_LEARNED | capi.TNN_LEARNED_SEED,)}[STRATEGY]
+    for qnt in (quantiles if flag_sets else ()):
         a = radius.calibrate(model, *ptr, pdist, k, quantile=qnt)
-        for fl in (capi.TNN_LEARNED, capi.TNN_LEARNED | capi.TNN_LEARNED_SEED):
+        for fl in flag_sets:
             def run():
                 T.tnn_radius_infer(model, *ptr, a, out=r2)
                 T.tnn_query(ix, *ptr, scale, tw, k, flags=fl, radius2=r2, out=out, scratch=scr,
@@ -414,9 +425,16 @@ def main():
     ap.add_argument("--radius-quantile", type=float, default=0.99,
                     help="calibration quantile of the radius safety factor (default 0.99); "
                          "0 sweeps 0.9-0.995 and keeps the fastest on the training queries")
+    ap.add_argument("--radius-strategy", default="auto",
+                    choices=("auto", "plain", "learned", "seeded"),
+                    help="auto (default): the fastest of plain TNN, learned radius and learned "
+                         "radius + plain seed on the training queries; the others force one "
+                         "(profilers distort the timing the automatic choice relies on)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a 256 MiB device-to-device copy (counter calibration)")
     args = ap.parse_args()
+    global STRATEGY
+    STRATEGY = args.radius_strategy
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(queries shard across GPUs with a replicated index; see the design notes)",
