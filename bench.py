@@ -74,6 +74,17 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def scratch_for(T, capi, ix, n, scale, tw, k, model=None):
+    """Scratch for plain TNN and for the learned search with the radius
+    predicted inside the call (the larger of the two workspaces)."""
+    import torch
+    need = T.tnn_query_workspace(ix, n, T.make_params(scale, tw, k))
+    if model is not None:
+        need = max(need, T.tnn_query_workspace(
+            ix, n, T.make_params(scale, tw, k, capi.TNN_LEARNED, radius_model=model)))
+    return torch.empty(max(need, 256), dtype=torch.uint8, device="cuda")
+
+
 def strategy_name(capi, flags):
     if not flags & capi.TNN_LEARNED:
         return "plain (the learned radius did not pay on the training queries)"
@@ -94,11 +105,10 @@ def choose_radius(T, capi, radius, model, ptr, pdist, ix, scale, tw, k, quantile
     plain TNN was kept."""
     import torch
     n = ptr[0].shape[0]
-    r2 = torch.empty(n, dtype=torch.float32, device="cuda")
     out = (torch.empty((n, k), dtype=torch.int32, device="cuda"),
            torch.empty((n, k), dtype=torch.float64, device="cuda"))
-    scr = torch.empty(max(T.tnn_query_workspace(ix, n, T.make_params(scale, tw, k)), 256),
-                      dtype=torch.uint8, device="cuda")
+    scr = scratch_for(T, capi, ix, n, scale, tw, k, model)
+
     def run_plain():
         T.tnn_query(ix, *ptr, scale, tw, k, out=out, scratch=scr, query_scale=query_scale)
 
@@ -113,10 +123,9 @@ def choose_radius(T, capi, radius, model, ptr, pdist, ix, scale, tw, k, quantile
     for qnt in (quantiles if flag_sets else ()):
         a = radius.calibrate(model, *ptr, pdist, k, quantile=qnt)
         for fl in flag_sets:
-            def run():
-                T.tnn_radius_infer(model, *ptr, a, out=r2)
-                T.tnn_query(ix, *ptr, scale, tw, k, flags=fl, radius2=r2, out=out, scratch=scr,
-                            query_scale=query_scale)
+            def run():  # radius predicted inside the call
+                T.tnn_query(ix, *ptr, scale, tw, k, flags=fl, radius_model=model, radius_alpha=a,
+                            out=out, scratch=scr, query_scale=query_scale)
             ms = timed(run, steps, warmup, stream)
             log(f"  quantile {qnt}, {'seeded' if fl & capi.TNN_LEARNED_SEED else 'unseeded'}: "
                 f"alpha {a:.3f}, {ms:.3f} ms on the training queries")
@@ -260,8 +269,7 @@ def run_config(name, args, T, capi, radius, synth, torch, stream):
     n = qs.n
     out = (torch.empty((n, k), dtype=torch.int32, device="cuda"),
            torch.empty((n, k), dtype=torch.float64, device="cuda"))
-    scratch = torch.empty(max(T.tnn_query_workspace(ix, n, T.make_params(scale, tw, k)), 256),
-                          dtype=torch.uint8, device="cuda")
+    scratch = scratch_for(T, capi, ix, n, scale, tw, k)
     steps = max(1, min(args.steps, 5))
     res = {"points": ps.n, "queries": n, "k": k, "seg_len": K, "t_window": tw,
            "index_build_s": build_s}
@@ -269,6 +277,10 @@ def run_config(name, args, T, capi, radius, synth, torch, stream):
     def plain():
         T.tnn_query(ix, *q, scale, tw, k, out=out, scratch=scratch)
 
+    ms = timed(plain, steps, 1, stream)
+    # small workloads take well under a millisecond per call: time enough calls
+    # that each measurement spans about 20 ms
+    steps = int(min(200, max(steps, 20.0 / max(ms, 1e-3))))
     ms = timed(plain, steps, 1, stream)
     ref = (out[0].clone(), out[1].clone())
     res["plain_qps"] = n / ms * 1e3
@@ -286,21 +298,19 @@ def run_config(name, args, T, capi, radius, synth, torch, stream):
     torch.cuda.synchronize()
     res["radius_train_s"] = time.perf_counter() - t0
     res["radius_train_queries"] = tq.n
-    r2 = torch.empty(n, dtype=torch.float32, device="cuda")
     best = choose_radius(T, capi, radius, model, ptr, pdist, ix, scale, tw, k,
                          RADIUS_QUANTILES if not args.radius_quantile else (args.radius_quantile,),
                          stream, steps=2)
     alpha, lflags = best[2], best[3]
+    scratch = scratch_for(T, capi, ix, n, scale, tw, k, model)
 
-    def learned():
-        if lflags:
-            T.tnn_radius_infer(model, *q, alpha, out=r2)
-        T.tnn_query(ix, *q, scale, tw, k, flags=lflags, radius2=r2, out=out, scratch=scratch)
+    def learned(**kw):  # the radius predicted inside the call
+        T.tnn_query(ix, *q, scale, tw, k, flags=lflags, radius_model=model if lflags else None,
+                    radius_alpha=alpha, out=out, scratch=scratch, **kw)
 
     ms_l = timed(learned, steps, 1, stream)
     st = T.new_stats()
-    T.tnn_query(ix, *q, scale, tw, k, flags=lflags, radius2=r2, out=out,
-                scratch=scratch, stats=st)
+    learned(stats=st)
     torch.cuda.synchronize()
     st = T.stats_dict(st)
     res.update(learned_qps=n / ms_l * 1e3, learned_speedup_vs_plain=ms / ms_l,
@@ -378,18 +388,15 @@ def run_query_scales(args, T, capi, radius, synth, torch, stream):
     best = choose_radius(T, capi, radius, model, ptr, pdist, ix, scale, tw, k, (BATCH_QUANTILE,),
                          stream, steps=2, query_scale=tr_rows)
     alpha, lflags = best[2], best[3]
-    r2 = torch.empty(n, dtype=torch.float32, device="cuda")
+    scratch = scratch_for(T, capi, ix, n, scale, tw, k, model)
 
-    def learned():
-        if lflags:
-            T.tnn_radius_infer(model, *q, alpha, out=r2)
-        T.tnn_query(ix, *q, scale, tw, k, flags=lflags, radius2=r2, out=out,
-                    scratch=scratch, query_scale=qscale)
+    def learned(**kw):  # the radius predicted inside the call
+        T.tnn_query(ix, *q, scale, tw, k, flags=lflags, radius_model=model if lflags else None,
+                    radius_alpha=alpha, out=out, scratch=scratch, query_scale=qscale, **kw)
 
     ms_l = timed(learned, steps, 1, stream)
     st = T.new_stats()
-    T.tnn_query(ix, *q, scale, tw, k, flags=lflags, radius2=r2, out=out,
-                scratch=scratch, stats=st, query_scale=qscale)
+    learned(stats=st)
     torch.cuda.synchronize()
     st = T.stats_dict(st)
     res.update(learned_qps=n / ms_l * 1e3, learned_speedup_vs_plain=ms / ms_l,
@@ -496,25 +503,33 @@ def main():
     alpha, lflags = best[2], best[3]
 
     # ---- learned TNN: the headline step (radius inference + search) ---------
-    def learned():
-        if lflags:
-            T.tnn_radius_infer(model, qx, qy, qz, qt, alpha, out=r2)
-        T.tnn_query(ix, qx, qy, qz, qt, scale, 0.0, k, flags=lflags, radius2=r2,
-                    out=out, scratch=scratch)
+    # one call: the library predicts the radius in the launch of its per-call
+    # preparation, then searches
+    scratch = scratch_for(T, capi, ix, qs.n, scale, 0.0, k, model)
+
+    def learned(**kw):
+        T.tnn_query(ix, qx, qy, qz, qt, scale, 0.0, k, flags=lflags,
+                    radius_model=model if lflags else None, radius_alpha=alpha, out=out,
+                    scratch=scratch, **kw)
 
     ms_learned = timed(learned, args.steps, args.warmup, stream)
 
-    def learned_search_only():
-        T.tnn_query(ix, qx, qy, qz, qt, scale, 0.0, k, flags=lflags, radius2=r2,
-                    out=out, scratch=scratch)
+    # the search alone (radius predicted beforehand, not timed): the time the
+    # roofline of the search kernel is taken over
+    if lflags:
+        T.tnn_radius_infer(model, qx, qy, qz, qt, alpha, out=r2)
+
+    def learned_search_only(**kw):
+        T.tnn_query(ix, qx, qy, qz, qt, scale, 0.0, k, flags=lflags, radius2=r2 if lflags else None,
+                    out=out, scratch=scratch, **kw)
 
     ms_search = timed(learned_search_only, args.steps, 1, stream)
     exact = bool(torch.equal(out[0], ref_idx)) and bool(torch.equal(out[1], ref_dist))
     stats = T.new_stats()
-    T.tnn_query(ix, qx, qy, qz, qt, scale, 0.0, k, flags=lflags, radius2=r2,
-                stats=stats, out=out, scratch=scratch)
+    learned(stats=stats)
     torch.cuda.synchronize()
     st = T.stats_dict(stats)
+    exact = exact and bool(torch.equal(out[0], ref_idx)) and bool(torch.equal(out[1], ref_dist))
     log(f"learned TNN: {ms_learned:.3f} ms/step ({ms_search:.3f} ms search), "
         f"{qs.n / ms_learned * 1e3:.0f} q/s, same as plain {exact}, fallbacks {st['fallbacks']}")
     log("learned stats:", st)
@@ -524,20 +539,14 @@ def main():
     wind = torch.from_numpy(np.random.default_rng(cfg["seed"] + 3000)
                             .normal(0.0, 15.0, (ps.n, 2)).astype(np.float32)).cuda()
     gka_out = torch.empty((qs.n, 2), dtype=torch.float64, device="cuda")
-    if lflags:
-        T.tnn_radius_infer(model, qx, qy, qz, qt, alpha, out=r2)
-    T.tnn_query(ix, qx, qy, qz, qt, scale, 0.0, k, flags=lflags, radius2=r2,
-                out=out, scratch=scratch)
+    learned()
     ms_gka = timed(lambda: T.tnn_gka_average(out[0], out[1], wind, out=gka_out), args.steps, 1,
                    stream)
     gka_sep = gka_out.clone()
 
     # the averaging as the search's epilogue, from the top-k in registers
     def learned_gka():
-        if lflags:
-            T.tnn_radius_infer(model, qx, qy, qz, qt, alpha, out=r2)
-        T.tnn_query(ix, qx, qy, qz, qt, scale, 0.0, k, flags=lflags, radius2=r2,
-                    out=out, scratch=scratch, gka_values=wind, gka_out=gka_out)
+        learned(gka_values=wind, gka_out=gka_out)
 
     ms_learned_gka = timed(learned_gka, args.steps, 1, stream)
     # byte comparison: queries without a past have NaN rows on both sides

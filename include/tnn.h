@@ -101,9 +101,10 @@ typedef struct {
                                first (1..64; 0 = 4).  TNN only. */
   int32_t waves_per_block;  /* launch shape: 1, 2, 4 or 8 waves of 64 lanes (0 = 4) */
   const float *d_radius2;   /* device [n_queries] predicted k-th distance (metric units,
-                               squared).  Required with TNN_LEARNED, else ignored.  Any
-                               value (0, inf, NaN) keeps results exact; it only changes
-                               the work done. */
+                               squared).  With TNN_LEARNED exactly one of d_radius2 and
+                               radius_model (below) is set; else ignored.  Any value (0,
+                               inf, NaN) keeps results exact; it only changes the work
+                               done. */
   unsigned long long *d_stats; /* device [TNN_STAT_COUNT] or NULL */
   const double *d_query_scale; /* device [n_queries][4] per-query scales (s_x, s_y, s_z,
                                s_t) replacing `scale` for each query, or NULL (`scale` is
@@ -126,7 +127,14 @@ typedef struct {
   double *d_gka_out;           /* device binary64 [n_queries][gka_comp]; NaN rows for
                                   queries without context (or without a metric) */
   int32_t gka_comp;            /* components per point, 1..8 (with d_gka_values) */
-  int32_t reserved;
+  /* Radius predicted inside the call: with TNN_LEARNED and radius_model set
+   * (and d_radius2 NULL), tnn_query predicts each query's k-th distance
+   * (radius_alpha * exp(out))^2 with the model, as tnn_radius_infer does, into
+   * its scratch, in the same launch as its per-call preparation; results are
+   * those of calling tnn_radius_infer first and passing d_radius2.  Not with
+   * TNN_BRUTE or in a tnn_query_batched item (TNN_E_UNSUPPORTED). */
+  float radius_alpha;          /* > 0, finite (with radius_model) */
+  const void *radius_model;    /* device tnn_radius_model, or NULL */
 } tnn_query_params;
 
 /* Human-readable name of a status code (static string). */
@@ -167,7 +175,8 @@ tnn_status tnn_index_info(const tnn_index *index, int64_t *n_points, int64_t *n_
 
 /* Scratch bytes tnn_query needs for n_queries queries with these params.
  * TNN: the per-call segment records (constants that depend on the scales)
- * and the counters of the search's work queues.  TNN_BRUTE: none (256).
+ * and the counters of the search's work queues (and 4 B per query for the
+ * predicted radius when params->radius_model is set).  TNN_BRUTE: none (256).
  * TNN_BRUTE | TNN_MIXED_BF16: the BF16 point operands (64 B per point,
  * padded to 128 points), |v|^2 per point, each query's per-chunk top-k lists
  * (12 B per slot, 1 to 8 chunks chosen from n_queries and the point count)

@@ -62,7 +62,7 @@ class TnnQueryParams(ctypes.Structure):
     _fields_ = [("scale", f64 * 4), ("t_window", f64), ("k", i32), ("flags", u32),
                 ("seed_segments", i32), ("waves_per_block", i32), ("d_radius2", P),
                 ("d_stats", P), ("d_query_scale", P), ("d_gka_values", P), ("d_gka_out", P),
-                ("gka_comp", i32), ("reserved", i32)]
+                ("gka_comp", i32), ("radius_alpha", f32), ("radius_model", P)]
 
 
 class TnnBatchItem(ctypes.Structure):

@@ -42,7 +42,13 @@ tnn_status check_params(const tnn_query_params *p, int64_t n_queries = 1) {
   if (p->k < 1 || p->k > kMaxK) return TNN_E_ARG;
   if (p->flags & ~(TNN_BRUTE | TNN_MIXED_BF16 | TNN_LEARNED | TNN_LEARNED_SEED)) return TNN_E_ARG;
   if ((p->flags & TNN_LEARNED_SEED) && !(p->flags & TNN_LEARNED)) return TNN_E_ARG;
-  if ((p->flags & TNN_LEARNED) && !p->d_radius2 && n_queries > 0) return TNN_E_ARG;
+  if ((p->flags & TNN_LEARNED) && !p->d_radius2 && !p->radius_model && n_queries > 0)
+    return TNN_E_ARG;
+  if (p->radius_model) {
+    if (p->d_radius2 || !(p->flags & TNN_LEARNED)) return TNN_E_ARG;
+    if (!(p->radius_alpha > 0.0f) || !std::isfinite(p->radius_alpha)) return TNN_E_ARG;
+    if (p->flags & TNN_BRUTE) return TNN_E_UNSUPPORTED;
+  }
   if ((p->flags & TNN_MIXED_BF16) && !(p->flags & TNN_BRUTE)) return TNN_E_UNSUPPORTED;
   // the BF16 operands carry the scales: one metric per call
   if ((p->flags & TNN_MIXED_BF16) && p->d_query_scale) return TNN_E_UNSUPPORTED;
@@ -70,6 +76,8 @@ QueryArgs make_args(const tnn_query_params *p) {
   a.seed_segments = p->seed_segments ? p->seed_segments : 4;
   a.floor_tau = 1e-300;  // set from the index by the callers that search
   a.radius2 = p->d_radius2;
+  a.model = static_cast<const tnn_radius_model *>(p->radius_model);
+  a.alpha = p->radius_alpha;
   a.stats = p->d_stats;
   a.gka_values = p->d_gka_values;
   a.gka_comp = p->d_gka_values ? p->gka_comp : 0;
@@ -77,14 +85,19 @@ QueryArgs make_args(const tnn_query_params *p) {
   return a;
 }
 
-// kSegRec float4 per segment, then 16 work-queue counters 256 bytes apart
-size_t prep_bytes(int64_t S) { return align_up(16 * kSegRec * (size_t)S) + 16 * 256; }
+// kSegRec float4 per segment, then 16 work-queue counters 256 bytes apart,
+// then (in-call radius prediction) one float per query
+size_t prep_bytes(int64_t S, int64_t n_radius = 0) {
+  return align_up(16 * kSegRec * (size_t)S) + 16 * 256 + align_up(4 * (size_t)n_radius);
+}
 
-Prep prep_view(void *scratch, int64_t S) {
+Prep prep_view(void *scratch, int64_t S, bool radius = false) {
   char *b = static_cast<char *>(scratch);
   Prep p;
   p.rec = reinterpret_cast<float4 *>(b);
   p.ticket = reinterpret_cast<unsigned long long *>(b + align_up(16 * kSegRec * (size_t)S));
+  p.radius2 = radius ? reinterpret_cast<float *>(b + align_up(16 * kSegRec * (size_t)S) + 16 * 256)
+                     : nullptr;
   return p;
 }
 
@@ -294,7 +307,9 @@ tnn_status tnn_query_workspace(const tnn_index *index, int64_t n_queries,
   if (params->flags & TNN_MIXED_BF16)
     *bytes = mixed_scratch_bytes(d->n_points, n_queries, params->k);
   else
-    *bytes = (params->flags & TNN_BRUTE) ? 256 : prep_bytes(d->n_seg);
+    *bytes = (params->flags & TNN_BRUTE)
+                 ? 256
+                 : prep_bytes(d->n_seg, params->radius_model ? n_queries : 0);
   return TNN_OK;
 }
 
@@ -333,10 +348,16 @@ tnn_status tnn_query(const tnn_index *index, tnn_points queries, const tnn_query
                                d->n_points, a.gka_out, st));
     return TNN_OK;
   }
-  const Prep pr = prep_view(d_scratch, d->n_seg);
+  const Prep pr = prep_view(d_scratch, d->n_seg, a.model != nullptr);
   QueryArgs at = a;
   at.floor_tau = radius_floor(d->lo, d->hi, a.s);
-  TNN_HIP_CHECK(launch_prep(*d, at, pr, st, params->d_query_scale != nullptr));
+  if (a.model && queries.n > 0) {
+    // the radius prediction shares the preparation's launch
+    at.radius2 = pr.radius2;
+    TNN_HIP_CHECK(launch_prep_infer(*d, at, pr, queries, st, params->d_query_scale != nullptr));
+  } else {
+    TNN_HIP_CHECK(launch_prep(*d, at, pr, st, params->d_query_scale != nullptr));
+  }
   TNN_HIP_CHECK(launch_query(*d, pr, at, queries, wpb, d_out_idx, d_out_dist, st,
                              params->d_query_scale));
   return TNN_OK;
@@ -419,7 +440,7 @@ tnn_status check_items(const tnn_batch_item *items, int32_t n) {
     const tnn_status c = check_params(&it.params, it.queries.n);
     if (c != TNN_OK) return c;
     if (it.params.flags & (TNN_BRUTE | TNN_MIXED_BF16)) return TNN_E_UNSUPPORTED;
-    if (it.params.d_query_scale) return TNN_E_UNSUPPORTED;
+    if (it.params.d_query_scale || it.params.radius_model) return TNN_E_UNSUPPORTED;
     const IndexDesc *d = desc_of(it.index);
     if (!scaled_box_ok(d->lo, d->hi, it.params.scale)) return TNN_E_UNSUPPORTED;
     if (it.queries.n > 0 && (!it.d_out_idx || !it.d_out_dist)) return TNN_E_ARG;

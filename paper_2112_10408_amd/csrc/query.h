@@ -43,6 +43,10 @@ hipError_t launch_batch(const BatchLaunch &bl, hipStream_t st);
 // per-call cylinder constants (each query forms its own).
 hipError_t launch_prep(const IndexDesc &ix, const QueryArgs &a, const Prep &pr, hipStream_t st,
                        bool per_query_scales = false);
+// The preparation and, in the same launch, the radius prediction of every
+// query into pr.radius2 with a.model and a.alpha.
+hipError_t launch_prep_infer(const IndexDesc &ix, const QueryArgs &a, const Prep &pr,
+                             const tnn_points &qs, hipStream_t st, bool per_query_scales);
 // query_scale: per-query scales [n][4] (device) or null for the shared ones.
 hipError_t launch_query(const IndexDesc &ix, const Prep &pr, const QueryArgs &a,
                         const tnn_points &qs, int waves_per_block, int32_t *out_idx,

@@ -5,6 +5,7 @@
 #include "bounds.h"
 #include "gka.h"
 #include "query.h"
+#include "radius_infer.h"
 
 namespace tnn {
 
@@ -81,6 +82,22 @@ __global__ void prep_kernel(IndexDesc ix, QueryArgs a, float4 *rec, unsigned lon
   if (s < kQueues && ticket) ticket[s * kTicketStride] = 0;
   if (s >= ix.n_seg) return;
   prep_one(ix, a, rec, s, raw);
+}
+
+// The preparation (workgroups below prep_blocks) and the radius prediction of
+// every query (the others, one tile loop each), in one launch: the two are
+// independent, and the search needs both.
+__global__ __launch_bounds__(64 * radius::kInferWaves) void prep_infer_kernel(
+    IndexDesc ix, QueryArgs a, float4 *rec, unsigned long long *ticket, bool raw,
+    int64_t prep_blocks, tnn_points q, float *radius2, int64_t infer_groups) {
+  if ((int64_t)blockIdx.x < prep_blocks) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < kQueues && ticket) ticket[s * kTicketStride] = 0;
+    if (s < ix.n_seg) prep_one(ix, a, rec, s, raw);
+    return;
+  }
+  radius::infer_tiles(a.model, q, a.alpha, radius2, nullptr, (int64_t)blockIdx.x - prep_blocks,
+                      infer_groups);
 }
 
 // Copy n float4 from global memory to LDS with this workgroup's threads, four
@@ -776,6 +793,19 @@ hipError_t launch_prep(const IndexDesc &ix, const QueryArgs &a, const Prep &pr, 
   const int64_t grid = ix.n_seg > 0 ? (ix.n_seg + tpb - 1) / tpb : 1;
   hipLaunchKernelGGL(prep_kernel, dim3((unsigned)grid), dim3(tpb), 0, st, ix, a, pr.rec,
                      pr.ticket, per_query_scales);
+  return hipGetLastError();
+}
+
+hipError_t launch_prep_infer(const IndexDesc &ix, const QueryArgs &a, const Prep &pr,
+                             const tnn_points &qs, hipStream_t st, bool per_query_scales) {
+  constexpr int tpb = 64 * radius::kInferWaves;
+  const int64_t prep_blocks = ix.n_seg > 0 ? (ix.n_seg + tpb - 1) / tpb : 1;
+  const int64_t per_group = (int64_t)radius::kInferTile * radius::kInferWaves;
+  const int64_t groups = (qs.n + per_group - 1) / per_group;
+  const int64_t infer_groups = groups < 1024 ? groups : 1024;
+  hipLaunchKernelGGL(prep_infer_kernel, dim3((unsigned)(prep_blocks + infer_groups)), dim3(tpb), 0,
+                     st, ix, a, pr.rec, pr.ticket, per_query_scales, prep_blocks, qs, pr.radius2,
+                     infer_groups);
   return hipGetLastError();
 }
 

@@ -50,6 +50,7 @@ constexpr int kSegRec = 4;
 struct Prep {
   float4 *rec;
   unsigned long long *ticket;  // work-queue counters of the resident search kernel
+  float *radius2;              // predicted radii (in-call prediction) or null
 };
 
 struct QueryArgs {
@@ -63,6 +64,9 @@ struct QueryArgs {
   const float *radius2;
   unsigned long long *stats;
   double floor_tau;    // smallest search radius a growing round starts from (radius_floor)
+  // radius predicted by the preparation launch (model null: none)
+  const tnn_radius_model *model;
+  float alpha;
   // Gaussian kernel averaging epilogue (gka_values null: none)
   const float *gka_values;
   int32_t gka_comp;

@@ -78,7 +78,8 @@ def tnn_build_segments(x, y, z, t, traj_offsets, seg_len, order_scale=(1.0, 1.0,
 
 
 def make_params(scale, t_window, k, flags=0, seed_segments=0, waves_per_block=0, radius2=None,
-                stats=None, query_scale=None, gka_values=None, gka_out=None):
+                stats=None, query_scale=None, gka_values=None, gka_out=None, radius_model=None,
+                radius_alpha=1.0):
     p = TnnQueryParams()
     for i in range(4):
         p.scale[i] = float(scale[i])
@@ -104,6 +105,9 @@ def make_params(scale, t_window, k, flags=0, seed_segments=0, waves_per_block=0,
         p.d_gka_values = _ptr(gka_values)
         p.d_gka_out = _ptr(gka_out)
         p.gka_comp = int(gka_values.shape[1])
+    if radius_model is not None:
+        p.radius_model = _ptr(radius_model)
+        p.radius_alpha = float(radius_alpha)
     return p
 
 
@@ -128,12 +132,15 @@ def stats_dict(stats):
 
 def tnn_query(index, qx, qy, qz, qt, scale, t_window, k, flags=0, seed_segments=0,
               waves_per_block=0, radius2=None, stats=None, out=None, scratch=None,
-              query_scale=None, gka_values=None, gka_out=None):
+              query_scale=None, gka_values=None, gka_out=None, radius_model=None,
+              radius_alpha=1.0):
     """Returns (idx int32 [nq, k], dist float64 [nq, k]) device tensors.
     query_scale: optional float64 [nq, 4] device tensor of per-query scales
     (replaces `scale`, which must still be valid).  gka_values (float32
     [n_points, n_comp]) with gka_out (float64 [nq, n_comp]): also the Gaussian
-    kernel average of the values over each query's neighbours."""
+    kernel average of the values over each query's neighbours.  radius_model
+    (with TNN_LEARNED, radius2 None): the library predicts the radius itself,
+    scaled by radius_alpha, in the launch of its per-call preparation."""
     L = capi.lib()
     nq = qx.shape[0]
     if query_scale is not None and query_scale.shape[0] != nq:
@@ -143,7 +150,7 @@ def tnn_query(index, qx, qy, qz, qt, scale, t_window, k, flags=0, seed_segments=
     if gka_values is not None and gka_out is None:
         gka_out = torch.empty((nq, gka_values.shape[1]), dtype=torch.float64, device=qx.device)
     params = make_params(scale, t_window, k, flags, seed_segments, waves_per_block, radius2, stats,
-                         query_scale, gka_values, gka_out)
+                         query_scale, gka_values, gka_out, radius_model, radius_alpha)
     need = tnn_query_workspace(index, nq, params)
     if scratch is None or scratch.numel() < need:
         scratch = torch.empty(max(need, 256), dtype=torch.uint8, device=qx.device)
@@ -157,7 +164,7 @@ def tnn_query(index, qx, qy, qz, qt, scale, t_window, k, flags=0, seed_segments=
 
 def tnn_query_noalloc(index, qx, qy, qz, qt, scale, t_window, k, flags=0, seed_segments=0,
                       waves_per_block=0, radius2=None, stats=None, out=None, query_scale=None,
-                      gka_values=None, gka_out=None):
+                      gka_values=None, gka_out=None, radius_model=None, radius_alpha=1.0):
     """tnn_query with the library's own per-device scratch (no scratch
     argument; the library allocates nothing).  Returns (idx, dist); `out`
     supplies them preallocated."""
@@ -166,7 +173,7 @@ def tnn_query_noalloc(index, qx, qy, qz, qt, scale, t_window, k, flags=0, seed_s
     if query_scale is not None and query_scale.shape[0] != nq:
         raise ValueError("query_scale needs one row per query")
     params = make_params(scale, t_window, k, flags, seed_segments, waves_per_block, radius2, stats,
-                         query_scale, gka_values, gka_out)
+                         query_scale, gka_values, gka_out, radius_model, radius_alpha)
     if out is None:
         out = (torch.empty((nq, k), dtype=torch.int32, device=qx.device),
                torch.empty((nq, k), dtype=torch.float64, device=qx.device))

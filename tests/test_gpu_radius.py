@@ -302,3 +302,38 @@ def test_learned_radius_gains_time_on_one_million_points():
     say(f"plain {mp:.4f} ms, learned step {ml:.4f} ms, gain {mp / ml:.3f}x")
     assert torch.equal(out[0], ref[0]) and torch.equal(out[1], ref[1])
     assert ml < mp
+
+
+@pytest.mark.parametrize("seeded", [False, True], ids=["unseeded", "seeded"])
+def test_radius_predicted_inside_the_call(setup, seeded):
+    """With the model passed to tnn_query the library predicts the radius in
+    its preparation launch: the same bytes and the same work counters as
+    predicting first with tnn_radius_infer, and the oracle's result; argument
+    checks of the combination."""
+    ps, ix, model, lo, hi, grids = setup
+    rng = np.random.default_rng(21)
+    qs = ps.take(np.sort(rng.choice(ps.n, 3000, replace=False)))
+    q = dev_points(qs)
+    k = 16
+    fl = capi.TNN_LEARNED | (capi.TNN_LEARNED_SEED if seeded else 0)
+    r2 = T.tnn_radius_infer(model, *q, alpha=2.5)
+    st_a, st_b = T.new_stats(), T.new_stats()
+    ai, ad = T.tnn_query(ix, *q, SCALE, 0.0, k, flags=fl, radius2=r2, stats=st_a)
+    bi, bd = T.tnn_query(ix, *q, SCALE, 0.0, k, flags=fl, radius_model=model, radius_alpha=2.5,
+                         stats=st_b)
+    torch.cuda.synchronize()
+    assert torch.equal(ai, bi) and torch.equal(ad, bd)
+    assert T.stats_dict(st_a) == T.stats_dict(st_b)
+    oi, od = oracle.knn(ps.soa(), qs.soa(), SCALE, 0.0, k)
+    assert_same(bi.cpu().numpy(), bd.cpu().numpy(), oi, od, "in-call radius")
+    bad = [dict(radius2=r2, radius_model=model, radius_alpha=2.5),   # both
+           dict(radius_model=model, radius_alpha=0.0),               # alpha not positive
+           dict(radius_model=model, radius_alpha=float("nan"))]
+    for kw in bad:
+        with pytest.raises(capi.TnnError) as e:
+            T.tnn_query(ix, *q, SCALE, 0.0, k, flags=fl, **kw)
+        assert e.value.code == capi.TNN_E_ARG
+    with pytest.raises(capi.TnnError) as e:
+        T.tnn_query(ix, *q, SCALE, 0.0, k, flags=capi.TNN_LEARNED | capi.TNN_BRUTE,
+                    radius_model=model, radius_alpha=2.5)
+    assert e.value.code == capi.TNN_E_UNSUPPORTED
