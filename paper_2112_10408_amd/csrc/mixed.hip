@@ -10,10 +10,17 @@
 // Each coordinate is split into three bfloat16 terms (h + m + l carries 24
 // bits) and the six products that matter (hh, hm, mh, hl, mm, lh) fill 24 of
 // the 32 K-slots of v_mfma_f32_16x16x32_bf16; the norms, pre-scaled by
-// (1 - gamma) and split the same way, fill six more.  The tile value is then
-//     c' = (1 - gamma)(|u|^2 + |v|^2) - 2 u.v  <=  d(q, p)
-// because the split, the float32 accumulation of 32 terms and the float32
-// inputs err by at most 1.6 * 2^-18 (|u|^2 + |v|^2), below gamma = 2^-16.
+// (1 - gamma) and split the same way, fill six more, and the last two carry
+// minus the query's current bound T (two bfloat16 terms on the query side,
+// ones on the point side).  The tile value is
+//     c = (1 - gamma)(|u|^2 + |v|^2) - 2 u.v - T .
+// Without the T terms it errs by at most 1.6 * 2^-18 (|u|^2 + |v|^2) (the
+// split, the float32 accumulation of 32 terms and the float32 inputs),
+// below gamma = 2^-16; the T terms add at most 31 * 2^-23 T < 2^-18 T to the
+// accumulation error.  So c < d - (1 - 2^-18) T, and with T >= tau (1 + 2^-16)
+// and T >= 2^-100 every pair whose distance is at most the query's k-th
+// distance bound tau gets a negative tile value: the sign bit is the filter,
+// and one OR over a batch of tile values tells whether any pair passes.
 #include <mutex>
 
 #include "bounds.h"
@@ -29,14 +36,18 @@ constexpr float kGamma = 0x1p-16f;
 // Largest scaled squared norm |u|^2 of a point or query the float32 tiles
 // take: tile values then stay below 4e30, far from float32 overflow.
 constexpr float kMaxNorm = (float)kMaxScaledNorm;
-constexpr int kWaves = 4;                 // waves per workgroup
-constexpr int kMQ = 16;                   // queries per wave (the MFMA rows)
-constexpr int kTileQ = kWaves * kMQ;      // queries per work item
-constexpr int kStage = 128;               // points per LDS stage
-constexpr int kStageTiles = kStage / 16;  // 16-column MFMA tiles per stage
-constexpr int kQCap = 64;                 // queued survivors per wave (one row of a tile)
-constexpr int kBatch = 4;                 // tiles whose reads and MFMAs are issued together
-constexpr int kMaxChunks = 8;             // point chunks per query tile
+constexpr int kWaves = 4;                   // waves per workgroup
+constexpr int kMQ = 16;                     // queries per MFMA row block
+constexpr int kRowBlocks = 4;               // row blocks per wave (four named A operands)
+constexpr int kWaveQ = kMQ * kRowBlocks;    // queries per wave
+constexpr int kTileQ = kWaves * kWaveQ;     // queries per work item
+constexpr int kStage = 128;                 // points per LDS stage
+constexpr int kStageTiles = kStage / 16;    // 16-column MFMA tiles per stage
+constexpr int kQCap = 64;                   // queued survivors per wave (one per lane)
+constexpr int kBatch = 2;                   // tiles whose tile values are tested together
+constexpr int kMaxChunks = 16;              // point chunks per query tile
+constexpr int kPilotStages = 32;            // stages of a tile's home range (pilot pass)
+constexpr int kShareSteps = 8;              // steps between two poolings of a tile's bounds
 // Workgroups resident on a full chip, nominally (256 CUs x 3): only sets
 // how finely the points are chunked, so the workspace size does not depend
 // on the device.
@@ -50,6 +61,18 @@ __device__ __forceinline__ __bf16 to_bf16(float x) {
   return __builtin_bit_cast(__bf16, h);
 }
 
+// Rounded toward +infinity (finite inputs).
+__device__ __forceinline__ __bf16 to_bf16_up(float x) {
+  const uint32_t u = __float_as_uint(x);
+  uint32_t t = u & 0xffff0000u;
+  if ((u & 0xffffu) != 0 && !(u >> 31)) t += 0x10000u;
+  return __builtin_bit_cast(__bf16, (unsigned short)(t >> 16));
+}
+
+__device__ __forceinline__ __bf16 neg_bf16(__bf16 b) {
+  return __builtin_bit_cast(__bf16, (unsigned short)(__builtin_bit_cast(unsigned short, b) ^ 0x8000u));
+}
+
 __device__ __forceinline__ float from_bf16(__bf16 b) {
   const unsigned short h = __builtin_bit_cast(unsigned short, b);
   return __uint_as_float((uint32_t)h << 16);
@@ -61,6 +84,32 @@ __device__ __forceinline__ void split3(float x, __bf16 &h, __bf16 &m, __bf16 &l)
   m = to_bf16(r1);
   const float r2 = r1 - from_bf16(m);
   l = to_bf16(r2);
+}
+
+// The bound slots of a query row: bfloat16 terms h, m with h + m >= T,
+// T = max(tau (1 + 2^-15) rounded to float, 2^-100) >= tau (1 + 2^-16), and
+// their sum as a float (for the statistics).  tau = +inf (no bound yet), or
+// T overflowing, gives h = +inf: every tile value of the row is -inf.
+// tau = -inf (a row that takes no part) gives h = -inf: tile values +inf.
+__device__ __forceinline__ void bound_terms(float tau, __bf16 &h, __bf16 &m, float &sum) {
+  const __bf16 zero = __builtin_bit_cast(__bf16, (unsigned short)0);
+  if (tau == -__builtin_huge_valf()) {
+    h = __builtin_bit_cast(__bf16, (unsigned short)0xff80u);
+    m = zero;
+    sum = -__builtin_huge_valf();
+    return;
+  }
+  const float t = fmaxf(tau * (1.0f + 0x1p-15f), 0x1p-100f);
+  const __bf16 th = to_bf16(t);
+  if (!(t < __builtin_huge_valf()) || !(from_bf16(th) < __builtin_huge_valf())) {
+    h = __builtin_bit_cast(__bf16, (unsigned short)0x7f80u);
+    m = zero;
+    sum = __builtin_huge_valf();
+    return;
+  }
+  h = th;
+  m = to_bf16_up(t - from_bf16(th));  // the difference is exact
+  sum = from_bf16(h) + from_bf16(m);
 }
 
 struct MixedCtx {
@@ -88,7 +137,7 @@ __device__ __forceinline__ bf16x8 point_group(const float v[4], float nvs, int g
 #pragma unroll
   for (int f = 0; f < 4; ++f) split3(v[f], h[f], m[f], l[f]);
   bf16x8 o;
-  const __bf16 one = to_bf16(1.0f), zero = to_bf16(0.0f);
+  const __bf16 one = to_bf16(1.0f);
   if (g == 0) {
 #pragma unroll
     for (int f = 0; f < 4; ++f) {
@@ -116,19 +165,21 @@ __device__ __forceinline__ bf16x8 point_group(const float v[4], float nvs, int g
     o[3] = nh;
     o[4] = nm;
     o[5] = nl;
-    o[6] = zero;
-    o[7] = zero;
+    o[6] = one;  // times the query's -T terms
+    o[7] = one;
   }
   return o;
 }
 
-// A operand (query side), paired slot by slot with point_group.
-__device__ __forceinline__ bf16x8 query_group(const float u[4], float nus, int g) {
+// A operand (query side), paired slot by slot with point_group; th, tm are
+// the query's bound terms (bound_terms), entered negated.
+__device__ __forceinline__ bf16x8 query_group(const float u[4], float nus, int g, __bf16 th,
+                                              __bf16 tm) {
   __bf16 h[4], m[4], l[4];
 #pragma unroll
   for (int f = 0; f < 4; ++f) split3(u[f], h[f], m[f], l[f]);
   bf16x8 o;
-  const __bf16 one = to_bf16(1.0f), zero = to_bf16(0.0f);
+  const __bf16 one = to_bf16(1.0f);
   if (g == 0) {
 #pragma unroll
     for (int f = 0; f < 4; ++f) {
@@ -156,8 +207,8 @@ __device__ __forceinline__ bf16x8 query_group(const float u[4], float nus, int g
     o[3] = one;
     o[4] = one;
     o[5] = one;
-    o[6] = zero;
-    o[7] = zero;
+    o[6] = neg_bf16(th);
+    o[7] = neg_bf16(tm);
   }
   return o;
 }
@@ -165,7 +216,8 @@ __device__ __forceinline__ bf16x8 query_group(const float u[4], float nus, int g
 // Per call: the point operands and |v|^2.  Operands are stored tile-major:
 // the 16-byte group g of point p sits at unit (p / 16 * 4 + g) * 16 + p % 16,
 // so a 16-point MFMA tile is 1 KB laid out lane by lane and a stage is one
-// contiguous block.  Operands are padded to whole stages with zeros.
+// contiguous block.  Operands are padded to whole stages with zeros (a
+// padding column's tile values are 0 or NaN: the time mask drops it).
 __global__ void mixed_prep_kernel(IndexDesc ix, MixedCtx mc, bf16x8 *ops, float *nv,
                                   int64_t n_pad) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -185,19 +237,124 @@ __global__ void mixed_prep_kernel(IndexDesc ix, MixedCtx mc, bf16x8 *ops, float 
   nv[p] = n;
 }
 
-// Per call: no chunk has a k-th distance yet; the work counter starts at 0.
-__global__ void mixed_reset_kernel(float *part_kd, int64_t n, unsigned long long *counter) {
+// Per call: no query has a bound yet; the block counts and the work counter
+// start at 0.
+__global__ void mixed_reset_kernel(float *bound, int64_t n, int32_t *bcount, int64_t nb,
+                                   unsigned long long *counter) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) part_kd[i] = __builtin_huge_valf();
+  if (i < n) bound[i] = __builtin_huge_valf();
+  if (i < nb) bcount[i] = 0;
   if (i == 0) *counter = 0;
+}
+
+// Scan order (not in the paper; any order gives the same result).  Every
+// query gets a home block: the index block nearest to it by the block box
+// lower bound, searched in the nearest superblock.  Queries are then
+// ordered by home block (a counting sort), so that a tile of kTileQ
+// consecutive queries is spatially compact, and a pilot pass scans each
+// tile's home range of stages first: its k-th distances, near the final
+// ones, bound the main pass from its first stage on.
+__global__ void mixed_home_kernel(IndexDesc ix, QueryArgs a, const float *qxp, const float *qyp,
+                                  const float *qzp, const float *qtp, int64_t nq, int32_t *home,
+                                  int32_t *bcount) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nq) return;
+  const QueryPoint qp = make_query(qxp[q], qyp[q], qzp[q], qtp[q], a.t_window);
+  int best_s = 0;
+  float lb_s = __builtin_huge_valf();
+  for (int sb = 0; sb < ix.n_super; ++sb) {
+    const float lb = block_lb(ix.sbox, sb, qp, a.sf);
+    if (lb < lb_s) {
+      lb_s = lb;
+      best_s = sb;
+    }
+  }
+  const int b_lo = best_s * kSuperBlocks;
+  const int b_hi = min(b_lo + kSuperBlocks, ix.n_blocks);
+  int best = b_lo;
+  float lb_b = __builtin_huge_valf();
+  for (int b = b_lo; b < b_hi; ++b) {
+    const float lb = block_lb(ix.box, b, qp, a.sf);
+    if (lb < lb_b) {
+      lb_b = lb;
+      best = b;
+    }
+  }
+  home[q] = best;
+  atomicAdd(bcount + best, 1);
+}
+
+// Exclusive prefix sums of the block counts, in place (one workgroup of
+// 1024 threads).
+__global__ __launch_bounds__(1024) void mixed_offsets_kernel(int32_t *bcount, int64_t nb) {
+  __shared__ int s_v[1024];
+  __shared__ int s_carry;
+  const int tid = (int)threadIdx.x;
+  if (tid == 0) s_carry = 0;
+  __syncthreads();
+  for (int64_t base = 0; base < nb; base += 1024) {
+    const int64_t i = base + tid;
+    const int v = i < nb ? bcount[i] : 0;
+    s_v[tid] = v;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+      const int add = tid >= o ? s_v[tid - o] : 0;
+      __syncthreads();
+      s_v[tid] += add;
+      __syncthreads();
+    }
+    const int carry = s_carry;
+    if (i < nb) bcount[i] = carry + s_v[tid] - v;
+    __syncthreads();
+    if (tid == 1023) s_carry = carry + s_v[1023];
+    __syncthreads();
+  }
+}
+
+// perm[position] = caller index, grouped by home block (the order within a
+// block is whatever the atomics give: only the scan order depends on it).
+__global__ void mixed_scatter_kernel(const int32_t *home, int64_t nq, int32_t *bcount,
+                                     int32_t *perm) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nq) return;
+  perm[atomicAdd(bcount + home[q], 1)] = (int32_t)q;
+}
+
+// First stage of each tile's home range: starting a little before the
+// first stage of its middle query's home block.
+__global__ void mixed_tile_start_kernel(IndexDesc ix, const int32_t *home, const int32_t *perm,
+                                        int64_t nq, int64_t n_tiles, int64_t n_steps,
+                                        int64_t *tstart) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_tiles) return;
+  int64_t mid = t * kTileQ + kTileQ / 2;
+  if (mid >= nq) mid = nq - 1;
+  const int b = home[perm[mid]];
+  const int64_t first = ix.pstart[(int64_t)b * kBlockSegs] / kStage;
+  int64_t s0 = (first - kPilotStages / 4) % n_steps;  // in [0, n_steps)
+  if (s0 < 0) s0 += n_steps;
+  tstart[t] = s0;
 }
 
 __device__ __forceinline__ float round_up_f(double x) {
   return x < kInf ? __double2float_ru(x) : __builtin_huge_valf();
 }
 
-// What only the rescoring needs, parked in LDS so that the scan loop keeps
-// few scalar registers live.
+// The pooled bound of a query: the least upper bound on its k-th distance
+// any of its lists has found (non-negative floats order as their bit
+// patterns, so a signed integer minimum is a float minimum; -0 is made +0
+// first).  Read and lowered at device scope, so that the items of a tile
+// on other dies see it.
+__device__ __forceinline__ void lower_bound_to(float *b, float v) {
+  __hip_atomic_fetch_min(reinterpret_cast<int *>(b), __float_as_int(v + 0.0f), __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ float read_bound(const float *b) {
+  return __hip_atomic_load(b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// The call's arguments the MFMA search needs beyond its arrays, parked in
+// LDS so that the scan loop keeps few scalar registers live.
 struct SlowArgs {
   double s[4];
   double t_window;
@@ -207,60 +364,173 @@ struct SlowArgs {
   int k;
 };
 
+// Pilot pass: the exact top-k of each query over its tile's home range
+// (stages t0 .. t0 + n_home - 1, mod n_steps) in binary64, one wave per
+// kPilotQ consecutive queries of the scan order (all in one tile), each
+// 64-point pass of the range loaded once for them.  The list goes to slot
+// n_slots - 1, its rounded-up k-th distance to the query's bound.
+constexpr int kPilotQ = 4;
+static_assert(kTileQ % kPilotQ == 0, "a pilot wave stays within one tile");
+__global__ __launch_bounds__(256) void mixed_pilot_kernel(
+    IndexDesc ix, QueryArgs a, const float *qxp, const float *qyp, const float *qzp,
+    const float *qtp, const int32_t *perm, int64_t nq, const int64_t *tstart, int n_home,
+    int64_t n_steps, int n_slots, double *part_d, int32_t *part_i, float *bound) {
+  const int64_t q0 = ((int64_t)blockIdx.x * (blockDim.x >> 6) + uniform_i((int)(threadIdx.x >> 6))) *
+                     kPilotQ;
+  if (q0 >= nq) return;
+  const int lane = lane_id();
+  const double s[4] = {a.s[0], a.s[1], a.s[2], a.s[3]};
+  // positions past the end repeat the last one and are not written
+  QueryPoint q[kPilotQ];
+  TopK tk[kPilotQ];
+#pragma unroll
+  for (int j = 0; j < kPilotQ; ++j) {
+    const int64_t qc = perm[q0 + j < nq ? q0 + j : nq - 1];
+    q[j] = make_query(qxp[qc], qyp[qc], qzp[qc], qtp[qc], a.t_window);
+    tk[j].init(a.k, a.inf);
+  }
+  const int64_t t0 = tstart[q0 / kTileQ];
+  const int64_t n = ix.n_points;
+  for (int h = 0; h < n_home; ++h) {
+    int64_t stage = t0 + h;
+    if (stage >= n_steps) stage -= n_steps;
+    for (int half = 0; half < kStage / kWave; ++half) {
+      const int64_t p = stage * kStage + half * kWave + lane;
+      const bool ok = p < n;
+      float4 pv = make_float4(0.f, 0.f, 0.f, 0.f);
+      int pid = kNoId;
+      if (ok) {
+        pv = ix.pt4[p];
+        pid = ix.pid[p];
+      }
+#pragma unroll
+      for (int j = 0; j < kPilotQ; ++j) {
+        const double d = exact_dist(s, q[j].x, q[j].y, q[j].z, q[j].t, pv.x, pv.y, pv.z, pv.w);
+        const bool gate = ok & (pv.w < q[j].thrf) & tk[j].admits(d, pid);
+        const uint64_t gm = ballot(gate);
+        if (gm) tk[j].offer(gm, d, pid);
+      }
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < kPilotQ; ++j) {
+    const int64_t qi = q0 + j;
+    if (qi < nq) {
+      const size_t o = ((size_t)qi * n_slots + (n_slots - 1)) * a.k;
+      if (lane < a.k) {
+        part_d[o + lane] = tk[j].d;
+        part_i[o + lane] = tk[j].id;
+      }
+      if (lane == 0) bound[qi] = round_up_f(tk[j].kd);
+    }
+  }
+  if (a.stats && lane == 0) {
+    const int nmine = (int)(nq - q0 < kPilotQ ? nq - q0 : kPilotQ);
+    atomicAdd(a.stats + TNN_STAT_RESCORED, (unsigned long long)n_home * kStage * nmine);
+  }
+}
+
 // LDS stage buffer: the operands of kStage points (tile-major), their
-// coordinates and their caller indices.
+// times and their caller indices (the rescoring reads a survivor's
+// coordinates from global memory).
 struct Stage {
   bf16x8 op[kStage * 4];
-  float4 pt[kStage];
+  float t[kStage];
   int pid[kStage];
 };
 
-// Work item = (query tile of kTileQ queries, chunk of the point stages).
-// A persistent grid of 4-wave workgroups takes items from a counter, chunk
-// by chunk.  The workgroup streams the chunk's stages through two LDS
-// buffers (loaded by all 256 lanes, one stage ahead), and each wave answers
-// its 16 queries against every stage: a tile whose values all exceed their
-// queries' bounds costs one LDS read, one MFMA and four compares per lane.
-// For the others the survivors (bound and time mask passed) go to the wave's
-// queue (slots from ballots), which is rescored in binary64 from the staged
-// coordinates (one lane per survivor) and merged into each query's top-k.
-// That top-k is kept in place in the chunk's list in global memory (L2
-// resident while the item runs): LDS holds only the stages, so four
-// workgroups fit on a CU.  A query's bound starts at the least k-th distance
-// among the chunks of its tile already finished (each is an upper bound on
-// the final k-th distance), and mixed_merge_kernel combines the chunk lists.
-__global__ __launch_bounds__(kWaves * 64) void mixed_brute_kernel(
-    IndexDesc ix, QueryArgs a, MixedCtx mc, const bf16x8 *ops, const float *nv, const float *qxp,
-    const float *qyp, const float *qzp, const float *qtp, int64_t nq, double *part_d,
-    int32_t *part_i, float *part_kd, unsigned long long *counter, int64_t n_tiles, int n_chunks,
-    int64_t n_steps, int64_t tile_stride) {
+constexpr int kStageBufs = 3;  // LDS stage buffers: loads run two stages ahead
+constexpr int kStageLoads = 3;  // load instructions per wave and stage
+
+// M0 is written only here: the compiler uses it for nothing else in this
+// file (no other LDS-direct load, no indexed register move), so the clobber
+// it warns about is taken on purpose.
+#pragma clang diagnostic push
+#pragma clang diagnostic ignored "-Winline-asm"
+// Loads straight into LDS (no registers): each lane's 16 or 4 bytes land at
+// the wave-uniform LDS byte address `lds` plus lane * size (M0 holds it).
+// Written out because the compiler, not seeing which buffer a later LDS
+// read hits, would wait for every such load right away; the waits are
+// explicit (stage_wait_barrier).
+__device__ __forceinline__ void lds_load16(const void *src, uint32_t lds) {
+  asm volatile("s_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, off"
+               :
+               : "v"(src), "s"(__builtin_amdgcn_readfirstlane(lds))
+               : "memory", "m0");
+}
+__device__ __forceinline__ void lds_load4(const void *src, uint32_t lds) {
+  asm volatile("s_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dword %0, off"
+               :
+               : "v"(src), "s"(__builtin_amdgcn_readfirstlane(lds))
+               : "memory", "m0");
+}
+
+#pragma clang diagnostic pop
+
+// Wait until this wave's stage loads have landed, except the newest
+// stage's kStageLoads when `keep_newest` (vector memory operations complete
+// in issue order), and until its LDS reads are done; then the workgroup
+// barrier, after which every wave's loads of the older stages are visible.
+__device__ __forceinline__ void stage_wait_barrier(bool keep_newest) {
+  static_assert(kStageLoads == 3, "the wait below keeps kStageLoads operations in flight");
+  if (keep_newest)
+    asm volatile("s_waitcnt vmcnt(3) lgkmcnt(0)\n\ts_barrier" ::: "memory");
+  else
+    asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
+__device__ __forceinline__ uint32_t lds_addr(const void *p) {
+  return (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) void *)p;
+}
+
+// Work item = (query tile of kTileQ queries in scan order, chunk of the
+// point stages).  A persistent grid of 4-wave workgroups takes items from a
+// counter, chunk by chunk.  The workgroup streams the chunk's stages
+// through three LDS buffers, loaded straight into LDS by all 256 lanes two
+// stages ahead, and each wave answers its 64 queries (four MFMA row blocks)
+// against every stage: each 16-point tile read from LDS feeds four MFMAs,
+// and a batch of 2 tiles (2,048 pairs) costs one OR over its 32 tile values
+// and one ballot when nothing passes.  Otherwise the survivors (negative
+// tile value, time mask passed) go to the wave's queue (slots from
+// ballots), which is rescored in binary64 (one lane per survivor) and
+// merged into each query's top-k; then the bound terms of the A operands
+// are refreshed.  That top-k is kept in place in the item's list in global
+// memory (L2 resident while the item runs).  A query's bound starts at the
+// least k-th distance among its lists already finished, the pilot pass's
+// first (each is an upper bound on the final k-th distance), and
+// mixed_merge_kernel combines the lists.
+__global__ __launch_bounds__(kWaves * 64, 4) void mixed_brute_kernel(
+    const float4 *pt4, const int32_t *pidv, int64_t n_real, SlowArgs sa, MixedCtx mc,
+    const bf16x8 *ops, const float *qxp,
+    const float *qyp, const float *qzp, const float *qtp, const int32_t *perm, int64_t nq,
+    double *part_d, int32_t *part_i, float *bound, unsigned long long *counter,
+    const int64_t *tstart, int64_t n_tiles, int n_chunks, int n_home, int n_steps,
+    int tile_stride) {
   // 16-byte aligned: the stage buffers are read with 16-byte LDS loads
   extern __shared__ float4 s_dyn4[];
   __shared__ SlowArgs s_a;
   __shared__ long long s_item;
-  __shared__ float4 s_q[kWaves][kMQ];   // query coordinates (x, y, z, t)
-  __shared__ float s_tau[kWaves][kMQ];  // bound on the top-k's k-th distance, rounded up
-  __shared__ float s_nu[kWaves][kMQ];   // |u|^2 of each query
-  __shared__ int s_qp[kWaves][kQCap];   // queued survivor: index in the stage
-  __shared__ float s_qc[kWaves][kQCap];  //                 its tile value
-  __shared__ unsigned char s_qm[kWaves][kQCap];  //         its query row
-  const int k = a.k;
+  __shared__ float4 s_q[kWaves][kWaveQ];    // query coordinates (x, y, z, t)
+  __shared__ float4 s_thr4[kWaves][kWaveQ / 4];  // time thresholds (float, rounded up)
+  __shared__ float s_tau[kWaves][kWaveQ];   // bound on the k-th distance, rounded up
+  __shared__ float s_trep[kWaves][kWaveQ];  // the bound terms' sum folded in the A operand
+  __shared__ float s_nu[kWaves][kWaveQ];    // |u|^2 of each query
+  __shared__ int s_qp[kWaves][kQCap];       // queued survivor: point slot
+  __shared__ int s_qi[kWaves][kQCap];       //                 its caller index
+  __shared__ float s_qc[kWaves][kQCap];     //                 tile value + bound terms
+  __shared__ unsigned char s_qm[kWaves][kQCap];  //            its query row
+  const int k = sa.k;
   const int lane = lane_id();
-  const int wave = (int)(threadIdx.x >> 6);
+  const int wave = uniform_i((int)(threadIdx.x >> 6));
   const int tid = (int)threadIdx.x;
   const int g = lane >> 4;    // K-group this lane supplies
   const int row = lane & 15;  // A row (query) / C column (point)
-  // dynamic LDS: the two stages
+  float *s_thr = reinterpret_cast<float *>(s_thr4[wave]);
+  // dynamic LDS: the stage buffers (and their LDS byte address, for the
+  // loads that write them)
   Stage *s_stage = reinterpret_cast<Stage *>(s_dyn4);
-  if (tid == 0) {
-    for (int f = 0; f < 4; ++f) s_a.s[f] = a.s[f];
-    s_a.t_window = a.t_window;
-    s_a.inf = a.inf;
-    s_a.nv = nv;
-    s_a.stats = a.stats;
-    s_a.k = k;
-  }
-  const int64_t n_real = ix.n_points;
+  const uint32_t lds_stage0 = uniform_i((int)lds_addr(s_dyn4));
+  if (tid == 0) s_a = sa;
   uint32_t rescored = 0;
   double max_err = 0.0;
   int64_t queries_done = 0;
@@ -270,9 +540,9 @@ __global__ __launch_bounds__(kWaves * 64) void mixed_brute_kernel(
   int *tkid_base = part_i;
   int64_t tk_stride = k;
 
-  // Rescore the wave's queued survivors (stage `st`, first point p0) in
-  // binary64, one lane each, and merge them query by query.
-  auto flush = [&](int queued, const Stage *st, int64_t p0) {
+  // Rescore the wave's queued survivors in binary64, one lane each (their
+  // coordinates read from global memory), and merge them query by query.
+  auto flush = [&](int queued) {
     const int kk = __builtin_amdgcn_readfirstlane(s_a.k);
     double sc[4];
 #pragma unroll
@@ -286,16 +556,16 @@ __global__ __launch_bounds__(kWaves * 64) void mixed_brute_kernel(
     bool valid = false;
     if (has) {
       mi = s_qm[wave][lane];
-      const int j = s_qp[wave][lane];
+      const int64_t p = s_qp[wave][lane];
       const float4 qv = s_q[wave][mi];
       const QueryPoint qp = make_query(qv.x, qv.y, qv.z, qv.w, tw);
-      const float4 pv = st->pt[j];
+      const float4 pv = pt4[p];
       d = exact_dist(sc, qp.x, qp.y, qp.z, qp.t, pv.x, pv.y, pv.z, pv.w);
-      pid = st->pid[j];
+      pid = s_qi[wave][lane];
       valid = (double)pv.w < qp.thr;
-      if (want_err) {
-        const double approx = (double)s_qc[wave][lane] +
-                              (double)kGamma * ((double)s_nu[wave][mi] + (double)s_a.nv[p0 + j]);
+      const float c = s_qc[wave][lane];
+      if (want_err && c > -__builtin_huge_valf() && c < __builtin_huge_valf()) {
+        const double approx = (double)c + (double)kGamma * ((double)s_nu[wave][mi] + (double)s_a.nv[p]);
         max_err = fmax(max_err, fabs(approx - d));
       }
     }
@@ -319,12 +589,13 @@ __global__ __launch_bounds__(kWaves * 64) void mixed_brute_kernel(
           tkd_base[m * tk_stride + lane] = tk.d;
           tkid_base[m * tk_stride + lane] = tk.id;
         }
-        if (lane == 0) s_tau[wave][m] = round_up_f(tk.kd);
+        if (lane == 0) s_tau[wave][m] = fminf(s_tau[wave][m], round_up_f(tk.kd));
       }
     }
     rescored += (uint32_t)queued;
   };
 
+  const int n_slots = n_chunks + 1;
   const int64_t n_items = n_tiles * n_chunks;
   for (;;) {
     if (tid == 0) s_item = (long long)atomicAdd(counter, 1ull);
@@ -332,203 +603,358 @@ __global__ __launch_bounds__(kWaves * 64) void mixed_brute_kernel(
     const long long item = s_item;
     if (item >= n_items) break;
     const int chunk = (int)(item / n_tiles);
-    const int64_t qbase = (item % n_tiles) * kTileQ + wave * kMQ;
+    const int64_t tile = item % n_tiles;
+    const int slot = chunk;
+    const int64_t qbase = tile * kTileQ + wave * kWaveQ;  // positions in scan order
 
-    // ---- this wave's queries: A operands, bounds, time thresholds
-    float tau[4], thr[4];
-    bf16x8 aop;
-    {
-      const int64_t qa = qbase + row;
-      float u[4] = {0, 0, 0, 0};
-      float nu = 0.0f;
-      if (qa < nq) nu = scaled(mc, qxp[qa], qyp[qa], qzp[qa], qtp[qa], u);
-      aop = query_group(u, (1.0f - kGamma) * nu, g);
-      if (g == 0) s_nu[wave][row] = nu;
-    }
+    // ---- this wave's queries: norms, bounds, time thresholds, A operands
+    float u[kRowBlocks][4];
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int64_t q = qbase + g * 4 + e;
-      float t = -__builtin_huge_valf();  // an inactive row lets nothing pass
-      float h = -__builtin_huge_valf();
-      // a query too far out for the float32 tiles takes no part (its rows
-      // are reported as (-1, NaN) by the merge)
-      if (q < nq && s_nu[wave][g * 4 + e] < kMaxNorm) {
-        t = __builtin_huge_valf();
-        for (int c = 0; c < n_chunks; ++c)
-          if (c != chunk) t = fminf(t, part_kd[q * n_chunks + c]);
-        h = round_up_f((double)qtp[q] - a.t_window);
+    for (int bb = 0; bb < kRowBlocks; ++bb) {
+      const int64_t qa = qbase + bb * kMQ + row;
+      float nu = 0.0f;
+#pragma unroll
+      for (int f = 0; f < 4; ++f) u[bb][f] = 0.0f;
+      if (qa < nq) {
+        const int64_t qc = perm[qa];
+        nu = scaled(mc, qxp[qc], qyp[qc], qzp[qc], qtp[qc], u[bb]);
       }
-      tau[e] = t;
-      thr[e] = h;
+      if (g == 0) s_nu[wave][bb * kMQ + row] = nu;
     }
-    if (lane < kMQ) {
+    if (lane < kWaveQ) {
       const int64_t q = qbase + lane;
-      s_q[wave][lane] = q < nq ? make_float4(qxp[q], qyp[q], qzp[q], qtp[q]) : make_float4(0, 0, 0, 0);
-      // NaN marks a query outside the tiles' range in its chunk bound
-      s_tau[wave][lane] = s_nu[wave][lane] < kMaxNorm ? __builtin_huge_valf() : __builtin_nanf("");
+      float t = -__builtin_huge_valf();  // a row that takes no part lets nothing pass
+      float h = -__builtin_huge_valf();
+      float4 qv = make_float4(0, 0, 0, 0);
+      if (q < nq) {
+        const int64_t qc = perm[q];
+        qv = make_float4(qxp[qc], qyp[qc], qzp[qc], qtp[qc]);
+        if (s_nu[wave][lane] < kMaxNorm) {
+          t = read_bound(bound + q);
+          h = round_up_f((double)qv.w - sa.t_window);
+        } else {
+          // too far out for the float32 tiles: NaN marks it in its bound
+          // (which no list lowers then), and the merge reports its rows as
+          // (-1, NaN)
+          t = __builtin_nanf("");
+          bound[q] = t;
+        }
+      }
+      s_q[wave][lane] = qv;
+      s_thr[lane] = h;
+      s_tau[wave][lane] = t;
     }
-    tk_stride = (int64_t)n_chunks * k;
-    tkd_base = part_d + ((size_t)qbase * n_chunks + chunk) * k;
-    tkid_base = part_i + ((size_t)qbase * n_chunks + chunk) * k;
-    for (int m = 0; m < kMQ && qbase + m < nq; ++m)
+    // the A operands of the two row blocks (named, not an array: a
+    // dynamically indexed array would live in scratch memory)
+    static_assert(kRowBlocks == 4, "four named A operands");
+    bf16x8 aop0, aop1, aop2, aop3;
+#pragma unroll
+    for (int bb = 0; bb < kRowBlocks; ++bb) {
+      const int r = bb * kMQ + row;
+      const float t = s_tau[wave][r];
+      __bf16 th, tm;
+      float sum;
+      bound_terms(t != t ? -__builtin_huge_valf() : t, th, tm, sum);
+      const bf16x8 o = query_group(u[bb], (1.0f - kGamma) * s_nu[wave][r], g, th, tm);
+      if (bb == 0) aop0 = o;
+      if (bb == 1) aop1 = o;
+      if (bb == 2) aop2 = o;
+      if (bb == 3) aop3 = o;
+      if (g == 3) s_trep[wave][r] = sum;
+    }
+    auto aop_of = [&](int bb) { return bb == 0 ? aop0 : bb == 1 ? aop1 : bb == 2 ? aop2 : aop3; };
+    tk_stride = (int64_t)n_slots * k;
+    tkd_base = part_d + ((size_t)qbase * n_slots + slot) * k;
+    tkid_base = part_i + ((size_t)qbase * n_slots + slot) * k;
+    for (int m = 0; m < kWaveQ && qbase + m < nq; ++m)
       if (lane < k) {
-        tkd_base[m * tk_stride + lane] = a.inf;
+        tkd_base[m * tk_stride + lane] = sa.inf;
         tkid_base[m * tk_stride + lane] = kNoId;
       }
 
-    // ---- stream the chunk's stages
-    const int64_t s_lo = n_steps * chunk / n_chunks, s_hi = n_steps * (chunk + 1) / n_chunks;
-    // stage of step si: (si * tile_stride) mod n_steps
-    int64_t sb = (int64_t)(((unsigned long long)s_lo * (unsigned long long)tile_stride) %
-                           (unsigned long long)n_steps);
-    bf16x8 r_op[2];  // this lane's share of the next stage
-    float4 r_pt = make_float4(0, 0, 0, 0);
-    int r_pid = kNoId;
-    auto load_stage = [&](int64_t stage) {
-      const bf16x8 *src = ops + stage * (kStage * 4);
-      r_op[0] = src[tid];
-      r_op[1] = src[tid + kWaves * 64];
-      // lanes 0..127 fetch the coordinates, 128..255 the indices
-      const int64_t p = stage * kStage + (tid & (kStage - 1));
-      if (tid < kStage) {
-        r_pt = p < n_real ? ix.pt4[p] : make_float4(0, 0, 0, __builtin_huge_valf());
-      } else {
-        r_pid = p < n_real ? ix.pid[p] : kNoId;
-      }
+    // ---- the item's stages: the chunk's share of the steps; step si scans
+    // stage (si * tile_stride) mod n_steps, so that the chunk is spread over
+    // the index, skipping the tile's home range (the pilot pass scanned it)
+    // (in scalar registers: a vector register loaded from memory would make
+    // the compiler wait for every load in flight, the stage loads included,
+    // where the loop first reads it)
+    // (stage numbers fit 32 bits: the host checks n_steps)
+    const int t0 = uniform_i((int)tstart[tile]);
+    int li = (int)((int64_t)n_steps * chunk / n_chunks);  // next step to load
+    const int l_end = (int)((int64_t)n_steps * (chunk + 1) / n_chunks);
+    int lx = (int)((int64_t)li * tile_stride % n_steps);
+    auto in_home = [&](int x) {
+      int d = x - t0;
+      if (d < 0) d += n_steps;
+      return d < n_home;
     };
-    auto store_stage = [&](int buf) {
-      Stage *dst = s_stage + buf;
-      dst->op[tid] = r_op[0];
-      dst->op[tid + kWaves * 64] = r_op[1];
+    // the stage of the next step to load, or -1 when the item has no more
+    auto next_stage = [&]() -> int {
+      while (li < l_end) {
+        const int x = lx;
+        ++li;
+        lx += tile_stride;
+        if (lx >= n_steps) lx -= n_steps;
+        if (!in_home(x)) return x;
+      }
+      return -1;
+    };
+    // Stage `stage` into buffer `buf`: all 256 lanes load two operand
+    // units; waves 0-1 load the times, waves 2-3 the caller indices (a
+    // padding point loads point 0's, which the scan never uses).
+    auto load_stage = [&](int stage, int buf) {
+      const uint32_t dst = lds_stage0 + (uint32_t)buf * (uint32_t)sizeof(Stage);
+      const bf16x8 *src = ops + (int64_t)stage * (kStage * 4);
+      lds_load16(src + tid, dst + (uint32_t)offsetof(Stage, op) + wave * 1024u);
+      lds_load16(src + kWaves * 64 + tid, dst + (uint32_t)offsetof(Stage, op) + (kWaves + wave) * 1024u);
+      const int64_t p = (int64_t)stage * kStage + (tid & (kStage - 1));
+      const int64_t pl = p < n_real ? p : 0;
       if (tid < kStage)
-        dst->pt[tid] = r_pt;
+        lds_load4(&pt4[pl].w, dst + (uint32_t)offsetof(Stage, t) + wave * 256u);
       else
-        dst->pid[tid - kStage] = r_pid;
+        lds_load4(pidv + pl, dst + (uint32_t)offsetof(Stage, pid) + (wave - 2) * 256u);
     };
-    auto next_stage = [&](int64_t x) {
-      x += tile_stride;
-      return x >= n_steps ? x - n_steps : x;
-    };
-    load_stage(sb);
-    store_stage(0);
-    int64_t sb_next = next_stage(sb);
-    if (s_lo + 1 < s_hi) load_stage(sb_next);
-    __syncthreads();
-    for (int64_t si = s_lo; si < s_hi; ++si) {
-      const int buf = (int)((si - s_lo) & 1);
-      const Stage *st = s_stage + buf;
-      const int64_t p0 = sb * kStage;
-      // all operand reads, then all MFMAs, then the tests: no dependency
-      // between tiles, so the latencies overlap
-      uint32_t near_tiles = 0;  // tiles with a value within its query's bound
+    static_assert(kStage == 2 * 64 && kWaves == 4, "stage loads assume 4 waves and 128 points");
+
+    // The bound terms of the A operands from the rows' current bounds.
+    auto refresh_bounds = [&]() {
+      if (g != 3) return;
 #pragma unroll
+      for (int bb = 0; bb < kRowBlocks; ++bb) {
+        const int r = bb * kMQ + row;
+        const float t = s_tau[wave][r];
+        __bf16 th, tm;
+        float sum;
+        bound_terms(t != t ? -__builtin_huge_valf() : t, th, tm, sum);
+        if (bb == 0) {
+          aop0[6] = neg_bf16(th);
+          aop0[7] = neg_bf16(tm);
+        }
+        if (bb == 1) {
+          aop1[6] = neg_bf16(th);
+          aop1[7] = neg_bf16(tm);
+        }
+        if (bb == 2) {
+          aop2[6] = neg_bf16(th);
+          aop2[7] = neg_bf16(tm);
+        }
+        if (bb == 3) {
+          aop3[6] = neg_bf16(th);
+          aop3[7] = neg_bf16(tm);
+        }
+        s_trep[wave][r] = sum;
+      }
+    };
+
+    // Queue one survivor set: `pm` (a ballot) holds the lanes whose column j
+    // passes for row r; v is the tile value.  Slots from the ballot.
+    int queued = 0;  // survivors waiting in the wave's queue
+    auto enqueue = [&](uint64_t pm, bool pass, int j, int r, float v, int64_t p0, const Stage *st) {
+      if (pass) {
+        const int slot = queued + (int)__builtin_amdgcn_mbcnt_hi(
+                                      (uint32_t)(pm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)pm, 0u));
+        s_qp[wave][slot] = (int)(p0 + j);
+        s_qi[wave][slot] = st->pid[j];
+        s_qc[wave][slot] = v + s_trep[wave][r];
+        s_qm[wave][slot] = (unsigned char)r;
+      }
+      queued += __popcll(pm);
+    };
+
+    // One stage: every batch of tiles through the filter; the survivors go
+    // to the queue (a full queue is flushed on the way).  Returns whether
+    // a flush happened.
+    auto scan_stage = [&](const Stage *st, int64_t p0) {
+      bool flushed = false;
+      bf16x8 bn[kBatch];  // the next batch's operands, read one batch ahead
+#pragma unroll
+      for (int c = 0; c < kBatch; ++c) bn[c] = st->op[c * 64 + lane];
+#pragma unroll 1
       for (int c0 = 0; c0 < kStageTiles; c0 += kBatch) {
-        bf16x8 b[kBatch];
+        f32x4 acc[kRowBlocks][kBatch];
+        {
+          bf16x8 b[kBatch];
 #pragma unroll
-        for (int c = 0; c < kBatch; ++c) b[c] = st->op[(c0 + c) * 64 + lane];
-        f32x4 acc[kBatch];
+          for (int c = 0; c < kBatch; ++c) b[c] = bn[c];
+          if (c0 + kBatch < kStageTiles) {
 #pragma unroll
-        for (int c = 0; c < kBatch; ++c) {
+            for (int c = 0; c < kBatch; ++c) bn[c] = st->op[(c0 + kBatch + c) * 64 + lane];
+          }
           const f32x4 z = {0.0f, 0.0f, 0.0f, 0.0f};
-          acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aop, b[c], z, 0, 0, 0);
+#pragma unroll
+          for (int c = 0; c < kBatch; ++c) {
+            acc[0][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aop0, b[c], z, 0, 0, 0);
+            acc[1][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aop1, b[c], z, 0, 0, 0);
+            acc[2][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aop2, b[c], z, 0, 0, 0);
+            acc[3][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aop3, b[c], z, 0, 0, 0);
+          }
         }
+        // sign bits of the batch's tile values, ORed as a tree
+        uint32_t o[kRowBlocks * kBatch];
 #pragma unroll
-        for (int c = 0; c < kBatch; ++c) {
-          bool near = false;
+        for (int c = 0; c < kBatch; ++c)
 #pragma unroll
-          for (int e = 0; e < 4; ++e) near |= acc[c][e] <= tau[e];
-          near_tiles |= (ballot(near) != 0 ? 1u : 0u) << (c0 + c);
+          for (int bb = 0; bb < kRowBlocks; ++bb)
+            o[c * kRowBlocks + bb] =
+                (__float_as_uint(acc[bb][c][0]) | __float_as_uint(acc[bb][c][1])) |
+                (__float_as_uint(acc[bb][c][2]) | __float_as_uint(acc[bb][c][3]));
+        static_assert(kRowBlocks * kBatch == 8, "the OR tree below takes 8 tiles");
+        const uint32_t any = ((o[0] | o[1]) | (o[2] | o[3])) | ((o[4] | o[5]) | (o[6] | o[7]));
+        if (ballot((int)any < 0) == 0) continue;
+        // the batch's MFMA tiles holding a negative value (bit c * kRowBlocks + bb)
+        uint32_t near = 0;
+#pragma unroll
+        for (int t = 0; t < kRowBlocks * kBatch; ++t)
+          near |= (ballot((int)o[t] < 0) != 0 ? 1u : 0u) << t;
+        // Each such tile's values again (the same MFMA, so that few
+        // registers stay live), and its survivors (negative tile value, the
+        // time mask, a real point; row g*4+e of block bb, column j) to the
+        // queue.
+        while (near) {
+          const int t = __ffs(near) - 1;
+          near &= near - 1;
+          const int c = t / kRowBlocks, bb = t % kRowBlocks;
+          const int j = (c0 + c) * 16 + row;
+          const f32x4 z = {0.0f, 0.0f, 0.0f, 0.0f};
+          const f32x4 v4 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aop_of(bb),
+                                                                  st->op[(c0 + c) * 64 + lane], z, 0, 0, 0);
+          const float pt = (p0 + j < n_real) ? st->t[j] : __builtin_huge_valf();
+          const float4 th4 = s_thr4[wave][bb * 4 + g];
+          const int r0 = bb * kMQ + g * 4;
+          bool ps[4];
+          uint64_t pm[4];
+          int np = 0;
+          ps[0] = (__float_as_int(v4[0]) < 0) & (pt < th4.x);
+          ps[1] = (__float_as_int(v4[1]) < 0) & (pt < th4.y);
+          ps[2] = (__float_as_int(v4[2]) < 0) & (pt < th4.z);
+          ps[3] = (__float_as_int(v4[3]) < 0) & (pt < th4.w);
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            pm[e] = ballot(ps[e]);
+            np += __popcll(pm[e]);
+          }
+          if (np == 0) continue;
+          if (queued + np <= kQCap) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+              if (pm[e] != 0) enqueue(pm[e], ps[e], j, r0 + e, v4[e], p0, st);
+            continue;
+          }
+          // a full queue: set by set, flushing whenever the next would not fit
+#pragma unroll 1
+          for (int e = 0; e < 4; ++e) {
+            const uint64_t m = e == 0 ? pm[0] : e == 1 ? pm[1] : e == 2 ? pm[2] : pm[3];
+            if (m == 0) continue;
+            if (queued + __popcll(m) > kQCap) {
+              flush(queued);
+              flushed = true;
+              queued = 0;
+            }
+            const bool pe = e == 0 ? ps[0] : e == 1 ? ps[1] : e == 2 ? ps[2] : ps[3];
+            const float ve = e == 0 ? v4[0] : e == 1 ? v4[1] : e == 2 ? v4[2] : v4[3];
+            enqueue(m, pe, j, r0 + e, ve, p0, st);
+          }
         }
       }
-      while (near_tiles) {
-        const int cb = __ffs(near_tiles) - 1;
-        near_tiles &= near_tiles - 1;
-        const f32x4 z = {0.0f, 0.0f, 0.0f, 0.0f};
-        const f32x4 acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aop, st->op[cb * 64 + lane], z, 0, 0, 0);
-        const int j = cb * 16 + row;  // this lane's point in the stage
-        const float pt = st->pt[j].w;
-        int queued = 0;
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          // row (query) g*4+e, column (point) j; padding has time +inf
-          const float v = acc1[e];
-          const bool pass = (v <= tau[e]) & (pt < thr[e]);
-          const uint64_t pm = ballot(pass);
-          if (pm == 0) continue;
-          const int np = __popcll(pm);
-          if (queued + np > kQCap) {
-            flush(queued, st, p0);
-            queued = 0;
-          }
-          if (pass) {
-            const int slot = queued + (int)__builtin_amdgcn_mbcnt_hi(
-                                          (uint32_t)(pm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)pm, 0u));
-            s_qp[wave][slot] = j;
-            s_qc[wave][slot] = v;
-            s_qm[wave][slot] = (unsigned char)(g * 4 + e);
-          }
-          queued += np;
-        }
-        if (queued == 0) continue;
-        flush(queued, st, p0);
-#pragma unroll
-        for (int e = 0; e < 4; ++e) tau[e] = fminf(tau[e], s_tau[wave][g * 4 + e]);
+      return flushed;
+    };
+
+    // Each step scans one buffer while the loads of the stage two steps
+    // ahead (issued as the step starts, into the buffer the previous step
+    // used) are in flight; a step ends once the next stage's loads have
+    // landed.  st0, st1, st2: the stages in the current buffer and the next
+    // two (-1: none).
+    int st0 = next_stage(), st1 = -1, st2 = -1;
+    if (st0 >= 0) load_stage(st0, 0);
+    if (st0 >= 0) st1 = next_stage();
+    if (st1 >= 0) load_stage(st1, 1);
+    // the loads of the previous item's last steps and this item's top-k
+    // initialisation are older: waited for as well
+    stage_wait_barrier(st1 >= 0);
+    int buf = 0;
+    int step_no = 0;
+    while (st0 >= 0) {
+      // Every kShareSteps steps the items of the tile that run at the same
+      // time pool their bounds: lower the query's pooled bound to this
+      // list's, and read it back (applied after the scan, so that the load
+      // has time to arrive).  Lane = row.
+      const bool share = ++step_no == kShareSteps;
+      if (share) step_no = 0;
+      float pooled = __builtin_huge_valf();
+      if (share && qbase + lane < nq) {
+        const float t = s_tau[wave][lane];
+        if (t >= 0.0f && t < __builtin_huge_valf()) lower_bound_to(bound + qbase + lane, t);
+        pooled = read_bound(bound + qbase + lane);
       }
-      // the other buffer was last read before the previous barrier
-      if (si + 1 < s_hi) store_stage(buf ^ 1);
-      __syncthreads();
-      sb = sb_next;
-      sb_next = next_stage(sb);
-      if (si + 2 < s_hi) load_stage(sb_next);
+      const int buf_load = buf == 0 ? 2 : buf - 1;  // (buf + 2) % 3
+      st2 = st1 >= 0 ? next_stage() : -1;
+      if (st2 >= 0) load_stage(st2, buf_load);
+      const bool flushed = scan_stage(s_stage + buf, (int64_t)st0 * kStage);
+      if (share) {
+        // the queued survivors, then the pooled bound (not for a row
+        // outside the tiles' range (NaN) or without a query)
+        if (queued > 0) flush(queued);
+        queued = 0;
+        const float t = s_tau[wave][lane];
+        if (t == t && pooled < t) s_tau[wave][lane] = pooled;
+        refresh_bounds();
+      } else if (flushed) {
+        refresh_bounds();
+      }
+      stage_wait_barrier(st2 >= 0);
+      st0 = st1;
+      st1 = st2;
+      buf = buf == 2 ? 0 : buf + 1;
     }
 
-    // ---- this chunk's top-k of each query, and its k-th distance
-    for (int m = 0; m < kMQ; ++m) {
-      const int64_t q = qbase + m;
-      if (q >= nq) break;
-      // the rounded-up k-th distance (+inf with fewer than k)
-      if (lane == 0) part_kd[q * n_chunks + chunk] = s_tau[wave][m];
+    if (queued > 0) flush(queued);
+    queued = 0;
+    // ---- this list's k-th distance bound to each query's pooled bound
+    if (lane < kWaveQ && qbase + lane < nq) {
+      const float t = s_tau[wave][lane];
+      if (t >= 0.0f && t < __builtin_huge_valf()) lower_bound_to(bound + qbase + lane, t);
     }
     if (chunk == 0) {
       const int64_t left = nq - qbase;
-      queries_done += left < 0 ? 0 : (left > kMQ ? kMQ : left);
+      queries_done += left < 0 ? 0 : (left > kWaveQ ? kWaveQ : left);
     }
     __syncthreads();
   }
-  if (a.stats) {
+  if (sa.stats) {
     for (int o = 32; o > 0; o >>= 1) max_err = fmax(max_err, __shfl_xor(max_err, o, 64));
     if (lane == 0) {
-      atomicAdd(a.stats + TNN_STAT_QUERIES, (unsigned long long)queries_done);
-      atomicAdd(a.stats + TNN_STAT_POINTS, (unsigned long long)(queries_done * ix.n_points));
-      atomicAdd(a.stats + TNN_STAT_RESCORED, (unsigned long long)rescored);
-      atomicMax(a.stats + TNN_STAT_MAX_ERR, (unsigned long long)__double_as_longlong(max_err));
+      atomicAdd(sa.stats + TNN_STAT_QUERIES, (unsigned long long)queries_done);
+      atomicAdd(sa.stats + TNN_STAT_POINTS, (unsigned long long)(queries_done * n_real));
+      atomicAdd(sa.stats + TNN_STAT_RESCORED, (unsigned long long)rescored);
+      atomicMax(sa.stats + TNN_STAT_MAX_ERR, (unsigned long long)__double_as_longlong(max_err));
     }
   }
 }
 
-// One wave per query: the exact top-k of the union of its chunks' partial
-// lists (each sorted by (distance, index), padded with (+inf, none)).
+// One wave per query: the exact top-k of the union of its partial lists
+// (each sorted by (distance, index), padded with (+inf, none)); position q
+// of the scan order is caller query perm[q].
 __global__ __launch_bounds__(256) void mixed_merge_kernel(const double *part_d,
                                                           const int32_t *part_i,
-                                                          const float *part_kd, int n_chunks,
-                                                          int64_t nq, int k, double inf,
-                                                          int32_t *out_idx, double *out_dist) {
+                                                          const float *bound, int n_slots,
+                                                          const int32_t *perm, int64_t nq, int k,
+                                                          double inf, int32_t *out_idx,
+                                                          double *out_dist) {
   const int64_t q = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (q >= nq) return;
   const int lane = lane_id();
-  bool out_of_range = false;
-  for (int c = 0; c < n_chunks; ++c) out_of_range = out_of_range || __builtin_isnan(part_kd[q * n_chunks + c]);
-  if (out_of_range) {  // the query's scaled norm exceeds the tiles' range
+  const int64_t qc = perm ? perm[q] : q;
+  if (bound && __builtin_isnan(bound[q])) {  // the query's scaled norm exceeds the tiles' range
     if (lane < k) {
-      out_idx[q * k + lane] = -1;
-      out_dist[q * k + lane] = inf - inf;  // NaN (no 64-bit literal)
+      out_idx[qc * k + lane] = -1;
+      out_dist[qc * k + lane] = inf - inf;  // NaN (no 64-bit literal)
     }
     return;
   }
   TopK tk;
   tk.init(k, inf);
-  for (int c = 0; c < n_chunks; ++c) {
-    const size_t o = ((size_t)q * n_chunks + c) * k;
+  for (int c = 0; c < n_slots; ++c) {
+    const size_t o = ((size_t)q * n_slots + c) * k;
     double d = inf;
     int id = kNoId;
     if (lane < k) {
@@ -546,8 +972,8 @@ __global__ __launch_bounds__(256) void mixed_merge_kernel(const double *part_d,
     if (gm) tk.offer(gm, d, id);
   }
   if (lane < k) {
-    out_idx[q * k + lane] = tk.id == kNoId ? -1 : tk.id;
-    out_dist[q * k + lane] = tk.d;
+    out_idx[qc * k + lane] = tk.id == kNoId ? -1 : tk.id;
+    out_dist[qc * k + lane] = tk.d;
   }
 }
 
@@ -559,27 +985,34 @@ static int64_t padded_points(int64_t n_points) {
 }
 
 // Point chunks per query tile: enough work items to keep a full chip busy
-// to the end, at most one chunk per stage.
+// to the end, each chunk at least kMinChunkStages stages (an item's set-up
+// writes its lists: short chunks would spend more on that than on the scan).
+constexpr int64_t kMinChunkStages = 64;
 static int mixed_chunks(int64_t n_points, int64_t nq) {
   const int64_t tiles = (nq + kTileQ - 1) / kTileQ;
   const int64_t stages = padded_points(n_points) / kStage;
   int64_t c = tiles > 0 ? (8 * kNominalSlots + tiles - 1) / tiles : 1;
   if (c > kMaxChunks) c = kMaxChunks;
-  if (c > stages) c = stages;
+  if (c > (stages + kMinChunkStages - 1) / kMinChunkStages)
+    c = (stages + kMinChunkStages - 1) / kMinChunkStages;
   return c < 1 ? 1 : (int)c;
 }
 
 namespace {
 struct MixedLayout {
-  int64_t np, chunks;
-  size_t ops, nv, part_d, part_i, part_kd, counter, total;
+  int64_t np, chunks, slots, tiles, max_blocks;
+  size_t ops, nv, part_d, part_i, bound, home, perm, bcount, tstart, counter, total;
 };
 
 MixedLayout mixed_layout(int64_t n_points, int64_t nq, int k) {
   MixedLayout l;
   l.np = padded_points(n_points);
   l.chunks = mixed_chunks(n_points, nq);
-  const size_t entries = (size_t)nq * l.chunks * k;
+  l.slots = l.chunks + 1;  // the chunks' lists and the pilot's
+  l.tiles = (nq + kTileQ - 1) / kTileQ;
+  // blocks of 64 segments, a segment holding at least one point
+  l.max_blocks = (n_points + kBlockSegs - 1) / kBlockSegs + 1;
+  const size_t entries = (size_t)nq * l.slots * k;
   size_t o = 0;
   l.ops = o;
   o += align_up((size_t)l.np * 64);
@@ -589,8 +1022,16 @@ MixedLayout mixed_layout(int64_t n_points, int64_t nq, int k) {
   o += align_up(entries * 8);
   l.part_i = o;
   o += align_up(entries * 4);
-  l.part_kd = o;
-  o += align_up((size_t)nq * l.chunks * 4);
+  l.bound = o;
+  o += align_up((size_t)nq * 4);
+  l.home = o;
+  o += align_up((size_t)nq * 4);
+  l.perm = o;
+  o += align_up((size_t)nq * 4);
+  l.bcount = o;
+  o += align_up((size_t)l.max_blocks * 4);
+  l.tstart = o;
+  o += align_up((size_t)l.tiles * 8);
   l.counter = o;
   o += 256;
   l.total = o;
@@ -648,28 +1089,54 @@ hipError_t launch_mixed_brute(const IndexDesc &ix, const QueryArgs &a, const tnn
   if (qs.n == 0) return hipSuccess;
   const MixedCtx mc = make_ctx(ix, a);
   const MixedLayout l = mixed_layout(ix.n_points, qs.n, a.k);
+  // stage numbers are 32-bit in the search kernel
+  if (ix.n_blocks > l.max_blocks || l.np / kStage > INT32_MAX) return hipErrorInvalidValue;
   char *base = static_cast<char *>(scratch);
   bf16x8 *ops = reinterpret_cast<bf16x8 *>(base + l.ops);
   float *nv = reinterpret_cast<float *>(base + l.nv);
   double *part_d = reinterpret_cast<double *>(base + l.part_d);
   int32_t *part_i = reinterpret_cast<int32_t *>(base + l.part_i);
-  float *part_kd = reinterpret_cast<float *>(base + l.part_kd);
+  float *bound = reinterpret_cast<float *>(base + l.bound);
+  int32_t *home = reinterpret_cast<int32_t *>(base + l.home);
+  int32_t *perm = reinterpret_cast<int32_t *>(base + l.perm);
+  int32_t *bcount = reinterpret_cast<int32_t *>(base + l.bcount);
+  int64_t *tstart = reinterpret_cast<int64_t *>(base + l.tstart);
   unsigned long long *counter = reinterpret_cast<unsigned long long *>(base + l.counter);
   const int64_t n_steps = l.np / kStage;
-  const int64_t n_tiles = (qs.n + kTileQ - 1) / kTileQ;
-  const int64_t n_kd = qs.n * l.chunks;
+  const int64_t n_kd = qs.n;
+  const int n_slots = (int)l.slots;
   if (n_steps == 0) {
     // no points: merging no lists leaves every slot a pad
     hipLaunchKernelGGL(mixed_merge_kernel, dim3((unsigned)((qs.n + 3) / 4)), dim3(256), 0, st,
-                       part_d, part_i, part_kd, 0, qs.n, a.k, a.inf, out_idx, out_dist);
+                       part_d, part_i, (const float *)nullptr, 0, (const int32_t *)nullptr, qs.n,
+                       a.k, a.inf,
+                       out_idx, out_dist);
     return hipGetLastError();
   }
   hipLaunchKernelGGL(mixed_prep_kernel, dim3((unsigned)((l.np + 255) / 256)), dim3(256), 0, st, ix,
                      mc, ops, nv, l.np);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(mixed_reset_kernel, dim3((unsigned)((n_kd + 255) / 256)), dim3(256), 0, st,
-                     part_kd, n_kd, counter);
+  const int64_t n_reset = n_kd > ix.n_blocks ? n_kd : ix.n_blocks;
+  hipLaunchKernelGGL(mixed_reset_kernel, dim3((unsigned)((n_reset + 255) / 256)), dim3(256), 0, st,
+                     bound, n_kd, bcount, (int64_t)ix.n_blocks, counter);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  // scan order: home blocks, counting sort, home ranges of the tiles
+  const unsigned qgrid = (unsigned)((qs.n + 255) / 256);
+  hipLaunchKernelGGL(mixed_home_kernel, dim3(qgrid), dim3(256), 0, st, ix, a, qs.x, qs.y, qs.z,
+                     qs.t, qs.n, home, bcount);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(mixed_offsets_kernel, dim3(1), dim3(1024), 0, st, bcount,
+                     (int64_t)ix.n_blocks);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(mixed_scatter_kernel, dim3(qgrid), dim3(256), 0, st, home, qs.n, bcount, perm);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(mixed_tile_start_kernel, dim3((unsigned)((l.tiles + 255) / 256)), dim3(256), 0,
+                     st, ix, home, perm, qs.n, l.tiles, n_steps, tstart);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   int64_t stride = 1;
@@ -685,17 +1152,32 @@ hipError_t launch_mixed_brute(const IndexDesc &ix, const QueryArgs &a, const tnn
     stride = (int64_t)(0.6180339887 * (double)n_steps) | 1;
     while (gcd(stride, n_steps) != 1) stride += 2;
   }
-  const size_t lds = 2 * sizeof(Stage);
-  const int64_t items = n_tiles * l.chunks;
+  const int n_home = (int)(n_steps < kPilotStages ? n_steps : kPilotStages);
+  const size_t lds = kStageBufs * sizeof(Stage);
   const int64_t resident = (int64_t)cu_count_mixed() * mixed_per_cu(lds);
+  const int64_t pilot_waves = (qs.n + kPilotQ - 1) / kPilotQ;
+  hipLaunchKernelGGL(mixed_pilot_kernel, dim3((unsigned)((pilot_waves + 3) / 4)), dim3(256), 0, st,
+                     ix, a, qs.x, qs.y, qs.z, qs.t, perm, qs.n, tstart, n_home, n_steps, n_slots,
+                     part_d, part_i, bound);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int64_t items = l.tiles * l.chunks;
   const int64_t grid = items < resident ? items : resident;
-  hipLaunchKernelGGL(mixed_brute_kernel, dim3((unsigned)grid), dim3(kWaves * 64), lds, st, ix, a,
-                     mc, ops, nv, qs.x, qs.y, qs.z, qs.t, qs.n, part_d, part_i, part_kd, counter,
-                     n_tiles, (int)l.chunks, n_steps, stride);
+  SlowArgs sa;
+  for (int f = 0; f < 4; ++f) sa.s[f] = a.s[f];
+  sa.t_window = a.t_window;
+  sa.inf = a.inf;
+  sa.nv = nv;
+  sa.stats = a.stats;
+  sa.k = a.k;
+  hipLaunchKernelGGL(mixed_brute_kernel, dim3((unsigned)grid), dim3(kWaves * 64), lds, st, ix.pt4,
+                     ix.pid, ix.n_points, sa, mc, ops, qs.x, qs.y, qs.z, qs.t, perm, qs.n, part_d,
+                     part_i, bound,
+                     counter, tstart, l.tiles, n_slots - 1, n_home, (int)n_steps, (int)stride);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(mixed_merge_kernel, dim3((unsigned)((qs.n + 3) / 4)), dim3(256), 0, st, part_d,
-                     part_i, part_kd, (int)l.chunks, qs.n, a.k, a.inf, out_idx, out_dist);
+                     part_i, bound, n_slots, perm, qs.n, a.k, a.inf, out_idx, out_dist);
   return hipGetLastError();
 }
 
