@@ -80,11 +80,15 @@ typedef struct {
 #define TNN_STAT_QUERIES 0
 #define TNN_STAT_BLOCKS 1      /* block lower bounds evaluated */
 #define TNN_STAT_SEGMENTS 2    /* segment (cylinder) lower bounds evaluated */
-#define TNN_STAT_POINTS 3      /* point distances computed ("comparisons", Sec. 4.2) */
+#define TNN_STAT_POINTS 3      /* point distances computed ("comparisons", Sec. 4.2); the BF16
+                                  linear search counts the (query, point) pairs of the stages it
+                                  scans, its pilot pass's included: a stage whose points all fail
+                                  a query tile's time mask is skipped */
 #define TNN_STAT_MERGES 4      /* top-k merges */
 #define TNN_STAT_ROUNDS 5      /* expansion rounds over all queries */
 #define TNN_STAT_FALLBACKS 6   /* learned radius held fewer than k points */
-#define TNN_STAT_RESCORED 7    /* binary64 rescoring of filtered candidates */
+#define TNN_STAT_RESCORED 7    /* binary64 rescoring of filtered candidates (the BF16 linear
+                                  search: also its pilot pass's binary64 pairs) */
 #define TNN_STAT_MAX_ERR 8     /* bit pattern of the largest |approx - exact| distance (double) */
 #define TNN_STAT_COUNT 16
 

@@ -364,6 +364,24 @@ struct SlowArgs {
   int k;
 };
 
+// Earliest time of each stage's points (+inf for a stage of padding only):
+// a stage not earlier than every query's time threshold in a tile holds no
+// candidate of the tile (every pair is masked, Sec. 3.4), and the tile
+// skips it.  One wave per stage.
+__global__ void mixed_stage_time_kernel(const float4 *pt4, int64_t n_real, int64_t n_steps,
+                                        float *stage_tmin) {
+  const int64_t stg = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (stg >= n_steps) return;
+  const int lane = lane_id();
+  float t = __builtin_huge_valf();
+  for (int h = 0; h < kStage / kWave; ++h) {
+    const int64_t p = stg * kStage + h * kWave + lane;
+    if (p < n_real) t = fminf(t, pt4[p].w);
+  }
+  for (int o = 32; o > 0; o >>= 1) t = fminf(t, __shfl_xor(t, o, 64));
+  if (lane == 0) stage_tmin[stg] = t;
+}
+
 // Pilot pass: the exact top-k of each query over its tile's home range
 // (stages t0 .. t0 + n_home - 1, mod n_steps) in binary64, one wave per
 // kPilotQ consecutive queries of the scan order (all in one tile), each
@@ -427,6 +445,7 @@ __global__ __launch_bounds__(256) void mixed_pilot_kernel(
   if (a.stats && lane == 0) {
     const int nmine = (int)(nq - q0 < kPilotQ ? nq - q0 : kPilotQ);
     atomicAdd(a.stats + TNN_STAT_RESCORED, (unsigned long long)n_home * kStage * nmine);
+    atomicAdd(a.stats + TNN_STAT_POINTS, (unsigned long long)n_home * kStage * nmine);
   }
 }
 
@@ -504,12 +523,13 @@ __global__ __launch_bounds__(kWaves * 64, 4) void mixed_brute_kernel(
     const bf16x8 *ops, const float *qxp,
     const float *qyp, const float *qzp, const float *qtp, const int32_t *perm, int64_t nq,
     double *part_d, int32_t *part_i, float *bound, unsigned long long *counter,
-    const int64_t *tstart, int64_t n_tiles, int n_chunks, int n_home, int n_steps,
-    int tile_stride) {
+    const int64_t *tstart, const float *stage_tmin, int64_t n_tiles, int n_chunks, int n_home,
+    int n_steps, int tile_stride) {
   // 16-byte aligned: the stage buffers are read with 16-byte LDS loads
   extern __shared__ float4 s_dyn4[];
   __shared__ SlowArgs s_a;
   __shared__ long long s_item;
+  __shared__ float s_wthr[kWaves];  // each wave's largest time threshold
   __shared__ float4 s_q[kWaves][kWaveQ];    // query coordinates (x, y, z, t)
   __shared__ float4 s_thr4[kWaves][kWaveQ / 4];  // time thresholds (float, rounded up)
   __shared__ float s_tau[kWaves][kWaveQ];   // bound on the k-th distance, rounded up
@@ -534,6 +554,7 @@ __global__ __launch_bounds__(kWaves * 64, 4) void mixed_brute_kernel(
   uint32_t rescored = 0;
   double max_err = 0.0;
   int64_t queries_done = 0;
+  unsigned long long pairs_scanned = 0;  // (query, point) pairs of the stages scanned
   // The current item's top-k of query row m lives in place in its chunk list
   // (in the L2 while the item runs): tkd_base[m * tk_stride + rank].
   double *tkd_base = part_d;
@@ -644,7 +665,16 @@ __global__ __launch_bounds__(kWaves * 64, 4) void mixed_brute_kernel(
       s_thr[lane] = h;
       s_tau[wave][lane] = t;
     }
-    // the A operands of the two row blocks (named, not an array: a
+    // the tile's largest time threshold: a stage not earlier is skipped
+    {
+      float h = s_thr[lane];
+      for (int o = 32; o > 0; o >>= 1) h = fmaxf(h, __shfl_xor(h, o, 64));
+      if (lane == 0) s_wthr[wave] = h;
+    }
+    __syncthreads();
+    const float thr_max = fmaxf(fmaxf(s_wthr[0], s_wthr[1]), fmaxf(s_wthr[2], s_wthr[3]));
+    static_assert(kWaves == 4, "four waves' thresholds");
+    // the A operands of the row blocks (named, not an array: a
     // dynamically indexed array would live in scratch memory)
     static_assert(kRowBlocks == 4, "four named A operands");
     bf16x8 aop0, aop1, aop2, aop3;
@@ -689,13 +719,24 @@ __global__ __launch_bounds__(kWaves * 64, 4) void mixed_brute_kernel(
       return d < n_home;
     };
     // the stage of the next step to load, or -1 when the item has no more
+    // Earliest times of the next 64 steps' stages, one per lane (steps
+    // win .. win + 63), read 64 at a time.
+    int win = li - 64;
+    float win_tmin = __builtin_huge_valf();
     auto next_stage = [&]() -> int {
       while (li < l_end) {
+        if (li >= win + 64) {
+          win = li;
+          const int step = li + lane;
+          win_tmin = step < l_end ? stage_tmin[(int64_t)step * tile_stride % n_steps]
+                                  : __builtin_huge_valf();
+        }
+        const float tmin = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(win_tmin), li - win));
         const int x = lx;
         ++li;
         lx += tile_stride;
         if (lx >= n_steps) lx -= n_steps;
-        if (!in_home(x)) return x;
+        if (!in_home(x) && tmin < thr_max) return x;
       }
       return -1;
     };
@@ -873,6 +914,7 @@ __global__ __launch_bounds__(kWaves * 64, 4) void mixed_brute_kernel(
     stage_wait_barrier(st1 >= 0);
     int buf = 0;
     int step_no = 0;
+    int scanned = 0;
     while (st0 >= 0) {
       // Every kShareSteps steps the items of the tile that run at the same
       // time pool their bounds: lower the query's pooled bound to this
@@ -905,6 +947,11 @@ __global__ __launch_bounds__(kWaves * 64, 4) void mixed_brute_kernel(
       st0 = st1;
       st1 = st2;
       buf = buf == 2 ? 0 : buf + 1;
+      ++scanned;
+    }
+    {
+      const int64_t left = nq - qbase;
+      pairs_scanned += (unsigned long long)scanned * kStage * (left > kWaveQ ? kWaveQ : left);
     }
 
     if (queued > 0) flush(queued);
@@ -924,7 +971,7 @@ __global__ __launch_bounds__(kWaves * 64, 4) void mixed_brute_kernel(
     for (int o = 32; o > 0; o >>= 1) max_err = fmax(max_err, __shfl_xor(max_err, o, 64));
     if (lane == 0) {
       atomicAdd(sa.stats + TNN_STAT_QUERIES, (unsigned long long)queries_done);
-      atomicAdd(sa.stats + TNN_STAT_POINTS, (unsigned long long)(queries_done * n_real));
+      atomicAdd(sa.stats + TNN_STAT_POINTS, pairs_scanned);
       atomicAdd(sa.stats + TNN_STAT_RESCORED, (unsigned long long)rescored);
       atomicMax(sa.stats + TNN_STAT_MAX_ERR, (unsigned long long)__double_as_longlong(max_err));
     }
@@ -1001,7 +1048,7 @@ static int mixed_chunks(int64_t n_points, int64_t nq) {
 namespace {
 struct MixedLayout {
   int64_t np, chunks, slots, tiles, max_blocks;
-  size_t ops, nv, part_d, part_i, bound, home, perm, bcount, tstart, counter, total;
+  size_t ops, nv, part_d, part_i, bound, home, perm, bcount, tstart, stage_tmin, counter, total;
 };
 
 MixedLayout mixed_layout(int64_t n_points, int64_t nq, int k) {
@@ -1032,6 +1079,8 @@ MixedLayout mixed_layout(int64_t n_points, int64_t nq, int k) {
   o += align_up((size_t)l.max_blocks * 4);
   l.tstart = o;
   o += align_up((size_t)l.tiles * 8);
+  l.stage_tmin = o;
+  o += align_up((size_t)(l.np / kStage) * 4);
   l.counter = o;
   o += 256;
   l.total = o;
@@ -1101,6 +1150,7 @@ hipError_t launch_mixed_brute(const IndexDesc &ix, const QueryArgs &a, const tnn
   int32_t *perm = reinterpret_cast<int32_t *>(base + l.perm);
   int32_t *bcount = reinterpret_cast<int32_t *>(base + l.bcount);
   int64_t *tstart = reinterpret_cast<int64_t *>(base + l.tstart);
+  float *stage_tmin = reinterpret_cast<float *>(base + l.stage_tmin);
   unsigned long long *counter = reinterpret_cast<unsigned long long *>(base + l.counter);
   const int64_t n_steps = l.np / kStage;
   const int64_t n_kd = qs.n;
@@ -1116,6 +1166,10 @@ hipError_t launch_mixed_brute(const IndexDesc &ix, const QueryArgs &a, const tnn
   hipLaunchKernelGGL(mixed_prep_kernel, dim3((unsigned)((l.np + 255) / 256)), dim3(256), 0, st, ix,
                      mc, ops, nv, l.np);
   hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(mixed_stage_time_kernel, dim3((unsigned)((n_steps + 3) / 4)), dim3(256), 0, st,
+                     ix.pt4, ix.n_points, n_steps, stage_tmin);
+  e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int64_t n_reset = n_kd > ix.n_blocks ? n_kd : ix.n_blocks;
   hipLaunchKernelGGL(mixed_reset_kernel, dim3((unsigned)((n_reset + 255) / 256)), dim3(256), 0, st,
@@ -1173,7 +1227,8 @@ hipError_t launch_mixed_brute(const IndexDesc &ix, const QueryArgs &a, const tnn
   hipLaunchKernelGGL(mixed_brute_kernel, dim3((unsigned)grid), dim3(kWaves * 64), lds, st, ix.pt4,
                      ix.pid, ix.n_points, sa, mc, ops, qs.x, qs.y, qs.z, qs.t, perm, qs.n, part_d,
                      part_i, bound,
-                     counter, tstart, l.tiles, n_slots - 1, n_home, (int)n_steps, (int)stride);
+                     counter, tstart, stage_tmin, l.tiles, n_slots - 1, n_home, (int)n_steps,
+                     (int)stride);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(mixed_merge_kernel, dim3((unsigned)((qs.n + 3) / 4)), dim3(256), 0, st, part_d,
