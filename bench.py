@@ -35,18 +35,24 @@ FLOPS_SEG_BOUND = 28       # float32
 FLOPS_POINT_F64 = 12       # binary64
 FLOPS_POINT_F32 = 2        # float32
 
+# The linear search on matrix cores: 16 algorithmic flop per (query, point)
+# pair (the distance as an augmented 4-term dot product: 8 multiply-adds),
+# against the dense BF16 MFMA peak (2.5 PFLOP/s).
+FLOPS_PAIR_BF16 = 16
+BF16_MFMA_PEAK_TFLOPS = 2500.0
+
 
 # HBM traffic of one learned-radius search launch on this workload, from two
 # rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE, KiB per dispatch), each
 # scaled by what the counter reads for a 256 MiB device-to-device copy
-# (FETCH_SIZE x 2.00, WRITE_SIZE x 1.00): 111,865 KiB fetched (x 2 = 229.1 MB)
+# (FETCH_SIZE x 2.00, WRITE_SIZE x 1.00): 111,974 KiB fetched (x 2 = 229.3 MB)
 # and 40,451 KiB written (41.4 MB).  It describes the kernel built from the
 # sources with this SHA-256 (the search kernel's sources and the C header)
 # only; after any change to them the figure is reported as null.
 KERNEL_SOURCES = ("query.hip", "query.h", "bounds.h", "wave.h", "gka.h", "tnn_internal.h")
 MEASURED_TRAFFIC = {
-    "sha256": "e9ab675f28578f129adafa1a0961034734da5a3cfc361732d7a15d647451733d",
-    "bytes_per_launch": 270.5e6,
+    "sha256": "94e17ec95448c9568d864094fb837fd9168d07c01bea91027f41c223b10e7c66",
+    "bytes_per_launch": 270.7e6,
 }
 
 
@@ -594,6 +600,18 @@ def main():
         result_extra["mixed_brute_exact"] = same_m
         result_extra["mixed_brute_rescored_per_query"] = mst["rescored"] / qs.n
         result_extra["mixed_max_abs_dist_err"] = mst["max_err"]
+        # Roofline of the BF16 linear search at 16 algorithmic flop per (query,
+        # point) pair: the pairs of the stages it scans (the pilot pass's
+        # included; stages a query tile's time mask rejects entirely are
+        # skipped), over the whole call (home blocks, pilot, MFMA scan, merge).
+        pairs = mst["points"]
+        result_extra["mixed_brute_roofline"] = {
+            "bound": "mfma", "unit": "TFLOP/s", "peak": BF16_MFMA_PEAK_TFLOPS,
+            "flop_per_pair": FLOPS_PAIR_BF16, "pairs": pairs, "pairs_all": qs.n * ps.n,
+            "achieved": FLOPS_PAIR_BF16 * pairs / (ms_mixed * 1e-3) / 1e12,
+            "frac": FLOPS_PAIR_BF16 * pairs / (ms_mixed * 1e-3) / 1e12 / BF16_MFMA_PEAK_TFLOPS,
+            "achieved_all_pairs": FLOPS_PAIR_BF16 * qs.n * ps.n / (ms_mixed * 1e-3) / 1e12,
+            "call_ms": ms_mixed}
 
     f32 = (FLOPS_BLOCK_BOUND * st["blocks"] + FLOPS_SEG_BOUND * st["segments"]
            + FLOPS_POINT_F32 * st["points"])
