@@ -692,7 +692,15 @@ __global__ __launch_bounds__(kWaves * 64, 4) void mixed_brute_kernel(
       if (bb == 3) aop3 = o;
       if (g == 3) s_trep[wave][r] = sum;
     }
-    auto aop_of = [&](int bb) { return bb == 0 ? aop0 : bb == 1 ? aop1 : bb == 2 ? aop2 : aop3; };
+    // block bb's tile against operand tile b (a branch per block: selecting
+    // among the named operands by value would put them in scratch memory)
+    auto mfma_block = [&](int bb, const bf16x8 &b) {
+      const f32x4 z = {0.0f, 0.0f, 0.0f, 0.0f};
+      if (bb == 0) return __builtin_amdgcn_mfma_f32_16x16x32_bf16(aop0, b, z, 0, 0, 0);
+      if (bb == 1) return __builtin_amdgcn_mfma_f32_16x16x32_bf16(aop1, b, z, 0, 0, 0);
+      if (bb == 2) return __builtin_amdgcn_mfma_f32_16x16x32_bf16(aop2, b, z, 0, 0, 0);
+      return __builtin_amdgcn_mfma_f32_16x16x32_bf16(aop3, b, z, 0, 0, 0);
+    };
     tk_stride = (int64_t)n_slots * k;
     tkd_base = part_d + ((size_t)qbase * n_slots + slot) * k;
     tkid_base = part_i + ((size_t)qbase * n_slots + slot) * k;
@@ -856,9 +864,7 @@ __global__ __launch_bounds__(kWaves * 64, 4) void mixed_brute_kernel(
           near &= near - 1;
           const int c = t / kRowBlocks, bb = t % kRowBlocks;
           const int j = (c0 + c) * 16 + row;
-          const f32x4 z = {0.0f, 0.0f, 0.0f, 0.0f};
-          const f32x4 v4 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aop_of(bb),
-                                                                  st->op[(c0 + c) * 64 + lane], z, 0, 0, 0);
+          const f32x4 v4 = mfma_block(bb, st->op[(c0 + c) * 64 + lane]);
           const float pt = (p0 + j < n_real) ? st->t[j] : __builtin_huge_valf();
           const float4 th4 = s_thr4[wave][bb * 4 + g];
           const int r0 = bb * kMQ + g * 4;
