@@ -23,6 +23,28 @@ SOURCE_FLAGS = {"mixed.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
 
 LITERAL64 = re.compile(r"\b(s_mov_b64|v_mov_b64|s_[a-z0-9_]+_b64)\b[^;]*\b0x[0-9a-fA-F]{9,}")
 
+# Kernels that must not use scratch memory: in the BF16 linear search a
+# scratch reload waits on the vector-memory counter, which also drains the
+# stage loads in flight (they complete in issue order).
+NO_SCRATCH = {"mixed.hip": ("mixed_brute_kernel",)}
+KERNEL_DESC = re.compile(r"\.amdhsa_kernel\s+(\S+)")
+PRIVATE_SIZE = re.compile(r"\.amdhsa_private_segment_fixed_size\s+(\d+)")
+
+
+def _scratch_users(asm_path, names):
+    """Kernels among `names` (substrings of the symbol) whose descriptor
+    reserves private (scratch) memory."""
+    bad, current = [], None
+    for ln in open(asm_path):
+        m = KERNEL_DESC.search(ln)
+        if m:
+            current = m.group(1)
+            continue
+        m = PRIVATE_SIZE.search(ln)
+        if m and current and int(m.group(1)) > 0 and any(n in current for n in names):
+            bad.append(current)
+    return bad
+
 
 def _compile(src):
     obj = os.path.join(BUILD, src + ".o")
@@ -41,6 +63,10 @@ def _compile(src):
             if bad:
                 r = subprocess.CompletedProcess(cmd, 1, "", "64-bit scalar literal in device code "
                                                 "(miscompiled on gfx950): " + "; ".join(bad[:5]))
+            scratch = _scratch_users(asm, NO_SCRATCH.get(src, ()))
+            if scratch:
+                r = subprocess.CompletedProcess(cmd, 1, "", "kernel uses scratch memory: "
+                                                + "; ".join(scratch))
     return src, obj, r
 
 
