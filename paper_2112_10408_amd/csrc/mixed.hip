@@ -391,8 +391,9 @@ constexpr int kPilotQ = 4;
 static_assert(kTileQ % kPilotQ == 0, "a pilot wave stays within one tile");
 __global__ __launch_bounds__(256) void mixed_pilot_kernel(
     IndexDesc ix, QueryArgs a, const float *qxp, const float *qyp, const float *qzp,
-    const float *qtp, const int32_t *perm, int64_t nq, const int64_t *tstart, int n_home,
-    int64_t n_steps, int n_slots, double *part_d, int32_t *part_i, float *bound) {
+    const float *qtp, const int32_t *perm, int64_t nq, const int64_t *tstart,
+    const float *stage_tmin, int n_home, int64_t n_steps, int n_slots, double *part_d,
+    int32_t *part_i, float *bound) {
   const int64_t q0 = ((int64_t)blockIdx.x * (blockDim.x >> 6) + uniform_i((int)(threadIdx.x >> 6))) *
                      kPilotQ;
   if (q0 >= nq) return;
@@ -409,9 +410,17 @@ __global__ __launch_bounds__(256) void mixed_pilot_kernel(
   }
   const int64_t t0 = tstart[q0 / kTileQ];
   const int64_t n = ix.n_points;
+  int scanned = 0;
+  // a stage not earlier than every one of these queries' time thresholds
+  // holds none of their candidates
+  float thr_max = -__builtin_huge_valf();
+#pragma unroll
+  for (int j = 0; j < kPilotQ; ++j) thr_max = fmaxf(thr_max, q[j].thrf);
   for (int h = 0; h < n_home; ++h) {
     int64_t stage = t0 + h;
     if (stage >= n_steps) stage -= n_steps;
+    if (!(stage_tmin[stage] < thr_max)) continue;
+    ++scanned;
     for (int half = 0; half < kStage / kWave; ++half) {
       const int64_t p = stage * kStage + half * kWave + lane;
       const bool ok = p < n;
@@ -444,8 +453,8 @@ __global__ __launch_bounds__(256) void mixed_pilot_kernel(
   }
   if (a.stats && lane == 0) {
     const int nmine = (int)(nq - q0 < kPilotQ ? nq - q0 : kPilotQ);
-    atomicAdd(a.stats + TNN_STAT_RESCORED, (unsigned long long)n_home * kStage * nmine);
-    atomicAdd(a.stats + TNN_STAT_POINTS, (unsigned long long)n_home * kStage * nmine);
+    atomicAdd(a.stats + TNN_STAT_RESCORED, (unsigned long long)scanned * kStage * nmine);
+    atomicAdd(a.stats + TNN_STAT_POINTS, (unsigned long long)scanned * kStage * nmine);
   }
 }
 
@@ -1217,8 +1226,8 @@ hipError_t launch_mixed_brute(const IndexDesc &ix, const QueryArgs &a, const tnn
   const int64_t resident = (int64_t)cu_count_mixed() * mixed_per_cu(lds);
   const int64_t pilot_waves = (qs.n + kPilotQ - 1) / kPilotQ;
   hipLaunchKernelGGL(mixed_pilot_kernel, dim3((unsigned)((pilot_waves + 3) / 4)), dim3(256), 0, st,
-                     ix, a, qs.x, qs.y, qs.z, qs.t, perm, qs.n, tstart, n_home, n_steps, n_slots,
-                     part_d, part_i, bound);
+                     ix, a, qs.x, qs.y, qs.z, qs.t, perm, qs.n, tstart, stage_tmin, n_home, n_steps,
+                     n_slots, part_d, part_i, bound);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int64_t items = l.tiles * l.chunks;
