@@ -1153,8 +1153,9 @@ hipError_t launch_mixed_brute(const IndexDesc &ix, const QueryArgs &a, const tnn
   if (qs.n == 0) return hipSuccess;
   const MixedCtx mc = make_ctx(ix, a);
   const MixedLayout l = mixed_layout(ix.n_points, qs.n, a.k);
-  // stage numbers are 32-bit in the search kernel
-  if (ix.n_blocks > l.max_blocks || l.np / kStage > INT32_MAX) return hipErrorInvalidValue;
+  // stage numbers, point slots and query positions are 32-bit in the search
+  if (ix.n_blocks > l.max_blocks || l.np > INT32_MAX || qs.n > INT32_MAX)
+    return hipErrorInvalidValue;
   char *base = static_cast<char *>(scratch);
   bf16x8 *ops = reinterpret_cast<bf16x8 *>(base + l.ops);
   float *nv = reinterpret_cast<float *>(base + l.nv);
