@@ -85,7 +85,8 @@ QueryArgs make_args(const tnn_query_params *p) {
   return a;
 }
 
-// kSegRec float4 per segment, then 16 work-queue counters 256 bytes apart,
+// kSegRec planes of one float4 per segment, then 16 work-queue counters 256
+// bytes apart,
 // then (in-call radius prediction) one float per query
 size_t prep_bytes(int64_t S, int64_t n_radius = 0) {
   return align_up(16 * kSegRec * (size_t)S) + 16 * 256 + align_up(4 * (size_t)n_radius);
@@ -98,6 +99,7 @@ Prep prep_view(void *scratch, int64_t S, bool radius = false) {
   p.ticket = reinterpret_cast<unsigned long long *>(b + align_up(16 * kSegRec * (size_t)S));
   p.radius2 = radius ? reinterpret_cast<float *>(b + align_up(16 * kSegRec * (size_t)S) + 16 * 256)
                      : nullptr;
+  p.n_seg = S;
   return p;
 }
 

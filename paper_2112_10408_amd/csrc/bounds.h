@@ -83,14 +83,14 @@ struct SegView {
 };
 
 __device__ __forceinline__ SegView load_seg(const Prep &pr, int64_t s) {
-  const float4 *r = pr.rec + kSegRec * s;
+  const int64_t S = pr.n_seg;
   SegView v;
-  v.r0 = r[0];
-  v.r1 = r[1];
-  v.r2 = r[2];
-  const float4 r3 = r[3];
-  v.ps = __float_as_int(r3.x);
-  v.pc = __float_as_int(r3.y);
+  v.r0 = pr.rec[s];
+  v.r1 = pr.rec[S + s];
+  v.r2 = pr.rec[2 * S + s];
+  const int2 r3 = reinterpret_cast<const int2 *>(pr.rec + 3 * S)[s];
+  v.ps = r3.x;
+  v.pc = r3.y;
   return v;
 }
 

@@ -65,14 +65,14 @@ __device__ __forceinline__ void prep_one(const IndexDesc &ix, const QueryArgs &a
   const double tz = (double)bz - (double)az;
   const double nt = sqrt(a.s[0] * tx * tx + a.s[1] * ty * ty + a.s[2] * tz * tz);
   const float slack = __double2float_ru(0x1p-17 * (nt + sqrt(n2)) * 0.5 * (1.0 + 0x1p-30));
-  float4 *r = rec + kSegRec * s;
-  r[0] = make_float4(ax, ay, az, ix.tmin[s]);
-  r[1] = make_float4(fx, fy, fz, ix.tmax[s]);
+  const int64_t S = ix.n_seg;
+  rec[s] = make_float4(ax, ay, az, ix.tmin[s]);
+  rec[S + s] = make_float4(fx, fy, fz, ix.tmax[s]);
   // with per-query scales the search forms these constants per query
   // (seg_lb_q) from the deviation bounds
-  r[2] = raw ? make_float4(ix.ex[s], ix.ey[s], ix.ez[s], 0.0f)
-              : make_float4(inv_n2, rad, slack, 0.0f);
-  r[3] = make_float4(__int_as_float(ix.pstart[s]), __int_as_float(ix.pcount[s]), 0.0f, 0.0f);
+  rec[2 * S + s] = raw ? make_float4(ix.ex[s], ix.ey[s], ix.ez[s], 0.0f)
+                       : make_float4(inv_n2, rad, slack, 0.0f);
+  reinterpret_cast<int2 *>(rec + 3 * S)[s] = make_int2(ix.pstart[s], ix.pcount[s]);
 }
 
 __global__ void prep_kernel(IndexDesc ix, QueryArgs a, float4 *rec, unsigned long long *ticket,
@@ -222,6 +222,33 @@ struct Searcher {
     }
   }
 
+  // This lane's segment record of block bb (an empty view past the end).
+  __device__ __forceinline__ SegView fetch_block(int bb) const {
+    const int64_t s = (int64_t)bb * kBlockSegs + lane;
+    SegView sv{};
+    if (s < ix.n_seg) sv = load_seg(pr, s);
+    return sv;
+  }
+
+  // Scan the segments of block bb (bound bmin, this lane's record sv) whose
+  // key lies in (prev, tau_cur], seeded segments excluded.  A segment's key
+  // is the larger of its cylinder bound and its block's bound: both hold for
+  // every member.
+  __device__ __forceinline__ void visit_block(int bb, float bmin, const SegView &sv,
+                                              double tau_cur, double prev, int seed_block,
+                                              uint64_t seed_mask) {
+    const int64_t S = ix.n_seg;
+    const int64_t s = (int64_t)bb * kBlockSegs + lane;
+    const float key_f = fmaxf(s < S ? seg_bound(sv) : __builtin_huge_valf(), bmin);
+    const double key = (double)key_f;
+    st.segs += (uint32_t)min((int64_t)kBlockSegs, S - (int64_t)bb * kBlockSegs);
+    const bool seeded = bb == seed_block && lane_in(seed_mask);
+    // a masked segment (infinite key) holds no candidate
+    const bool cand = s < S && key < kInf && key <= tau_cur && key > prev && !seeded;
+    const uint64_t cm = ballot(cand);
+    if (cm) scan(cm, bb, sv.ps, sv.pc, key_f);
+  }
+
   // One expansion round.  A segment's key is the larger of its cylinder
   // bound and its block's bound; every segment with prev < key <= min(tau,
   // k-th) is scanned (seeded segments excluded).  Rounds use increasing tau,
@@ -232,7 +259,6 @@ struct Searcher {
   __device__ float round(double prev, double tau, int seed_block, uint64_t seed_mask) {
     const int nb = ix.n_blocks;
     const int ns = ix.n_super;
-    const int64_t S = ix.n_seg;
     const float finf = __builtin_huge_valf();
     float maxfin = 0.0f;
     // superblock level: 64 superblock bounds per pass
@@ -262,22 +288,9 @@ struct Searcher {
           const int bl = pick_min(m, lbb, bmin);
           m &= ~(1ull << bl);
           const double tau_cur = fmin(tau, tk.kd);
-          const double lbb_b = (double)bmin;
-          if (lbb_b > tau_cur) break;
+          if ((double)bmin > tau_cur) break;
           const int bb = b0 + bl;
-          const int64_t s = (int64_t)bb * kBlockSegs + lane;
-          SegView sv{};
-          if (s < S) sv = load_seg(pr, s);
-          const int ps_l = sv.ps, pc_l = sv.pc;
-          // both bounds hold for every member; the larger one decides the round
-          const float key_f = fmaxf(s < S ? seg_bound(sv) : finf, bmin);
-          const double key = (double)key_f;
-          st.segs += (uint32_t)min((int64_t)kBlockSegs, S - (int64_t)bb * kBlockSegs);
-          const bool seeded = bb == seed_block && lane_in(seed_mask);
-          // a masked segment (infinite key) holds no candidate
-          const bool cand = s < S && key < kInf && key <= tau_cur && key > prev && !seeded;
-          const uint64_t cm = ballot(cand);
-          if (cm) scan(cm, bb, ps_l, pc_l, key_f);
+          visit_block(bb, bmin, fetch_block(bb), tau_cur, prev, seed_block, seed_mask);
         }
       }
     }

@@ -40,17 +40,20 @@ static_assert(sizeof(IndexDesc) <= sizeof(tnn_index), "index descriptor too larg
 constexpr uint32_t kIndexMagic = 0x544e4e31u;  // "TNN1"
 
 // Per-call segment records (the radius and projection constants depend on
-// the scales), kSegRec float4 per segment in index order:
+// the scales), in four planes of n_seg entries each (plane f of segment s at
+// rec[f * n_seg + s], so that the 64 lanes of a wave reading the records of
+// 64 consecutive segments read 1 KiB of contiguous memory per plane):
 //   [0] A.x, A.y, A.z, t_min
 //   [1] (B - A).x, .y, .z (float32 differences), t_max
 //   [2] 1 / |AB|_s^2 (0 for a degenerate segment), radius R = sqrt(sum s_f
 //       e_f^2) rounded up, absolute slack 2^-17 |AB|_s rounded up, 0
-//   [3] first point slot, member count (int32 bits), 0, 0
+//   [3] first point slot, member count (an int2 array over the plane)
 constexpr int kSegRec = 4;
 struct Prep {
   float4 *rec;
   unsigned long long *ticket;  // work-queue counters of the resident search kernel
   float *radius2;              // predicted radii (in-call prediction) or null
+  int64_t n_seg;               // entries per record plane
 };
 
 struct QueryArgs {
