@@ -416,26 +416,52 @@ __global__ __launch_bounds__(256) void mixed_pilot_kernel(
   float thr_max = -__builtin_huge_valf();
 #pragma unroll
   for (int j = 0; j < kPilotQ; ++j) thr_max = fmaxf(thr_max, q[j].thrf);
-  for (int h = 0; h < n_home; ++h) {
+  // The home range's stages that can hold a candidate of these queries (one
+  // stage per lane, read at once), then the points of each such stage, both
+  // halves requested together.
+  static_assert(kPilotStages <= kWave, "one home stage per lane");
+  uint64_t live = 0;
+  {
+    float tm = __builtin_huge_valf();
+    if (lane < n_home) {
+      int64_t stage = t0 + lane;
+      if (stage >= n_steps) stage -= n_steps;
+      tm = stage_tmin[stage];
+    }
+    live = ballot(tm < thr_max);
+  }
+  constexpr int kHalves = kStage / kWave;
+  while (live) {
+    const int h = __ffsll((long long)live) - 1;
+    live &= live - 1;
     int64_t stage = t0 + h;
     if (stage >= n_steps) stage -= n_steps;
-    if (!(stage_tmin[stage] < thr_max)) continue;
     ++scanned;
-    for (int half = 0; half < kStage / kWave; ++half) {
+    float4 pv[kHalves];
+    int pid[kHalves];
+    bool ok[kHalves];
+    // (unconditional loads, a padding lane reading point 0, which the gate
+    // drops: a branch around each load, or a use scheduled among them, would
+    // make the compiler wait for the first half's before requesting the
+    // second's; the launch has points)
+#pragma unroll
+    for (int half = 0; half < kHalves; ++half) {
       const int64_t p = stage * kStage + half * kWave + lane;
-      const bool ok = p < n;
-      float4 pv = make_float4(0.f, 0.f, 0.f, 0.f);
-      int pid = kNoId;
-      if (ok) {
-        pv = ix.pt4[p];
-        pid = ix.pid[p];
-      }
+      ok[half] = p < n;
+      const int64_t pl = ok[half] ? p : 0;
+      pv[half] = ix.pt4[pl];
+      pid[half] = ix.pid[pl];
+    }
+    __builtin_amdgcn_sched_barrier(0);  // every load issued before the first use
+#pragma unroll
+    for (int half = 0; half < kHalves; ++half) {
 #pragma unroll
       for (int j = 0; j < kPilotQ; ++j) {
-        const double d = exact_dist(s, q[j].x, q[j].y, q[j].z, q[j].t, pv.x, pv.y, pv.z, pv.w);
-        const bool gate = ok & (pv.w < q[j].thrf) & tk[j].admits(d, pid);
+        const double d = exact_dist(s, q[j].x, q[j].y, q[j].z, q[j].t, pv[half].x, pv[half].y,
+                                    pv[half].z, pv[half].w);
+        const bool gate = ok[half] & (pv[half].w < q[j].thrf) & tk[j].admits(d, pid[half]);
         const uint64_t gm = ballot(gate);
-        if (gm) tk[j].offer(gm, d, pid);
+        if (gm) tk[j].offer(gm, d, pid[half]);
       }
     }
   }
@@ -824,27 +850,23 @@ __global__ __launch_bounds__(kWaves * 64, 4) void mixed_brute_kernel(
     // a flush happened.
     auto scan_stage = [&](const Stage *st, int64_t p0) {
       bool flushed = false;
-      bf16x8 bn[kBatch];  // the next batch's operands, read one batch ahead
+      // The stage's tiles through the filter, batch by batch (straight-line
+      // code: the loop is unrolled), noting the tiles that hold a negative
+      // value: bit (c * kRowBlocks + bb) for point tile c and row block bb.
+      static_assert(kStageTiles * kRowBlocks == 32, "one bit per tile of the stage");
+      uint32_t near = 0;
 #pragma unroll
-      for (int c = 0; c < kBatch; ++c) bn[c] = st->op[c * 64 + lane];
-#pragma unroll 1
       for (int c0 = 0; c0 < kStageTiles; c0 += kBatch) {
         f32x4 acc[kRowBlocks][kBatch];
         {
-          bf16x8 b[kBatch];
-#pragma unroll
-          for (int c = 0; c < kBatch; ++c) b[c] = bn[c];
-          if (c0 + kBatch < kStageTiles) {
-#pragma unroll
-            for (int c = 0; c < kBatch; ++c) bn[c] = st->op[(c0 + kBatch + c) * 64 + lane];
-          }
           const f32x4 z = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
           for (int c = 0; c < kBatch; ++c) {
-            acc[0][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aop0, b[c], z, 0, 0, 0);
-            acc[1][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aop1, b[c], z, 0, 0, 0);
-            acc[2][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aop2, b[c], z, 0, 0, 0);
-            acc[3][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aop3, b[c], z, 0, 0, 0);
+            const bf16x8 b = st->op[(c0 + c) * 64 + lane];
+            acc[0][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aop0, b, z, 0, 0, 0);
+            acc[1][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aop1, b, z, 0, 0, 0);
+            acc[2][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aop2, b, z, 0, 0, 0);
+            acc[3][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aop3, b, z, 0, 0, 0);
           }
         }
         // sign bits of the batch's tile values, ORed as a tree
@@ -859,57 +881,54 @@ __global__ __launch_bounds__(kWaves * 64, 4) void mixed_brute_kernel(
         static_assert(kRowBlocks * kBatch == 8, "the OR tree below takes 8 tiles");
         const uint32_t any = ((o[0] | o[1]) | (o[2] | o[3])) | ((o[4] | o[5]) | (o[6] | o[7]));
         if (ballot((int)any < 0) == 0) continue;
-        // the batch's MFMA tiles holding a negative value (bit c * kRowBlocks + bb)
-        uint32_t near = 0;
 #pragma unroll
         for (int t = 0; t < kRowBlocks * kBatch; ++t)
-          near |= (ballot((int)o[t] < 0) != 0 ? 1u : 0u) << t;
-        // Each such tile's values again (the same MFMA, so that few
-        // registers stay live), and its survivors (negative tile value, the
-        // time mask, a real point; row g*4+e of block bb, column j) to the
-        // queue.
-        while (near) {
-          const int t = __ffs(near) - 1;
-          near &= near - 1;
-          const int c = t / kRowBlocks, bb = t % kRowBlocks;
-          const int j = (c0 + c) * 16 + row;
-          const f32x4 v4 = mfma_block(bb, st->op[(c0 + c) * 64 + lane]);
-          const float pt = (p0 + j < n_real) ? st->t[j] : __builtin_huge_valf();
-          const float4 th4 = s_thr4[wave][bb * 4 + g];
-          const int r0 = bb * kMQ + g * 4;
-          bool ps[4];
-          uint64_t pm[4];
-          int np = 0;
-          ps[0] = (__float_as_int(v4[0]) < 0) & (pt < th4.x);
-          ps[1] = (__float_as_int(v4[1]) < 0) & (pt < th4.y);
-          ps[2] = (__float_as_int(v4[2]) < 0) & (pt < th4.z);
-          ps[3] = (__float_as_int(v4[3]) < 0) & (pt < th4.w);
+          near |= (ballot((int)o[t] < 0) != 0 ? 1u : 0u) << (c0 * kRowBlocks + t);
+      }
+      // Each such tile's values again (the same MFMA, so that few registers
+      // stay live), and its survivors (negative tile value, the time mask, a
+      // real point; row g*4+e of block bb, column j) to the queue.
+      while (near) {
+        const int t = __ffs(near) - 1;
+        near &= near - 1;
+        const int c = t / kRowBlocks, bb = t % kRowBlocks;
+        const int j = c * 16 + row;
+        const f32x4 v4 = mfma_block(bb, st->op[c * 64 + lane]);
+        const float pt = (p0 + j < n_real) ? st->t[j] : __builtin_huge_valf();
+        const float4 th4 = s_thr4[wave][bb * 4 + g];
+        const int r0 = bb * kMQ + g * 4;
+        bool ps[4];
+        uint64_t pm[4];
+        int np = 0;
+        ps[0] = (__float_as_int(v4[0]) < 0) & (pt < th4.x);
+        ps[1] = (__float_as_int(v4[1]) < 0) & (pt < th4.y);
+        ps[2] = (__float_as_int(v4[2]) < 0) & (pt < th4.z);
+        ps[3] = (__float_as_int(v4[3]) < 0) & (pt < th4.w);
 #pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            pm[e] = ballot(ps[e]);
-            np += __popcll(pm[e]);
-          }
-          if (np == 0) continue;
-          if (queued + np <= kQCap) {
+        for (int e = 0; e < 4; ++e) {
+          pm[e] = ballot(ps[e]);
+          np += __popcll(pm[e]);
+        }
+        if (np == 0) continue;
+        if (queued + np <= kQCap) {
 #pragma unroll
-            for (int e = 0; e < 4; ++e)
-              if (pm[e] != 0) enqueue(pm[e], ps[e], j, r0 + e, v4[e], p0, st);
-            continue;
-          }
-          // a full queue: set by set, flushing whenever the next would not fit
+          for (int e = 0; e < 4; ++e)
+            if (pm[e] != 0) enqueue(pm[e], ps[e], j, r0 + e, v4[e], p0, st);
+          continue;
+        }
+        // a full queue: set by set, flushing whenever the next would not fit
 #pragma unroll 1
-          for (int e = 0; e < 4; ++e) {
-            const uint64_t m = e == 0 ? pm[0] : e == 1 ? pm[1] : e == 2 ? pm[2] : pm[3];
-            if (m == 0) continue;
-            if (queued + __popcll(m) > kQCap) {
-              flush(queued);
-              flushed = true;
-              queued = 0;
-            }
-            const bool pe = e == 0 ? ps[0] : e == 1 ? ps[1] : e == 2 ? ps[2] : ps[3];
-            const float ve = e == 0 ? v4[0] : e == 1 ? v4[1] : e == 2 ? v4[2] : v4[3];
-            enqueue(m, pe, j, r0 + e, ve, p0, st);
+        for (int e = 0; e < 4; ++e) {
+          const uint64_t m = e == 0 ? pm[0] : e == 1 ? pm[1] : e == 2 ? pm[2] : pm[3];
+          if (m == 0) continue;
+          if (queued + __popcll(m) > kQCap) {
+            flush(queued);
+            flushed = true;
+            queued = 0;
           }
+          const bool pe = e == 0 ? ps[0] : e == 1 ? ps[1] : e == 2 ? ps[2] : ps[3];
+          const float ve = e == 0 ? v4[0] : e == 1 ? v4[1] : e == 2 ? v4[2] : v4[3];
+          enqueue(m, pe, j, r0 + e, ve, p0, st);
         }
       }
       return flushed;
