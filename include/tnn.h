@@ -182,9 +182,11 @@ tnn_status tnn_index_info(const tnn_index *index, int64_t *n_points, int64_t *n_
  * and the counters of the search's work queues (and 4 B per query for the
  * predicted radius when params->radius_model is set).  TNN_BRUTE: none (256).
  * TNN_BRUTE | TNN_MIXED_BF16: the BF16 point operands (64 B per point,
- * padded to 128 points), |v|^2 per point, each query's per-chunk top-k lists
- * (12 B per slot, 1 to 8 chunks chosen from n_queries and the point count)
- * with their k-th distances, and a work counter.  tnn_query writes all of it
+ * padded to 128 points), |v|^2 per point, each query's top-k lists (12 B per
+ * slot: one list per point chunk, 1 to 16 chunks chosen from n_queries and
+ * the point count, plus the pilot pass's), its bound, home block and place
+ * in the scan order, per-block query counts, the tiles' first stages, each
+ * stage's earliest time, and a work counter.  tnn_query writes all of it
  * itself, so the buffer needs no initialisation, but two calls in flight at
  * once must not share it. */
 tnn_status tnn_query_workspace(const tnn_index *index, int64_t n_queries,
