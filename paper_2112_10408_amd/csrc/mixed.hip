@@ -47,7 +47,7 @@ constexpr int kQCap = 64;                   // queued survivors per wave (one pe
 constexpr int kBatch = 2;                   // tiles whose tile values are tested together
 constexpr int kMaxChunks = 16;              // point chunks per query tile
 constexpr int kPilotStages = 32;            // stages of a tile's home range (pilot pass)
-constexpr int kShareSteps = 8;              // steps between two poolings of a tile's bounds
+constexpr int kShareSteps = 16;             // steps between two poolings of a tile's bounds
 // Workgroups resident on a full chip, nominally (256 CUs x 3): only sets
 // how finely the points are chunked, so the workspace size does not depend
 // on the device.
@@ -618,14 +618,18 @@ __global__ __launch_bounds__(kWaves * 64, 4) void mixed_brute_kernel(
       const float4 pv = pt4[p];
       d = exact_dist(sc, qp.x, qp.y, qp.z, qp.t, pv.x, pv.y, pv.z, pv.w);
       pid = s_qi[wave][lane];
-      valid = (double)pv.w < qp.thr;
+      // a candidate beyond the row's bound cannot be among the query's k
+      // nearest (the bound is the rounded-up k-th distance of some list of k
+      // of its candidates), so it skips the merge; a row whose survivors all
+      // fail this reads no list
+      valid = (double)pv.w < qp.thr && d <= (double)s_tau[wave][mi];
       const float c = s_qc[wave][lane];
       if (want_err && c > -__builtin_huge_valf() && c < __builtin_huge_valf()) {
         const double approx = (double)c + (double)kGamma * ((double)s_nu[wave][mi] + (double)s_a.nv[p]);
         max_err = fmax(max_err, fabs(approx - d));
       }
     }
-    uint64_t pending = ballot(has);
+    uint64_t pending = ballot(has && valid);
     while (pending) {
       const int m = __builtin_amdgcn_readlane(mi, __ffsll((long long)pending) - 1);
       const bool mine = has && mi == m;
