@@ -51,7 +51,7 @@ BF16_MFMA_PEAK_TFLOPS = 2500.0
 # only; after any change to them the figure is reported as null.
 KERNEL_SOURCES = ("query.hip", "query.h", "bounds.h", "wave.h", "gka.h", "tnn_internal.h")
 MEASURED_TRAFFIC = {
-    "sha256": "9647871164313367861981df987d7314b01b8431211ac105934a0cbccc5ac73f",
+    "sha256": "0e07743439cb80045322a46d5b68aa5a2a169915f21dda81937dde218b281f35",
     "bytes_per_launch": 252.0e6,
 }
 
@@ -459,7 +459,7 @@ def main():
     global STRATEGY
     STRATEGY = args.radius_strategy
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(queries shard across GPUs with a replicated index; see the design notes)",
               file=sys.stderr)
         sys.exit(2)

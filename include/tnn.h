@@ -43,9 +43,9 @@ typedef int32_t tnn_status;
 #define TNN_E_NONFINITE (-3)   /* a coordinate is NaN or infinite */
 #define TNN_E_WORKSPACE (-4)   /* buffer smaller than the size the matching *_workspace call gave */
 #define TNN_E_HIP (-5)         /* a HIP runtime call failed */
-#define TNN_E_UNSUPPORTED (-6) /* valid request outside this build's limits */
+#define TNN_E_UNSUPPORTED (-6) /* valid request outside the library's limits */
 #define TNN_E_FORMAT (-7)      /* a checkpoint that is not a complete, intact checkpoint of
-                                  this build's radius model */
+                                  this library's radius model */
 
 /* Structure-of-arrays float32 points in device memory: x, y, z (km), t (s). */
 typedef struct {

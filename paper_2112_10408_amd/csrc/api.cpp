@@ -116,7 +116,7 @@ const char *tnn_status_string(tnn_status s) {
     case TNN_E_WORKSPACE: return "workspace too small";
     case TNN_E_HIP: return "HIP runtime error";
     case TNN_E_UNSUPPORTED: return "unsupported request";
-    case TNN_E_FORMAT: return "not a valid checkpoint for this build";
+    case TNN_E_FORMAT: return "not a valid checkpoint for this library version";
     default: return "unknown status";
   }
 }

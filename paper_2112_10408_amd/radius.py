@@ -58,7 +58,7 @@ def save(model, path):
 
 def load(path, device="cuda"):
     """Device model from a checkpoint file (TnnError TNN_E_FORMAT if the file
-    is not an intact checkpoint of this build's model)."""
+    is not an intact checkpoint of this library's model)."""
     with open(path, "rb") as f:
         data = f.read()
     return T.tnn_radius_model_load(data, device=device)
