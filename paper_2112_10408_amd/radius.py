@@ -1,4 +1,4 @@
-"""Host driver for the learned k-th radius: label, train, calibrate, save.
+"""Host side of the learned k-th radius: label, train, calibrate, save.
 
 Labels are the k-th distances that plain TNN returns for a set of training
 queries (the method's own output).  Every arithmetic step runs in the

@@ -3,8 +3,8 @@
 The library's host-only logic (csrc/host.cpp: offset validation, the spatial
 ordering of segments, buffer layouts, the autotuner's cache format, the
 radius-model checkpoint header) and the C oracle are built with g++ / gcc
-and -fsanitize=address,undefined, then exercised by the self-test drivers in
-tests/native/.  A sanitizer report aborts the driver, failing the test."""
+and -fsanitize=address,undefined, then exercised by the self-test programs in
+tests/native/.  A sanitizer report aborts the program, failing the test."""
 import os
 import shutil
 import subprocess
