@@ -122,10 +122,13 @@ typedef struct {
   /* Optional Gaussian kernel averaging of the neighbours' measurements (Sec.
    * 3.2, Eq. gka; the definition of tnn_gka_average, below): with
    * d_gka_values set, each query's d_gka_out row receives the average of
-   * d_gka_values over its k neighbours.  TNN (and tnn_query_batched items)
-   * compute it from the search's registers as soon as a query's neighbours
-   * are final; the linear searches run tnn_gka_average's kernel after the
-   * search.  Results equal tnn_gka_average on the returned idx and dist. */
+   * d_gka_values over its k neighbours.  tnn_query runs tnn_gka_average's
+   * kernel on the stream right after the search, on the outputs it has just
+   * written (on the 1M-point workload this adds less to the call than
+   * computing the average inside the search kernel, whose vector units it
+   * would share); tnn_query_batched items compute it from the search's
+   * registers as soon as a query's neighbours are final.  Results equal
+   * tnn_gka_average on the returned idx and dist. */
   const float *d_gka_values;   /* device float32 [n_points][gka_comp], row p = the
                                   measurement at caller point p; NULL = no averaging */
   double *d_gka_out;           /* device binary64 [n_queries][gka_comp]; NaN rows for

@@ -455,9 +455,9 @@ write_out:
     out_idx[qi * a.k + se.lane] = se.tk.id == kNoId ? -1 : se.tk.id;
     out_dist[qi * a.k + se.lane] = se.tk.d;
   }
-  // Gaussian kernel averaging straight from the registers of the top-k (a
-  // kernel instance of its own: its registers would cost the plain search
-  // occupancy)
+  // Gaussian kernel averaging straight from the registers of the top-k (the
+  // batched search's instances that average; the single-call path averages
+  // with a kernel of its own after the search)
   if constexpr (Gka)
     gka_context_average(se.lane < a.k && se.tk.id != kNoId && se.tk.d < kInf, se.tk.id, se.tk.d,
                         a.gka_values, a.gka_comp, a.gka_out + qi * a.gka_comp);
@@ -513,8 +513,8 @@ __device__ __forceinline__ void answer_query(const IndexDesc &ix, const Prep &pr
 
 // qscale (last, so the other arguments keep their places): per-query scales
 // when PerQ, else unused.  Stats: the call collects statistics (a.stats set).
-// Gka: the call averages values over each query's neighbours (a.gka_values).
-template <bool PerQ, bool Stats, bool Gka>
+// (An averaging the call asks for runs as a kernel of its own afterwards.)
+template <bool PerQ, bool Stats>
 __global__ __launch_bounds__(512) void tnn_query_kernel(IndexDesc ix, Prep pr, QueryArgs a,
                                                         const float *qx, const float *qy,
                                                         const float *qz, const float *qt,
@@ -522,8 +522,8 @@ __global__ __launch_bounds__(512) void tnn_query_kernel(IndexDesc ix, Prep pr, Q
                                                         double *out_dist, const double *qscale) {
   const int64_t qi = (int64_t)blockIdx.x * (blockDim.x >> 6) + uniform_i((int)(threadIdx.x >> 6));
   if (qi >= nq) return;
-  answer_query<PerQ, Stats, Gka>(ix, pr, a, load_query_in(qx, qy, qz, qt, a, qi), qi, out_idx,
-                                 out_dist, ix.box, ix.sbox, qscale);
+  answer_query<PerQ, Stats, false>(ix, pr, a, load_query_in(qx, qy, qz, qt, a, qi), qi, out_idx,
+                                   out_dist, ix.box, ix.sbox, qscale);
 }
 
 // Same search with the block boxes staged once per workgroup in LDS (small
@@ -533,11 +533,10 @@ __global__ __launch_bounds__(512) void tnn_query_kernel(IndexDesc ix, Prep pr, Q
 // BoxesInLds: the block boxes fit in LDS too (the superblock boxes always
 // do); a template argument so that every box read is a plain LDS or global
 // access rather than a generic one.  PerQ: every query has its own scales.
-// Stats: the call collects statistics (a.stats set).  Gka: the call averages
-// values over each query's neighbours.  The per-query-scale instances are
-// compiled for 5 waves per SIMD (96 VGPRs; 113 and 4 waves otherwise); the
-// shared-scale ones fit 7 as they are (68 VGPRs).
-template <bool BoxesInLds, bool PerQ, bool Stats, bool Gka>
+// Stats: the call collects statistics (a.stats set).  The per-query-scale
+// instances are compiled for 5 waves per SIMD (96 VGPRs; 113 and 4 waves
+// otherwise); the shared-scale ones fit 7 as they are (67 VGPRs).
+template <bool BoxesInLds, bool PerQ, bool Stats>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(PerQ ? 5 : 1))) void
 tnn_query_lds_kernel(
     IndexDesc ix, Prep pr, QueryArgs a, const float *qx, const float *qy, const float *qz,
@@ -573,8 +572,8 @@ tnn_query_lds_kernel(
       if (base >= hi) break;
       const int64_t end = base + step < hi ? base + step : hi;
       for (int64_t qi = base; qi < end; ++qi)
-        answer_query<PerQ, Stats, Gka>(ix, pr, a, load_query_in(qx, qy, qz, qt, a, qi), qi,
-                                       out_idx, out_dist, box, s_box, qscale);
+        answer_query<PerQ, Stats, false>(ix, pr, a, load_query_in(qx, qy, qz, qt, a, qi), qi,
+                                         out_idx, out_dist, box, s_box, qscale);
     }
   }
 #else
@@ -582,8 +581,8 @@ tnn_query_lds_kernel(
   const int64_t stride = (int64_t)gridDim.x * wpb;
   for (int64_t qi = (int64_t)blockIdx.x * wpb + uniform_i((int)(threadIdx.x >> 6)); qi < nq;
        qi += stride)
-    answer_query<PerQ, Stats, Gka>(ix, pr, a, load_query_in(qx, qy, qz, qt, a, qi), qi, out_idx,
-                                   out_dist, box, s_box, qscale);
+    answer_query<PerQ, Stats, false>(ix, pr, a, load_query_in(qx, qy, qz, qt, a, qi), qi, out_idx,
+                                     out_dist, box, s_box, qscale);
 #endif
 }
 
@@ -872,15 +871,13 @@ hipError_t launch_query(const IndexDesc &ix, const Prep &pr, const QueryArgs &a,
     const int in_lds = sl + bl <= kLdsBoxBytes ? 1 : 0;
     const size_t lds = in_lds ? sl + bl : sl;
     const bool perq = query_scale != nullptr;
-    using Kern = decltype(&tnn_query_lds_kernel<true, true, true, true>);
-#define TNN_LDS_KERNELS(G)                                                                    \
-  tnn_query_lds_kernel<false, false, false, G>, tnn_query_lds_kernel<true, false, false, G>, \
-      tnn_query_lds_kernel<false, true, false, G>, tnn_query_lds_kernel<true, true, false, G>, \
-      tnn_query_lds_kernel<false, false, true, G>, tnn_query_lds_kernel<true, false, true, G>, \
-      tnn_query_lds_kernel<false, true, true, G>, tnn_query_lds_kernel<true, true, true, G>
-    static const Kern kerns[16] = {TNN_LDS_KERNELS(false), TNN_LDS_KERNELS(true)};
-#undef TNN_LDS_KERNELS
-    const int variant = in_lds + (perq ? 2 : 0) + (a.stats ? 4 : 0) + (a.gka_values ? 8 : 0);
+    using Kern = decltype(&tnn_query_lds_kernel<true, true, true>);
+    static const Kern kerns[8] = {
+        tnn_query_lds_kernel<false, false, false>, tnn_query_lds_kernel<true, false, false>,
+        tnn_query_lds_kernel<false, true, false>,  tnn_query_lds_kernel<true, true, false>,
+        tnn_query_lds_kernel<false, false, true>,  tnn_query_lds_kernel<true, false, true>,
+        tnn_query_lds_kernel<false, true, true>,   tnn_query_lds_kernel<true, true, true>};
+    const int variant = in_lds + (perq ? 2 : 0) + (a.stats ? 4 : 0);
     const Kern kern = kerns[variant];
     const int per_cu = resident_per_cu(variant, waves_per_block, lds, [&](int *n) {
       return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, kern, waves_per_block * kWave, lds);
@@ -892,14 +889,10 @@ hipError_t launch_query(const IndexDesc &ix, const Prep &pr, const QueryArgs &a,
                        qs.x, qs.y, qs.z, qs.t, qs.n, out_idx, out_dist, query_scale);
     return hipGetLastError();
   }
-  using GKern = decltype(&tnn_query_kernel<true, true, true>);
-  static const GKern gkerns[8] = {
-      tnn_query_kernel<false, false, false>, tnn_query_kernel<true, false, false>,
-      tnn_query_kernel<false, true, false>,  tnn_query_kernel<true, true, false>,
-      tnn_query_kernel<false, false, true>,  tnn_query_kernel<true, false, true>,
-      tnn_query_kernel<false, true, true>,   tnn_query_kernel<true, true, true>};
-  const GKern kern =
-      gkerns[(query_scale ? 1 : 0) + (a.stats ? 2 : 0) + (a.gka_values ? 4 : 0)];
+  using GKern = decltype(&tnn_query_kernel<true, true>);
+  static const GKern gkerns[4] = {tnn_query_kernel<false, false>, tnn_query_kernel<true, false>,
+                                  tnn_query_kernel<false, true>, tnn_query_kernel<true, true>};
+  const GKern kern = gkerns[(query_scale ? 1 : 0) + (a.stats ? 2 : 0)];
   hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(waves_per_block * kWave), 0, st, ix, pr, a,
                      qs.x, qs.y, qs.z, qs.t, qs.n, out_idx, out_dist, query_scale);
   return hipGetLastError();
