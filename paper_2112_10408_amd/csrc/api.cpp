@@ -337,9 +337,8 @@ tnn_status tnn_query(const tnn_index *index, tnn_points queries, const tnn_query
     return TNN_E_UNSUPPORTED;
   // The averaging (Sec. 3.2, Eq. gka), when asked for, runs as a kernel of
   // its own right after the search, on the outputs the search has just
-  // written (still in the L2): on the 1M-point workload it adds 11 us per
-  // 100k queries at k = 32, where computing it inside the search kernel
-  // added 23 us (it competes with the search for its vector units).
+  // written: computed inside the search kernel instead, it took longer (its
+  // exponentials and wave sums compete with the search for the vector units).
   QueryArgs as = a;
   as.gka_values = nullptr;
   as.gka_out = nullptr;

@@ -389,10 +389,10 @@ def test_gka_average_matches_oracle(k, n_comp):
                          ids=["plain", "learned", "brute", "bf16"])
 @pytest.mark.parametrize("k,n_comp", [(1, 1), (8, 2), (32, 3), (64, 8)])
 def test_gka_epilogue_of_the_search(flags, k, n_comp):
-    """The averaging requested with the search (computed from the top-k in
-    registers on the TNN paths, by the averaging kernel after the linear
-    searches) equals tnn_gka_average on the returned context bit for bit, and
-    the oracle's average within 1e-12; the neighbours are unchanged."""
+    """The averaging requested with the search (the averaging kernel run on
+    the call's stream right after the search) equals tnn_gka_average on the
+    returned context bit for bit, and the oracle's average within 1e-12; the
+    neighbours are unchanged."""
     ps = synth.trajectories(60, 90, 40.0, 900.0, seed=23)
     _, qi = synth.sample_queries(ps, 600, seed=24)
     qs = ps.take(np.concatenate([qi, np.argsort(ps.t)[:3]]))
