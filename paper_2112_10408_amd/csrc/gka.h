@@ -1,6 +1,6 @@
 // Gaussian kernel averaging over one query's k-NN context (Sec. 3.2, Eq.
-// gka), held one slot per lane of a wavefront: the standalone averaging
-// kernel and the search's epilogue run this same code.
+// gka), held one slot per lane of a wavefront: the one-query averaging
+// kernel and the batched search's epilogue run this same code.
 #pragma once
 #include "wave.h"
 

@@ -70,7 +70,7 @@ struct QueryArgs {
   // radius predicted by the preparation launch (model null: none)
   const tnn_radius_model *model;
   float alpha;
-  // Gaussian kernel averaging epilogue (gka_values null: none)
+  // Gaussian kernel averaging asked with the search (gka_values null: none)
   const float *gka_values;
   int32_t gka_comp;
   double *gka_out;

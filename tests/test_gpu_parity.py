@@ -388,7 +388,7 @@ def test_gka_average_matches_oracle(k, n_comp):
 @pytest.mark.parametrize("flags", [capi.TNN_PLAIN, capi.TNN_LEARNED, capi.TNN_BRUTE, MIXED],
                          ids=["plain", "learned", "brute", "bf16"])
 @pytest.mark.parametrize("k,n_comp", [(1, 1), (8, 2), (32, 3), (64, 8)])
-def test_gka_epilogue_of_the_search(flags, k, n_comp):
+def test_gka_asked_of_the_search(flags, k, n_comp):
     """The averaging requested with the search (the averaging kernel run on
     the call's stream right after the search) equals tnn_gka_average on the
     returned context bit for bit, and the oracle's average within 1e-12; the
@@ -420,9 +420,10 @@ def test_gka_epilogue_of_the_search(flags, k, n_comp):
     assert np.allclose(got[ok], want[ok], rtol=1e-12, atol=1e-12)
 
 
-def test_gka_epilogue_per_query_scales_and_batched():
-    """The epilogue under per-query scales (a row without a metric gets a NaN
-    average) and in a batched launch (each item its own values)."""
+def test_gka_asked_per_query_scales_and_batched():
+    """The averaging asked under per-query scales (a row without a metric
+    gets a NaN average) and in a batched launch (the search's epilogue, each
+    item its own values)."""
     ps = synth.trajectories(40, 80, 40.0, 900.0, seed=25)
     qs, _ = synth.sample_queries(ps, 300, seed=26)
     ix = build(ps, 16)
