@@ -13,7 +13,7 @@ namespace tnn {
 namespace {
 
 using namespace radius;
-constexpr int kTrainBlock = 64;  // samples per workgroup in the backward pass
+constexpr int kTrainBlock = 64;  // samples per workgroup in the forward/backward pass
 
 __host__ __device__ inline uint64_t splitmix64(uint64_t x) {
   x += 0x9e3779b97f4a7c15ull;
@@ -106,129 +106,256 @@ __global__ __launch_bounds__(64 * kInferWaves) void infer_kernel(
   infer_tiles(m, q, alpha, radius2, logr, blockIdx.x, gridDim.x);
 }
 
-// Forward and backward over kTrainBlock samples per workgroup; writes this
-// workgroup's un-normalised gradient sum (2 r dout/dtheta) and its loss
-// partials (sum r^2, count) to partial[blockIdx].
 // Sample b of the batch is samples[order[first + b]] (order: a permutation of
 // the samples, device int32), or samples[first + b] without one.
 __device__ __forceinline__ int64_t sample_of(const int32_t *order, int64_t first, int64_t b) {
   return order ? (int64_t)order[first + b] : first + b;
 }
 
-__global__ __launch_bounds__(kTrainBlock) void fwd_bwd_kernel(const tnn_radius_model *m,
-                                                              tnn_points smp, const double *dist,
-                                                              const int32_t *order, int32_t k,
-                                                              int64_t first, int64_t batch,
-                                                              float *partial) {
-  __shared__ float W[NP];
-  __shared__ float F[kTrainBlock][NI];
-  __shared__ float H1[kTrainBlock][H + 1];   // h1
-  __shared__ float H2[kTrainBlock][H + 1];   // h2
-  __shared__ float G2[kTrainBlock][H + 1];   // dL/dz2
-  __shared__ float G1[kTrainBlock][H + 1];   // dL/dz1
-  __shared__ float GO[kTrainBlock];      // dL/dout (un-normalised: 2 r)
-  __shared__ float R2[kTrainBlock];
-  const int t = threadIdx.x;
-  for (int i = t; i < NP; i += blockDim.x) W[i] = m->params[i];
-  __syncthreads();
-  const int64_t b = (int64_t)blockIdx.x * kTrainBlock + t;
-  float go = 0.0f, r2 = 0.0f;
+// Forward and backward over kTrainBlock samples per workgroup, one wave per
+// tile of 32 samples; writes this workgroup's un-normalised gradient sum
+// (2 r dout/dtheta) and its loss partials (sum r^2, count) to
+// partial[blockIdx].  A tile's three dense contractions run on the matrix
+// cores with float32 operands, in the lane layout of the inference
+// (v_mfma_f32_32x32x2f32): the hidden layer (32 samples x 64 inputs x 64
+// units), the delta through the hidden weights (32 samples x 64 units x 64
+// inputs) and the hidden weights' gradient (64 units x 32 samples x 64
+// inputs).  The first layer, the output layer and the biases, whose
+// gradients are short sums over the workgroup's samples, run on the vector
+// units from LDS.
+constexpr int kTrainTile = 32;
+constexpr int kTrainWaves = kTrainBlock / kTrainTile;
+constexpr int kRow = H + 1;  // padded LDS row
+static_assert(kTrainWaves == 2, "two tiles per workgroup: their hidden-weight gradients are "
+                                "exchanged through the two activation areas");
+static_assert(kTrainWaves * kTrainTile * kRow >= H * H, "an activation area holds a tile's "
+                                                        "hidden-weight gradient");
+
+__global__ __launch_bounds__(64 * kTrainWaves) void fwd_bwd_kernel(
+    const tnn_radius_model *m, tnn_points smp, const double *dist, const int32_t *order, int32_t k,
+    int64_t first, int64_t batch, float *partial) {
+  static_assert(NI == 6 && H == 64, "the tiling covers 6 inputs and 64 hidden units");
+  __shared__ float W2s[H][kRow];  // W2s[unit][input]
+  __shared__ float4 W1s[H][2];    // per unit: weights 0..3 | weights 4, 5, bias
+  __shared__ float H1[kTrainWaves][kTrainTile][kRow];  // h1[sample][unit]
+  __shared__ float H2[kTrainWaves][kTrainTile][kRow];  // h2[sample][unit]
+  __shared__ float G2[kTrainWaves][kTrainTile][kRow];  // dL/dz2
+  __shared__ float G1[kTrainWaves][kTrainTile][kRow];  // output-layer terms, then dL/dz1
+  __shared__ float F[kTrainWaves][kTrainTile][NI];
+  __shared__ float GO[kTrainWaves][kTrainTile];  // dL/dout (un-normalised: 2 r)
+  __shared__ float R2[kTrainWaves][kTrainTile];
+  __shared__ float LB[kTrainWaves][kTrainTile];  // 1 for a labelled sample
+  const float *__restrict__ W = m->params;
+  const int wv = threadIdx.x >> 6;
+  const int l = threadIdx.x & 63;
+  const int col = l & 31;   // sample (A rows) or unit / input (B, D columns) within a block
+  const int half = l >> 5;  // which of the two K entries of a step
+  // All of a thread's hidden-weight loads are issued before the sample's
+  // dependent loads and written to LDS after them, so that the latencies
+  // overlap (a rolled loop waits out one load latency per element).
+  constexpr int kThreads = 64 * kTrainWaves, kPer = H * H / kThreads;
+  static_assert(H * H % kThreads == 0, "hidden weights split evenly over the threads");
+  float w2v[kPer];
+#pragma unroll
+  for (int r = 0; r < kPer; ++r) w2v[r] = W[OW2 + threadIdx.x + r * kThreads];
+  // the lane's sample (both halves of the wave hold the same 32 samples)
+  const int64_t b = (int64_t)blockIdx.x * kTrainBlock + wv * kTrainTile + col;
   float f[NI] = {};
+  bool lab = false;
+  float y = 0.0f;
   if (b < batch) {
     const int64_t si = sample_of(order, first, b);
     features(m, smp.x[si], smp.y[si], smp.z[si], smp.t[si], f);
     const double dk = dist[si * k + (k - 1)];
-    const bool lab = dk > 0.0 && dk < __builtin_huge_val();
-    for (int j = 0; j < H; ++j) {
-      float a = W[OB1 + j];
+    lab = dk > 0.0 && dk < __builtin_huge_val();
+    if (lab) y = (float)(0.5 * log(dk));
+  }
+  // the hidden weights into LDS (their loads were issued first)
 #pragma unroll
-      for (int c = 0; c < NI; ++c) a += W[OW1 + j * NI + c] * f[c];
-      G1[t][j] = a;  // z1 for now; replaced by dL/dz1 below
-      H1[t][j] = fmaxf(a, 0.0f);
+  for (int r = 0; r < kPer; ++r) {
+    const int i = threadIdx.x + r * kThreads;
+    W2s[i / H][i % H] = w2v[r];
+  }
+  for (int u = threadIdx.x; u < H; u += blockDim.x) {
+    W1s[u][0] = make_float4(W[OW1 + u * NI], W[OW1 + u * NI + 1], W[OW1 + u * NI + 2],
+                            W[OW1 + u * NI + 3]);
+    W1s[u][1] = make_float4(W[OW1 + u * NI + 4], W[OW1 + u * NI + 5], W[OB1 + u], 0.0f);
+  }
+  if (half == 0)
+#pragma unroll
+    for (int c = 0; c < NI; ++c) F[wv][col][c] = f[c];
+  __syncthreads();
+  float(*h1)[kRow] = H1[wv];
+  float(*h2)[kRow] = H2[wv];
+  float(*g2)[kRow] = G2[wv];
+  float(*g1)[kRow] = G1[wv];
+
+  // forward: z2 = b2 + W2 h1 on the matrix cores, h1 formed per K-step
+  f32x16 c0, c1;
+  {
+    const float b2_0 = W[OB2 + col], b2_1 = W[OB2 + 32 + col];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      c0[e] = b2_0;
+      c1[e] = b2_1;
     }
+  }
+#pragma unroll 4
+  for (int st = 0; st < H / 2; ++st) {
+    const int u = 2 * st + half;
+    const float4 wa = W1s[u][0], wb = W1s[u][1];
+    const float a =
+        wb.z + wa.x * f[0] + wa.y * f[1] + wa.z * f[2] + wa.w * f[3] + wb.x * f[4] + wb.y * f[5];
+    const float hu = fmaxf(a, 0.0f);
+    h1[col][u] = hu;
+    c0 = __builtin_amdgcn_mfma_f32_32x32x2f32(hu, W2s[col][u], c0, 0, 0, 0);
+    c1 = __builtin_amdgcn_mfma_f32_32x32x2f32(hu, W2s[32 + col][u], c1, 0, 0, 0);
+  }
+  // output layer: per (sample, unit) terms summed over units through LDS
+  const float w3_0 = W[OW3 + col], w3_1 = W[OW3 + 32 + col];
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    const int row = (e >> 2) * 8 + half * 4 + (e & 3);
+    const float a0 = fmaxf(c0[e], 0.0f), a1 = fmaxf(c1[e], 0.0f);
+    h2[row][col] = a0;
+    h2[row][32 + col] = a1;
+    g1[row][col] = w3_0 * a0 + w3_1 * a1;
+  }
+  wave_sync();
+  if (l < kTrainTile) {
     float out = W[OB3];
-    for (int j = 0; j < H; ++j) {
-      float a = W[OB2 + j];
-      for (int c = 0; c < H; ++c) a += W[OW2 + j * H + c] * H1[t][c];
-      const float h2 = fmaxf(a, 0.0f);
-      H2[t][j] = h2;
-      G2[t][j] = a > 0.0f ? 1.0f : 0.0f;  // relu gate, scaled below
-      out += W[OW3 + j] * h2;
-    }
+#pragma unroll
+    for (int u = 0; u < kTrainTile; ++u) out += g1[l][u];
+    float go = 0.0f, r2 = 0.0f;
     if (lab) {
-      const float y = (float)(0.5 * log(dk));
       const float r = out - y;
       go = 2.0f * r;
       r2 = r * r;
     }
-    for (int j = 0; j < H; ++j) G2[t][j] *= go * W[OW3 + j];
-    for (int c = 0; c < H; ++c) {
-      float a = 0.0f;
-      for (int j = 0; j < H; ++j) a += G2[t][j] * W[OW2 + j * H + c];
-      G1[t][c] = G1[t][c] > 0.0f ? a : 0.0f;
+    GO[wv][l] = go;
+    R2[wv][l] = r2;
+    LB[wv][l] = lab ? 1.0f : 0.0f;
+  }
+  wave_sync();
+  // dL/dz2 = go w3 where z2 > 0
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    const int row = (e >> 2) * 8 + half * 4 + (e & 3);
+    const float go = GO[wv][row];
+    g2[row][col] = c0[e] > 0.0f ? go * w3_0 : 0.0f;
+    g2[row][32 + col] = c1[e] > 0.0f ? go * w3_1 : 0.0f;
+  }
+  wave_sync();
+  // dL/dz1 = (W2^T dL/dz2) where z1 > 0: A = dL/dz2 (sample x unit), B = W2
+  // (unit x input)
+  {
+    f32x16 d0, d1;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) d0[e] = d1[e] = 0.0f;
+#pragma unroll 4
+    for (int st = 0; st < H / 2; ++st) {
+      const int j = 2 * st + half;
+      const float a = g2[col][j];
+      d0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a, W2s[j][col], d0, 0, 0, 0);
+      d1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a, W2s[j][32 + col], d1, 0, 0, 0);
     }
-    for (int c = 0; c < NI; ++c) F[t][c] = f[c];
-    GO[t] = go;
-    R2[t] = lab ? r2 : 0.0f;
-  } else {
-    for (int j = 0; j < H; ++j) H1[t][j] = H2[t][j] = G2[t][j] = G1[t][j] = 0.0f;
-    for (int c = 0; c < NI; ++c) F[t][c] = 0.0f;
-    GO[t] = 0.0f;
-    R2[t] = 0.0f;
+    wave_sync();  // the output-layer terms in g1 have been read
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const int row = (e >> 2) * 8 + half * 4 + (e & 3);
+      g1[row][col] = h1[row][col] > 0.0f ? d0[e] : 0.0f;
+      g1[row][32 + col] = h1[row][32 + col] > 0.0f ? d1[e] : 0.0f;
+    }
+  }
+  // the tile's hidden-weight gradient, sum over samples of dL/dz2[s][unit]
+  // h1[s][input]: A = dL/dz2^T (unit x sample), B = h1 (sample x input)
+  f32x16 acc[2][2];
+#pragma unroll
+  for (int jb = 0; jb < 2; ++jb)
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) acc[jb][cb][e] = 0.0f;
+#pragma unroll 4
+  for (int st = 0; st < kTrainTile / 2; ++st) {
+    const int s = 2 * st + half;
+    const float a0 = g2[s][col], a1 = g2[s][32 + col];
+    const float b0 = h1[s][col], b1 = h1[s][32 + col];
+    acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b0, acc[0][0], 0, 0, 0);
+    acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b1, acc[0][1], 0, 0, 0);
+    acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b0, acc[1][0], 0, 0, 0);
+    acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b1, acc[1][1], 0, 0, 0);
   }
   __syncthreads();
+
+  // the small gradients over the workgroup's samples, tile by tile
   float *out = partial + (size_t)blockIdx.x * (NP + 3);
-  for (int p = t; p < NP; p += blockDim.x) {
-    float acc = 0.0f;
-    if (p < OB1) {
-      const int j = p / NI, c = p % NI;
-      for (int s = 0; s < kTrainBlock; ++s) acc += G1[s][j] * F[s][c];
-    } else if (p < OW2) {
-      const int j = p - OB1;
-      for (int s = 0; s < kTrainBlock; ++s) acc += G1[s][j];
-    } else if (p < OB2) {
-      const int j = (p - OW2) / H, c = (p - OW2) % H;
-      for (int s = 0; s < kTrainBlock; ++s) acc += G2[s][j] * H1[s][c];
-    } else if (p < OW3) {
-      const int j = p - OB2;
-      for (int s = 0; s < kTrainBlock; ++s) acc += G2[s][j];
-    } else if (p < OB3) {
-      const int j = p - OW3;
-      for (int s = 0; s < kTrainBlock; ++s) acc += GO[s] * H2[s][j];
-    } else {
-      for (int s = 0; s < kTrainBlock; ++s) acc += GO[s];
-    }
-    out[p] = acc;
-  }
-  if (t == 0) {
-    float l = 0.0f, c = 0.0f;
-    for (int s = 0; s < kTrainBlock; ++s) {
-      l += R2[s];
-      const int64_t bs = (int64_t)blockIdx.x * kTrainBlock + s;
-      if (bs < batch) {
-        const double dk = dist[sample_of(order, first, bs) * k + (k - 1)];
-        c += (dk > 0.0 && dk < __builtin_huge_val()) ? 1.0f : 0.0f;
+  for (int q = threadIdx.x; q < NP - H * H; q += blockDim.x) {
+    const int p = q < OW2 ? q : q + H * H;  // every parameter but the hidden weights
+    float a = 0.0f;
+    for (int w = 0; w < kTrainWaves; ++w) {
+      if (p < OB1) {
+        const int j = p / NI, c = p % NI;
+        for (int s = 0; s < kTrainTile; ++s) a += G1[w][s][j] * F[w][s][c];
+      } else if (p < OW2) {
+        for (int s = 0; s < kTrainTile; ++s) a += G1[w][s][p - OB1];
+      } else if (p < OW3) {
+        for (int s = 0; s < kTrainTile; ++s) a += G2[w][s][p - OB2];
+      } else if (p < OB3) {
+        for (int s = 0; s < kTrainTile; ++s) a += GO[w][s] * H2[w][s][p - OW3];
+      } else {
+        for (int s = 0; s < kTrainTile; ++s) a += GO[w][s];
       }
     }
-    out[NP] = l;
-    out[NP + 1] = c;
+    out[p] = a;
   }
+  if (threadIdx.x == 0) {
+    float loss = 0.0f, cnt = 0.0f;
+    for (int w = 0; w < kTrainWaves; ++w)
+      for (int s = 0; s < kTrainTile; ++s) {
+        loss += R2[w][s];
+        cnt += LB[w][s];
+      }
+    out[NP] = loss;
+    out[NP + 1] = cnt;
+  }
+  __syncthreads();
+  // hidden weights: tile 0's gradient in the H1 area, tile 1's in H2, summed
+  float *xg = wv == 0 ? &H1[0][0][0] : &H2[0][0][0];
+#pragma unroll
+  for (int jb = 0; jb < 2; ++jb)
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const int j = jb * 32 + (e >> 2) * 8 + half * 4 + (e & 3);
+        xg[j * H + cb * 32 + col] = acc[jb][cb][e];
+      }
+  __syncthreads();
+  const float *x0 = &H1[0][0][0], *x1 = &H2[0][0][0];
+  for (int i = threadIdx.x; i < H * H; i += blockDim.x) out[OW2 + i] = x0[i] + x1[i];
 }
 
 // Sum of the partials in block order (deterministic), divided by the number
 // of labelled samples.
-__global__ void reduce_kernel(const float *partial, int nblk, float *grad, float *loss) {
+// The loops are unrolled so that 16 loads are in flight at a time (a rolled
+// loop waits out one load latency per block); the sums stay in block order.
+__global__ void reduce_kernel(const float *__restrict__ partial, int nblk, float *grad,
+                              float *loss) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   float n = 0.0f;
+#pragma unroll 16
   for (int b = 0; b < nblk; ++b) n += partial[(size_t)b * (NP + 3) + NP + 1];
   const float inv = 1.0f / fmaxf(n, 1.0f);
   if (p < NP) {
     float a = 0.0f;
+#pragma unroll 16
     for (int b = 0; b < nblk; ++b) a += partial[(size_t)b * (NP + 3) + p];
     grad[p] = a * inv;
   }
   if (p == 0 && loss) {
     float l = 0.0f;
+#pragma unroll 16
     for (int b = 0; b < nblk; ++b) l += partial[(size_t)b * (NP + 3) + NP];
     *loss = l * inv;
   }
@@ -398,7 +525,7 @@ tnn_status launch_grad(const void *d_model, tnn_points smp, const double *d_dist
   if (!scratch || bytes < train_scratch(batch)) return TNN_E_WORKSPACE;
   const int nblk = (int)((batch + kTrainBlock - 1) / kTrainBlock);
   float *partial = static_cast<float *>(scratch);
-  hipLaunchKernelGGL(fwd_bwd_kernel, dim3(nblk), dim3(kTrainBlock), 0, st,
+  hipLaunchKernelGGL(fwd_bwd_kernel, dim3(nblk), dim3(64 * kTrainWaves), 0, st,
                      static_cast<const tnn_radius_model *>(d_model), smp, d_dist, d_order, k,
                      first, batch, partial);
   TNN_HIP_CHECK(hipGetLastError());
