@@ -194,6 +194,30 @@ def test_gradient_in_a_given_order_matches_oracle(setup):
     assert np.linalg.norm(g - go) <= 1e-4 * np.linalg.norm(go) + 1e-7
 
 
+def test_gradient_skips_unlabelled_samples(setup):
+    """Samples whose k-th distance is +inf (fewer than k earlier points) or 0
+    carry no label and add nothing to the gradient or the loss, wherever they
+    sit: first and last rows of each 32-sample tile, in both workgroups of a
+    ragged batch of 97."""
+    ps, ix, model, lo, hi, grids = setup
+    k = 8
+    rng = np.random.default_rng(12)
+    qs = ps.take(rng.choice(ps.n, 97, replace=False))
+    _, dist = oracle.knn(ps.soa(), qs.soa(), SCALE, 0.0, k)
+    dist = np.ascontiguousarray(dist)
+    dist[[0, 31, 32, 63, 64, 96], k - 1] = np.inf
+    dist[[5, 40, 70], k - 1] = 0.0
+    g, loss = T.tnn_radius_grad(model, *dev_points(qs), torch.from_numpy(dist).cuda(), k, 0, qs.n)
+    g = g.cpu().numpy().astype(np.float64)
+    theta = T.radius_params(model).cpu().numpy().astype(np.float64)
+    X = oracle.radius_features(*qs.soa(), lo, hi, *grids)
+    y = oracle.radius_label(dist[:, k - 1])
+    assert np.isnan(y).sum() >= 9
+    lo_, go = oracle.mlp_loss_grad(theta, X, y)
+    assert float(loss.item()) == pytest.approx(lo_, rel=1e-4, abs=1e-6)
+    assert np.linalg.norm(g - go) <= 1e-4 * np.linalg.norm(go) + 1e-7
+
+
 @pytest.mark.parametrize("quantile", [0.0, 0.5, 0.9, 0.99, 1.0])
 def test_calibration_matches_oracle_quantile(setup, quantile):
     """The safety factor computed on the device (inference, log-residuals,
