@@ -9,6 +9,7 @@
 
 #include "gka.h"
 #include "host.h"
+#include "kdorder.h"
 #include "query.h"
 
 using namespace tnn;
@@ -185,32 +186,26 @@ tnn_status tnn_build_segments(tnn_points pts, const int64_t *h_traj_offsets, int
                                  F(L.tf[2]), F(L.tf[3]), F(L.tf[4]), F(L.tf[5]), F(L.tf[6]),
                                  F(L.tf[7]), F(L.tf[8]), F(L.tf[9]), F(L.tf[10]), F(L.keys), status,
                                  st));
-  uint32_t status_h = 0;
-  std::vector<float> keys;
+  // the kd order of the segments (identity without order scales) and each
+  // segment's first point slot in that order, on the device: the splits
+  // depend on S alone, so the host lists them without reading anything back
+  TNN_HIP_CHECK(launch_iota(I(L.perm), S, st));
+  std::vector<host::KdSplit> splits;
   if (order_scale && S > 0) {
-    keys.resize(4 * (size_t)S);
-    TNN_HIP_CHECK(hipMemcpyAsync(keys.data(), F(L.keys), 16 * S, hipMemcpyDeviceToHost, st));
+    int64_t level_begin[host::kKdMaxLevels + 1];
+    int n_levels = 0;
+    splits.resize((size_t)host::kd_splits(S, kBlockSegs, nullptr, nullptr, nullptr));
+    host::kd_splits(S, kBlockSegs, splits.data(), level_begin, &n_levels);
+    auto *d_splits = reinterpret_cast<host::KdSplit *>(m + L.kdsplits);
+    if (!splits.empty())
+      TNN_HIP_CHECK(hipMemcpyAsync(d_splits, splits.data(), sizeof(host::KdSplit) * splits.size(),
+                                   hipMemcpyHostToDevice, st));
+    // dpstart serves as the partition's staging area until it is written
+    for (int lv = 0; lv < n_levels; ++lv)
+      TNN_HIP_CHECK(launch_kd_level(F(L.keys), I(L.perm), I(L.dpstart), d_splits + level_begin[lv],
+                                    level_begin[lv + 1] - level_begin[lv], st));
   }
-  TNN_HIP_CHECK(hipMemcpyAsync(&status_h, status, 4, hipMemcpyDeviceToHost, st));
-  TNN_HIP_CHECK(hipStreamSynchronize(st));
-  if (status_h & 2u) return TNN_E_NONFINITE;
-  if (status_h & 1u) return TNN_E_UNSORTED;
-
-  std::vector<int32_t> perm(S);
-  std::iota(perm.begin(), perm.end(), 0);
-  if (order_scale && S > 0) host::kd_order(perm.data(), S, keys.data(), kBlockSegs);
-  std::vector<int32_t> dpstart(S);
-  {
-    int64_t acc = 0;
-    for (int64_t j = 0; j < S; ++j) {
-      dpstart[j] = (int32_t)acc;
-      acc += tcf[perm[j]] & 0xffff;
-    }
-  }
-  if (S > 0) {
-    TNN_HIP_CHECK(hipMemcpyAsync(I(L.perm), perm.data(), 4 * S, hipMemcpyHostToDevice, st));
-    TNN_HIP_CHECK(hipMemcpyAsync(I(L.dpstart), dpstart.data(), 4 * S, hipMemcpyHostToDevice, st));
-  }
+  TNN_HIP_CHECK(launch_point_offsets(I(L.perm), I(L.tcf), S, I(L.dpstart), st));
   const float *src_f[11];
   float *dst_f[11];
   for (int i = 0; i < 11; ++i) {
@@ -250,10 +245,16 @@ tnn_status tnn_build_segments(tnn_points pts, const int64_t *h_traj_offsets, int
   d.sfirst = I(L.sfirst);
   d.box = F(L.box);
   TNN_HIP_CHECK(launch_block_box(d, F(L.box), st));
+  // the one read-back: the data checks and the block boxes (the kernels
+  // above are safe on rejected data; nothing is returned from it)
+  uint32_t status_h = 0;
   std::vector<float> box(8 * (size_t)nb);
   if (nb > 0)
     TNN_HIP_CHECK(hipMemcpyAsync(box.data(), F(L.box), 32 * nb, hipMemcpyDeviceToHost, st));
+  TNN_HIP_CHECK(hipMemcpyAsync(&status_h, status, 4, hipMemcpyDeviceToHost, st));
   TNN_HIP_CHECK(hipStreamSynchronize(st));
+  if (status_h & 2u) return TNN_E_NONFINITE;
+  if (status_h & 1u) return TNN_E_UNSORTED;
   const int64_t ns = (nb + kSuperBlocks - 1) / kSuperBlocks;
   std::vector<float> sbox(8 * (size_t)ns);
   for (int64_t sb = 0; sb < ns; ++sb)

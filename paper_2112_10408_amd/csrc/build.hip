@@ -1,5 +1,6 @@
 // Index construction kernels (Sec. 3.4: partition into runs of K points,
 // segment from first to last point, approximation error) and the test export.
+#include "kdorder.h"
 #include "query.h"
 #include "wave.h"
 
@@ -175,6 +176,229 @@ __global__ void export_kernel(IndexDesc ix, float *seg_f32, int32_t *seg_i32, in
   if (block_box && i < ix.n_blocks) {
     for (int f = 0; f < 8; ++f) block_box[8 * i + f] = ix.box[8 * i + f];
   }
+}
+
+// ---------------------------------------------------------------------------
+// kd order on the device, one level per launch and one workgroup per split.
+// ---------------------------------------------------------------------------
+constexpr int kKdThreads = 1024;
+constexpr int kKdWaves = kKdThreads / kWave;
+
+__global__ void iota_kernel(int32_t *perm, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) perm[i] = (int32_t)i;
+}
+
+// Unsigned image of a float32 key with the same order (-0 taken as +0, so
+// that equal keys compare equal).
+__device__ __forceinline__ uint32_t kd_ordered(float v) {
+  const uint32_t u = __float_as_uint(v == 0.0f ? 0.0f : v);
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+// A split range [start, start + n) of perm: the widest key axis over the
+// range (extent hi - lo, the first of equal extents), the entry of rank m by
+// (key on that axis, segment index) found by radix selection over the 64-bit
+// (ordered key, index) with 8-bit digits, then a stable partition of the
+// range into the entries below it and the rest, staged in tmp and copied
+// back.
+__global__ __launch_bounds__(kKdThreads) void kd_split_kernel(const float4 *__restrict__ keys,
+                                                              int32_t *perm, int32_t *tmp,
+                                                              const host::KdSplit *splits) {
+  const host::KdSplit sp = splits[blockIdx.x];
+  int32_t *r = perm + sp.start;
+  int32_t *o = tmp + sp.start;
+  const int n = sp.n, m = sp.m;
+  const int t = threadIdx.x, lane = t & (kWave - 1), w = t / kWave;
+  __shared__ float s_ext[kKdWaves][8];
+  __shared__ uint32_t s_hist[256];
+  __shared__ uint64_t s_pref, s_piv;
+  __shared__ int s_rank, s_cnt, s_axis;
+  __shared__ int s_wl[kKdWaves], s_wv[kKdWaves];
+
+  // widest axis
+  float lo[4], hi[4];
+#pragma unroll
+  for (int f = 0; f < 4; ++f) {
+    lo[f] = __builtin_huge_valf();
+    hi[f] = -__builtin_huge_valf();
+  }
+  for (int i = t; i < n; i += kKdThreads) {
+    const float4 k = keys[r[i]];
+    const float v[4] = {k.x, k.y, k.z, k.w};
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+      lo[f] = fminf(lo[f], v[f]);
+      hi[f] = fmaxf(hi[f], v[f]);
+    }
+  }
+#pragma unroll
+  for (int f = 0; f < 4; ++f)
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+      lo[f] = fminf(lo[f], __shfl_xor(lo[f], off));
+      hi[f] = fmaxf(hi[f], __shfl_xor(hi[f], off));
+    }
+  if (lane == 0)
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+      s_ext[w][f] = lo[f];
+      s_ext[w][4 + f] = hi[f];
+    }
+  __syncthreads();
+  if (t == 0) {
+    float l[4], h[4];
+    for (int f = 0; f < 4; ++f) {
+      l[f] = s_ext[0][f];
+      h[f] = s_ext[0][4 + f];
+      for (int x = 1; x < kKdWaves; ++x) {
+        l[f] = fminf(l[f], s_ext[x][f]);
+        h[f] = fmaxf(h[f], s_ext[x][4 + f]);
+      }
+    }
+    int axis = 0;
+    for (int f = 1; f < 4; ++f)
+      if (h[f] - l[f] > h[axis] - l[axis]) axis = f;
+    s_axis = axis;
+    s_pref = 0;
+    s_rank = m;
+  }
+  __syncthreads();
+  const int axis = s_axis;
+  auto composite = [&](int i, int32_t *id_out) -> uint64_t {
+    const int32_t id = r[i];
+    const float4 k = keys[id];
+    const float v = axis == 0 ? k.x : axis == 1 ? k.y : axis == 2 ? k.z : k.w;
+    *id_out = id;
+    return ((uint64_t)kd_ordered(v) << 32) | (uint32_t)id;
+  };
+
+  // the entry of rank m: digits from the top until one candidate is left
+  // (the composites are distinct, so at the latest after the last digit)
+  uint64_t mask = 0;
+  for (int pass = 0; pass < 8; ++pass) {
+    const int shift = 56 - 8 * pass;
+    for (int b = t; b < 256; b += kKdThreads) s_hist[b] = 0;
+    __syncthreads();
+    const uint64_t pref = s_pref;
+    for (int i = t; i < n; i += kKdThreads) {
+      int32_t id;
+      const uint64_t c = composite(i, &id);
+      if ((c & mask) == pref) atomicAdd(&s_hist[(c >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    if (t == 0) {
+      const uint32_t rank = (uint32_t)s_rank;
+      uint32_t cum = 0;
+      int d = 0;
+      while (d < 255 && rank >= cum + s_hist[d]) cum += s_hist[d++];
+      s_rank = (int)(rank - cum);
+      s_pref = pref | ((uint64_t)d << shift);
+      s_cnt = (int)s_hist[d];
+    }
+    __syncthreads();
+    mask |= (uint64_t)255 << shift;
+    if (s_cnt <= 1) break;
+  }
+  {
+    const uint64_t pref = s_pref;
+    if (t == 0) s_piv = pref;  // all digits fixed, or overwritten below
+    __syncthreads();
+    for (int i = t; i < n; i += kKdThreads) {
+      int32_t id;
+      const uint64_t c = composite(i, &id);
+      if ((c & mask) == pref) s_piv = c;
+    }
+    __syncthreads();
+  }
+  const uint64_t pivot = s_piv;
+
+  // stable partition: entries below the pivot to o[0, m), the rest to
+  // o[m, n), each in range order, chunk by chunk
+  int nl = 0, nr = 0;
+  for (int base = 0; base < n; base += kKdThreads) {
+    const int i = base + t;
+    const bool valid = i < n;
+    int32_t id = 0;
+    bool left = false;
+    if (valid) left = composite(i, &id) < pivot;
+    const uint64_t bl = ballot(left), bv = ballot(valid);
+    if (lane == 0) {
+      s_wl[w] = __popcll(bl);
+      s_wv[w] = __popcll(bv);
+    }
+    __syncthreads();
+    int offl = 0, offv = 0, totl = 0, totv = 0;
+    for (int x = 0; x < kKdWaves; ++x) {
+      if (x < w) {
+        offl += s_wl[x];
+        offv += s_wv[x];
+      }
+      totl += s_wl[x];
+      totv += s_wv[x];
+    }
+    if (valid) {
+      if (left) {
+        const uint64_t below = bl & ((1ull << lane) - 1ull);
+        o[nl + offl + __popcll(below)] = id;
+      } else {
+        const uint64_t below = (bv & ~bl) & ((1ull << lane) - 1ull);
+        o[m + nr + (offv - offl) + __popcll(below)] = id;
+      }
+    }
+    nl += totl;
+    nr += totv - totl;
+    __syncthreads();
+  }
+  for (int i = t; i < n; i += kKdThreads) r[i] = o[i];
+}
+
+// One workgroup: each thread sums a contiguous run of the counts, the run
+// sums are scanned in LDS, then each thread writes its run's offsets.
+__global__ __launch_bounds__(1024) void point_offsets_kernel(const int32_t *perm,
+                                                             const int32_t *cnt_flags,
+                                                             int64_t n_seg, int32_t *dpstart) {
+  __shared__ int64_t s[1024];
+  const int t = threadIdx.x;
+  const int64_t per = (n_seg + 1023) / 1024;
+  const int64_t b0 = t * per < n_seg ? t * per : n_seg;
+  const int64_t b1 = b0 + per < n_seg ? b0 + per : n_seg;
+  int64_t sum = 0;
+  for (int64_t i = b0; i < b1; ++i) sum += cnt_flags[perm[i]] & 0xffff;
+  s[t] = sum;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    const int64_t v = t >= off ? s[t - off] : 0;
+    __syncthreads();
+    s[t] += v;
+    __syncthreads();
+  }
+  int64_t acc = s[t] - sum;
+  for (int64_t i = b0; i < b1; ++i) {
+    dpstart[i] = (int32_t)acc;
+    acc += cnt_flags[perm[i]] & 0xffff;
+  }
+}
+
+hipError_t launch_iota(int32_t *perm, int64_t n, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(iota_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, perm, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_kd_level(const float *keys, int32_t *perm, int32_t *tmp,
+                           const host::KdSplit *splits, int64_t n_splits, hipStream_t st) {
+  if (n_splits == 0) return hipSuccess;
+  hipLaunchKernelGGL(kd_split_kernel, dim3((unsigned)n_splits), dim3(kKdThreads), 0, st,
+                     reinterpret_cast<const float4 *>(keys), perm, tmp, splits);
+  return hipGetLastError();
+}
+
+hipError_t launch_point_offsets(const int32_t *perm, const int32_t *cnt_flags, int64_t n_seg,
+                                int32_t *dpstart, hipStream_t st) {
+  if (n_seg == 0) return hipSuccess;
+  hipLaunchKernelGGL(point_offsets_kernel, dim3(1), dim3(1024), 0, st, perm, cnt_flags, n_seg,
+                     dpstart);
+  return hipGetLastError();
 }
 
 hipError_t launch_seg_stats(const tnn_points &pts, const int32_t *start, const int32_t *cnt_flags,

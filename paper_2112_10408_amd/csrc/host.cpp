@@ -6,6 +6,8 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <utility>
+#include <vector>
 
 namespace tnn {
 namespace host {
@@ -47,35 +49,75 @@ BuildLayout build_layout(int64_t n, int64_t S, int64_t block, int64_t superblock
   L.keys = take(16 * (size_t)S);
   L.perm = take(4 * (size_t)S);
   L.dpstart = take(4 * (size_t)S);
+  L.kdsplits = take(sizeof(KdSplit) * (size_t)kd_splits(S, block, nullptr, nullptr, nullptr));
   L.status = take(32);
   L.total = o;
   return L;
 }
 
-void kd_order(int32_t *idx, int64_t n, const float *keys, int64_t block) {
-  if (n <= block) return;
-  float lo[4], hi[4];
-  for (int f = 0; f < 4; ++f) {
-    lo[f] = INFINITY;
-    hi[f] = -INFINITY;
-  }
-  for (int64_t i = 0; i < n; ++i)
-    for (int f = 0; f < 4; ++f) {
-      const float v = keys[4 * (size_t)idx[i] + f];
-      lo[f] = std::min(lo[f], v);
-      hi[f] = std::max(hi[f], v);
+int64_t kd_splits(int64_t S, int64_t block, KdSplit *splits, int64_t *level_begin,
+                  int *n_levels) {
+  // ranges of the current level: (start, n), in order
+  std::vector<std::pair<int64_t, int64_t>> cur, next;
+  if (S > 0) cur.push_back({0, S});
+  int64_t count = 0;
+  int levels = 0;
+  for (;;) {
+    next.clear();
+    const int64_t first = count;
+    for (const auto &r : cur) {
+      const int64_t n = r.second;
+      if (n <= block) {
+        next.push_back(r);
+        continue;
+      }
+      int64_t m = ((n / 2 + block - 1) / block) * block;
+      if (m >= n) m = (n - 1) / block * block;
+      if (splits) splits[count] = KdSplit{(int32_t)r.first, (int32_t)n, (int32_t)m, 0};
+      ++count;
+      next.push_back({r.first, m});
+      next.push_back({r.first + m, n - m});
     }
-  int axis = 0;
-  for (int f = 1; f < 4; ++f)
-    if (hi[f] - lo[f] > hi[axis] - lo[axis]) axis = f;
-  int64_t m = ((n / 2 + block - 1) / block) * block;
-  if (m >= n) m = (n - 1) / block * block;
-  std::nth_element(idx, idx + m, idx + n, [&](int32_t a, int32_t b) {
-    const float ka = keys[4 * (size_t)a + axis], kb = keys[4 * (size_t)b + axis];
-    return ka < kb || (ka == kb && a < b);
-  });
-  kd_order(idx, m, keys, block);
-  kd_order(idx + m, n - m, keys, block);
+    if (count == first) break;
+    if (level_begin) level_begin[levels] = first;
+    ++levels;
+    cur.swap(next);
+  }
+  if (level_begin) level_begin[levels] = count;
+  if (n_levels) *n_levels = levels;
+  return count;
+}
+
+void kd_order(int32_t *idx, int64_t n, const float *keys, int64_t block) {
+  const int64_t ns = kd_splits(n, block, nullptr, nullptr, nullptr);
+  std::vector<KdSplit> sp((size_t)ns);
+  kd_splits(n, block, sp.data(), nullptr, nullptr);
+  std::vector<int32_t> tmp;
+  for (const KdSplit &s : sp) {
+    int32_t *r = idx + s.start;
+    float lo[4], hi[4];
+    for (int f = 0; f < 4; ++f) {
+      lo[f] = INFINITY;
+      hi[f] = -INFINITY;
+    }
+    for (int64_t i = 0; i < s.n; ++i)
+      for (int f = 0; f < 4; ++f) {
+        const float v = keys[4 * (size_t)r[i] + f];
+        lo[f] = std::min(lo[f], v);
+        hi[f] = std::max(hi[f], v);
+      }
+    int axis = 0;
+    for (int f = 1; f < 4; ++f)
+      if (hi[f] - lo[f] > hi[axis] - lo[axis]) axis = f;
+    auto less = [&](int32_t a, int32_t b) {
+      const float ka = keys[4 * (size_t)a + axis], kb = keys[4 * (size_t)b + axis];
+      return ka < kb || (ka == kb && a < b);
+    };
+    tmp.assign(r, r + s.n);
+    std::nth_element(tmp.begin(), tmp.begin() + s.m, tmp.end(), less);
+    const int32_t pivot = tmp[(size_t)s.m];
+    std::stable_partition(r, r + s.n, [&](int32_t a) { return less(a, pivot); });
+  }
 }
 
 size_t cache_key(char *out, size_t cap, const char *arch, int n_items, long long total_q,

@@ -26,17 +26,34 @@ struct BuildLayout {
   size_t pt4, pid;
   size_t f[11], pstart, pcount, sorig, sfirst;
   size_t box, sbox;
-  size_t tf[11], tstart, tcf, keys, perm, dpstart, status;
+  size_t tf[11], tstart, tcf, keys, perm, dpstart, kdsplits, status;
   size_t total;
 };
 BuildLayout build_layout(int64_t n, int64_t S, int64_t block, int64_t superblock);
 
 inline size_t align256(size_t v) { return (v + 255) / 256 * 256; }
 
-// Recursive median split of idx[0, n) along the widest of the 4 key axes
-// (keys[4 * idx[i] + f]); split points fall on multiples of `block` so that
-// every block but the last is full.  Ties are broken by the index, so the
-// order is deterministic.
+// The kd order of segments into blocks: a range of the order longer than
+// `block` splits along the widest of its 4 key axes into its m smallest
+// entries (by key, ties by index) and the rest, m = n / 2 rounded up to a
+// multiple of `block` (so every block but the last is full), each part
+// keeping the order the range had; the parts split again until no range is
+// longer than `block`.  The splits depend on the entry count alone: level by
+// level, split ranges only (a range of at most `block` entries stays as it
+// is).  The device builds the order with these splits.
+struct KdSplit {
+  int32_t start, n, m, pad;
+};
+// Splits of the kd order of S entries, level after level; level L holds
+// splits[level_begin[L] .. level_begin[L + 1]).  Returns the split count
+// (splits and level_begin may be null to count only; level_begin then needs
+// one more entry than there are levels, at most 64).
+int64_t kd_splits(int64_t S, int64_t block, KdSplit *splits, int64_t *level_begin,
+                  int *n_levels);
+constexpr int kKdMaxLevels = 64;
+
+// The same order on the host (reference for the tests): idx[0, n) is
+// reordered in place; keys[4 * idx[i] + f].
 void kd_order(int32_t *idx, int64_t n, const float *keys, int64_t block);
 
 // Autotuner cache: one line per tuned problem, "<key> <chunk> <waves> <blocks>".

@@ -2,6 +2,7 @@
 // under the address and undefined-behaviour sanitizers by
 // tests/test_sanitizers.py.  Exits 0 and prints "host ok" when every check
 // holds; any sanitizer report aborts with a non-zero status.
+#include <algorithm>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -57,6 +58,74 @@ static void kd_ordering() {
     for (int64_t i = 0; i < n; ++i) again[i] = (int32_t)i;
     kd_order(again.data(), n, keys.data(), 64);
     CHECK(again == idx);
+    // every split: its first m entries below the rest by (key on the range's
+    // widest axis, index); later splits only reorder within the two parts
+    std::vector<KdSplit> sp((size_t)kd_splits(n, 64, nullptr, nullptr, nullptr));
+    kd_splits(n, 64, sp.data(), nullptr, nullptr);
+    for (const KdSplit &s : sp) {
+      float lo[4], hi[4];
+      for (int f = 0; f < 4; ++f) {
+        lo[f] = 1e30f;
+        hi[f] = -1e30f;
+      }
+      for (int i = s.start; i < s.start + s.n; ++i)
+        for (int f = 0; f < 4; ++f) {
+          lo[f] = std::min(lo[f], keys[4 * (size_t)idx[i] + f]);
+          hi[f] = std::max(hi[f], keys[4 * (size_t)idx[i] + f]);
+        }
+      int ax = 0;
+      for (int f = 1; f < 4; ++f)
+        if (hi[f] - lo[f] > hi[ax] - lo[ax]) ax = f;
+      auto key = [&](int32_t a) { return std::make_pair(keys[4 * (size_t)a + ax], a); };
+      std::pair<float, int32_t> lmax(-1e30f, -1), rmin(1e30f, 1 << 30);
+      for (int i = s.start; i < s.start + s.m; ++i) lmax = std::max(lmax, key(idx[i]));
+      for (int i = s.start + s.m; i < s.start + s.n; ++i) rmin = std::min(rmin, key(idx[i]));
+      CHECK(lmax < rmin);
+    }
+  }
+}
+
+// The split list: level by level, disjoint ranges in order, every split
+// longer than a block with m a positive multiple of the block below n; the
+// ranges left unsplit at the end are at most a block long and all but the
+// last are full.
+static void kd_split_lists() {
+  for (int64_t S : {0, 1, 64, 65, 128, 129, 200, 4097, 100000, 1234567}) {
+    const int64_t ns = kd_splits(S, 64, nullptr, nullptr, nullptr);
+    std::vector<KdSplit> sp((size_t)ns);
+    int64_t lb[kKdMaxLevels + 1];
+    int levels = -1;
+    CHECK(kd_splits(S, 64, sp.data(), lb, &levels) == ns);
+    CHECK(levels >= 0 && levels <= kKdMaxLevels && lb[levels] == ns);
+    CHECK((S <= 64) == (ns == 0));
+    // final ranges: replay the splits level by level
+    std::vector<std::pair<int64_t, int64_t>> cur;
+    if (S > 0) cur.push_back({0, S});
+    for (int L = 0; L < levels; ++L) {
+      int64_t end = 0;
+      std::vector<std::pair<int64_t, int64_t>> next;
+      size_t j = 0;
+      for (int64_t i = lb[L]; i < lb[L + 1]; ++i) {
+        const KdSplit &s = sp[(size_t)i];
+        CHECK(s.start >= end && s.n > 64 && s.m > 0 && s.m < s.n && s.m % 64 == 0);
+        end = s.start + s.n;
+        CHECK(end <= S);
+        while (j < cur.size() && cur[j].first < s.start) next.push_back(cur[j++]);
+        CHECK(j < cur.size() && cur[j].first == s.start && cur[j].second == s.n);
+        ++j;
+        next.push_back({s.start, s.m});
+        next.push_back({s.start + s.m, s.n - s.m});
+      }
+      while (j < cur.size()) next.push_back(cur[j++]);
+      cur.swap(next);
+    }
+    int64_t pos = 0;
+    for (size_t i = 0; i < cur.size(); ++i) {
+      CHECK(cur[i].first == pos && cur[i].second <= 64);
+      CHECK(i + 1 == cur.size() || cur[i].second == 64);
+      pos += cur[i].second;
+    }
+    CHECK(pos == S);
   }
 }
 
@@ -133,6 +202,7 @@ static void layouts() {
       r.push_back({L.keys, 16 * S});
       r.push_back({L.perm, 4 * S});
       r.push_back({L.dpstart, 4 * S});
+      r.push_back({L.kdsplits, sizeof(KdSplit) * (size_t)kd_splits(S, 64, nullptr, nullptr, nullptr)});
       r.push_back({L.status, 32});
       for (size_t i = 0; i < r.size(); ++i) {
         CHECK(r[i].first % 256 == 0);
@@ -147,6 +217,7 @@ int main() {
   layouts();
   offsets_and_counts();
   kd_ordering();
+  kd_split_lists();
   cache_lines();
   checkpoints();
   std::printf("host ok\n");
