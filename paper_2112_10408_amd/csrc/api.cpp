@@ -204,6 +204,7 @@ tnn_status tnn_build_segments(tnn_points pts, const int64_t *h_traj_offsets, int
     for (int lv = 0; lv < n_levels; ++lv)
       TNN_HIP_CHECK(launch_kd_level(F(L.keys), I(L.perm), I(L.dpstart), d_splits + level_begin[lv],
                                     level_begin[lv + 1] - level_begin[lv], st));
+    TNN_HIP_CHECK(launch_kd_leaves(F(L.keys), I(L.perm), S, st));
   }
   TNN_HIP_CHECK(launch_point_offsets(I(L.perm), I(L.tcf), S, I(L.dpstart), st));
   const float *src_f[11];

@@ -352,6 +352,87 @@ __global__ __launch_bounds__(kKdThreads) void kd_split_kernel(const float4 *__re
   for (int i = t; i < n; i += kKdThreads) r[i] = o[i];
 }
 
+// Inside every block of the kd order (kBlockSegs entries, the last one
+// shorter) the splits go on down to single entries: a range of n >= 2
+// entries splits along its widest axis into its n/2 smallest (by key, ties
+// by segment index) and the rest, each part keeping its order.  One wave per
+// block, lane = position; per level each lane finds its range, the range's
+// extents and its own rank in it by reading every lane, and moves to its new
+// position through LDS.
+__global__ __launch_bounds__(kWave) void kd_leaf_kernel(const float4 *__restrict__ keys,
+                                                        int32_t *perm, int64_t n_seg) {
+  __shared__ int32_t s_id[kWave];
+  const int64_t b0 = (int64_t)blockIdx.x * kBlockSegs;
+  const int lane = lane_id();
+  const int n = (int)(n_seg - b0 < kBlockSegs ? n_seg - b0 : kBlockSegs);
+  const bool ok = lane < n;
+  int32_t id = ok ? perm[b0 + lane] : 0;
+  for (int level = 0; (1 << level) < n; ++level) {
+    // this lane's range at this level: descend from [0, n)
+    int rs = 0, rn = n;
+    for (int d = 0; d < level; ++d) {
+      const int m = rn / 2;
+      if (lane < rs + m) {
+        rn = m;
+      } else {
+        rs += m;
+        rn -= m;
+      }
+    }
+    const float4 k = ok ? keys[id] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    const bool in_split = ok && rn >= 2;
+    // extents of the lane's range
+    float lo[4], hi[4];
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+      lo[f] = __builtin_huge_valf();
+      hi[f] = -__builtin_huge_valf();
+    }
+    for (int j = 0; j < n; ++j) {
+      const float kx = __shfl(k.x, j), ky = __shfl(k.y, j), kz = __shfl(k.z, j),
+                  kw = __shfl(k.w, j);
+      if (j >= rs && j < rs + rn) {
+        lo[0] = fminf(lo[0], kx);
+        hi[0] = fmaxf(hi[0], kx);
+        lo[1] = fminf(lo[1], ky);
+        hi[1] = fmaxf(hi[1], ky);
+        lo[2] = fminf(lo[2], kz);
+        hi[2] = fmaxf(hi[2], kz);
+        lo[3] = fminf(lo[3], kw);
+        hi[3] = fmaxf(hi[3], kw);
+      }
+    }
+    int axis = 0;
+#pragma unroll
+    for (int f = 1; f < 4; ++f)
+      if (hi[f] - lo[f] > hi[axis] - lo[axis]) axis = f;
+    const float key = axis == 0 ? k.x : axis == 1 ? k.y : axis == 2 ? k.z : k.w;
+    const uint64_t c = ((uint64_t)kd_ordered(key) << 32) | (uint32_t)id;
+    // rank in the range (axes may differ between ranges: each lane compares
+    // within its own range, where every lane took the same axis)
+    int rank = 0;
+    for (int j = 0; j < n; ++j) {
+      const uint32_t hj = (uint32_t)__shfl((int)(uint32_t)(c >> 32), j);
+      const uint32_t lj = (uint32_t)__shfl((int)(uint32_t)c, j);
+      if (j >= rs && j < rs + rn && (((uint64_t)hj << 32) | lj) < c) ++rank;
+    }
+    const int m = rn / 2;
+    const bool left = in_split && rank < m;
+    const uint64_t bl = ballot(left);
+    // position: the range's lefts first, then the rest, each in lane order
+    const uint64_t below = ((1ull << lane) - 1ull) & ~((1ull << rs) - 1ull);
+    const int lefts_before = __popcll(bl & below);
+    const int pos = !in_split ? lane
+                    : left    ? rs + lefts_before
+                              : rs + m + (lane - rs - lefts_before);
+    if (ok) s_id[pos] = id;
+    wave_sync();
+    id = ok ? s_id[lane] : 0;
+    wave_sync();
+  }
+  if (ok) perm[b0 + lane] = id;
+}
+
 // One workgroup: each thread sums a contiguous run of the counts, the run
 // sums are scanned in LDS, then each thread writes its run's offsets.
 __global__ __launch_bounds__(1024) void point_offsets_kernel(const int32_t *perm,
@@ -390,6 +471,13 @@ hipError_t launch_kd_level(const float *keys, int32_t *perm, int32_t *tmp,
   if (n_splits == 0) return hipSuccess;
   hipLaunchKernelGGL(kd_split_kernel, dim3((unsigned)n_splits), dim3(kKdThreads), 0, st,
                      reinterpret_cast<const float4 *>(keys), perm, tmp, splits);
+  return hipGetLastError();
+}
+
+hipError_t launch_kd_leaves(const float *keys, int32_t *perm, int64_t n_seg, hipStream_t st) {
+  if (n_seg == 0) return hipSuccess;
+  hipLaunchKernelGGL(kd_leaf_kernel, dim3((unsigned)((n_seg + kBlockSegs - 1) / kBlockSegs)),
+                     dim3(kWave), 0, st, reinterpret_cast<const float4 *>(keys), perm, n_seg);
   return hipGetLastError();
 }
 

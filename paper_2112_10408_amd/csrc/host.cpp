@@ -89,18 +89,16 @@ int64_t kd_splits(int64_t S, int64_t block, KdSplit *splits, int64_t *level_begi
 }
 
 void kd_order(int32_t *idx, int64_t n, const float *keys, int64_t block) {
-  const int64_t ns = kd_splits(n, block, nullptr, nullptr, nullptr);
-  std::vector<KdSplit> sp((size_t)ns);
-  kd_splits(n, block, sp.data(), nullptr, nullptr);
   std::vector<int32_t> tmp;
-  for (const KdSplit &s : sp) {
-    int32_t *r = idx + s.start;
+  // r[0, len) into its m smallest by (key on the widest axis, index) and
+  // the rest, each part keeping its order
+  auto split_range = [&](int32_t *r, int64_t len, int64_t m) {
     float lo[4], hi[4];
     for (int f = 0; f < 4; ++f) {
       lo[f] = INFINITY;
       hi[f] = -INFINITY;
     }
-    for (int64_t i = 0; i < s.n; ++i)
+    for (int64_t i = 0; i < len; ++i)
       for (int f = 0; f < 4; ++f) {
         const float v = keys[4 * (size_t)r[i] + f];
         lo[f] = std::min(lo[f], v);
@@ -113,10 +111,36 @@ void kd_order(int32_t *idx, int64_t n, const float *keys, int64_t block) {
       const float ka = keys[4 * (size_t)a + axis], kb = keys[4 * (size_t)b + axis];
       return ka < kb || (ka == kb && a < b);
     };
-    tmp.assign(r, r + s.n);
-    std::nth_element(tmp.begin(), tmp.begin() + s.m, tmp.end(), less);
-    const int32_t pivot = tmp[(size_t)s.m];
-    std::stable_partition(r, r + s.n, [&](int32_t a) { return less(a, pivot); });
+    tmp.assign(r, r + len);
+    std::nth_element(tmp.begin(), tmp.begin() + m, tmp.end(), less);
+    const int32_t pivot = tmp[(size_t)m];
+    std::stable_partition(r, r + len, [&](int32_t a) { return less(a, pivot); });
+  };
+  const int64_t ns = kd_splits(n, block, nullptr, nullptr, nullptr);
+  std::vector<KdSplit> sp((size_t)ns);
+  kd_splits(n, block, sp.data(), nullptr, nullptr);
+  for (const KdSplit &s : sp) split_range(idx + s.start, s.n, s.m);
+  // inside each block (the last one shorter) the splits go on down to single
+  // entries, m = n / 2, level by level
+  for (int64_t b0 = 0; b0 < n; b0 += block) {
+    const int64_t c = std::min<int64_t>(block, n - b0);
+    std::vector<std::pair<int64_t, int64_t>> cur{{b0, c}}, next;
+    bool any = true;
+    while (any) {
+      any = false;
+      next.clear();
+      for (const auto &rg : cur) {
+        if (rg.second < 2) {
+          next.push_back(rg);
+          continue;
+        }
+        any = true;
+        split_range(idx + rg.first, rg.second, rg.second / 2);
+        next.push_back({rg.first, rg.second / 2});
+        next.push_back({rg.first + rg.second / 2, rg.second - rg.second / 2});
+      }
+      cur.swap(next);
+    }
   }
 }
 

@@ -38,9 +38,11 @@ inline size_t align256(size_t v) { return (v + 255) / 256 * 256; }
 // entries (by key, ties by index) and the rest, m = n / 2 rounded up to a
 // multiple of `block` (so every block but the last is full), each part
 // keeping the order the range had; the parts split again until no range is
-// longer than `block`.  The splits depend on the entry count alone: level by
-// level, split ranges only (a range of at most `block` entries stays as it
-// is).  The device builds the order with these splits.
+// longer than `block`; each final range (a block, the last one shorter) is
+// then sorted along its own widest axis (ties by index).  The splits depend
+// on the entry count alone: level by level, split ranges only (a range of at
+// most `block` entries stays as it is).  The device builds the order with
+// these splits.
 struct KdSplit {
   int32_t start, n, m, pad;
 };

@@ -19,6 +19,12 @@ hipError_t launch_iota(int32_t *perm, int64_t n, hipStream_t st);
 hipError_t launch_kd_level(const float *keys, int32_t *perm, int32_t *tmp,
                            const host::KdSplit *splits, int64_t n_splits, hipStream_t st);
 
+// After the last level: inside every block of kBlockSegs entries of perm
+// (the last one shorter) the splits continue down to single entries, a range
+// of n entries splitting into its n/2 smallest along its widest axis and the
+// rest.
+hipError_t launch_kd_leaves(const float *keys, int32_t *perm, int64_t n_seg, hipStream_t st);
+
 // dpstart[i] = sum over j < i of the member count of segment perm[j]
 // (cnt_flags bits 0..15); the total must fit in int32.
 hipError_t launch_point_offsets(const int32_t *perm, const int32_t *cnt_flags, int64_t n_seg,

@@ -82,6 +82,30 @@ static void kd_ordering() {
       for (int i = s.start + s.m; i < s.start + s.n; ++i) rmin = std::min(rmin, key(idx[i]));
       CHECK(lmax < rmin);
     }
+    // inside every block the first half of each halving range below the
+    // rest (checked on the top halving: the block's first n / 2 entries)
+    for (int64_t b0 = 0; b0 < n; b0 += 64) {
+      const int64_t c = std::min<int64_t>(64, n - b0);
+      if (c < 2) continue;
+      float lo[4], hi[4];
+      for (int f = 0; f < 4; ++f) {
+        lo[f] = 1e30f;
+        hi[f] = -1e30f;
+      }
+      for (int64_t i = b0; i < b0 + c; ++i)
+        for (int f = 0; f < 4; ++f) {
+          lo[f] = std::min(lo[f], keys[4 * (size_t)idx[i] + f]);
+          hi[f] = std::max(hi[f], keys[4 * (size_t)idx[i] + f]);
+        }
+      int ax = 0;
+      for (int f = 1; f < 4; ++f)
+        if (hi[f] - lo[f] > hi[ax] - lo[ax]) ax = f;
+      auto key = [&](int32_t a) { return std::make_pair(keys[4 * (size_t)a + ax], a); };
+      std::pair<float, int32_t> lmax(-1e30f, -1), rmin(1e30f, 1 << 30);
+      for (int64_t i = b0; i < b0 + c / 2; ++i) lmax = std::max(lmax, key(idx[i]));
+      for (int64_t i = b0 + c / 2; i < b0 + c; ++i) rmin = std::min(rmin, key(idx[i]));
+      CHECK(lmax < rmin);
+    }
   }
 }
 

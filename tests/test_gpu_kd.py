@@ -2,7 +2,8 @@
 segment order it produces equals a numpy rendering of the same splits (a
 range longer than a block splits along its widest key axis into its m
 smallest entries by key, ties by segment number, and the rest, each part
-keeping its order; m = n/2 rounded up to a multiple of the block).  Sizes
+keeping its order; m = n/2 rounded up to a multiple of the block; inside
+each block the splits go on, m = n/2, down to single segments).  Sizes
 from a single split to ranges of tens of thousands of segments (several
 partition chunks per workgroup), with tied keys, zero order scales and one
 point per segment."""
@@ -35,36 +36,53 @@ def _segment_keys(ps, seg_len, order_scale):
     return np.array(rows, dtype=np.float32).reshape(-1, 4)
 
 
-def _kd_reference(keys):
-    S = keys.shape[0]
-    idx = np.arange(S, dtype=np.int64)
-    ranges = [(0, S)]
+def _split(idx, keys, s, n, m):
+    """idx[s:s+n] into its m smallest by (key on the range's widest axis,
+    segment number) and the rest, each part keeping its order."""
+    r = idx[s:s + n].copy()
+    k = keys[r]
+    ext = k.max(axis=0) - k.min(axis=0)
+    ax = 0
+    for f in range(1, 4):
+        if ext[f] > ext[ax]:
+            ax = f
+    order = np.lexsort((r, k[:, ax] + np.float32(0.0)))  # -0 as +0
+    left = np.zeros(n, dtype=bool)
+    left[order[:m]] = True
+    idx[s:s + n] = np.concatenate([r[left], r[~left]])
+
+
+def _levels(ranges, idx, keys, m_of):
     while True:
         nxt, split = [], False
         for s, n in ranges:
-            if n <= BLOCK:
+            m = m_of(n)
+            if m is None:
                 nxt.append((s, n))
                 continue
-            m = ((n // 2 + BLOCK - 1) // BLOCK) * BLOCK
-            if m >= n:
-                m = (n - 1) // BLOCK * BLOCK
-            r = idx[s:s + n].copy()
-            k = keys[r]
-            ext = k.max(axis=0) - k.min(axis=0)
-            ax = 0
-            for f in range(1, 4):
-                if ext[f] > ext[ax]:
-                    ax = f
-            kv = k[:, ax] + np.float32(0.0)  # -0 as +0
-            order = np.lexsort((r, kv))
-            left = np.zeros(n, dtype=bool)
-            left[order[:m]] = True
-            idx[s:s + n] = np.concatenate([r[left], r[~left]])
+            _split(idx, keys, s, n, m)
             nxt += [(s, m), (s + m, n - m)]
             split = True
         ranges = nxt
         if not split:
-            return idx
+            return
+
+
+def _block_m(n):
+    if n <= BLOCK:
+        return None
+    m = ((n // 2 + BLOCK - 1) // BLOCK) * BLOCK
+    return (n - 1) // BLOCK * BLOCK if m >= n else m
+
+
+def _kd_reference(keys):
+    S = keys.shape[0]
+    idx = np.arange(S, dtype=np.int64)
+    _levels([(0, S)], idx, keys, _block_m)
+    # inside each block the splits go on down to single entries, m = n // 2
+    _levels([(b, min(BLOCK, S - b)) for b in range(0, S, BLOCK)], idx, keys,
+            lambda n: n // 2 if n >= 2 else None)
+    return idx
 
 
 @pytest.mark.parametrize("n_traj,n_pts,seg_len,order_scale,dups", [
