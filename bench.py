@@ -45,14 +45,16 @@ BF16_MFMA_PEAK_TFLOPS = 2500.0
 # HBM traffic of one learned-radius search launch on this workload, from two
 # rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE, KiB per dispatch), each
 # scaled by what the counter reads for a 256 MiB device-to-device copy
-# (FETCH_SIZE x 2.00, WRITE_SIZE x 1.00): 103,004 KiB fetched (x 2 = 210.9 MB)
+# (FETCH_SIZE x 2.00, WRITE_SIZE x 1.00): 100,210 KiB fetched (x 2 = 205.2 MB)
 # and 40,451 KiB written (41.4 MB).  It describes the kernel built from the
-# sources with this SHA-256 (the search kernel's sources and the C header)
-# only; after any change to them the figure is reported as null.
-KERNEL_SOURCES = ("query.hip", "query.h", "bounds.h", "wave.h", "gka.h", "tnn_internal.h")
+# sources with this SHA-256 (the search kernel's sources, the index build's
+# ordering of segments and points, and the C header) only; after any change
+# to them the figure is reported as null.
+KERNEL_SOURCES = ("query.hip", "query.h", "bounds.h", "wave.h", "gka.h", "tnn_internal.h",
+                  "build.hip", "host.cpp")
 MEASURED_TRAFFIC = {
-    "sha256": "6bf1c0e3a04856df96f2a2974eb9ede95d6db14747f12b2735a3b253de65ff42",
-    "bytes_per_launch": 252.4e6,
+    "sha256": "523b82cfe86b9923fe2d4b5965b4b38ae55a306f1de9a4a8e1f565a91c6c5463",
+    "bytes_per_launch": 246.6e6,
 }
 
 
