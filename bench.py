@@ -53,7 +53,7 @@ BF16_MFMA_PEAK_TFLOPS = 2500.0
 KERNEL_SOURCES = ("query.hip", "query.h", "bounds.h", "wave.h", "gka.h", "tnn_internal.h",
                   "build.hip", "host.cpp")
 MEASURED_TRAFFIC = {
-    "sha256": "523b82cfe86b9923fe2d4b5965b4b38ae55a306f1de9a4a8e1f565a91c6c5463",
+    "sha256": "37ee3f3e9fcf9e648d0f1adb2699adf1a87eae0df436fd356a4e1cede0a5248d",
     "bytes_per_launch": 246.6e6,
 }
 

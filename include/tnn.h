@@ -163,9 +163,11 @@ tnn_status tnn_build_segments_workspace(const int64_t *h_traj_offsets, int64_t n
  * error e_f = max |P_f - Q_f| over members P, Q the clamped Euclidean
  * projection of P on AB, computed in binary64 and rounded up to float32.
  * Segments are reordered into spatially compact blocks of 64 (recursive median
- * split along the widest axis scaled by sqrt(order_scale); NULL keeps
- * trajectory order), points are copied in segment order, and each block gets
- * the bounding box of its points.
+ * split along the widest axis scaled by sqrt(order_scale), split points on
+ * multiples of 64, ties by segment number, each part keeping its order; inside
+ * a block the halving goes on down to single segments; made on the device;
+ * NULL keeps trajectory order), points are copied in segment order, and each
+ * block gets the bounding box of its points.
  * pts: device SoA, trajectory-contiguous, times non-decreasing within each
  * trajectory (else TNN_E_UNSORTED), finite (else TNN_E_NONFINITE).
  * order_scale: host double[4] or NULL.  d_mem/bytes: device buffer of at least
