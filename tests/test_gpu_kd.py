@@ -41,3 +41,20 @@ def test_kd_order_matches_reference(n_traj, n_pts, seg_len, order_scale, dups):
     want = kd_reference(segment_keys(ps, seg_len, order_scale))
     assert got.shape == want.shape
     assert np.array_equal(got, want)
+
+
+def test_no_order_scale_keeps_trajectory_order():
+    """Without order scales the segments stay in trajectory order (no kd
+    order), and the searches still return the oracle's neighbours."""
+    import oracle
+    from gpu_util import assert_same, dev_points
+
+    ps = synth.trajectories(50, 130, 300.0, 3 * 3600.0, seed=77)
+    ix = build(ps, 8, None)
+    got = T.tnn_debug_export_index(ix)["seg_i32"][:, 0].cpu().numpy()
+    assert np.array_equal(got, np.arange(ix.n_segments))
+    qs, _ = synth.sample_queries(ps, 200, seed=78)
+    gi, gd = T.tnn_query(ix, *dev_points(qs), synth.SCALE, 0.0, 16)
+    torch.cuda.synchronize()
+    oi, od = oracle.knn(ps.soa(), qs.soa(), synth.SCALE, 0.0, 16)
+    assert_same(gi.cpu().numpy(), gd.cpu().numpy(), oi, od, "trajectory order")
