@@ -73,7 +73,7 @@ def test_inference_matches_oracle_forward(setup):
     assert np.allclose(r2.cpu().numpy(), (1.5 * np.exp(lg)) ** 2, rtol=1e-5)
 
 
-@pytest.mark.parametrize("batch", [1, 63, 64, 1000])
+@pytest.mark.parametrize("batch", [1, 63, 64, 1000, 1100])
 def test_gradient_matches_oracle_backprop(setup, batch):
     ps, ix, model, lo, hi, grids = setup
     k = 8
